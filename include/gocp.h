@@ -1,0 +1,240 @@
+/*
+ * gocp.h -- C ABI of the MI355X (gfx950) GOCP ADAPT-VQE hot path.
+ *
+ * The library maps a molecular Hamiltonian to Pauli strings, builds the
+ * excitation pool, partitions it into commuting families, and runs the
+ * statevector work of adaptive VQE on the GPU: energies, the gradient screen
+ * over the whole pool, and the fifth-order Taylor state update.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Qubit q is bit q of a basis index; |1> means occupied.  Spin-orbital /
+ *   qubit 2p+s is spatial orbital p with spin s (0 alpha, 1 beta).
+ * - A Pauli term is stored in folded form: bit masks (x, z) and a real
+ *   coefficient c such that the term maps psi to
+ *       (c P psi)[d] = c * (-1)^popcount(d & z) * psi[d ^ x].
+ *   This equals c_std * P(x, z) with P(x, z) the tensor product of I, X, Z, Y
+ *   (Y = iXZ) and c_std = c * i^popcount(x & z).
+ * - Statevectors are caller-owned device buffers of 2^n interleaved complex
+ *   numbers: GOCP_C128 = (double re, double im), GOCP_C64 = (float re,
+ *   float im).  Work with GOCP_C64 keeps every accumulation, reduction,
+ *   renormalisation and selection in FP64.
+ * - Every call returns GOCP_OK (0) or a negative status; gocp_last_error()
+ *   returns a thread-local message for the last failure.  No call throws.
+ * - Host input arrays are copied during the call; output arrays are
+ *   caller-allocated.  Handles (ham, pool) are immutable after creation,
+ *   may be shared between threads, and are freed by their *_free call.
+ * - Calls on a context are ordered on that context's HIP stream.  Calls that
+ *   return host values synchronise that stream before returning.
+ * - Host-only calls (Hamiltonian load, pool build, partition, queries) touch
+ *   no GPU and work on hosts without one.
+ */
+#ifndef GOCP_H
+#define GOCP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GOCP_OK        0
+#define GOCP_EINVAL   -1   /* bad argument (null pointer, out-of-range value)   */
+#define GOCP_ENOMEM   -2   /* host or device allocation failed                  */
+#define GOCP_EDEVICE  -3   /* HIP runtime error, or no usable gfx950 device     */
+#define GOCP_ESHAPE   -4   /* qubit counts of handles / buffers disagree        */
+#define GOCP_ENOTSUP  -5   /* outside supported sizes (1..30 qubits)            */
+#define GOCP_EBUSY    -6   /* serving: request not finished yet                 */
+#define GOCP_ENUMERIC -7   /* a non-finite value was produced                   */
+
+#define GOCP_JW 0          /* Jordan-Wigner                                     */
+#define GOCP_BK 1          /* Bravyi-Kitaev (Fenwick-tree encoding)             */
+
+#define GOCP_C128 0        /* complex128 statevector                            */
+#define GOCP_C64  1        /* complex64 statevector, FP64 accumulation          */
+
+typedef struct gocp_ctx gocp_ctx;
+typedef struct gocp_ham gocp_ham;
+typedef struct gocp_pool gocp_pool;
+typedef struct gocp_batch gocp_batch;
+typedef struct gocp_server gocp_server;
+
+/* Thread-local text of the last error (never NULL). */
+const char *gocp_last_error(void);
+/* Library version as an integer, major*10000 + minor*100 + patch. */
+int gocp_version(void);
+
+/* ======================================================================
+ * Host-only calls
+ * ==================================================================== */
+
+/*
+ * pauli_hamiltonian_load -- Eq. 2 to Eq. 3 (Sec. II.A).
+ * Builds H = e_core + sum_PQ h_PQ a+_P a_Q + 1/2 sum_PQRS <PQ|RS> a+_P a+_Q a_S a_R
+ * over 2*n_spatial spin-orbitals, with <PQ|RS> = (pr|qs) for matching spins,
+ * and maps it with `mapping` (GOCP_JW or GOCP_BK) to a sum of folded Pauli
+ * terms.  Terms whose coefficient magnitude is below 1e-12 are dropped.
+ *   h1  : n_spatial*n_spatial FP64, row-major h[p][q], symmetric.
+ *   eri : n_spatial^4 FP64, row-major (pq|rs) in chemist order.
+ * Errors: EINVAL (null pointers, n_spatial < 1), ENOTSUP (2*n_spatial > 30).
+ */
+int pauli_hamiltonian_load(int n_spatial, const double *h1, const double *eri,
+                           double e_core, int mapping, gocp_ham **out);
+
+/*
+ * Wrap an explicit folded Pauli sum (x[i], z[i], c[i]), i < n_terms, on
+ * n_qubits qubits.  Like terms are combined; |c| < 1e-12 terms dropped.  The
+ * sum must be a real symmetric matrix (every term with popcount(x&z) even).
+ * Errors: EINVAL (odd-Y term, null pointers), ENOTSUP (n_qubits > 30).
+ */
+int pauli_hamiltonian_load_terms(int n_qubits, int64_t n_terms, const uint32_t *x,
+                                 const uint32_t *z, const double *c, gocp_ham **out);
+
+/* Sizes: qubits, Pauli terms, distinct X masks (classes).  Any output may be NULL. */
+int gocp_ham_info(const gocp_ham *h, int32_t *n_qubits, int64_t *n_terms, int32_t *n_classes);
+
+/*
+ * Copy the terms, sorted by (x, z), into caller arrays of length >= capacity.
+ * Errors: EINVAL if capacity < n_terms (query n_terms with gocp_ham_info).
+ */
+int gocp_ham_terms(const gocp_ham *h, int64_t capacity, uint32_t *x, uint32_t *z, double *c);
+int gocp_ham_free(gocp_ham *h);
+
+/*
+ * pool_build -- the operator pool (Sec. II.B; sizes of Table II).
+ * Spin-conserving occupied -> virtual singles tau = a+_a a_i and doubles
+ * tau = a+_a a+_b a_j a_i (i<j occupied, a<b virtual, equal S_z), occupied
+ * spin-orbitals 0..n_electrons-1; generator A = tau - tau^+ mapped with
+ * `mapping`.  Order: singles by (i, a), then doubles by (i, j, a, b).
+ * Every generator has one X mask and 2 (single) or 8 (double) strings.
+ * Errors: EINVAL (n_electrons odd, <= 0 or >= n_qubits), ENOTSUP (> 30 qubits).
+ */
+int pool_build(int n_qubits, int n_electrons, int mapping, gocp_pool **out);
+
+/* Sizes: qubits, operators M, total strings S.  Any output may be NULL. */
+int gocp_pool_info(const gocp_pool *p, int32_t *n_qubits, int32_t *n_ops, int32_t *n_strings);
+
+/* Operator k: kind (1 single, 2 double), spin-orbital indices (i, a, -1, -1)
+ * or (i, j, a, b), and its X mask.  Errors: EINVAL if k is out of range. */
+int gocp_pool_op(const gocp_pool *p, int32_t k, int32_t *kind, int32_t idx[4], uint32_t *xmask);
+
+/* All strings: op_offsets[M+1] (CSR), z[S], c[S] folded coefficients; x per op
+ * via gocp_pool_op.  Arrays caller-allocated with the sizes from gocp_pool_info. */
+int gocp_pool_strings(const gocp_pool *p, int32_t *op_offsets, uint32_t *z, double *c);
+int gocp_pool_free(gocp_pool *p);
+
+/*
+ * gocp_partition -- Greedy Operator Commutativity Partitioning (Sec. III.A,
+ * Algorithm 1).  Edge (i, j) iff the operator commutator [A_i, A_j] != 0,
+ * evaluated exactly in integer arithmetic.  Vertices are visited by
+ * descending degree (ties: ascending pool index) and each joins the
+ * lowest-indexed family (creation order) that holds none of its neighbours,
+ * else opens a new family.  Bit-exact and deterministic.
+ *   family_of : M int32 outputs (family index of each operator).
+ *   n_families: output K.
+ *   order     : optional M int32 outputs, the visit order (may be NULL).
+ */
+int gocp_partition(const gocp_pool *p, int32_t *family_of, int32_t *n_families, int32_t *order);
+
+/* Number of conflict-graph edges and the degree of each operator (deg may be NULL). */
+int gocp_conflict_degrees(const gocp_pool *p, int64_t *n_edges, int32_t *deg);
+
+/*
+ * Basis index of the Hartree-Fock reference: occupations of spin-orbitals
+ * 0..n_electrons-1, encoded with `mapping` (BK: b = beta n over GF(2)).
+ */
+int gocp_hf_index(int n_qubits, int n_electrons, int mapping, uint64_t *index);
+
+/* ======================================================================
+ * Device calls
+ * ==================================================================== */
+
+/*
+ * Create a context on HIP device `device`, ordering its work on `stream`
+ * (a hipStream_t; NULL selects the default stream).  The context owns its
+ * scratch device memory and uploads each ham/pool once per device, on first
+ * use.  One context per host thread.
+ * Errors: EDEVICE (no such device or not gfx950).
+ */
+int gocp_ctx_create(int device, void *stream, gocp_ctx **out);
+int gocp_ctx_destroy(gocp_ctx *ctx);
+/* Change the stream of later calls (e.g. to torch's current stream). */
+int gocp_ctx_set_stream(gocp_ctx *ctx, void *stream);
+/* Block until all work queued on the context's stream has finished. */
+int gocp_ctx_synchronize(gocp_ctx *ctx);
+
+/* Write the basis state |index> into psi_dev (2^n_qubits amplitudes). */
+int gocp_state_basis(gocp_ctx *ctx, int n_qubits, uint64_t index, void *psi_dev, int dtype);
+
+/*
+ * energy -- Eq. 1: E = Re<psi|H|psi> / <psi|psi>, FP64, written to *e_out
+ * (host).  Synchronises.  Errors: ESHAPE, ENUMERIC (zero or non-finite norm).
+ */
+int energy(gocp_ctx *ctx, const gocp_ham *h, const void *psi_dev, int dtype, double *e_out);
+
+/*
+ * sigma = H psi into sigma_dev (2^n complex128, FP64 accumulation), and the
+ * energy as in `energy` into *e_out if e_out is not NULL (then synchronises).
+ */
+int gocp_apply_hamiltonian(gocp_ctx *ctx, const gocp_ham *h, const void *psi_dev, int dtype,
+                           void *sigma_dev, double *e_out);
+
+/*
+ * pool_gradients -- Eq. 4 for every pool operator, no pruning:
+ *   g_j = <psi|[H, A_j]|psi> / <psi|psi> = 2 Re<H psi|A_j psi> / <psi|psi>.
+ * g_out: M FP64 values, on the host (g_on_device = 0; synchronises) or on the
+ * device (g_on_device = 1; stream-ordered, no synchronisation).
+ * The screen runs one pass per commuting family of the pool's partition.
+ * Errors: ESHAPE (qubit counts differ).
+ */
+int pool_gradients(gocp_ctx *ctx, const gocp_ham *h, const gocp_pool *p, const void *psi_dev,
+                   int dtype, double *g_out, int g_on_device);
+
+/*
+ * taylor5_apply -- Eq. 5-6: psi <- T5(theta/s)^s psi / ||.||, in place, with
+ * T5(x) = sum_{n=0..5} x^n/n! A_k^n evaluated as the chain v_n = A_k v_{n-1},
+ * s = max(1, ceil(|theta| * ||A_k||_1 / 0.5)) substeps, and one FP64
+ * renormalisation at the end.  theta == 0 leaves psi unchanged and reports
+ * s = 0.  *n_substeps_out (may be NULL) receives s.  Stream-ordered.
+ * Errors: EINVAL (k out of range, non-finite theta).
+ */
+int taylor5_apply(gocp_ctx *ctx, const gocp_pool *p, int32_t k, double theta, void *psi_dev,
+                  int dtype, int32_t *n_substeps_out);
+
+/* ---------------------------------------------------------------------
+ * ADAPT loop (Sec. II.B with the Sec. III.B update), device-resident.
+ * One iteration: gradient screen, selection (largest |g_j|; gradients within
+ * a relative 1e-12 of the largest tie and the lowest index wins), stop if
+ * ||g||_2 < grad_tol, exact line minimisation of the energy along the chosen
+ * generator with earlier angles frozen, the taylor5 update, new energy.
+ * ------------------------------------------------------------------- */
+typedef struct {
+    double grad_tol;        /* stop when ||g||_2 < grad_tol (0: never)               */
+    int32_t max_iter;       /* operators appended at most                            */
+    int32_t use_graph;      /* 1: replay one captured hipGraph per iteration         */
+} gocp_adapt_params;
+
+typedef struct {
+    int32_t n_iter;         /* operators appended                                    */
+    int32_t converged;      /* 1 if stopped by grad_tol                              */
+    double *energies;       /* caller array, max_iter+1: E_0 (start) .. E_n_iter     */
+    int32_t *ops;           /* caller array, max_iter: chosen pool indices           */
+    double *thetas;         /* caller array, max_iter: angles                        */
+    double *gnorms;         /* caller array, max_iter+1: ||g||_2 of each screen      */
+    double *gmax;           /* caller array, max_iter+1: largest |g_j| (may be NULL) */
+    int32_t *substeps;      /* caller array, max_iter: Taylor substeps (may be NULL) */
+} gocp_adapt_result;
+
+/*
+ * adapt_solve -- ADAPT from the state in psi_dev (normally the HF state),
+ * updating psi_dev in place.  Synchronises; fills *res.
+ * Errors: ESHAPE, EINVAL (max_iter < 0, null arrays), ENUMERIC.
+ */
+int adapt_solve(gocp_ctx *ctx, const gocp_ham *h, const gocp_pool *p, void *psi_dev, int dtype,
+                const gocp_adapt_params *params, gocp_adapt_result *res);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GOCP_H */

@@ -1,0 +1,271 @@
+"""Python binding of libgocp: argument marshalling only.
+
+Every function forwards to the C ABI entry point of the same name (see
+include/gocp.h); all computation happens in the library.  Device buffers are
+torch tensors on a ROCm device (complex128 or complex64, contiguous); torch
+supplies memory and streams, nothing else.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from ._lib import load, check, AdaptParams, AdaptResult
+
+__all__ = ["MAPPINGS", "Hamiltonian", "Pool", "Context", "pauli_hamiltonian_load",
+           "pauli_hamiltonian_load_terms", "pool_build", "gocp_partition", "hf_index",
+           "state_basis", "energy", "apply_hamiltonian", "pool_gradients", "taylor5_apply",
+           "adapt_solve", "version"]
+
+MAPPINGS = {"jw": 0, "bk": 1, 0: 0, 1: 1}
+C128, C64 = 0, 1
+
+
+def _mapping(m) -> int:
+    if m not in MAPPINGS:
+        raise ValueError(f"mapping must be 'jw' or 'bk', got {m!r}")
+    return MAPPINGS[m]
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def version() -> int:
+    return load().gocp_version()
+
+
+class Hamiltonian:
+    """Handle of a folded Pauli-sum Hamiltonian (host object, uploaded on use)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        lib = load()
+        nq, nt, nc = C.c_int32(), C.c_int64(), C.c_int32()
+        check(lib.gocp_ham_info(self._h, C.byref(nq), C.byref(nt), C.byref(nc)))
+        self.n_qubits, self.n_terms, self.n_classes = nq.value, nt.value, nc.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def terms(self):
+        """(x, z, c) arrays sorted by (x, z): folded coefficients."""
+        n = self.n_terms
+        x = np.zeros(n, dtype=np.uint32)
+        z = np.zeros(n, dtype=np.uint32)
+        c = np.zeros(n, dtype=np.float64)
+        check(load().gocp_ham_terms(self._h, n, _ptr(x, C.c_uint32), _ptr(z, C.c_uint32),
+                                    _ptr(c, C.c_double)))
+        return x, z, c
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            load().gocp_ham_free(h)
+
+
+class Pool:
+    """Handle of an operator pool with its GOCP partition (host object)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        lib = load()
+        nq, m, s = C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib.gocp_pool_info(self._h, C.byref(nq), C.byref(m), C.byref(s)))
+        self.n_qubits, self.n_ops, self.n_strings = nq.value, m.value, s.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def op(self, k: int):
+        """(kind, indices, xmask) of operator k; indices padded with -1."""
+        kind = C.c_int32()
+        idx = (C.c_int32 * 4)()
+        xm = C.c_uint32()
+        check(load().gocp_pool_op(self._h, k, C.byref(kind), idx, C.byref(xm)))
+        return kind.value, tuple(i for i in idx if i >= 0), xm.value
+
+    def strings(self):
+        """(offsets[M+1], xmask per op [M], z[S], c[S])."""
+        off = np.zeros(self.n_ops + 1, dtype=np.int32)
+        z = np.zeros(self.n_strings, dtype=np.uint32)
+        c = np.zeros(self.n_strings, dtype=np.float64)
+        check(load().gocp_pool_strings(self._h, _ptr(off, C.c_int32), _ptr(z, C.c_uint32),
+                                       _ptr(c, C.c_double)))
+        xm = np.array([self.op(k)[2] for k in range(self.n_ops)], dtype=np.uint32)
+        return off, xm, z, c
+
+    def degrees(self):
+        ne = C.c_int64()
+        deg = np.zeros(self.n_ops, dtype=np.int32)
+        check(load().gocp_conflict_degrees(self._h, C.byref(ne), _ptr(deg, C.c_int32)))
+        return ne.value, deg
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            load().gocp_pool_free(h)
+
+
+def pauli_hamiltonian_load(h1, eri, e_core: float, mapping) -> Hamiltonian:
+    h1 = _f64(h1)
+    eri = _f64(eri)
+    n = h1.shape[0]
+    if h1.shape != (n, n) or eri.shape != (n, n, n, n):
+        raise ValueError("h1 must be (n, n) and eri (n, n, n, n)")
+    out = C.c_void_p()
+    check(load().pauli_hamiltonian_load(n, _ptr(h1, C.c_double), _ptr(eri, C.c_double),
+                                        float(e_core), _mapping(mapping), C.byref(out)))
+    return Hamiltonian(out)
+
+
+def pauli_hamiltonian_load_terms(n_qubits: int, x, z, c) -> Hamiltonian:
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    z = np.ascontiguousarray(z, dtype=np.uint32)
+    c = _f64(c)
+    out = C.c_void_p()
+    check(load().pauli_hamiltonian_load_terms(n_qubits, len(x), _ptr(x, C.c_uint32),
+                                              _ptr(z, C.c_uint32), _ptr(c, C.c_double),
+                                              C.byref(out)))
+    return Hamiltonian(out)
+
+
+def pool_build(n_qubits: int, n_electrons: int, mapping) -> Pool:
+    out = C.c_void_p()
+    check(load().pool_build(n_qubits, n_electrons, _mapping(mapping), C.byref(out)))
+    return Pool(out)
+
+
+def gocp_partition(pool: Pool):
+    """(family_of[M], n_families, order[M]) of Algorithm 1."""
+    fam = np.zeros(pool.n_ops, dtype=np.int32)
+    order = np.zeros(pool.n_ops, dtype=np.int32)
+    k = C.c_int32()
+    check(load().gocp_partition(pool.handle, _ptr(fam, C.c_int32), C.byref(k),
+                                _ptr(order, C.c_int32)))
+    return fam, k.value, order
+
+
+def hf_index(n_qubits: int, n_electrons: int, mapping) -> int:
+    out = C.c_uint64()
+    check(load().gocp_hf_index(n_qubits, n_electrons, _mapping(mapping), C.byref(out)))
+    return out.value
+
+
+# ---------------------------------------------------------------- device side
+
+def _state(psi):
+    import torch
+    if not psi.is_cuda:
+        raise ValueError("state must be a device tensor")
+    if not psi.is_contiguous():
+        raise ValueError("state must be contiguous")
+    if psi.dtype == torch.complex128:
+        return C.c_void_p(psi.data_ptr()), C128
+    if psi.dtype == torch.complex64:
+        return C.c_void_p(psi.data_ptr()), C64
+    raise ValueError("state must be complex128 or complex64")
+
+
+class Context:
+    """A device context bound to a HIP device and stream (torch's current one by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+        self._c = C.c_void_p()
+        check(load().gocp_ctx_create(device, C.c_void_p(sp), C.byref(self._c)))
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._c
+
+    def set_stream(self, stream):
+        sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+        check(load().gocp_ctx_set_stream(self._c, C.c_void_p(sp)))
+
+    def synchronize(self):
+        check(load().gocp_ctx_synchronize(self._c))
+
+    def close(self):
+        c, self._c = getattr(self, "_c", None), None
+        if c:
+            load().gocp_ctx_destroy(c)
+
+    def __del__(self):
+        self.close()
+
+
+def state_basis(ctx: Context, n_qubits: int, index: int, psi):
+    p, dt = _state(psi)
+    check(load().gocp_state_basis(ctx.handle, n_qubits, index, p, dt))
+
+
+def energy(ctx: Context, ham: Hamiltonian, psi) -> float:
+    p, dt = _state(psi)
+    e = C.c_double()
+    check(load().energy(ctx.handle, ham.handle, p, dt, C.byref(e)))
+    return e.value
+
+
+def apply_hamiltonian(ctx: Context, ham: Hamiltonian, psi, sigma, want_energy: bool = True):
+    import torch
+    if sigma.dtype != torch.complex128 or not sigma.is_cuda or not sigma.is_contiguous():
+        raise ValueError("sigma must be a contiguous complex128 device tensor")
+    p, dt = _state(psi)
+    e = C.c_double()
+    check(load().gocp_apply_hamiltonian(ctx.handle, ham.handle, p, dt, C.c_void_p(sigma.data_ptr()),
+                                        C.byref(e) if want_energy else None))
+    return e.value if want_energy else None
+
+
+def pool_gradients(ctx: Context, ham: Hamiltonian, pool: Pool, psi, out=None):
+    """Gradients of every pool operator; host numpy array, or into a device tensor `out`."""
+    p, dt = _state(psi)
+    if out is None:
+        g = np.zeros(pool.n_ops, dtype=np.float64)
+        check(load().pool_gradients(ctx.handle, ham.handle, pool.handle, p, dt,
+                                    _ptr(g, C.c_double), 0))
+        return g
+    check(load().pool_gradients(ctx.handle, ham.handle, pool.handle, p, dt,
+                                C.cast(C.c_void_p(out.data_ptr()), C.POINTER(C.c_double)), 1))
+    return out
+
+
+def taylor5_apply(ctx: Context, pool: Pool, k: int, theta: float, psi) -> int:
+    p, dt = _state(psi)
+    s = C.c_int32()
+    check(load().taylor5_apply(ctx.handle, pool.handle, k, float(theta), p, dt, C.byref(s)))
+    return s.value
+
+
+def adapt_solve(ctx: Context, ham: Hamiltonian, pool: Pool, psi, max_iter: int,
+                grad_tol: float = 0.0, use_graph: bool = True):
+    """Run ADAPT in place on psi; returns a dict of per-iteration records."""
+    p, dt = _state(psi)
+    n = max_iter
+    e = np.zeros(n + 1)
+    ops = np.zeros(max(n, 1), dtype=np.int32)
+    th = np.zeros(max(n, 1))
+    gn = np.zeros(n + 1)
+    gm = np.zeros(n + 1)
+    ns = np.zeros(max(n, 1), dtype=np.int32)
+    res = AdaptResult(0, 0, _ptr(e, C.c_double), _ptr(ops, C.c_int32), _ptr(th, C.c_double),
+                      _ptr(gn, C.c_double), _ptr(gm, C.c_double), _ptr(ns, C.c_int32))
+    prm = AdaptParams(float(grad_tol), int(max_iter), 1 if use_graph else 0)
+    check(load().adapt_solve(ctx.handle, ham.handle, pool.handle, p, dt, C.byref(prm), C.byref(res)))
+    k = res.n_iter
+    nscr = k + (1 if res.converged else 0)
+    return dict(n_iter=k, converged=bool(res.converged), energies=e[:k + 1], ops=ops[:k].tolist(),
+                thetas=th[:k], gnorms=gn[:nscr], gmax=gm[:nscr], substeps=ns[:k].tolist())

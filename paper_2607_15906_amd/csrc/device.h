@@ -1,0 +1,109 @@
+// Device-side data structures shared by the HIP sources (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "internal.h"
+
+namespace gocp {
+
+// Waves per workgroup of the tile kernels, and lanes per wave on CDNA.
+constexpr int kWave = 64;
+constexpr int kNW = 16;
+constexpr int kTile = kWave;           // amplitudes per tile (one per lane)
+constexpr int kPairBlock = 256;        // threads (= amplitude pairs) per pair-kernel block
+
+// A folded Pauli string as the kernels read it: 16 bytes, one scalar load.
+struct HTerm {
+    double c;
+    uint32_t z;
+    uint32_t pad;
+};
+
+// An X-mask class of H (or a pool operator): its mask and string range.
+struct HClass {
+    uint32_t x;
+    int32_t s0, s1;
+    int32_t pad;
+};
+
+// Per-iteration ADAPT state of one instance, resident in device memory.
+struct AdaptState {
+    int32_t iter;          // operators appended so far
+    int32_t max_iter;
+    int32_t done;          // set when converged or max_iter reached
+    int32_t converged;
+    int32_t jsel;          // operator chosen by the current screen
+    int32_t nsub;          // Taylor substeps of the current update
+    int32_t status;        // 0 ok, else a GOCP_E* code raised on the device
+    int32_t pad0;
+    double grad_tol;
+    double theta;          // angle of the current update
+    double e_num;          // sum Re<psi|sigma> of the stored state
+    double nrm;            // sum |psi|^2 of the stored state
+    double energy;         // e_num / nrm
+    double gnorm, gmax;
+    double pred;           // line-search landscape value at theta
+    // history (device arrays; may be null for one-shot calls)
+    double *hist_e;        // max_iter + 1
+    int32_t *hist_op;      // max_iter
+    double *hist_theta;    // max_iter
+    double *hist_gnorm;    // max_iter + 1
+    double *hist_gmax;     // max_iter + 1
+    int32_t *hist_nsub;    // max_iter
+    double *hist_pred;     // max_iter
+    double *g;             // M gradients of the latest screen
+};
+
+// One instance as the kernels see it.
+struct InstDev {
+    // Hamiltonian, grouped by X mask
+    const HClass *hcls;
+    const HTerm *hterm;
+    const int32_t *cls_split;   // kNW + 1: class range of each wave
+    // pool
+    const HClass *pop;          // one record per operator
+    const HTerm *pterm;
+    const double *op_norm1;
+    const int32_t *op_sched;    // pool indices in family order
+    const int32_t *op_split;    // kNW + 1: range of op_sched for each wave
+    // buffers (psi, v, w in the state precision; sigma FP64)
+    void *psi;
+    double2 *sigma;
+    void *v;
+    void *w;
+    double *part_e;             // n_tiles
+    double *part_n;             // n_tiles
+    double *part_g;             // n_tiles * M
+    double *part_l;             // 3 * n_tiles + 2 * n_pblk (line-search dots)
+    double *part_t;             // n_pblk (Taylor norms)
+    int32_t *counters;          // 4 arrival counters (tile, grad, line, pair)
+    AdaptState *st;
+    int32_t n_qubits;
+    int32_t M;
+    int32_t n_tiles;
+    int32_t n_pblk;
+};
+
+struct DeviceHam {
+    int device = -1;
+    HClass *hcls = nullptr;
+    HTerm *hterm = nullptr;
+    int32_t *cls_split = nullptr;
+};
+
+struct DevicePool {
+    int device = -1;
+    HClass *pop = nullptr;
+    HTerm *pterm = nullptr;
+    double *op_norm1 = nullptr;
+    int32_t *op_sched = nullptr;
+    int32_t *op_split = nullptr;
+};
+
+void hip_check(hipError_t e, const char *what);
+
+}  // namespace gocp

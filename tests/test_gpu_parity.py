@@ -1,0 +1,240 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Sizes: 4 qubits (one partial tile and a partial pair block: the ragged case),
+8 qubits (several tiles), 12 and 14 qubits (the paper's register sizes,
+hundreds of tiles), 16 qubits for sampled checks.  Tolerances: FP64 path
+1e-12 relative on energies and gradients (rounding of sums of a few thousand
+terms), 1e-10 Ha on ADAPT energies; complex64 states: 1e-6 Ha and fidelity
+1 - 1e-6.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle.mapping import hamiltonian, hf_index
+from oracle.pool import pool_operators
+from oracle.statevec import apply_h, energy as o_energy, gradients as o_gradients, taylor5 as o_taylor5, select
+from oracle.adapt import adapt_run
+from workloads import molecular_integrals, electron_count
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2607_15906_amd as g
+    return g
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    return g.Context(0)
+
+
+_cache = {}
+
+
+def system(g, nq, mapping, seed=None):
+    key = (nq, mapping, seed)
+    if key not in _cache:
+        n = nq // 2
+        ne = electron_count(n)
+        h1, eri, ec = molecular_integrals(n, nq if seed is None else seed)
+        H = hamiltonian(h1, eri, ec, mapping)
+        ops = [A for _, _, A in pool_operators(nq, ne, mapping)]
+        _cache[key] = dict(H=H, ops=ops, ne=ne, hf=hf_index(nq, ne, mapping),
+                           gH=g.pauli_hamiltonian_load(h1, eri, ec, mapping),
+                           gP=g.pool_build(nq, ne, mapping))
+    return _cache[key]
+
+
+def rand_state(nq, seed, complex_=True):
+    rng = np.random.default_rng(seed)
+    psi = rng.standard_normal(1 << nq) + (1j * rng.standard_normal(1 << nq) if complex_ else 0)
+    return (psi / np.linalg.norm(psi)).astype(np.complex128)
+
+
+def to_dev(psi, dtype="c128"):
+    t = torch.from_numpy(np.ascontiguousarray(psi))
+    if dtype == "c64":
+        t = t.to(torch.complex64)
+    return t.to("cuda")
+
+
+@pytest.mark.parametrize("nq", [4, 8, 12, 14])
+@pytest.mark.parametrize("mapping", ["jw", "bk"])
+def test_energy_and_sigma(g, ctx, nq, mapping):
+    _say(f"[energy] nq={nq} {mapping}")
+    s = system(g, nq, mapping)
+    psi = rand_state(nq, 10 + nq)
+    sig_ref = apply_h(s["H"], psi)
+    e_ref = o_energy(s["H"], psi, sig_ref)
+    d = to_dev(psi)
+    e = g.energy(ctx, s["gH"], d)
+    assert abs(e - e_ref) <= 1e-12 * max(1.0, abs(e_ref))
+    sig = torch.zeros(1 << nq, dtype=torch.complex128, device="cuda")
+    e2 = g.apply_hamiltonian(ctx, s["gH"], d, sig)
+    assert e2 == e                                           # deterministic
+    err = np.abs(sig.cpu().numpy() - sig_ref).max()
+    assert err <= 1e-12 * max(1.0, np.abs(sig_ref).max())
+
+
+@pytest.mark.parametrize("nq", [4, 8, 12, 14])
+@pytest.mark.parametrize("mapping", ["jw", "bk"])
+def test_pool_gradients(g, ctx, nq, mapping):
+    _say(f"[grad] nq={nq} {mapping}")
+    s = system(g, nq, mapping)
+    psi = rand_state(nq, 20 + nq) * 1.7          # unnormalised on purpose
+    g_ref = o_gradients(s["ops"], psi, apply_h(s["H"], psi))
+    gg = g.pool_gradients(ctx, s["gH"], s["gP"], to_dev(psi))
+    assert np.abs(gg - g_ref).max() <= 1e-12 * max(1.0, np.abs(g_ref).max())
+    # device output variant
+    out = torch.zeros(s["gP"].n_ops, dtype=torch.float64, device="cuda")
+    g.pool_gradients(ctx, s["gH"], s["gP"], to_dev(psi), out=out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), gg)
+
+
+def test_gradients_at_hf_full_14q(g, ctx):
+    _say("[grad] hf 14q")
+    s = system(g, 14, "jw")
+    psi = np.zeros(1 << 14, dtype=np.complex128)
+    psi[s["hf"]] = 1.0
+    g_ref = o_gradients(s["ops"], psi, apply_h(s["H"], psi))
+    gg = g.pool_gradients(ctx, s["gH"], s["gP"], to_dev(psi))
+    assert np.abs(gg - g_ref).max() <= 1e-13
+    assert select(gg)[0] == select(g_ref)[0]
+
+
+@pytest.mark.parametrize("nq,j,theta", [(4, 0, 0.3), (4, 2, -2.2), (8, 5, 1.1), (8, 20, -0.05),
+                                        (12, 40, 0.9), (14, 3, -1.6), (14, 150, 2.9)])
+@pytest.mark.parametrize("mapping", ["jw", "bk"])
+def test_taylor5(g, ctx, nq, j, theta, mapping):
+    _say(f"[taylor] nq={nq} j={j} theta={theta} {mapping}")
+    s = system(g, nq, mapping)
+    psi = rand_state(nq, 30 + nq + j)
+    ref, s_ref = o_taylor5(s["ops"][j], theta, psi)
+    d = to_dev(psi)
+    ns = g.taylor5_apply(ctx, s["gP"], j, theta, d)
+    assert ns == s_ref
+    assert np.abs(d.cpu().numpy() - ref).max() <= 1e-13
+
+
+def test_taylor5_theta_zero_is_noop(g, ctx):
+    s = system(g, 8, "jw")
+    psi = rand_state(8, 5)
+    d = to_dev(psi)
+    assert g.taylor5_apply(ctx, s["gP"], 3, 0.0, d) == 0
+    assert np.array_equal(d.cpu().numpy(), psi)
+
+
+def test_state_basis_and_hf_energy(g, ctx):
+    s = system(g, 12, "bk")
+    d = torch.empty(1 << 12, dtype=torch.complex128, device="cuda")
+    g.state_basis(ctx, 12, s["hf"], d)
+    torch.cuda.synchronize()
+    ref = np.zeros(1 << 12, dtype=np.complex128)
+    ref[s["hf"]] = 1.0
+    assert np.array_equal(d.cpu().numpy(), ref)
+    assert abs(g.energy(ctx, s["gH"], d) - o_energy(s["H"], ref)) < 1e-12
+
+
+def test_shape_errors(g, ctx):
+    s12 = system(g, 12, "jw")
+    s14 = system(g, 14, "jw")
+    d = to_dev(rand_state(12, 1))
+    with pytest.raises(g.GocpError) as e:
+        g.pool_gradients(ctx, s12["gH"], s14["gP"], d)
+    assert e.value.code == -4
+    with pytest.raises(g.GocpError):
+        g.taylor5_apply(ctx, s12["gP"], s12["gP"].n_ops, 0.1, d)
+
+
+def _adapt_gpu(g, ctx, s, nq, iters, dtype="c128", tol=0.0, use_graph=True):
+    psi = np.zeros(1 << nq, dtype=np.complex128)
+    psi[s["hf"]] = 1.0
+    d = to_dev(psi, dtype)
+    r = g.adapt_solve(ctx, s["gH"], s["gP"], d, iters, grad_tol=tol, use_graph=use_graph)
+    return r, d.cpu().numpy().astype(np.complex128)
+
+
+def _check_against_oracle(s, r, psi_gpu, iters, tol=0.0, etol=1e-10):
+    """Follow the GPU's operator choices in the oracle; each choice must be a
+    valid selection there, and energies, angles and the state must agree."""
+    hf = np.zeros_like(psi_gpu)
+    hf[s["hf"]] = 1.0
+    o = adapt_run(s["H"], s["ops"], hf, iters, grad_tol=tol, forced_ops=r["ops"] + [0],
+                  keep_gradients=True)
+    assert len(o["ops"]) == r["n_iter"]
+    for k, j in enumerate(r["ops"]):
+        a = np.abs(o["grads"][k])
+        assert a[j] >= a.max() * (1 - 1e-9), (k, j, a[j], a.max())
+    assert np.abs(np.array(o["energies"]) - r["energies"]).max() <= etol
+    assert np.abs(np.array(o["thetas"]) - r["thetas"]).max() <= 1e-8
+    assert np.abs(np.array(o["gnorms"]) - r["gnorms"]).max() <= 1e-9
+    assert o["substeps"] == r["substeps"]
+    fid = abs(np.vdot(o["psi"], psi_gpu)) ** 2
+    assert fid >= 1 - 1e-12
+    return o
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_adapt_4q_10_iterations(g, ctx, use_graph):
+    _say(f"[adapt] 4q graph={use_graph}")
+    s = system(g, 4, "jw")
+    r, psi = _adapt_gpu(g, ctx, s, 4, 10, use_graph=use_graph)
+    _check_against_oracle(s, r, psi, 10)
+
+
+@pytest.mark.parametrize("mapping", ["jw", "bk"])
+def test_adapt_12q_30_iterations(g, ctx, mapping):
+    _say(f"[adapt] 12q {mapping}")
+    s = system(g, 12, mapping)
+    r, psi = _adapt_gpu(g, ctx, s, 12, 30)
+    assert r["n_iter"] == 30
+    _check_against_oracle(s, r, psi, 30)
+
+
+def test_adapt_12q_jw_equals_bk(g, ctx):
+    rj, _ = _adapt_gpu(g, ctx, system(g, 12, "jw"), 12, 30)
+    rb, _ = _adapt_gpu(g, ctx, system(g, 12, "bk"), 12, 30)
+    assert rj["ops"] == rb["ops"]
+    assert np.abs(rj["energies"] - rb["energies"]).max() <= 1e-10
+
+
+def test_adapt_convergence_stop(g, ctx):
+    s = system(g, 4, "jw")
+    r, psi = _adapt_gpu(g, ctx, s, 4, 50, tol=1e-6)
+    assert r["converged"] and r["n_iter"] < 50
+    assert len(r["gnorms"]) == r["n_iter"] + 1 and r["gnorms"][-1] < 1e-6
+    _check_against_oracle(s, r, psi, 50, tol=1e-6)
+
+
+def test_adapt_14q_first_iterations(g, ctx):
+    _say("[adapt] 14q 4 iterations")
+    s = system(g, 14, "jw")
+    r, psi = _adapt_gpu(g, ctx, s, 14, 4)
+    _check_against_oracle(s, r, psi, 4)
+
+
+@pytest.mark.parametrize("mapping", ["jw", "bk"])
+def test_complex64_form_14q(g, ctx, mapping):
+    """complex64 statevector with FP64 accumulation against the FP64 path."""
+    _say(f"[c64] 14q {mapping}")
+    s = system(g, 14, mapping)
+    r64, psi64 = _adapt_gpu(g, ctx, s, 14, 30, "c128")
+    r32, psi32 = _adapt_gpu(g, ctx, s, 14, 30, "c64")
+    assert np.abs(r32["energies"] - r64["energies"]).max() <= 1e-6
+    fid = abs(np.vdot(psi64, psi32)) ** 2 / (np.vdot(psi32, psi32).real)
+    assert fid >= 1 - 1e-6
+    assert r32["ops"] == r64["ops"]
