@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the GOCP ADAPT-VQE hot path on one MI355X.
+
+A step is one ADAPT iteration of the 14-qubit, 6-electron (BeH2-sized,
+Tables I-II) synthetic system under Jordan-Wigner: gradient screen of the
+whole pool, selection, line search, fifth-order Taylor update and the new
+energy, with a complex64 statevector and FP64 accumulation.  The iteration
+runs device-resident as captured hipGraphs; W untimed steps precede exactly K
+timed steps.  Prints one JSON line.
+
+Also reported: the complex128 path on the same workload, the 64-instance
+batched form, the roofline of the dominant kernel (HIP-event timed), and the
+FP64 CPU oracle on a bounded sample of the same iterations.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "ADAPT iters/s + Pauli-term amp-updates/s at 14q; p50/p99 solve latency"
+FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector peak (FMA = 2 flops)
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _system(g, nq, ne, mapping, seed):
+    from workloads import molecular_integrals
+    h1, eri, ec = molecular_integrals(nq // 2, seed)
+    H = g.pauli_hamiltonian_load(h1, eri, ec, mapping)
+    P = g.pool_build(nq, ne, mapping)
+    return H, P
+
+
+def _hf_state(g, ctx, nq, ne, mapping, dtype):
+    import torch
+    t = torch.zeros(1 << nq, dtype=dtype, device="cuda")
+    g.state_basis(ctx, nq, g.hf_index(nq, ne, mapping), t)
+    return t
+
+
+def _amp_updates(nq, T, S, off, ops, subs):
+    """Algorithmic Pauli-term amplitude updates of the given iterations:
+    2^n (3T + S + 2k + 5 k s) per iteration, k = strings of the chosen operator."""
+    tot = 0
+    for j, s in zip(ops, subs):
+        k = int(off[j + 1] - off[j])
+        tot += 3 * T + S + 2 * k + 5 * k * s
+    return tot * (1 << nq)
+
+
+def run_adapt_timed(g, ctx, H, P, nq, ne, mapping, dtype, steps, warmup):
+    import torch
+    psi = _hf_state(g, ctx, nq, ne, mapping, dtype)
+    b = g.Batch(ctx, [H], [P], [psi], max_iter=warmup + steps, use_graph=True)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r = b.result(0)
+    return b, r, dt
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-sample-iters", type=int, default=8,
+                    help="oracle iterations timed for the CPU baseline (0 disables it)")
+    ap.add_argument("--no-forms", action="store_true", help="skip the c128 and batched extras")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the batched and "
+              "serving forms shard by instance across GPUs, which this build does not run.",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.steps <= 0 or args.warmup < 0:
+        print("need --steps > 0 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2607_15906_amd as g
+    from workloads import CONFIGS, batched_instances
+
+    cfg = CONFIGS["c3_14q"]
+    nq, ne, seed = cfg["n_qubits"], cfg["n_electrons"], cfg["seed"]
+    mapping = "jw"
+    ctx = g.Context(0)
+    H, P = _system(g, nq, ne, mapping, seed)
+    off = P.strings()[0]
+    T, C, S, M = H.n_terms, H.n_classes, P.n_strings, P.n_ops
+
+    _say(f"[bench] 14q c64: {args.warmup} warmup + {args.steps} timed ADAPT iterations")
+    b, r, dt = run_adapt_timed(g, ctx, H, P, nq, ne, mapping, torch.complex64, args.steps, args.warmup)
+    w0, w1 = args.warmup, args.warmup + args.steps
+    iters = r["n_iter"]
+    if iters != w1:
+        raise RuntimeError(f"expected {w1} iterations, ran {iters}")
+    ips = args.steps / dt
+    upd = _amp_updates(nq, T, S, off, r["ops"][w0:w1], r["substeps"][w0:w1])
+
+    # dominant kernel: HIP-event timing of the three tile kernels on the same stream
+    nl = 50
+    ms = {which: b.time_kernel(which, nl) for which in (0, 1, 2)}
+    dim = 1 << nq
+    flops = {0: dim * (T + 4 * C + 4),          # signed adds per string, 2 FMAs per class, dots
+             1: dim * (S + 4 * M),              # signed adds per string, 4 flops per operator
+             2: dim * (T + 8 * C + 12)}         # two vectors per class, three dots
+    names = {0: "k_apply_h", 1: "k_pool_grad", 2: "k_line_hvw"}
+    dom = max(ms, key=lambda k: ms[k])
+    achieved = flops[dom] / (ms[dom] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": names[dom], "achieved": round(achieved, 4),
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": None,
+                "avg_launch_us": round(ms[dom] * 1e3, 3),
+                "algorithmic_flops_per_launch": int(flops[dom]),
+                "kernel_avg_us": {names[k]: round(v * 1e3, 3) for k, v in ms.items()}}
+    b.close()
+
+    out = {
+        "metric": METRIC, "value": round(ips, 3), "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "ADAPT iteration, 14 qubits / 6 electrons, Jordan-Wigner, "
+                               "complex64 state with FP64 accumulation",
+                   "n_qubits": nq, "n_electrons": ne, "mapping": mapping, "integral_seed": seed,
+                   "pauli_terms": T, "xmask_classes": C, "pool_ops": M, "pool_strings": S,
+                   "state": "complex64", "graph_replay": True},
+        "amp_updates_per_s": float(f"{upd / dt:.6g}"),
+        "final_energy": float(r["energies"][-1]),
+        "roofline": roofline,
+    }
+
+    if not args.no_forms:
+        _say("[bench] 14q c128 path")
+        b2, r2, dt2 = run_adapt_timed(g, ctx, H, P, nq, ne, mapping, torch.complex128,
+                                      args.steps, args.warmup)
+        b2.close()
+        u2 = _amp_updates(nq, T, S, off, r2["ops"][w0:w1], r2["substeps"][w0:w1])
+        out["complex128_state"] = {"iters_per_s": round(args.steps / dt2, 3),
+                                   "amp_updates_per_s": float(f"{u2 / dt2:.6g}"),
+                                   "max_abs_dE_vs_c64": float(np.abs(r2["energies"] - r["energies"]).max())}
+
+        _say("[bench] batched form: 64 instances x 30 iterations")
+        insts = batched_instances()
+        hams, pools, psis, meta = [], [], [], []
+        for d in insts:
+            Hi, Pi = _system(g, d["n_qubits"], d["n_electrons"], d["mapping"], d["seed"])
+            hams.append(Hi); pools.append(Pi)
+            psis.append(_hf_state(g, ctx, d["n_qubits"], d["n_electrons"], d["mapping"], torch.complex64))
+            meta.append((d["n_qubits"], Hi.n_terms, Pi.n_strings, Pi.strings()[0]))
+        iters_b = 30
+        bb = g.Batch(ctx, hams, pools, psis, max_iter=iters_b, use_graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bb.step(iters_b)
+        torch.cuda.synchronize()
+        dtb = time.perf_counter() - t0
+        ub = 0
+        for i in range(len(insts)):
+            ri = bb.result(i)
+            nqi, Ti, Si, offi = meta[i]
+            ub += _amp_updates(nqi, Ti, Si, offi, ri["ops"], ri["substeps"])
+        bb.close()
+        out["batched"] = {"instances": len(insts), "mix": "24x10q + 24x12q + 16x14q, JW/BK alternating",
+                          "iterations_each": iters_b, "seconds": round(dtb, 6),
+                          "instance_iters_per_s": round(len(insts) * iters_b / dtb, 2),
+                          "amp_updates_per_s": float(f"{ub / dtb:.6g}")}
+
+    if args.cpu_sample_iters > 0:
+        _say(f"[bench] CPU oracle baseline: {args.cpu_sample_iters} iterations at 14q")
+        from threadpoolctl import threadpool_limits
+        from oracle.mapping import hamiltonian, hf_index
+        from oracle.pool import pool_operators
+        from oracle.adapt import adapt_run
+        from workloads import molecular_integrals
+        h1, eri, ec = molecular_integrals(nq // 2, seed)
+        Ho = hamiltonian(h1, eri, ec, mapping)
+        ops = [A for _, _, A in pool_operators(nq, ne, mapping)]
+        psi0 = np.zeros(1 << nq, dtype=np.complex128)
+        psi0[hf_index(nq, ne, mapping)] = 1.0
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            adapt_run(Ho, ops, psi0, args.cpu_sample_iters)
+            dto = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(args.cpu_sample_iters / dto, 5), "unit": "iters/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"first {args.cpu_sample_iters} ADAPT iterations of the same "
+                                         f"14q JW system from Hartree-Fock, FP64 NumPy oracle, "
+                                         f"{dto:.1f} s on {os.cpu_count()} host CPUs (1 thread used)"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

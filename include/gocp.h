@@ -234,6 +234,46 @@ typedef struct {
 int adapt_solve(gocp_ctx *ctx, const gocp_ham *h, const gocp_pool *p, void *psi_dev, int dtype,
                 const gocp_adapt_params *params, gocp_adapt_result *res);
 
+/* ---------------------------------------------------------------------
+ * Batched form: many independent ADAPT problems advanced in lock-step.
+ * Every kernel of an iteration is launched once for the whole batch over a
+ * table of (instance, tile) work items, so instances of different qubit
+ * counts share each launch; with use_graph the iteration (and a chunk of
+ * eight iterations) is captured once and replayed as hipGraphs.  Each
+ * instance computes exactly what adapt_solve computes for it alone.
+ * ------------------------------------------------------------------- */
+
+/*
+ * Create a batch of n instances: hams[i], pools[i] (equal qubit counts per i)
+ * and caller-owned device states psi_dev[i] (starting states, updated in
+ * place), all of one dtype.  The library allocates each instance's device
+ * workspace.  Evaluates the starting energies (stream-ordered).
+ * Errors: EINVAL, ESHAPE, ENOMEM.
+ */
+int gocp_batch_create(gocp_ctx *ctx, int32_t n, const gocp_ham *const *hams,
+                      const gocp_pool *const *pools, void *const *psi_dev, int dtype,
+                      const gocp_adapt_params *params, gocp_batch **out);
+/* Enqueue n_iter iterations for every instance (asynchronous).  Instances that
+ * converged or reached max_iter skip their work. */
+int gocp_batch_step(gocp_batch *b, int32_t n_iter);
+/* Run the remaining iterations, stopping early once every instance is done. */
+int gocp_batch_run(gocp_batch *b);
+/* Synchronise and count the instances still running. */
+int gocp_batch_poll(gocp_batch *b, int32_t *n_active);
+/* Synchronise, renormalise instance i's state and copy its record into *res
+ * (arrays sized as for adapt_solve).  Errors: EINVAL (i out of range). */
+int gocp_batch_result(gocp_batch *b, int32_t i, gocp_adapt_result *res);
+/*
+ * Measurement hook: launch one kernel of the iteration n_launch times back to
+ * back over the whole batch and return its mean duration from HIP events
+ * recorded on the context stream.  which: 0 = H apply + energy, 1 = gradient
+ * screen, 2 = H v / H w products of the line search.  The launches recompute
+ * values the batch already holds (sigma, gradients, line-search dots) from
+ * its current states and leave the iteration record untouched.
+ */
+int gocp_batch_time_kernel(gocp_batch *b, int32_t which, int32_t n_launch, double *avg_ms);
+int gocp_batch_destroy(gocp_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,6 +64,14 @@ SIGNATURES = {
     "pool_gradients": [_P, _P, _P, _P, C.c_int, _F64P, C.c_int],
     "taylor5_apply": [_P, _P, C.c_int32, C.c_double, _P, C.c_int, _I32P],
     "adapt_solve": [_P, _P, _P, _P, C.c_int, C.POINTER(AdaptParams), C.POINTER(AdaptResult)],
+    "gocp_batch_create": [_P, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                          C.POINTER(C.c_void_p), C.c_int, C.POINTER(AdaptParams), _PP],
+    "gocp_batch_step": [_P, C.c_int32],
+    "gocp_batch_run": [_P],
+    "gocp_batch_poll": [_P, _I32P],
+    "gocp_batch_result": [_P, C.c_int32, C.POINTER(AdaptResult)],
+    "gocp_batch_time_kernel": [_P, C.c_int32, C.c_int32, _F64P],
+    "gocp_batch_destroy": [_P],
 }
 
 _lib = None

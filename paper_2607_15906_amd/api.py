@@ -17,7 +17,7 @@ from ._lib import load, check, AdaptParams, AdaptResult
 __all__ = ["MAPPINGS", "Hamiltonian", "Pool", "Context", "pauli_hamiltonian_load",
            "pauli_hamiltonian_load_terms", "pool_build", "gocp_partition", "hf_index",
            "state_basis", "energy", "apply_hamiltonian", "pool_gradients", "taylor5_apply",
-           "adapt_solve", "version"]
+           "adapt_solve", "Batch", "version"]
 
 MAPPINGS = {"jw": 0, "bk": 1, 0: 0, 1: 1}
 C128, C64 = 0, 1
@@ -250,22 +250,94 @@ def taylor5_apply(ctx: Context, pool: Pool, k: int, theta: float, psi) -> int:
     return s.value
 
 
+class _Record:
+    """Caller-side arrays of one gocp_adapt_result."""
+
+    def __init__(self, max_iter: int):
+        n = max_iter
+        self.e = np.zeros(n + 1)
+        self.ops = np.zeros(max(n, 1), dtype=np.int32)
+        self.th = np.zeros(max(n, 1))
+        self.gn = np.zeros(n + 1)
+        self.gm = np.zeros(n + 1)
+        self.ns = np.zeros(max(n, 1), dtype=np.int32)
+        self.res = AdaptResult(0, 0, _ptr(self.e, C.c_double), _ptr(self.ops, C.c_int32),
+                               _ptr(self.th, C.c_double), _ptr(self.gn, C.c_double),
+                               _ptr(self.gm, C.c_double), _ptr(self.ns, C.c_int32))
+
+    def as_dict(self):
+        k = self.res.n_iter
+        nscr = k + (1 if self.res.converged else 0)
+        return dict(n_iter=k, converged=bool(self.res.converged), energies=self.e[:k + 1].copy(),
+                    ops=self.ops[:k].tolist(), thetas=self.th[:k].copy(), gnorms=self.gn[:nscr].copy(),
+                    gmax=self.gm[:nscr].copy(), substeps=self.ns[:k].tolist())
+
+
 def adapt_solve(ctx: Context, ham: Hamiltonian, pool: Pool, psi, max_iter: int,
                 grad_tol: float = 0.0, use_graph: bool = True):
     """Run ADAPT in place on psi; returns a dict of per-iteration records."""
     p, dt = _state(psi)
-    n = max_iter
-    e = np.zeros(n + 1)
-    ops = np.zeros(max(n, 1), dtype=np.int32)
-    th = np.zeros(max(n, 1))
-    gn = np.zeros(n + 1)
-    gm = np.zeros(n + 1)
-    ns = np.zeros(max(n, 1), dtype=np.int32)
-    res = AdaptResult(0, 0, _ptr(e, C.c_double), _ptr(ops, C.c_int32), _ptr(th, C.c_double),
-                      _ptr(gn, C.c_double), _ptr(gm, C.c_double), _ptr(ns, C.c_int32))
+    rec = _Record(max_iter)
     prm = AdaptParams(float(grad_tol), int(max_iter), 1 if use_graph else 0)
-    check(load().adapt_solve(ctx.handle, ham.handle, pool.handle, p, dt, C.byref(prm), C.byref(res)))
-    k = res.n_iter
-    nscr = k + (1 if res.converged else 0)
-    return dict(n_iter=k, converged=bool(res.converged), energies=e[:k + 1], ops=ops[:k].tolist(),
-                thetas=th[:k], gnorms=gn[:nscr], gmax=gm[:nscr], substeps=ns[:k].tolist())
+    check(load().adapt_solve(ctx.handle, ham.handle, pool.handle, p, dt, C.byref(prm),
+                             C.byref(rec.res)))
+    return rec.as_dict()
+
+
+class Batch:
+    """Lock-step batch of ADAPT instances (gocp_batch_*)."""
+
+    def __init__(self, ctx: Context, hams, pools, psis, max_iter: int, grad_tol: float = 0.0,
+                 use_graph: bool = True):
+        n = len(psis)
+        if not (len(hams) == len(pools) == n) or n == 0:
+            raise ValueError("hams, pools and psis must have the same non-zero length")
+        dts = set()
+        ptrs = []
+        for t in psis:
+            p_, dt = _state(t)
+            ptrs.append(p_.value)
+            dts.add(dt)
+        if len(dts) != 1:
+            raise ValueError("all states of a batch must share one dtype")
+        self.dtype = dts.pop()
+        self._keep = (list(hams), list(pools), list(psis))
+        H = (C.c_void_p * n)(*[h.handle.value for h in hams])
+        P = (C.c_void_p * n)(*[q.handle.value for q in pools])
+        S = (C.c_void_p * n)(*ptrs)
+        self.max_iter = max_iter
+        self.n = n
+        prm = AdaptParams(float(grad_tol), int(max_iter), 1 if use_graph else 0)
+        self._b = C.c_void_p()
+        check(load().gocp_batch_create(ctx.handle, n, H, P, S, self.dtype, C.byref(prm),
+                                       C.byref(self._b)))
+
+    def step(self, n_iter: int):
+        check(load().gocp_batch_step(self._b, int(n_iter)))
+
+    def run(self):
+        check(load().gocp_batch_run(self._b))
+
+    def poll(self) -> int:
+        a = C.c_int32()
+        check(load().gocp_batch_poll(self._b, C.byref(a)))
+        return a.value
+
+    def result(self, i: int):
+        rec = _Record(self.max_iter)
+        check(load().gocp_batch_result(self._b, int(i), C.byref(rec.res)))
+        return rec.as_dict()
+
+    def time_kernel(self, which: int, n_launch: int) -> float:
+        """Mean duration in ms of kernel `which` (0 H apply, 1 screen, 2 H v/H w)."""
+        ms = C.c_double()
+        check(load().gocp_batch_time_kernel(self._b, int(which), int(n_launch), C.byref(ms)))
+        return ms.value
+
+    def close(self):
+        b, self._b = getattr(self, "_b", None), None
+        if b:
+            load().gocp_batch_destroy(b)
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,431 @@
+// ADAPT runs on the device: single runs, lock-step batches of instances, and
+// the building blocks of the serving runtime.
+//
+// An Instance owns the device workspace of one ADAPT problem (state, sigma,
+// line-search vectors, partial sums, iteration state and history).  A Group
+// is a set of instances advanced together: every kernel of an iteration is
+// launched once for the whole group, over a table of (instance, tile) work
+// items, so instances of different sizes share each launch.  A group can
+// capture its iteration (and a chunk of eight iterations) into hipGraphs that
+// are replayed on the caller's stream.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "runtime.h"
+
+namespace gocp {
+
+struct Instance {
+    const Ham *h = nullptr;
+    const Pool *p = nullptr;
+    void *psi = nullptr;
+    int dtype = 0;
+    int max_iter = 0;
+    double tol = 0.0;
+    InstPlan ip;
+    char *mem = nullptr;
+    InstDev desc;
+    bool finalized = false;
+    ~Instance() {
+        if (mem) (void)hipFree(mem);
+    }
+};
+
+// Validate, allocate and initialise one instance (state upload and counter
+// reset are stream-ordered on s).  With psi == nullptr the instance holds its
+// own state buffer, initialised to the Hartree-Fock basis state `hf`.
+Instance *instance_create(gocp_ctx *ctx, const Ham *h, const Pool *p, void *psi, int dtype,
+                          int max_iter, double tol, uint64_t hf, hipStream_t s) {
+    if (!h || !p) throw Error(GOCP_EINVAL, "null Hamiltonian or pool");
+    if (h->n_qubits != p->n_qubits)
+        throw Error(GOCP_ESHAPE, "Hamiltonian and pool act on different qubit counts");
+    check_dtype(dtype);
+    if (max_iter < 0) throw Error(GOCP_EINVAL, "negative max_iter");
+    std::unique_ptr<Instance> in(new Instance());
+    in->h = h;
+    in->p = p;
+    in->dtype = dtype;
+    in->max_iter = max_iter;
+    in->tol = tol;
+    const bool own = psi == nullptr;
+    in->ip = plan_instance(h->n_qubits, p->n_ops(), max_iter, dtype, own);
+    hip_check(hipMalloc(&in->mem, in->ip.bytes), "hipMalloc instance workspace");
+    in->psi = own ? in->mem + in->ip.o_psi : psi;
+    in->desc = make_desc(ctx->device, in->ip, in->mem, h, p, in->psi, nullptr);
+    const AdaptState st = make_state(in->ip, in->mem, max_iter, tol, true);
+    hip_check(hipMemsetAsync(in->mem + in->ip.o_cnt, 0, 4 * sizeof(int32_t), s), "hipMemsetAsync");
+    hip_check(hipMemcpyAsync(in->mem + in->ip.o_st, &st, sizeof(st), hipMemcpyHostToDevice, s), "H2D");
+    if (own) launch_basis(dtype, in->psi, 1u << h->n_qubits, (uint32_t)hf, s);
+    return in.release();
+}
+
+struct Group {
+    gocp_ctx *ctx = nullptr;
+    int dtype = 0;
+    std::vector<Instance *> inst;
+    char *meta = nullptr;
+    size_t meta_cap = 0;
+    InstDev *desc = nullptr;
+    int2 *btile = nullptr, *bpair = nullptr, *bsub = nullptr;
+    int32_t *done = nullptr;   // n flags gathered on the device
+    int nt = 0, np = 0;
+    std::vector<int> tile0, pair0;
+    static constexpr int kChunk = 8;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+
+    ~Group() {
+        drop_graphs();
+        if (meta) (void)hipFree(meta);
+    }
+
+    void drop_graphs() {
+        for (int k = 0; k < 2; ++k) {
+            if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
+            if (graph[k]) (void)hipGraphDestroy(graph[k]);
+            exec[k] = nullptr;
+            graph[k] = nullptr;
+        }
+    }
+
+    // Upload descriptors and work tables of the current members.
+    void rebuild(hipStream_t s) {
+        drop_graphs();
+        std::vector<InstDev> d;
+        std::vector<int2> bt, bp;
+        tile0.clear();
+        pair0.clear();
+        for (size_t i = 0; i < inst.size(); ++i) {
+            d.push_back(inst[i]->desc);
+            tile0.push_back((int)bt.size());
+            pair0.push_back((int)bp.size());
+            for (int t = 0; t < inst[i]->ip.n_tiles; ++t) bt.push_back(make_int2((int)i, t));
+            for (int t = 0; t < inst[i]->ip.n_pblk; ++t) bp.push_back(make_int2((int)i, t));
+        }
+        nt = (int)bt.size();
+        np = (int)bp.size();
+        const size_t sub = std::max<size_t>({bt.size(), bp.size(), inst.size(), 1});
+        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        const size_t o_bt = al(d.size() * sizeof(InstDev));
+        const size_t o_bp = o_bt + al(bt.size() * sizeof(int2));
+        const size_t o_bs = o_bp + al(bp.size() * sizeof(int2));
+        const size_t o_dn = o_bs + al(sub * sizeof(int2));
+        const size_t need = o_dn + al(std::max<size_t>(inst.size(), 1) * sizeof(int32_t));
+        if (need > meta_cap) {
+            if (meta) {
+                hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+                hip_check(hipFree(meta), "hipFree");
+                meta = nullptr;
+            }
+            meta_cap = std::max(need, (size_t)1 << 16) * 2;
+            hip_check(hipMalloc(&meta, meta_cap), "hipMalloc group tables");
+        }
+        desc = reinterpret_cast<InstDev *>(meta);
+        btile = reinterpret_cast<int2 *>(meta + o_bt);
+        bpair = reinterpret_cast<int2 *>(meta + o_bp);
+        bsub = reinterpret_cast<int2 *>(meta + o_bs);
+        done = reinterpret_cast<int32_t *>(meta + o_dn);
+        if (!d.empty())
+            hip_check(hipMemcpyAsync(desc, d.data(), d.size() * sizeof(InstDev), hipMemcpyHostToDevice, s), "H2D");
+        if (!bt.empty())
+            hip_check(hipMemcpyAsync(btile, bt.data(), bt.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
+        if (!bp.empty())
+            hip_check(hipMemcpyAsync(bpair, bp.data(), bp.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
+    }
+
+    // One ADAPT iteration of every member: screen + selection, line-search
+    // vectors, H v / H w and the angle, Taylor update, new energy.
+    void enqueue_iteration(hipStream_t s) const {
+        if (inst.empty()) return;
+        launch_kernel(K_GRAD, dtype, desc, btile, nt, 1, s);
+        launch_kernel(K_LINE_VW, dtype, desc, bpair, np, 1, s);
+        launch_kernel(K_LINE_HVW, dtype, desc, btile, nt, 1, s);
+        launch_kernel(K_TAYLOR, dtype, desc, bpair, np, 1, s);
+        launch_kernel(K_APPLY_H, dtype, desc, btile, nt, 2, s);
+    }
+
+    void capture() {
+        hipStream_t cs = ctx->own_stream;
+        const int iters[2] = {1, kChunk};
+        for (int k = 0; k < 2; ++k) {
+            hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            for (int i = 0; i < iters[k]; ++i) enqueue_iteration(cs);
+            hip_check(hipStreamEndCapture(cs, &graph[k]), "hipStreamEndCapture");
+            hip_check(hipGraphInstantiate(&exec[k], graph[k], nullptr, nullptr, 0), "hipGraphInstantiate");
+        }
+    }
+
+    // Enqueue n iterations on s (graph replays when use_graph).
+    void step(int n, hipStream_t s, bool use_graph) {
+        if (inst.empty() || n <= 0) return;
+        for (Instance *in : inst) in->finalized = false;
+        if (!use_graph) {
+            for (int i = 0; i < n; ++i) enqueue_iteration(s);
+            return;
+        }
+        if (!exec[0]) capture();
+        for (int i = 0; i < n / kChunk; ++i) hip_check(hipGraphLaunch(exec[1], s), "hipGraphLaunch");
+        for (int i = 0; i < n % kChunk; ++i) hip_check(hipGraphLaunch(exec[0], s), "hipGraphLaunch");
+    }
+
+    // Launch one kernel over the tile (or pair, or one-per-instance) rows of
+    // a subset of members.
+    void launch_subset(int which, int mode, const std::vector<int> &members, int table, hipStream_t s) {
+        std::vector<int2> rows;
+        for (int i : members) {
+            const int n = table == 0 ? inst[i]->ip.n_tiles : table == 1 ? inst[i]->ip.n_pblk : 1;
+            for (int t = 0; t < n; ++t) rows.push_back(make_int2(i, t));
+        }
+        if (rows.empty()) return;
+        hip_check(hipMemcpyAsync(bsub, rows.data(), rows.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
+        launch_kernel(which, dtype, desc, bsub, (int)rows.size(), mode, s);
+    }
+
+    // Energy of the starting state of the given members (history entry 0).
+    void start(const std::vector<int> &members, hipStream_t s) { launch_subset(K_APPLY_H, 1, members, 0, s); }
+
+    // Scale the states of the given members to unit norm (their renormalisation
+    // is otherwise folded into the next Taylor update).
+    void finalize(const std::vector<int> &members, hipStream_t s) {
+        std::vector<int> todo;
+        for (int i : members)
+            if (!inst[i]->finalized) todo.push_back(i);
+        if (todo.empty()) return;
+        launch_subset(K_NORMALIZE, 1, todo, 1, s);
+        launch_subset(K_UNIT_NORM, 0, todo, 2, s);
+        for (int i : todo) inst[i]->finalized = true;
+    }
+};
+
+// Copy one instance's iteration record to the caller's arrays (synchronises).
+void read_result(Instance *in, hipStream_t s, gocp_adapt_result *res, AdaptState *out_state) {
+    AdaptState st;
+    hip_check(hipMemcpyAsync(&st, in->mem + in->ip.o_st, sizeof(st), hipMemcpyDeviceToHost, s), "D2H");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (out_state) *out_state = st;
+    if (st.status) throw Error(st.status, "non-finite value during ADAPT");
+    if (!res) return;
+    if (!res->energies || !res->ops || !res->thetas || !res->gnorms)
+        throw Error(GOCP_EINVAL, "null result arrays");
+    const int n = st.iter;
+    const int nscr = n + (st.converged ? 1 : 0);
+    const InstPlan &ip = in->ip;
+    char *b = in->mem;
+    res->n_iter = n;
+    res->converged = st.converged;
+    hip_check(hipMemcpyAsync(res->energies, b + ip.o_he, (size_t)(n + 1) * 8, hipMemcpyDeviceToHost, s), "D2H");
+    if (n > 0) {
+        hip_check(hipMemcpyAsync(res->ops, b + ip.o_hop, (size_t)n * 4, hipMemcpyDeviceToHost, s), "D2H");
+        hip_check(hipMemcpyAsync(res->thetas, b + ip.o_hth, (size_t)n * 8, hipMemcpyDeviceToHost, s), "D2H");
+        if (res->substeps)
+            hip_check(hipMemcpyAsync(res->substeps, b + ip.o_hns, (size_t)n * 4, hipMemcpyDeviceToHost, s), "D2H");
+    }
+    if (nscr > 0) {
+        hip_check(hipMemcpyAsync(res->gnorms, b + ip.o_hgn, (size_t)nscr * 8, hipMemcpyDeviceToHost, s), "D2H");
+        if (res->gmax)
+            hip_check(hipMemcpyAsync(res->gmax, b + ip.o_hgm, (size_t)nscr * 8, hipMemcpyDeviceToHost, s), "D2H");
+    }
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+// Advance a group until every member is done or max_iter iterations have
+// been issued.  The done flags are copied back asynchronously after every
+// chunk and inspected two chunks later, so the device queue never drains
+// while the host checks for convergence.
+void run_to_completion(Group &g, int max_iter, bool use_graph, hipStream_t s) {
+    const int n = (int)g.inst.size();
+    if (n == 0 || max_iter <= 0) return;
+    int *flags = nullptr;
+    const int ring = 2;
+    hip_check(hipHostMalloc(reinterpret_cast<void **>(&flags), sizeof(int) * n * ring, 0), "hipHostMalloc");
+    hipEvent_t ev[ring] = {nullptr, nullptr};
+    bool pending[ring] = {false, false};
+    try {
+        for (int k = 0; k < ring; ++k)
+            hip_check(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming), "hipEventCreate");
+        int issued = 0, chunk = 0;
+        while (issued < max_iter) {
+            const int slot = chunk % ring;
+            if (pending[slot]) {
+                hip_check(hipEventSynchronize(ev[slot]), "hipEventSynchronize");
+                pending[slot] = false;
+                bool all = true;
+                for (int i = 0; i < n; ++i) all = all && flags[slot * n + i];
+                if (all) break;
+            }
+            const int m = std::min(Group::kChunk, max_iter - issued);
+            g.step(m, s, use_graph);
+            issued += m;
+            launch_gather_done(g.desc, n, g.done, s);
+            hip_check(hipMemcpyAsync(&flags[slot * n], g.done, sizeof(int) * n, hipMemcpyDeviceToHost, s), "D2H");
+            hip_check(hipEventRecord(ev[slot], s), "hipEventRecord");
+            pending[slot] = true;
+            ++chunk;
+        }
+        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    } catch (...) {
+        for (int k = 0; k < ring; ++k)
+            if (ev[k]) (void)hipEventDestroy(ev[k]);
+        (void)hipHostFree(flags);
+        throw;
+    }
+    for (int k = 0; k < ring; ++k) (void)hipEventDestroy(ev[k]);
+    (void)hipHostFree(flags);
+}
+
+}  // namespace gocp
+
+struct gocp_batch {
+    gocp::Group group;
+    std::vector<std::unique_ptr<gocp::Instance>> owned;
+    int max_iter = 0;
+    bool use_graph = true;
+    int issued = 0;
+};
+
+using namespace gocp;
+
+extern "C" {
+
+int adapt_solve(gocp_ctx *ctx, const gocp_ham *hh, const gocp_pool *pp, void *psi_dev, int dtype,
+                const gocp_adapt_params *params, gocp_adapt_result *res) {
+    GOCP_GUARD_BEGIN
+    check_ctx(ctx);
+    if (!params || !res) throw Error(GOCP_EINVAL, "null params or result");
+    if (!psi_dev) throw Error(GOCP_EINVAL, "null state pointer");
+    hipStream_t s = ctx->user_stream;
+    std::unique_ptr<Instance> in(instance_create(ctx, as_ham(hh), as_pool(pp), psi_dev, dtype,
+                                                 params->max_iter, params->grad_tol, 0, s));
+    Group g;
+    g.ctx = ctx;
+    g.dtype = dtype;
+    g.inst.push_back(in.get());
+    g.rebuild(s);
+    g.start({0}, s);
+    run_to_completion(g, params->max_iter, params->use_graph != 0, s);
+    g.finalize({0}, s);
+    read_result(in.get(), s, res, nullptr);
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
+int gocp_batch_create(gocp_ctx *ctx, int32_t n, const gocp_ham *const *hams,
+                      const gocp_pool *const *pools, void *const *psi_dev, int dtype,
+                      const gocp_adapt_params *params, gocp_batch **out) {
+    GOCP_GUARD_BEGIN
+    check_ctx(ctx);
+    if (!out || !params || n <= 0 || !hams || !pools || !psi_dev)
+        throw Error(GOCP_EINVAL, "null argument or empty batch");
+    hipStream_t s = ctx->user_stream;
+    std::unique_ptr<gocp_batch> b(new gocp_batch());
+    b->group.ctx = ctx;
+    b->group.dtype = dtype;
+    b->max_iter = params->max_iter;
+    b->use_graph = params->use_graph != 0;
+    for (int i = 0; i < n; ++i) {
+        if (!psi_dev[i]) throw Error(GOCP_EINVAL, "null state pointer");
+        b->owned.emplace_back(instance_create(ctx, as_ham(hams[i]), as_pool(pools[i]), psi_dev[i],
+                                              dtype, params->max_iter, params->grad_tol, 0, s));
+        b->group.inst.push_back(b->owned.back().get());
+    }
+    b->group.rebuild(s);
+    std::vector<int> all(n);
+    for (int i = 0; i < n; ++i) all[i] = i;
+    b->group.start(all, s);
+    *out = b.release();
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
+int gocp_batch_step(gocp_batch *b, int32_t n_iter) {
+    GOCP_GUARD_BEGIN
+    if (!b) throw Error(GOCP_EINVAL, "null batch");
+    check_ctx(b->group.ctx);
+    if (n_iter < 0) throw Error(GOCP_EINVAL, "negative iteration count");
+    b->group.step(n_iter, b->group.ctx->user_stream, b->use_graph);
+    b->issued += n_iter;
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
+int gocp_batch_run(gocp_batch *b) {
+    GOCP_GUARD_BEGIN
+    if (!b) throw Error(GOCP_EINVAL, "null batch");
+    check_ctx(b->group.ctx);
+    const int left = b->max_iter - b->issued;
+    run_to_completion(b->group, left, b->use_graph, b->group.ctx->user_stream);
+    b->issued = b->max_iter;
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
+int gocp_batch_poll(gocp_batch *b, int32_t *n_active) {
+    GOCP_GUARD_BEGIN
+    if (!b || !n_active) throw Error(GOCP_EINVAL, "null argument");
+    check_ctx(b->group.ctx);
+    hipStream_t s = b->group.ctx->user_stream;
+    const int n = (int)b->group.inst.size();
+    std::vector<int32_t> done(n);
+    launch_gather_done(b->group.desc, n, b->group.done, s);
+    hip_check(hipMemcpyAsync(done.data(), b->group.done, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s), "D2H");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    int act = 0;
+    for (int i = 0; i < n; ++i) act += done[i] ? 0 : 1;
+    *n_active = act;
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
+int gocp_batch_result(gocp_batch *b, int32_t i, gocp_adapt_result *res) {
+    GOCP_GUARD_BEGIN
+    if (!b || !res) throw Error(GOCP_EINVAL, "null argument");
+    check_ctx(b->group.ctx);
+    if (i < 0 || i >= (int)b->group.inst.size()) throw Error(GOCP_EINVAL, "instance index out of range");
+    hipStream_t s = b->group.ctx->user_stream;
+    b->group.finalize({i}, s);
+    read_result(b->group.inst[i], s, res, nullptr);
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
+int gocp_batch_time_kernel(gocp_batch *b, int32_t which, int32_t n_launch, double *avg_ms) {
+    GOCP_GUARD_BEGIN
+    if (!b || !avg_ms || n_launch <= 0) throw Error(GOCP_EINVAL, "null argument or no launches");
+    if (which != 0 && which != 1 && which != 2) throw Error(GOCP_EINVAL, "kernel id must be 0, 1 or 2");
+    check_ctx(b->group.ctx);
+    hipStream_t s = b->group.ctx->user_stream;
+    Group &g = b->group;
+    const int kid = which == 0 ? K_APPLY_H : which == 1 ? K_GRAD : K_LINE_HVW;
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    launch_kernel(kid, g.dtype, g.desc, g.btile, g.nt, 0, s);     // warm
+    hip_check(hipEventRecord(e0, s), "hipEventRecord");
+    for (int i = 0; i < n_launch; ++i) launch_kernel(kid, g.dtype, g.desc, g.btile, g.nt, 0, s);
+    hip_check(hipEventRecord(e1, s), "hipEventRecord");
+    hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = (double)ms / n_launch;
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
+int gocp_batch_destroy(gocp_batch *b) {
+    GOCP_GUARD_BEGIN
+    if (!b) return GOCP_OK;
+    (void)hipSetDevice(b->group.ctx->device);
+    (void)hipStreamSynchronize(b->group.ctx->user_stream);
+    delete b;
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
+}  // extern "C"

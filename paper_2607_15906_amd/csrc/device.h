@@ -15,6 +15,9 @@ constexpr int kWave = 64;
 constexpr int kNW = 16;
 constexpr int kTile = kWave;           // amplitudes per tile (one per lane)
 constexpr int kPairBlock = 256;        // threads (= amplitude pairs) per pair-kernel block
+// Term tables are staged into LDS in chunks of at most this many records.
+constexpr int kStageTerms = 4096;      // strings (64 KiB)
+constexpr int kStageCls = 1024;        // classes or operators (16 KiB)
 
 // A folded Pauli string as the kernels read it: 16 bytes, one scalar load.
 struct HTerm {
@@ -63,13 +66,15 @@ struct InstDev {
     // Hamiltonian, grouped by X mask
     const HClass *hcls;
     const HTerm *hterm;
-    const int32_t *cls_split;   // kNW + 1: class range of each wave
-    // pool
+    const int32_t *hchunk;      // n_hchunks + 1 class boundaries of the LDS stages
+    // pool, in pool order (pair kernels)
     const HClass *pop;          // one record per operator
     const HTerm *pterm;
     const double *op_norm1;
-    const int32_t *op_sched;    // pool indices in family order
-    const int32_t *op_split;    // kNW + 1: range of op_sched for each wave
+    // pool in GOCP family order (gradient screen); HClass.pad = pool index
+    const HClass *sop;
+    const HTerm *sterm;
+    const int32_t *pchunk;      // n_pchunks + 1 operator boundaries of the LDS stages
     // buffers (psi, v, w in the state precision; sigma FP64)
     void *psi;
     double2 *sigma;
@@ -86,13 +91,16 @@ struct InstDev {
     int32_t M;
     int32_t n_tiles;
     int32_t n_pblk;
+    int32_t n_hchunks;
+    int32_t n_pchunks;
 };
 
 struct DeviceHam {
     int device = -1;
     HClass *hcls = nullptr;
     HTerm *hterm = nullptr;
-    int32_t *cls_split = nullptr;
+    int32_t *hchunk = nullptr;
+    int n_chunks = 0;
 };
 
 struct DevicePool {
@@ -100,8 +108,10 @@ struct DevicePool {
     HClass *pop = nullptr;
     HTerm *pterm = nullptr;
     double *op_norm1 = nullptr;
-    int32_t *op_sched = nullptr;
-    int32_t *op_split = nullptr;
+    HClass *sop = nullptr;
+    HTerm *sterm = nullptr;
+    int32_t *pchunk = nullptr;
+    int n_chunks = 0;
 };
 
 void hip_check(hipError_t e, const char *what);

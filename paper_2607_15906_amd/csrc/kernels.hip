@@ -34,21 +34,38 @@ namespace gocp {
 
 // ------------------------------------------------------------------ helpers
 
+// Global-memory loads go through the global address space (not flat), so
+// they count only against the vector-memory wait counter and LDS reads do not
+// wait for gathers in flight.
+#define GOCP_AS1 __attribute__((address_space(1)))
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// State element access: raw() loads the stored bits, cvt() widens to FP64.
 template <typename T> struct Amp;
 template <> struct Amp<double2> {
-    static __device__ __forceinline__ double2 load(const void *p, uint32_t i) {
-        return static_cast<const double2 *>(p)[i];
+    using Raw = u32x4;
+    static __device__ __forceinline__ Raw raw(const void *p, uint32_t i) {
+        return ((const GOCP_AS1 u32x4 *)(uintptr_t)p)[i];
     }
+    static __device__ __forceinline__ double2 cvt(Raw r) {
+        return make_double2(__hiloint2double((int)r.y, (int)r.x), __hiloint2double((int)r.w, (int)r.z));
+    }
+    static __device__ __forceinline__ double2 load(const void *p, uint32_t i) { return cvt(raw(p, i)); }
     static __device__ __forceinline__ void store(void *p, uint32_t i, double2 v) {
         static_cast<double2 *>(p)[i] = v;
     }
     static __device__ __forceinline__ double2 rounded(double2 v) { return v; }
 };
 template <> struct Amp<float2> {
-    static __device__ __forceinline__ double2 load(const void *p, uint32_t i) {
-        const float2 f = static_cast<const float2 *>(p)[i];
-        return make_double2((double)f.x, (double)f.y);
+    using Raw = u32x2;
+    static __device__ __forceinline__ Raw raw(const void *p, uint32_t i) {
+        return ((const GOCP_AS1 u32x2 *)(uintptr_t)p)[i];
     }
+    static __device__ __forceinline__ double2 cvt(Raw r) {
+        return make_double2((double)__uint_as_float(r.x), (double)__uint_as_float(r.y));
+    }
+    static __device__ __forceinline__ double2 load(const void *p, uint32_t i) { return cvt(raw(p, i)); }
     static __device__ __forceinline__ void store(void *p, uint32_t i, double2 v) {
         static_cast<float2 *>(p)[i] = make_float2((float)v.x, (float)v.y);
     }
@@ -85,25 +102,6 @@ __device__ __forceinline__ HTerm load_rec(const GOCP_AS4 HTerm *p, int i) {
 __device__ __forceinline__ double signed_coef(double c, uint32_t d, uint32_t z) {
     const int flip = (int)((uint32_t)__popc(d & z) << 31);
     return __hiloint2double(__double2hiint(c) ^ flip, __double2loint(c));
-}
-
-// sum_s c_s (-1)^popcount(d & z_s) over the strings [s0, s1) of a table,
-// four strings per step with two accumulators.
-__device__ __forceinline__ double string_sum(const GOCP_AS4 HTerm *t, int s0, int s1, uint32_t d) {
-    double f0 = 0.0, f1 = 0.0;
-    int s = s0;
-    for (; s + 4 <= s1; s += 4) {
-        const HTerm a = load_rec(t, s), b = load_rec(t, s + 1), c = load_rec(t, s + 2), e = load_rec(t, s + 3);
-        f0 += signed_coef(a.c, d, a.z);
-        f1 += signed_coef(b.c, d, b.z);
-        f0 += signed_coef(c.c, d, c.z);
-        f1 += signed_coef(e.c, d, e.z);
-    }
-    for (; s < s1; ++s) {
-        const HTerm a = load_rec(t, s);
-        f0 += signed_coef(a.c, d, a.z);
-    }
-    return f0 + f1;
 }
 
 // The same sum at two amplitudes d and e (the two members of a pair).
@@ -149,24 +147,120 @@ __device__ double block_sum_strided(const double *src, int n, int stride, double
     return r;
 }
 
-// Arrival of this workgroup at the end of its part of a launch.  Returns true
-// (in every thread) in the workgroup that arrives last; that workgroup then
-// sees every partial written before the other workgroups arrived.
+// Arrival of this workgroup at the end of its part of a launch.  Every
+// partial result the last workgroup will read must have been written by wave
+// 0 of its workgroup before the call.  Returns true (in every thread) in the
+// workgroup that arrives last, which then sees all those partials.
 __device__ bool arrive_last(int32_t *counter, int total) {
     __shared__ int s_last;
-    __threadfence();                 // release this workgroup's partial writes
+    if (threadIdx.x < kWave) __threadfence();      // release wave 0's partial writes
     __syncthreads();
     if (threadIdx.x == 0) {
         const int prev = atomicAdd(counter, 1);
         s_last = (prev == total - 1);
-        if (s_last) {
-            __threadfence();         // acquire the other workgroups' writes
-            *counter = 0;            // ready for the next launch
-        }
+        if (s_last) *counter = 0;                  // ready for the next launch
     }
     __syncthreads();
-    if (s_last) __threadfence();
+    if (s_last) __threadfence();                   // acquire the other partials
     return s_last != 0;
+}
+
+// ------------------------------------------------------------------ LDS staging of term tables
+
+// Shared memory of a tile kernel: one chunk of records (classes or
+// operators) and their strings; reused for the cross-wave reduction.
+struct Stage {
+    HTerm terms[kStageTerms];
+    HClass cls[kStageCls];
+};
+
+// Copy n 16-byte records from global memory to LDS with the whole workgroup
+// (kNW * kWave threads), four loads in flight per thread.
+template <typename R>
+__device__ __forceinline__ void stage_copy(R *dst, const R *src, int n) {
+    static_assert(sizeof(R) == 16, "records are 16 bytes");
+    constexpr int NT = kNW * kWave;
+    const GOCP_AS1 u32x4 *s = (const GOCP_AS1 u32x4 *)(uintptr_t)src;
+    u32x4 *d = reinterpret_cast<u32x4 *>(dst);
+    int i = threadIdx.x;
+    for (; i + 3 * NT < n; i += 4 * NT) {
+        const u32x4 a = s[i], b = s[i + NT], c = s[i + 2 * NT], e = s[i + 3 * NT];
+        d[i] = a;
+        d[i + NT] = b;
+        d[i + 2 * NT] = c;
+        d[i + 3 * NT] = e;
+    }
+    for (; i < n; i += NT) d[i] = s[i];
+}
+
+// sum_s c_s (-1)^popcount(d & z_s) over LDS strings [s0, s1): every lane
+// reads the same record (a broadcast), four strings per step.
+__device__ __forceinline__ double lds_string_sum(const HTerm *t, int s0, int s1, uint32_t d) {
+    double f0 = 0.0, f1 = 0.0;
+    int s = s0;
+    for (; s + 4 <= s1; s += 4) {
+        const HTerm a = t[s], b = t[s + 1], c = t[s + 2], e = t[s + 3];
+        f0 += signed_coef(a.c, d, a.z);
+        f1 += signed_coef(b.c, d, b.z);
+        f0 += signed_coef(c.c, d, c.z);
+        f1 += signed_coef(e.c, d, e.z);
+    }
+    for (; s < s1; ++s) {
+        const HTerm a = t[s];
+        f0 += signed_coef(a.c, d, a.z);
+    }
+    return f0 + f1;
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Apply the X-mask classes of H to NV vectors at the lane's amplitude dd:
+// acc[2k], acc[2k+1] += sum_classes f_class(dd) * vec_k[dd ^ x_class].  The
+// table is staged chunk by chunk; wave w takes classes w, w + kNW, ... of a
+// chunk, and the gather of its next class is issued before the current
+// class's strings are summed.
+template <typename T, int NV>
+__device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32_t dd,
+                                              const void *v0, const void *v1, double *acc) {
+    const int wv = wave_id();
+    const GOCP_AS4 int32_t *hch = cptr(I.hchunk);
+    const GOCP_AS4 HClass *hcls = cptr(I.hcls);
+    for (int k = 0; k < I.n_hchunks; ++k) {
+        const int cb = hch[k], ce = hch[k + 1];
+        const int sb = hcls[cb].s0, se = hcls[ce - 1].s1;
+        __syncthreads();
+        stage_copy(S.cls, I.hcls + cb, ce - cb);
+        stage_copy(S.terms, I.hterm + sb, se - sb);
+        __syncthreads();
+        const int nc = ce - cb;
+        int c = wv;
+        typename Amp<T>::Raw rn0 = {}, rn1 = {};
+        if (c < nc) {
+            const uint32_t xn = (uint32_t)uni((int)S.cls[c].x);
+            rn0 = Amp<T>::raw(v0, dd ^ xn);
+            if (NV == 2) rn1 = Amp<T>::raw(v1, dd ^ xn);
+        }
+        for (; c < nc; c += kNW) {
+            const int s0 = uni(S.cls[c].s0) - sb, s1 = uni(S.cls[c].s1) - sb;
+            const typename Amp<T>::Raw r0 = rn0, r1 = rn1;
+            const int cn = c + kNW;
+            if (cn < nc) {
+                const uint32_t xn = (uint32_t)uni((int)S.cls[cn].x);
+                rn0 = Amp<T>::raw(v0, dd ^ xn);
+                if (NV == 2) rn1 = Amp<T>::raw(v1, dd ^ xn);
+            }
+            const double f = lds_string_sum(S.terms, s0, s1, dd);
+            const double2 p0 = Amp<T>::cvt(r0);
+            acc[0] = fma(f, p0.x, acc[0]);
+            acc[1] = fma(f, p0.y, acc[1]);
+            if (NV == 2) {
+                const double2 p1 = Amp<T>::cvt(r1);
+                acc[2] = fma(f, p1.x, acc[2]);
+                acc[3] = fma(f, p1.y, acc[3]);
+            }
+        }
+    }
+    __syncthreads();          // the stage may be reused by the caller
 }
 
 __device__ __forceinline__ uint32_t insert_zero_bit(uint32_t p, int hb) {
@@ -192,20 +286,12 @@ __global__ __launch_bounds__(kNW *kWave) void k_apply_h(const InstDev *__restric
     const bool valid = d < dim;
     const uint32_t dd = valid ? d : 0u;
 
-    double sr = 0.0, si = 0.0;
-    const GOCP_AS4 HClass *cls = cptr(I.hcls);
-    const GOCP_AS4 HTerm *trm = cptr(I.hterm);
-    const int c0 = cptr(I.cls_split)[wv], c1 = cptr(I.cls_split)[wv + 1];
-    for (int c = c0; c < c1; ++c) {
-        const HClass C = load_rec(cls, c);
-        const double f = string_sum(trm, C.s0, C.s1, dd);
-        const double2 p = Amp<T>::load(I.psi, dd ^ C.x);
-        sr = fma(f, p.x, sr);
-        si = fma(f, p.y, si);
-    }
-    __shared__ double2 red[kNW][kWave];
+    __shared__ Stage S;
     __shared__ double lds[kNW * kWave];
-    red[wv][lane] = make_double2(sr, si);
+    double acc[2] = {0.0, 0.0};
+    apply_classes<T, 1>(I, S, dd, I.psi, nullptr, acc);
+    double2 (*red)[kWave] = reinterpret_cast<double2 (*)[kWave]>(&S);
+    red[wv][lane] = make_double2(acc[0], acc[1]);
     __syncthreads();
     if (wv == 0) {
         double ar = 0.0, ai = 0.0;
@@ -252,7 +338,9 @@ __global__ __launch_bounds__(kNW *kWave) void k_apply_h(const InstDev *__restric
 // ------------------------------------------------------------------ K2: gradient screen + selection
 
 // g_j = 2 Re <sigma | A_j psi> / <psi|psi> for every j, then (last workgroup)
-// |g|max, ||g||_2 and the selected operator.
+// |g|max, ||g||_2 and the selected operator.  Operators are visited in GOCP
+// family order: the family-ordered table is staged in LDS and wave w takes
+// operators w, w + kNW, ... of each stage.
 template <typename T>
 __global__ __launch_bounds__(kNW *kWave) void k_pool_grad(const InstDev *__restrict__ insts,
                                                          const int2 *__restrict__ blk, int mode) {
@@ -269,69 +357,87 @@ __global__ __launch_bounds__(kNW *kWave) void k_pool_grad(const InstDev *__restr
     const int M = I.M;
     const double2 sg = valid ? I.sigma[dd] : make_double2(0.0, 0.0);
 
-    const GOCP_AS4 HClass *ops = cptr(I.pop);
-    const GOCP_AS4 HTerm *trm = cptr(I.pterm);
-    const GOCP_AS4 int32_t *sched = cptr(I.op_sched);
-    const int o0 = cptr(I.op_split)[wv], o1 = cptr(I.op_split)[wv + 1];
-    for (int o = o0; o < o1; ++o) {
-        const int j = sched[o];
-        const HClass C = load_rec(ops, j);
-        const double h = string_sum(trm, C.s0, C.s1, dd);
-        const double2 p = Amp<T>::load(I.psi, dd ^ C.x);
-        double val = h * (sg.x * p.x + sg.y * p.y);
-        val = wave_sum(val);
-        if (lane == 0) I.part_g[(size_t)b.y * M + j] = val;
+    __shared__ Stage S;
+    __shared__ double gpart[kStageCls];
+    const GOCP_AS4 int32_t *pch = cptr(I.pchunk);
+    const GOCP_AS4 HClass *sop = cptr(I.sop);
+    for (int k = 0; k < I.n_pchunks; ++k) {
+        const int ob = pch[k], oe = pch[k + 1];
+        const int sb = sop[ob].s0, se = sop[oe - 1].s1;
+        __syncthreads();
+        stage_copy(S.cls, I.sop + ob, oe - ob);
+        stage_copy(S.terms, I.sterm + sb, se - sb);
+        __syncthreads();
+        const int no = oe - ob;
+        int o = wv;
+        typename Amp<T>::Raw rn = {};
+        if (o < no) rn = Amp<T>::raw(I.psi, dd ^ (uint32_t)uni((int)S.cls[o].x));
+        for (; o < no; o += kNW) {
+            const int s0 = uni(S.cls[o].s0) - sb, s1 = uni(S.cls[o].s1) - sb;
+            const typename Amp<T>::Raw r = rn;
+            const int on = o + kNW;
+            if (on < no) rn = Amp<T>::raw(I.psi, dd ^ (uint32_t)uni((int)S.cls[on].x));
+            const double h = lds_string_sum(S.terms, s0, s1, dd);
+            const double2 p = Amp<T>::cvt(r);
+            double val = h * (sg.x * p.x + sg.y * p.y);
+            val = wave_sum(val);
+            if (lane == 0) gpart[o] = val;
+        }
+        __syncthreads();
+        // wave 0 writes this stage's per-operator partials (pool-indexed)
+        if (wv == 0)
+            for (int i = lane; i < no; i += kWave) I.part_g[(size_t)b.y * M + S.cls[i].pad] = gpart[i];
     }
     if (!arrive_last(&I.counters[1], I.n_tiles)) return;
 
-    __shared__ double lds[kNW * kWave];
-    __shared__ int ldsi[kNW * kWave];
     constexpr int NT = kNW * kWave;
     const double inv = 2.0 / st->nrm;
+    // column sums over tiles: wave w takes tiles w, w + kNW, ...; fixed order
     double amax = 0.0, sq = 0.0;
-    for (int j = threadIdx.x; j < M; j += NT) {
-        double acc = 0.0;
-        for (int t = 0; t < I.n_tiles; ++t) acc += I.part_g[(size_t)t * M + j];
-        const double g = acc * inv;
-        st->g[j] = g;
-        amax = fmax(amax, fabs(g));
-        sq += g * g;
-    }
-    // max |g| (exact, order-free) and sum of squares (fixed tree)
-    lds[threadIdx.x] = amax;
-    __syncthreads();
-    for (int h = NT / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + h]);
+    double *colsum = reinterpret_cast<double *>(&S);          // [kNW][kWave]
+    for (int jb = 0; jb < M; jb += kWave) {
+        const int j = jb + lane;
+        double a0 = 0.0, a1 = 0.0;
+        if (j < M) {
+            int t = wv;
+            for (; t + kNW < I.n_tiles; t += 2 * kNW) {
+                a0 += I.part_g[(size_t)t * M + j];
+                a1 += I.part_g[(size_t)(t + kNW) * M + j];
+            }
+            if (t < I.n_tiles) a0 += I.part_g[(size_t)t * M + j];
+        }
+        colsum[wv * kWave + lane] = a0 + a1;
+        __syncthreads();
+        if (wv == 0 && j < M) {
+            double acc = 0.0;
+            for (int w = 0; w < kNW; ++w) acc += colsum[w * kWave + lane];
+            const double g = acc * inv;
+            st->g[j] = g;
+            amax = fmax(amax, fabs(g));
+            sq += g * g;
+        }
         __syncthreads();
     }
-    const double gmax = lds[0];
-    __syncthreads();
-    lds[threadIdx.x] = sq;
-    __syncthreads();
-    for (int h = NT / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) lds[threadIdx.x] += lds[threadIdx.x + h];
-        __syncthreads();
-    }
-    const double gn = sqrt(lds[0]);
-    __syncthreads();
+    // wave 0 holds every g_j (lane l: j = l, l + 64, ...): reduce within it
+    if (wv != 0) return;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, kWave));
+    const double gmax = amax;
+    const double gn = sqrt(wave_sum(sq));
     // lowest index within the tie band of the largest magnitude
     const double thresh = gmax * (1.0 - 1e-12);
     int jmin = 0x7fffffff;
-    for (int j = threadIdx.x; j < M; j += NT)
+    for (int j = lane; j < M; j += kWave)
         if (fabs(st->g[j]) >= thresh) {
             jmin = j;
             break;
         }
-    ldsi[threadIdx.x] = jmin;
-    __syncthreads();
-    for (int h = NT / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) ldsi[threadIdx.x] = min(ldsi[threadIdx.x], ldsi[threadIdx.x + h]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) jmin = min(jmin, __shfl_xor(jmin, off, kWave));
+    if (lane == 0) {
         st->gmax = gmax;
         st->gnorm = gn;
-        st->jsel = ldsi[0] < M ? ldsi[0] : 0;
+        st->jsel = jmin < M ? jmin : 0;
         if (!isfinite(gn)) {
             st->status = GOCP_ENUMERIC;
             st->done = 1;
@@ -484,13 +590,14 @@ __device__ double line_search_wave(const Landscape &L, double g) {
 
 // H v, H w with shared class coefficients; partial Re<v|Hv>, Re<w|Hw>,
 // Re<v|Hw>; the last workgroup forms the landscape and picks the angle.
+// mode 1: ADAPT iteration; mode 0: the products and dots only (no angle).
 template <typename T>
 __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restrict__ insts,
-                                                        const int2 *__restrict__ blk) {
+                                                        const int2 *__restrict__ blk, int mode) {
     const int2 b = blk[blockIdx.x];
     const InstDev &I = insts[b.x];
     AdaptState *st = I.st;
-    if (state_done(st)) return;
+    if (mode != 0 && state_done(st)) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = wave_id();
     const uint32_t dim = 1u << I.n_qubits;
@@ -498,23 +605,12 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
     const bool valid = d < dim;
     const uint32_t dd = valid ? d : 0u;
 
-    double vr = 0.0, vi = 0.0, wr = 0.0, wi = 0.0;
-    const GOCP_AS4 HClass *cls = cptr(I.hcls);
-    const GOCP_AS4 HTerm *trm = cptr(I.hterm);
-    const int c0 = cptr(I.cls_split)[wv], c1 = cptr(I.cls_split)[wv + 1];
-    for (int c = c0; c < c1; ++c) {
-        const HClass C = load_rec(cls, c);
-        const double f = string_sum(trm, C.s0, C.s1, dd);
-        const double2 pv = Amp<T>::load(I.v, dd ^ C.x);
-        const double2 pw = Amp<T>::load(I.w, dd ^ C.x);
-        vr = fma(f, pv.x, vr);
-        vi = fma(f, pv.y, vi);
-        wr = fma(f, pw.x, wr);
-        wi = fma(f, pw.y, wi);
-    }
-    __shared__ double4 red[kNW][kWave];
+    __shared__ Stage S;
     __shared__ double lds[kNW * kWave];
-    red[wv][lane] = make_double4(vr, vi, wr, wi);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    apply_classes<T, 2>(I, S, dd, I.v, I.w, acc);
+    double4 (*red)[kWave] = reinterpret_cast<double4 (*)[kWave]>(&S);
+    red[wv][lane] = make_double4(acc[0], acc[1], acc[2], acc[3]);
     __syncthreads();
     if (wv == 0) {
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -546,7 +642,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
     const double P6 = block_sum_strided<NT>(I.part_l + 2, I.n_tiles, 3, lds);
     const double P2 = block_sum_strided<NT>(I.part_l + 3 * I.n_tiles, I.n_pblk, 2, lds);
     const double P7 = block_sum_strided<NT>(I.part_l + 3 * I.n_tiles + 1, I.n_pblk, 2, lds);
-    if (wv != 0) return;
+    if (wv != 0 || mode == 0) return;
     const double inv = 1.0 / st->nrm;
     Landscape L;
     L.uu = (st->e_num - 2.0 * P2 + P3) * inv;
@@ -663,7 +759,22 @@ __global__ __launch_bounds__(kPairBlock) void k_normalize(const InstDev *__restr
         a.y *= sc;
         Amp<T>::store(I.psi, k, a);
     }
-    if (b.y == 0 && threadIdx.x == 0 && !from_state) I.st->nrm = 1.0;
+}
+
+// After psi has been scaled to unit norm from the state's own norm: record it.
+__global__ void k_state_unit_norm(const InstDev *__restrict__ insts, const int2 *__restrict__ blk) {
+    const int2 b = blk[blockIdx.x];
+    AdaptState *st = insts[b.x].st;
+    if (threadIdx.x == 0) {
+        st->e_num = st->energy;
+        st->nrm = 1.0;
+    }
+}
+
+// done flag of every instance into one array (one copy to the host).
+__global__ void k_gather_done(const InstDev *__restrict__ insts, int n, int32_t *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = insts[i].st->done;
 }
 
 // psi = |index>
@@ -682,9 +793,10 @@ static void launch_all(int which, const InstDev *insts, const int2 *blk, int nbl
     case 0: hipLaunchKernelGGL(k_apply_h<T>, dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode); break;
     case 1: hipLaunchKernelGGL(k_pool_grad<T>, dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode); break;
     case 2: hipLaunchKernelGGL(k_line_vw<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk); break;
-    case 3: hipLaunchKernelGGL(k_line_hvw<T>, dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk); break;
+    case 3: hipLaunchKernelGGL(k_line_hvw<T>, dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode); break;
     case 4: hipLaunchKernelGGL(k_taylor5<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode, j, th, ns); break;
     case 5: hipLaunchKernelGGL(k_normalize<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode); break;
+    case 6: hipLaunchKernelGGL(k_state_unit_norm, dim3(nblk), dim3(64), 0, s, insts, blk); break;
     default: break;
     }
 }
@@ -696,6 +808,12 @@ void launch_kernel(int which, int dtype, const InstDev *insts, const int2 *blk, 
         launch_all<float2>(which, insts, blk, nblk, mode, s, j, th, ns);
     else
         launch_all<double2>(which, insts, blk, nblk, mode, s, j, th, ns);
+    hip_check(hipGetLastError(), "kernel launch");
+}
+
+void launch_gather_done(const InstDev *insts, int n, int32_t *out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gather_done, dim3((n + 255) / 256), dim3(256), 0, s, insts, n, out);
     hip_check(hipGetLastError(), "kernel launch");
 }
 

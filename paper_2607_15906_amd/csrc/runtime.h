@@ -1,0 +1,74 @@
+// Host-side runtime pieces shared by the device C ABI sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "device.h"
+
+struct gocp_ctx {
+    int device = 0;
+    hipStream_t user_stream = nullptr;   // where calls are ordered (NULL: default stream)
+    hipStream_t own_stream = nullptr;    // private stream used for graph capture
+    char *arena = nullptr;               // workspace of the one-shot calls
+    size_t arena_cap = 0;
+    std::string arch;
+    int n_cu = 0;
+};
+
+namespace gocp {
+
+enum {
+    K_APPLY_H = 0, K_GRAD = 1, K_LINE_VW = 2, K_LINE_HVW = 3, K_TAYLOR = 4, K_NORMALIZE = 5,
+    K_UNIT_NORM = 6
+};
+
+void launch_kernel(int which, int dtype, const InstDev *insts, const int2 *blk, int nblk, int mode,
+                   hipStream_t s, int j = 0, double th = 0.0, int ns = 0);
+void launch_basis(int dtype, void *psi, uint32_t dim, uint32_t index, hipStream_t s);
+void launch_gather_done(const InstDev *insts, int n, int32_t *out, hipStream_t s);
+
+// Byte offsets of one instance's buffers inside its workspace.
+struct InstPlan {
+    int n_qubits = 0, M = 0, max_iter = 0, dtype = 0;
+    int n_tiles = 0, n_pblk = 0;
+    size_t o_sigma = 0, o_v = 0, o_w = 0, o_pe = 0, o_pn = 0, o_pg = 0, o_pl = 0, o_pt = 0,
+           o_cnt = 0, o_st = 0, o_he = 0, o_hop = 0, o_hth = 0, o_hgn = 0, o_hgm = 0, o_hns = 0,
+           o_hpr = 0, o_g = 0, o_psi = 0;
+    size_t bytes = 0;
+};
+
+// Lay out the workspace of one instance; own_psi reserves room for the state too.
+InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi);
+
+const DeviceHam *device_ham(const Ham &h, int dev);
+const DevicePool *device_pool(const Pool &p, int dev);
+
+InstDev make_desc(int device, const InstPlan &ip, char *base, const Ham *h, const Pool *p, void *psi,
+                  double2 *sigma_override);
+AdaptState make_state(const InstPlan &ip, char *base, int max_iter, double grad_tol, bool hist);
+
+const Ham *as_ham(const gocp_ham *h);
+const Pool *as_pool(const gocp_pool *p);
+void check_ctx(gocp_ctx *ctx);
+void check_dtype(int dtype);
+
+}  // namespace gocp
+
+#define GOCP_GUARD_BEGIN try {
+#define GOCP_GUARD_END                                   \
+    }                                                    \
+    catch (const gocp::Error &e) {                       \
+        gocp::set_last_error(e.what());                  \
+        return e.code;                                   \
+    }                                                    \
+    catch (const std::bad_alloc &) {                     \
+        gocp::set_last_error("host allocation failed");  \
+        return GOCP_ENOMEM;                              \
+    }                                                    \
+    catch (const std::exception &e) {                    \
+        gocp::set_last_error(e.what());                  \
+        return GOCP_EINVAL;                              \
+    }

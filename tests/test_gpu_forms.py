@@ -1,0 +1,105 @@
+"""GPU tests of the batched form and the measurement hook (through the C ABI).
+
+A batch launches each kernel once for all its instances; every instance must
+compute exactly what it computes alone (same work split, same reduction
+order), so batched and solo records are compared bit for bit.
+"""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from workloads import molecular_integrals, electron_count
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2607_15906_amd as g
+    return g
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    return g.Context(0)
+
+
+def _inst(g, nq, mapping, seed):
+    ne = electron_count(nq // 2)
+    h1, eri, ec = molecular_integrals(nq // 2, seed)
+    return (g.pauli_hamiltonian_load(h1, eri, ec, mapping), g.pool_build(nq, ne, mapping),
+            g.hf_index(nq, ne, mapping), nq)
+
+
+def _psi(nq, hf, dtype):
+    t = torch.zeros(1 << nq, dtype=dtype, device="cuda")
+    t[hf] = 1.0
+    return t
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_batched_equals_solo(g, ctx, dtype):
+    _say(f"[batch] mixed sizes {dtype}")
+    specs = [(4, "jw", 1), (8, "bk", 2), (12, "jw", 3), (10, "bk", 4), (14, "jw", 5), (8, "jw", 6)]
+    insts = [_inst(g, *s) for s in specs]
+    iters = 12
+    psis = [_psi(nq, hf, dtype) for (_, _, hf, nq) in insts]
+    b = g.Batch(ctx, [i[0] for i in insts], [i[1] for i in insts], psis, max_iter=iters)
+    b.step(5)
+    b.step(iters - 5)
+    assert b.poll() == 0
+    for k, (H, P, hf, nq) in enumerate(insts):
+        rb = b.result(k)
+        solo = _psi(nq, hf, dtype)
+        rs = g.adapt_solve(ctx, H, P, solo, iters)
+        assert rb["ops"] == rs["ops"]
+        assert np.array_equal(rb["energies"], rs["energies"])
+        assert np.array_equal(rb["thetas"], rs["thetas"])
+        assert np.array_equal(rb["gnorms"], rs["gnorms"])
+        assert torch.equal(psis[k], solo)
+    b.close()
+
+
+def test_batch_run_stops_when_all_converged(g, ctx):
+    insts = [_inst(g, 4, "jw", 11), _inst(g, 4, "bk", 12), _inst(g, 8, "jw", 13)]
+    psis = [_psi(nq, hf, torch.complex128) for (_, _, hf, nq) in insts]
+    b = g.Batch(ctx, [i[0] for i in insts], [i[1] for i in insts], psis, max_iter=400,
+                grad_tol=1e-3)
+    b.run()
+    assert b.poll() == 0
+    for k in range(3):
+        r = b.result(k)
+        assert r["converged"] and r["gnorms"][-1] < 1e-3
+        solo = _psi(insts[k][3], insts[k][2], torch.complex128)
+        rs = g.adapt_solve(ctx, insts[k][0], insts[k][1], solo, 400, grad_tol=1e-3)
+        assert rs["n_iter"] == r["n_iter"] and np.array_equal(rs["energies"], r["energies"])
+    b.close()
+
+
+def test_batch_graph_and_direct_launch_agree(g, ctx):
+    H, P, hf, nq = _inst(g, 12, "jw", 21)
+    p1, p2 = _psi(nq, hf, torch.complex128), _psi(nq, hf, torch.complex128)
+    r1 = g.adapt_solve(ctx, H, P, p1, 20, use_graph=True)
+    r2 = g.adapt_solve(ctx, H, P, p2, 20, use_graph=False)
+    assert np.array_equal(r1["energies"], r2["energies"]) and r1["ops"] == r2["ops"]
+
+
+def test_kernel_timing_hook_leaves_record_unchanged(g, ctx):
+    H, P, hf, nq = _inst(g, 12, "bk", 31)
+    psi = _psi(nq, hf, torch.complex128)
+    b = g.Batch(ctx, [H], [P], [psi], max_iter=10)
+    b.step(4)
+    for which in (0, 1, 2):
+        assert b.time_kernel(which, 3) > 0.0
+    b.step(6)
+    r = b.result(0)
+    solo = _psi(nq, hf, torch.complex128)
+    rs = g.adapt_solve(ctx, H, P, solo, 10)
+    assert np.array_equal(r["energies"], rs["energies"]) and r["ops"] == rs["ops"]
+    b.close()
