@@ -112,14 +112,16 @@ def main():
     ips = args.steps / dt
     upd = _amp_updates(nq, T, S, off, r["ops"][w0:w1], r["substeps"][w0:w1])
 
-    # dominant kernel: HIP-event timing of the three tile kernels on the same stream
+    # dominant kernel: HIP-event timing of the two tile kernels on the same stream
     nl = 50
-    ms = {which: b.time_kernel(which, nl) for which in (0, 1, 2)}
+    ms = {which: b.time_kernel(which, nl) for which in (0, 1)}
     dim = 1 << nq
-    flops = {0: dim * (T + 4 * C + 4),          # signed adds per string, 2 FMAs per class, dots
-             1: dim * (S + 4 * M),              # signed adds per string, 4 flops per operator
-             2: dim * (T + 8 * C + 12)}         # two vectors per class, three dots
-    names = {0: "k_apply_h", 1: "k_pool_grad", 2: "k_line_hvw"}
+    # algorithmic FP64 flops per launch: one signed add per (string, amplitude),
+    # a real-by-complex multiply-add (4 flops) per (class or operator, amplitude)
+    # and the dot products
+    flops = {0: dim * (T + 4 * C + 4) + dim * (S + 4 * M),   # H psi + energy + screen
+             1: dim * (T + 8 * C + 12)}                      # H v and H w + three dots
+    names = {0: "k_energy_screen", 1: "k_line_hvw"}
     dom = max(ms, key=lambda k: ms[k])
     achieved = flops[dom] / (ms[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": names[dom], "achieved": round(achieved, 4),

@@ -266,10 +266,10 @@ int gocp_batch_result(gocp_batch *b, int32_t i, gocp_adapt_result *res);
 /*
  * Measurement hook: launch one kernel of the iteration n_launch times back to
  * back over the whole batch and return its mean duration from HIP events
- * recorded on the context stream.  which: 0 = H apply + energy, 1 = gradient
- * screen, 2 = H v / H w products of the line search.  The launches recompute
- * values the batch already holds (sigma, gradients, line-search dots) from
- * its current states and leave the iteration record untouched.
+ * recorded on the context stream.  which: 0 = H psi + energy + gradient
+ * screen, 1 = H v / H w products of the line search.  The launches recompute
+ * values the batch already holds (sigma, energy, gradients, line-search dots)
+ * from its current states and leave the iteration record untouched.
  */
 int gocp_batch_time_kernel(gocp_batch *b, int32_t which, int32_t n_launch, double *avg_ms);
 int gocp_batch_destroy(gocp_batch *b);

@@ -138,15 +138,16 @@ struct Group {
             hip_check(hipMemcpyAsync(bpair, bp.data(), bp.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
     }
 
-    // One ADAPT iteration of every member: screen + selection, line-search
-    // vectors, H v / H w and the angle, Taylor update, new energy.
+    // One ADAPT iteration of every member (the screen and selection of the
+    // current state were done by the previous launch of k_energy_screen):
+    // line-search vectors, H v / H w and the angle, Taylor update, then the
+    // new state's energy together with its screen and selection.
     void enqueue_iteration(hipStream_t s) const {
         if (inst.empty()) return;
-        launch_kernel(K_GRAD, dtype, desc, btile, nt, 1, s);
         launch_kernel(K_LINE_VW, dtype, desc, bpair, np, 1, s);
         launch_kernel(K_LINE_HVW, dtype, desc, btile, nt, 1, s);
         launch_kernel(K_TAYLOR, dtype, desc, bpair, np, 1, s);
-        launch_kernel(K_APPLY_H, dtype, desc, btile, nt, 2, s);
+        launch_kernel(K_ENERGY_SCREEN, dtype, desc, btile, nt, 2, s);
     }
 
     void capture() {
@@ -186,8 +187,10 @@ struct Group {
         launch_kernel(which, dtype, desc, bsub, (int)rows.size(), mode, s);
     }
 
-    // Energy of the starting state of the given members (history entry 0).
-    void start(const std::vector<int> &members, hipStream_t s) { launch_subset(K_APPLY_H, 1, members, 0, s); }
+    // Energy, screen and selection of the starting state of the given members.
+    void start(const std::vector<int> &members, hipStream_t s) {
+        launch_subset(K_ENERGY_SCREEN, 1, members, 0, s);
+    }
 
     // Scale the states of the given members to unit norm (their renormalisation
     // is otherwise folded into the next Taylor update).
@@ -396,11 +399,11 @@ int gocp_batch_result(gocp_batch *b, int32_t i, gocp_adapt_result *res) {
 int gocp_batch_time_kernel(gocp_batch *b, int32_t which, int32_t n_launch, double *avg_ms) {
     GOCP_GUARD_BEGIN
     if (!b || !avg_ms || n_launch <= 0) throw Error(GOCP_EINVAL, "null argument or no launches");
-    if (which != 0 && which != 1 && which != 2) throw Error(GOCP_EINVAL, "kernel id must be 0, 1 or 2");
+    if (which != 0 && which != 1) throw Error(GOCP_EINVAL, "kernel id must be 0 or 1");
     check_ctx(b->group.ctx);
     hipStream_t s = b->group.ctx->user_stream;
     Group &g = b->group;
-    const int kid = which == 0 ? K_APPLY_H : which == 1 ? K_GRAD : K_LINE_HVW;
+    const int kid = which == 0 ? K_ENERGY_SCREEN : K_LINE_HVW;
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");

@@ -268,17 +268,31 @@ __device__ __forceinline__ uint32_t insert_zero_bit(uint32_t p, int hb) {
     return ((p >> hb) << (hb + 1)) | lo;
 }
 
-// ------------------------------------------------------------------ K1: sigma = H psi, energy
+// ------------------------------------------------------------------ energy + gradient screen
 
-// mode: 0 one-shot (energy to st), 1 initial state of an ADAPT run (E_0),
-//       2 end of an ADAPT iteration (E_{k+1}, iteration counter).
+// One launch per state, per 64-amplitude tile:
+//   1. sigma = H psi on the tile (FP64), and the tile's <psi|sigma>, <psi|psi>;
+//   2. when a screen is due, the tile's share of
+//      g_j = 2 Re <sigma | A_j psi> / <psi|psi> for every pool operator, with
+//      the tile's own sigma values taken from LDS.  Operators are visited in
+//      GOCP family order (the family-ordered table is staged in LDS; wave w
+//      takes operators w, w + kNW, ... of each stage);
+//   3. the last workgroup to finish forms the energy, the norm, the
+//      gradients, |g|max, ||g||_2 and the selected operator.
+// mode 0: one-shot (energy; gradients when the instance has a pool);
+// mode 1: starting state of an ADAPT run (E_0 and the first screen);
+// mode 2: state after an update: iteration counter + 1, its energy, and the
+//         next screen unless the iteration budget is spent.
 template <typename T>
-__global__ __launch_bounds__(kNW *kWave) void k_apply_h(const InstDev *__restrict__ insts,
-                                                       const int2 *__restrict__ blk, int mode) {
+__global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__restrict__ insts,
+                                                             const int2 *__restrict__ blk, int mode) {
     const int2 b = blk[blockIdx.x];
     const InstDev &I = insts[b.x];
     AdaptState *st = I.st;
     if (mode != 0 && state_done(st)) return;
+    const int it = mode == 2 ? cptr(&st->iter)[0] + 1 : 0;
+    const int M = I.M;
+    const bool screen = M > 0 && (mode == 0 || it < cptr(&st->max_iter)[0]);
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = wave_id();
     const uint32_t dim = 1u << I.n_qubits;
@@ -287,7 +301,11 @@ __global__ __launch_bounds__(kNW *kWave) void k_apply_h(const InstDev *__restric
     const uint32_t dd = valid ? d : 0u;
 
     __shared__ Stage S;
+    __shared__ double2 s_sig[kWave];
+    __shared__ double gpart[kStageCls];
     __shared__ double lds[kNW * kWave];
+
+    // 1. sigma on the tile
     double acc[2] = {0.0, 0.0};
     apply_classes<T, 1>(I, S, dd, I.psi, nullptr, acc);
     double2 (*red)[kWave] = reinterpret_cast<double2 (*)[kWave]>(&S);
@@ -304,6 +322,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_apply_h(const InstDev *__restric
         double pe = valid ? own.x * ar + own.y * ai : 0.0;
         double pn = valid ? own.x * own.x + own.y * own.y : 0.0;
         if (valid) I.sigma[d] = make_double2(ar, ai);
+        s_sig[lane] = valid ? make_double2(ar, ai) : make_double2(0.0, 0.0);
         pe = wave_sum(pe);
         pn = wave_sum(pn);
         if (lane == 0) {
@@ -311,139 +330,115 @@ __global__ __launch_bounds__(kNW *kWave) void k_apply_h(const InstDev *__restric
             I.part_n[b.y] = pn;
         }
     }
-    if (!arrive_last(&I.counters[0], I.n_tiles)) return;
-    const double e_num = block_sum_strided<kNW * kWave>(I.part_e, I.n_tiles, 1, lds);
-    const double nrm = block_sum_strided<kNW * kWave>(I.part_n, I.n_tiles, 1, lds);
-    if (threadIdx.x == 0) {
-        const double e = e_num / nrm;
-        st->e_num = e_num;
-        st->nrm = nrm;
-        st->energy = e;
-        if (!(nrm > 0.0) || !isfinite(e)) {
-            st->status = GOCP_ENUMERIC;
-            st->done = 1;
-        }
-        if (mode == 1) {
-            if (st->hist_e) st->hist_e[0] = e;
-            if (st->max_iter <= 0) st->done = 1;
-        } else if (mode == 2) {
-            const int it = st->iter + 1;
-            if (st->hist_e) st->hist_e[it] = e;
-            st->iter = it;
-            if (it >= st->max_iter) st->done = 1;
-        }
-    }
-}
+    __syncthreads();
 
-// ------------------------------------------------------------------ K2: gradient screen + selection
-
-// g_j = 2 Re <sigma | A_j psi> / <psi|psi> for every j, then (last workgroup)
-// |g|max, ||g||_2 and the selected operator.  Operators are visited in GOCP
-// family order: the family-ordered table is staged in LDS and wave w takes
-// operators w, w + kNW, ... of each stage.
-template <typename T>
-__global__ __launch_bounds__(kNW *kWave) void k_pool_grad(const InstDev *__restrict__ insts,
-                                                         const int2 *__restrict__ blk, int mode) {
-    const int2 b = blk[blockIdx.x];
-    const InstDev &I = insts[b.x];
-    AdaptState *st = I.st;
-    if (mode != 0 && state_done(st)) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = wave_id();
-    const uint32_t dim = 1u << I.n_qubits;
-    const uint32_t d = (uint32_t)b.y * kTile + lane;
-    const bool valid = d < dim;
-    const uint32_t dd = valid ? d : 0u;
-    const int M = I.M;
-    const double2 sg = valid ? I.sigma[dd] : make_double2(0.0, 0.0);
-
-    __shared__ Stage S;
-    __shared__ double gpart[kStageCls];
-    const GOCP_AS4 int32_t *pch = cptr(I.pchunk);
-    const GOCP_AS4 HClass *sop = cptr(I.sop);
-    for (int k = 0; k < I.n_pchunks; ++k) {
-        const int ob = pch[k], oe = pch[k + 1];
-        const int sb = sop[ob].s0, se = sop[oe - 1].s1;
-        __syncthreads();
-        stage_copy(S.cls, I.sop + ob, oe - ob);
-        stage_copy(S.terms, I.sterm + sb, se - sb);
-        __syncthreads();
-        const int no = oe - ob;
-        int o = wv;
-        typename Amp<T>::Raw rn = {};
-        if (o < no) rn = Amp<T>::raw(I.psi, dd ^ (uint32_t)uni((int)S.cls[o].x));
-        for (; o < no; o += kNW) {
-            const int s0 = uni(S.cls[o].s0) - sb, s1 = uni(S.cls[o].s1) - sb;
-            const typename Amp<T>::Raw r = rn;
-            const int on = o + kNW;
-            if (on < no) rn = Amp<T>::raw(I.psi, dd ^ (uint32_t)uni((int)S.cls[on].x));
-            const double h = lds_string_sum(S.terms, s0, s1, dd);
-            const double2 p = Amp<T>::cvt(r);
-            double val = h * (sg.x * p.x + sg.y * p.y);
-            val = wave_sum(val);
-            if (lane == 0) gpart[o] = val;
-        }
-        __syncthreads();
-        // wave 0 writes this stage's per-operator partials (pool-indexed)
-        if (wv == 0)
-            for (int i = lane; i < no; i += kWave) I.part_g[(size_t)b.y * M + S.cls[i].pad] = gpart[i];
-    }
-    if (!arrive_last(&I.counters[1], I.n_tiles)) return;
-
-    constexpr int NT = kNW * kWave;
-    const double inv = 2.0 / st->nrm;
-    // column sums over tiles: wave w takes tiles w, w + kNW, ...; fixed order
-    double amax = 0.0, sq = 0.0;
-    double *colsum = reinterpret_cast<double *>(&S);          // [kNW][kWave]
-    for (int jb = 0; jb < M; jb += kWave) {
-        const int j = jb + lane;
-        double a0 = 0.0, a1 = 0.0;
-        if (j < M) {
-            int t = wv;
-            for (; t + kNW < I.n_tiles; t += 2 * kNW) {
-                a0 += I.part_g[(size_t)t * M + j];
-                a1 += I.part_g[(size_t)(t + kNW) * M + j];
+    // 2. gradient screen on the tile
+    if (screen) {
+        const double2 sg = s_sig[lane];
+        const GOCP_AS4 int32_t *pch = cptr(I.pchunk);
+        const GOCP_AS4 HClass *sop = cptr(I.sop);
+        for (int k = 0; k < I.n_pchunks; ++k) {
+            const int ob = pch[k], oe = pch[k + 1];
+            const int sb = sop[ob].s0, se = sop[oe - 1].s1;
+            __syncthreads();
+            stage_copy(S.cls, I.sop + ob, oe - ob);
+            stage_copy(S.terms, I.sterm + sb, se - sb);
+            __syncthreads();
+            const int no = oe - ob;
+            int o = wv;
+            typename Amp<T>::Raw rn = {};
+            if (o < no) rn = Amp<T>::raw(I.psi, dd ^ (uint32_t)uni((int)S.cls[o].x));
+            for (; o < no; o += kNW) {
+                const int s0 = uni(S.cls[o].s0) - sb, s1 = uni(S.cls[o].s1) - sb;
+                const typename Amp<T>::Raw r = rn;
+                const int on = o + kNW;
+                if (on < no) rn = Amp<T>::raw(I.psi, dd ^ (uint32_t)uni((int)S.cls[on].x));
+                const double h = lds_string_sum(S.terms, s0, s1, dd);
+                const double2 p = Amp<T>::cvt(r);
+                double val = h * (sg.x * p.x + sg.y * p.y);
+                val = wave_sum(val);
+                if (lane == 0) gpart[o] = val;
             }
-            if (t < I.n_tiles) a0 += I.part_g[(size_t)t * M + j];
+            __syncthreads();
+            // wave 0 writes this stage's per-operator partials (pool-indexed)
+            if (wv == 0)
+                for (int i = lane; i < no; i += kWave) I.part_g[(size_t)b.y * M + S.cls[i].pad] = gpart[i];
         }
-        colsum[wv * kWave + lane] = a0 + a1;
-        __syncthreads();
-        if (wv == 0 && j < M) {
-            double acc = 0.0;
-            for (int w = 0; w < kNW; ++w) acc += colsum[w * kWave + lane];
-            const double g = acc * inv;
-            st->g[j] = g;
-            amax = fmax(amax, fabs(g));
-            sq += g * g;
-        }
-        __syncthreads();
     }
-    // wave 0 holds every g_j (lane l: j = l, l + 64, ...): reduce within it
-    if (wv != 0) return;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, kWave));
-    const double gmax = amax;
-    const double gn = sqrt(wave_sum(sq));
-    // lowest index within the tie band of the largest magnitude
-    const double thresh = gmax * (1.0 - 1e-12);
-    int jmin = 0x7fffffff;
-    for (int j = lane; j < M; j += kWave)
-        if (fabs(st->g[j]) >= thresh) {
-            jmin = j;
-            break;
+    if (!arrive_last(&I.counters[0], I.n_tiles)) return;
+
+    // 3. last workgroup
+    constexpr int NT = kNW * kWave;
+    const double e_num = block_sum_strided<NT>(I.part_e, I.n_tiles, 1, lds);
+    const double nrm = block_sum_strided<NT>(I.part_n, I.n_tiles, 1, lds);
+    double amax = 0.0, sq = 0.0;
+    if (screen) {
+        // column sums over tiles: wave w takes tiles w, w + kNW, ...; fixed order
+        const double inv = 2.0 / nrm;
+        double *colsum = reinterpret_cast<double *>(&S);          // [kNW][kWave]
+        for (int jb = 0; jb < M; jb += kWave) {
+            const int j = jb + lane;
+            double a0 = 0.0, a1 = 0.0;
+            if (j < M) {
+                int t = wv;
+                for (; t + kNW < I.n_tiles; t += 2 * kNW) {
+                    a0 += I.part_g[(size_t)t * M + j];
+                    a1 += I.part_g[(size_t)(t + kNW) * M + j];
+                }
+                if (t < I.n_tiles) a0 += I.part_g[(size_t)t * M + j];
+            }
+            colsum[wv * kWave + lane] = a0 + a1;
+            __syncthreads();
+            if (wv == 0 && j < M) {
+                double a = 0.0;
+                for (int w = 0; w < kNW; ++w) a += colsum[w * kWave + lane];
+                const double g = a * inv;
+                st->g[j] = g;
+                amax = fmax(amax, fabs(g));
+                sq += g * g;
+            }
+            __syncthreads();
         }
+    }
+    if (wv != 0) return;
+    // wave 0 holds every g_j (lane l: j = l, l + 64, ...)
+    double gmax = 0.0, gn = 0.0;
+    int jmin = 0x7fffffff;
+    if (screen) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) jmin = min(jmin, __shfl_xor(jmin, off, kWave));
-    if (lane == 0) {
+        for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, kWave));
+        gmax = amax;
+        gn = sqrt(wave_sum(sq));
+        // lowest index within the tie band of the largest magnitude
+        const double thresh = gmax * (1.0 - 1e-12);
+        for (int j = lane; j < M; j += kWave)
+            if (fabs(st->g[j]) >= thresh) {
+                jmin = j;
+                break;
+            }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) jmin = min(jmin, __shfl_xor(jmin, off, kWave));
+    }
+    if (lane != 0) return;
+    const double e = e_num / nrm;
+    st->e_num = e_num;
+    st->nrm = nrm;
+    st->energy = e;
+    bool bad = !(nrm > 0.0) || !isfinite(e);
+    if (mode == 1) {
+        if (st->hist_e) st->hist_e[0] = e;
+        if (st->max_iter <= 0) st->done = 1;
+    } else if (mode == 2) {
+        st->iter = it;
+        if (st->hist_e) st->hist_e[it] = e;
+        if (it >= st->max_iter) st->done = 1;
+    }
+    if (screen) {
         st->gmax = gmax;
         st->gnorm = gn;
         st->jsel = jmin < M ? jmin : 0;
-        if (!isfinite(gn)) {
-            st->status = GOCP_ENUMERIC;
-            st->done = 1;
-        }
+        bad = bad || !isfinite(gn);
         if (mode != 0) {
-            const int it = st->iter;
             if (st->hist_gnorm) st->hist_gnorm[it] = gn;
             if (st->hist_gmax) st->hist_gmax[it] = gmax;
             if (gn < st->grad_tol) {
@@ -451,6 +446,10 @@ __global__ __launch_bounds__(kNW *kWave) void k_pool_grad(const InstDev *__restr
                 st->done = 1;
             }
         }
+    }
+    if (bad) {
+        st->status = GOCP_ENUMERIC;
+        st->done = 1;
     }
 }
 
@@ -790,8 +789,7 @@ template <typename T>
 static void launch_all(int which, const InstDev *insts, const int2 *blk, int nblk, int mode,
                        hipStream_t s, int j = 0, double th = 0.0, int ns = 0) {
     switch (which) {
-    case 0: hipLaunchKernelGGL(k_apply_h<T>, dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode); break;
-    case 1: hipLaunchKernelGGL(k_pool_grad<T>, dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode); break;
+    case 0: hipLaunchKernelGGL(k_energy_screen<T>, dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode); break;
     case 2: hipLaunchKernelGGL(k_line_vw<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk); break;
     case 3: hipLaunchKernelGGL(k_line_hvw<T>, dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode); break;
     case 4: hipLaunchKernelGGL(k_taylor5<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode, j, th, ns); break;

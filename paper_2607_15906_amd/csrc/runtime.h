@@ -21,7 +21,7 @@ struct gocp_ctx {
 namespace gocp {
 
 enum {
-    K_APPLY_H = 0, K_GRAD = 1, K_LINE_VW = 2, K_LINE_HVW = 3, K_TAYLOR = 4, K_NORMALIZE = 5,
+    K_ENERGY_SCREEN = 0, K_LINE_VW = 2, K_LINE_HVW = 3, K_TAYLOR = 4, K_NORMALIZE = 5,
     K_UNIT_NORM = 6
 };
 

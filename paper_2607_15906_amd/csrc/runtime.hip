@@ -389,7 +389,7 @@ int energy(gocp_ctx *ctx, const gocp_ham *hh, const void *psi_dev, int dtype, do
     check_ctx(ctx);
     if (!e_out) throw Error(GOCP_EINVAL, "null output");
     OneShot o = one_shot(ctx, as_ham(hh), nullptr, psi_dev, dtype);
-    launch_kernel(K_APPLY_H, dtype, o.desc, o.btile, o.nt, 0, ctx->user_stream);
+    launch_kernel(K_ENERGY_SCREEN, dtype, o.desc, o.btile, o.nt, 0, ctx->user_stream);
     const AdaptState st = read_state(ctx, o);
     if (st.status) throw Error(st.status, "non-finite energy or zero norm");
     *e_out = st.energy;
@@ -403,7 +403,7 @@ int gocp_apply_hamiltonian(gocp_ctx *ctx, const gocp_ham *hh, const void *psi_de
     check_ctx(ctx);
     if (!sigma_dev) throw Error(GOCP_EINVAL, "null sigma pointer");
     OneShot o = one_shot(ctx, as_ham(hh), nullptr, psi_dev, dtype, static_cast<double2 *>(sigma_dev));
-    launch_kernel(K_APPLY_H, dtype, o.desc, o.btile, o.nt, 0, ctx->user_stream);
+    launch_kernel(K_ENERGY_SCREEN, dtype, o.desc, o.btile, o.nt, 0, ctx->user_stream);
     if (e_out) {
         const AdaptState st = read_state(ctx, o);
         if (st.status) throw Error(st.status, "non-finite energy or zero norm");
@@ -421,8 +421,7 @@ int pool_gradients(gocp_ctx *ctx, const gocp_ham *hh, const gocp_pool *pp, const
     const Ham *h = as_ham(hh);
     const Pool *p = as_pool(pp);
     OneShot o = one_shot(ctx, h, p, psi_dev, dtype);
-    launch_kernel(K_APPLY_H, dtype, o.desc, o.btile, o.nt, 0, ctx->user_stream);
-    launch_kernel(K_GRAD, dtype, o.desc, o.btile, o.nt, 0, ctx->user_stream);
+    launch_kernel(K_ENERGY_SCREEN, dtype, o.desc, o.btile, o.nt, 0, ctx->user_stream);
     const size_t gbytes = (size_t)p->n_ops() * sizeof(double);
     if (g_on_device) {
         hip_check(hipMemcpyAsync(g_out, o.base + o.ip.o_g, gbytes, hipMemcpyDeviceToDevice,

@@ -95,7 +95,7 @@ def test_kernel_timing_hook_leaves_record_unchanged(g, ctx):
     psi = _psi(nq, hf, torch.complex128)
     b = g.Batch(ctx, [H], [P], [psi], max_iter=10)
     b.step(4)
-    for which in (0, 1, 2):
+    for which in (0, 1):
         assert b.time_kernel(which, 3) > 0.0
     b.step(6)
     r = b.result(0)
