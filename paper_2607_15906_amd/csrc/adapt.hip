@@ -58,7 +58,8 @@ Instance *instance_create(gocp_ctx *ctx, const Ham *h, const Pool *p, void *psi,
     in->psi = own ? in->mem + in->ip.o_psi : psi;
     in->desc = make_desc(ctx->device, in->ip, in->mem, h, p, in->psi, nullptr);
     const AdaptState st = make_state(in->ip, in->mem, max_iter, tol, true);
-    hip_check(hipMemsetAsync(in->mem + in->ip.o_cnt, 0, 4 * sizeof(int32_t), s), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(in->mem + in->ip.o_cnt, 0, in->ip.n_counters * sizeof(int32_t), s),
+              "hipMemsetAsync");
     hip_check(hipMemcpyAsync(in->mem + in->ip.o_st, &st, sizeof(st), hipMemcpyHostToDevice, s), "H2D");
     if (own) launch_basis(dtype, in->psi, 1u << h->n_qubits, (uint32_t)hf, s);
     return in.release();

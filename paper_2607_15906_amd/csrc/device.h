@@ -18,6 +18,8 @@ constexpr int kPairBlock = 256;        // threads (= amplitude pairs) per pair-k
 // Term tables are staged into LDS in chunks of at most this many records.
 constexpr int kStageTerms = 4096;      // strings (64 KiB)
 constexpr int kStageCls = 1024;        // classes or operators (16 KiB)
+// Tiles per group in the two-level reduction of the gradient screen.
+constexpr int kGroup = 16;
 
 // A folded Pauli string as the kernels read it: 16 bytes, one scalar load.
 struct HTerm {
@@ -83,9 +85,11 @@ struct InstDev {
     double *part_e;             // n_tiles
     double *part_n;             // n_tiles
     double *part_g;             // n_tiles * M
+    double *part_g2;            // n_groups * M (sums over groups of kGroup tiles)
     double *part_l;             // 3 * n_tiles + 2 * n_pblk (line-search dots)
     double *part_t;             // n_pblk (Taylor norms)
-    int32_t *counters;          // 4 arrival counters (tile, grad, line, pair)
+    int32_t *counters;          // arrival counters: [0] screen, [2] line search,
+                                // [4 + g] group g of the screen reduction
     AdaptState *st;
     int32_t n_qubits;
     int32_t M;
@@ -93,6 +97,8 @@ struct InstDev {
     int32_t n_pblk;
     int32_t n_hchunks;
     int32_t n_pchunks;
+    int32_t n_groups;
+    int32_t pad1;
 };
 
 struct DeviceHam {

@@ -147,22 +147,49 @@ __device__ double block_sum_strided(const double *src, int n, int stride, double
     return r;
 }
 
-// Arrival of this workgroup at the end of its part of a launch.  Every
-// partial result the last workgroup will read must have been written by wave
-// 0 of its workgroup before the call.  Returns true (in every thread) in the
-// workgroup that arrives last, which then sees all those partials.
+// Cross-workgroup partial results.  A workgroup's partials are written with
+// device-coherent stores (they bypass the per-XCD L2), each writer waits for
+// its stores to complete, and only then is the arrival counter incremented;
+// the last workgroup to arrive reads the partials with device-coherent loads.
+// This needs no L2 writeback or invalidation, which would otherwise stall the
+// workgroups still running on the same XCD.
+__device__ __forceinline__ void st_coh(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coh(const double *p) {
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Returns true (in every thread) in the workgroup that arrives last.
 __device__ bool arrive_last(int32_t *counter, int total) {
     __shared__ int s_last;
-    if (threadIdx.x < kWave) __threadfence();      // release wave 0's partial writes
+    __builtin_amdgcn_s_waitcnt(0);       // this wave's coherent stores have completed
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int prev = atomicAdd(counter, 1);
+        const int prev = __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_last = (prev == total - 1);
-        if (s_last) *counter = 0;                  // ready for the next launch
+        if (s_last) __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    if (s_last) __threadfence();                   // acquire the other partials
     return s_last != 0;
+}
+
+// Sum of n coherent partials at stride `stride`, in index order per thread
+// and a fixed tree over threads; the result is returned to every thread.
+template <int NT>
+__device__ double block_sum_coh(const double *src, int n, int stride, double *lds) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) acc += ld_coh(src + (size_t)i * stride);
+    lds[threadIdx.x] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) lds[threadIdx.x] += lds[threadIdx.x + h];
+        __syncthreads();
+    }
+    const double r = lds[0];
+    __syncthreads();
+    return r;
 }
 
 // ------------------------------------------------------------------ LDS staging of term tables
@@ -326,8 +353,8 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
         pe = wave_sum(pe);
         pn = wave_sum(pn);
         if (lane == 0) {
-            I.part_e[b.y] = pe;
-            I.part_n[b.y] = pn;
+            st_coh(&I.part_e[b.y], pe);
+            st_coh(&I.part_n[b.y], pn);
         }
     }
     __syncthreads();
@@ -362,18 +389,33 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
             __syncthreads();
             // wave 0 writes this stage's per-operator partials (pool-indexed)
             if (wv == 0)
-                for (int i = lane; i < no; i += kWave) I.part_g[(size_t)b.y * M + S.cls[i].pad] = gpart[i];
+                for (int i = lane; i < no; i += kWave) st_coh(&I.part_g[(size_t)b.y * M + S.cls[i].pad], gpart[i]);
         }
     }
-    if (!arrive_last(&I.counters[0], I.n_tiles)) return;
-
-    // 3. last workgroup
+    // 3a. the last workgroup of each group of kGroup tiles sums the group's
+    //     screen partials (fixed tile order) into part_g2
+    const int grp = b.y / kGroup;
+    const int t0 = grp * kGroup, t1 = min(t0 + kGroup, I.n_tiles);
+    if (!arrive_last(&I.counters[4 + grp], t1 - t0)) return;
     constexpr int NT = kNW * kWave;
-    const double e_num = block_sum_strided<NT>(I.part_e, I.n_tiles, 1, lds);
-    const double nrm = block_sum_strided<NT>(I.part_n, I.n_tiles, 1, lds);
+    if (screen) {
+        for (int j = threadIdx.x; j < M; j += NT) {
+            double a[kGroup];
+#pragma unroll
+            for (int t = 0; t < kGroup; ++t) a[t] = t0 + t < t1 ? ld_coh(&I.part_g[(size_t)(t0 + t) * M + j]) : 0.0;
+            double sum = 0.0;
+#pragma unroll
+            for (int t = 0; t < kGroup; ++t) sum += a[t];
+            st_coh(&I.part_g2[(size_t)grp * M + j], sum);
+        }
+    }
+    // 3b. the last group to finish forms energy, norm, gradients, selection
+    if (!arrive_last(&I.counters[0], I.n_groups)) return;
+    const double e_num = block_sum_coh<NT>(I.part_e, I.n_tiles, 1, lds);
+    const double nrm = block_sum_coh<NT>(I.part_n, I.n_tiles, 1, lds);
     double amax = 0.0, sq = 0.0;
     if (screen) {
-        // column sums over tiles: wave w takes tiles w, w + kNW, ...; fixed order
+        // column sums over groups: wave w takes groups w, w + kNW, ...; fixed order
         const double inv = 2.0 / nrm;
         double *colsum = reinterpret_cast<double *>(&S);          // [kNW][kWave]
         for (int jb = 0; jb < M; jb += kWave) {
@@ -381,11 +423,11 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
             double a0 = 0.0, a1 = 0.0;
             if (j < M) {
                 int t = wv;
-                for (; t + kNW < I.n_tiles; t += 2 * kNW) {
-                    a0 += I.part_g[(size_t)t * M + j];
-                    a1 += I.part_g[(size_t)(t + kNW) * M + j];
+                for (; t + kNW < I.n_groups; t += 2 * kNW) {
+                    a0 += ld_coh(&I.part_g2[(size_t)t * M + j]);
+                    a1 += ld_coh(&I.part_g2[(size_t)(t + kNW) * M + j]);
                 }
-                if (t < I.n_tiles) a0 += I.part_g[(size_t)t * M + j];
+                if (t < I.n_groups) a0 += ld_coh(&I.part_g2[(size_t)t * M + j]);
             }
             colsum[wv * kWave + lane] = a0 + a1;
             __syncthreads();
@@ -629,18 +671,35 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
         p5 = wave_sum(p5);
         p6 = wave_sum(p6);
         if (lane == 0) {
-            I.part_l[3 * b.y] = p3;
-            I.part_l[3 * b.y + 1] = p5;
-            I.part_l[3 * b.y + 2] = p6;
+            st_coh(&I.part_l[3 * b.y], p3);
+            st_coh(&I.part_l[3 * b.y + 1], p5);
+            st_coh(&I.part_l[3 * b.y + 2], p6);
         }
     }
     if (!arrive_last(&I.counters[2], I.n_tiles)) return;
+    // the five dot products, each summed in a fixed order (loads issued together)
     constexpr int NT = kNW * kWave;
-    const double P3 = block_sum_strided<NT>(I.part_l, I.n_tiles, 3, lds);
-    const double P5 = block_sum_strided<NT>(I.part_l + 1, I.n_tiles, 3, lds);
-    const double P6 = block_sum_strided<NT>(I.part_l + 2, I.n_tiles, 3, lds);
-    const double P2 = block_sum_strided<NT>(I.part_l + 3 * I.n_tiles, I.n_pblk, 2, lds);
-    const double P7 = block_sum_strided<NT>(I.part_l + 3 * I.n_tiles + 1, I.n_pblk, 2, lds);
+    double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < I.n_tiles; i += NT) {
+        q[0] += ld_coh(&I.part_l[3 * i]);
+        q[1] += ld_coh(&I.part_l[3 * i + 1]);
+        q[2] += ld_coh(&I.part_l[3 * i + 2]);
+    }
+    for (int i = threadIdx.x; i < I.n_pblk; i += NT) {
+        q[3] += ld_coh(&I.part_l[3 * I.n_tiles + 2 * i]);
+        q[4] += ld_coh(&I.part_l[3 * I.n_tiles + 2 * i + 1]);
+    }
+    double *tr = reinterpret_cast<double *>(&S);               // [5][NT]
+#pragma unroll
+    for (int k = 0; k < 5; ++k) tr[k * NT + threadIdx.x] = q[k];
+    __syncthreads();
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+#pragma unroll
+            for (int k = 0; k < 5; ++k) tr[k * NT + threadIdx.x] += tr[k * NT + threadIdx.x + h];
+        __syncthreads();
+    }
+    const double P3 = tr[0], P5 = tr[NT], P6 = tr[2 * NT], P2 = tr[3 * NT], P7 = tr[4 * NT];
     if (wv != 0 || mode == 0) return;
     const double inv = 1.0 / st->nrm;
     Landscape L;

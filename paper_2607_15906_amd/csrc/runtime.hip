@@ -155,9 +155,12 @@ InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi) {
     ip.o_pe = a.take(ip.n_tiles * 8);
     ip.o_pn = a.take(ip.n_tiles * 8);
     ip.o_pg = a.take((size_t)ip.n_tiles * std::max(M, 1) * 8);
+    ip.n_groups = (ip.n_tiles + kGroup - 1) / kGroup;
+    ip.o_pg2 = a.take((size_t)ip.n_groups * std::max(M, 1) * 8);
+    ip.n_counters = 4 + (size_t)ip.n_groups;
     ip.o_pl = a.take((3 * (size_t)ip.n_tiles + 2 * (size_t)ip.n_pblk) * 8);
     ip.o_pt = a.take((size_t)ip.n_pblk * 8);
-    ip.o_cnt = a.take(4 * sizeof(int32_t));
+    ip.o_cnt = a.take(ip.n_counters * sizeof(int32_t));
     ip.o_st = a.take(sizeof(AdaptState));
     ip.o_he = a.take(hist * 8);
     ip.o_hop = a.take(hist * 4);
@@ -200,6 +203,8 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
     I.part_e = reinterpret_cast<double *>(b + ip.o_pe);
     I.part_n = reinterpret_cast<double *>(b + ip.o_pn);
     I.part_g = reinterpret_cast<double *>(b + ip.o_pg);
+    I.part_g2 = reinterpret_cast<double *>(b + ip.o_pg2);
+    I.n_groups = ip.n_groups;
     I.part_l = reinterpret_cast<double *>(b + ip.o_pl);
     I.part_t = reinterpret_cast<double *>(b + ip.o_pt);
     I.counters = reinterpret_cast<int32_t *>(b + ip.o_cnt);
@@ -290,7 +295,7 @@ OneShot one_shot(gocp_ctx *ctx, const Ham *h, const Pool *p, const void *psi, in
     char *b = ctx->arena;
     o.base = b;
     hipStream_t s = ctx->user_stream;
-    hip_check(hipMemsetAsync(b + o.ip.o_cnt, 0, 4 * sizeof(int32_t), s), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(b + o.ip.o_cnt, 0, o.ip.n_counters * sizeof(int32_t), s), "hipMemsetAsync");
     InstDev I = make_desc(ctx->device, o.ip, b, h, p, const_cast<void *>(psi), sigma_override);
     AdaptState st = make_state(o.ip, b, 0, 0.0, false);
     hip_check(hipMemcpyAsync(b + o.ip.o_st, &st, sizeof(st), hipMemcpyHostToDevice, s), "H2D");
