@@ -72,6 +72,86 @@ def run_adapt_timed(g, ctx, H, P, nq, ne, mapping, dtype, steps, warmup):
     return b, r, dt
 
 
+def serving_bench(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, load=0.7):
+    """Poisson stream of ADAPT solves (8-16 qubits, ||g|| < 1e-3, at most 300
+    iterations), complex64 states.  Capacity is measured first with all
+    requests submitted at once; the timed stream then arrives at `load` times
+    that capacity.  Latency is submission to completion (library clock)."""
+    import numpy as np
+    import torch
+    from workloads import serving_requests
+    specs = serving_requests(n_req + warm, rate_hz=1.0)
+    reqs = []
+    for d in specs:
+        H, P = _system(g, d["n_qubits"], d["n_electrons"], d["mapping"], d["seed"])
+        reqs.append((d, H, P))
+    tol, max_iter = 1e-3, 300
+    budget = 8 << 30
+
+    def drain(srv, tickets, done):
+        for t in list(tickets):
+            r = srv.poll(t)
+            if r is not None:
+                done[t] = r
+                tickets.remove(t)
+
+    # capacity: everything at once
+    srv = g.Server(ctx, budget, max_slots, dtype=1, iters_per_step=iters_per_step)
+    t0 = time.perf_counter()
+    pend = [srv.submit(H, P, max_iter, tol) for (_, H, P) in reqs[warm:]]
+    done = {}
+    while pend:
+        drain(srv, pend, done)
+        time.sleep(0.0005)
+    cap = n_req / (time.perf_counter() - t0)
+    srv.close()
+
+    # timed Poisson stream at `load` x capacity (warm-up requests first)
+    rate = load * cap
+    srv = g.Server(ctx, budget, max_slots, dtype=1, iters_per_step=iters_per_step)
+    arrivals = [d["arrival_s"] / rate for (d, _, _) in reqs]
+    pend, done, meas = [], {}, []
+    t0 = time.perf_counter()
+    for k, (d, H, P) in enumerate(reqs):
+        while time.perf_counter() - t0 < arrivals[k]:
+            drain(srv, pend, done)
+            time.sleep(0.0002)
+        t = srv.submit(H, P, max_iter, tol)
+        pend.append(t)
+        if k >= warm:
+            meas.append(t)
+    t_first = None
+    while pend:
+        drain(srv, pend, done)
+        time.sleep(0.0005)
+    st = srv.stats()
+    srv.close()
+    lat = np.array([(done[t][2]["t_done_ns"] - done[t][2]["t_submit_ns"]) * 1e-6 for t in meas])
+    t_sub = min(done[t][2]["t_submit_ns"] for t in meas)
+    t_end = max(done[t][2]["t_done_ns"] for t in meas)
+    ok = sum(1 for t in meas if done[t][0] == 0)
+    conv = sum(1 for t in meas if done[t][1] is not None and done[t][1]["converged"])
+
+    # sequential plain FP64: one adapt_solve at a time, complex128
+    t0 = time.perf_counter()
+    nseq = 0
+    for (d, H, P) in reqs[warm:]:
+        psi = _hf_state(g, ctx, d["n_qubits"], d["n_electrons"], d["mapping"], torch.complex128)
+        g.adapt_solve(ctx, H, P, psi, max_iter, grad_tol=tol)
+        nseq += 1
+    torch.cuda.synchronize()
+    seq = nseq / (time.perf_counter() - t0)
+    return {"requests": n_req, "warmup_requests": warm, "qubits": "uniform over {8,10,12,14,16}",
+            "grad_tol": tol, "max_iter": max_iter, "state": "complex64", "max_slots": max_slots,
+            "iters_per_step": iters_per_step, "hbm_budget_bytes": budget,
+            "capacity_solves_per_s": round(cap, 2), "offered_rate_hz": round(rate, 2),
+            "solves_per_s": round(n_req / ((t_end - t_sub) * 1e-9), 2),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "completed_ok": ok, "converged": conv, "server_steps": st["steps"],
+            "sequential_fp64_solves_per_s": round(seq, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +160,11 @@ def main():
     ap.add_argument("--cpu-sample-iters", type=int, default=8,
                     help="oracle iterations timed for the CPU baseline (0 disables it)")
     ap.add_argument("--no-forms", action="store_true", help="skip the c128 and batched extras")
+    ap.add_argument("--serve-requests", type=int, default=96,
+                    help="measured requests of the serving stream (after 16 warm-up requests)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run a plain device-to-device copy of this many MiB (a known-size "
+                         "kernel that calibrates memory-traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the batched and "
@@ -94,6 +179,14 @@ def main():
     import torch
     import paper_2607_15906_amd as g
     from workloads import CONFIGS, batched_instances
+
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cfg = CONFIGS["c3_14q"]
     nq, ne, seed = cfg["n_qubits"], cfg["n_electrons"], cfg["seed"]
@@ -182,6 +275,9 @@ def main():
                           "iterations_each": iters_b, "seconds": round(dtb, 6),
                           "instance_iters_per_s": round(len(insts) * iters_b / dtb, 2),
                           "amp_updates_per_s": float(f"{ub / dtb:.6g}")}
+
+        _say("[bench] serving form: Poisson stream of ADAPT solves")
+        out["serving"] = serving_bench(g, ctx, n_req=args.serve_requests, warm=16)
 
     if args.cpu_sample_iters > 0:
         _say(f"[bench] CPU oracle baseline: {args.cpu_sample_iters} iterations at 14q")

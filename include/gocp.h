@@ -47,6 +47,7 @@ extern "C" {
 #define GOCP_ENOTSUP  -5   /* outside supported sizes (1..30 qubits)            */
 #define GOCP_EBUSY    -6   /* serving: request not finished yet                 */
 #define GOCP_ENUMERIC -7   /* a non-finite value was produced                   */
+#define GOCP_ECANCELED -8  /* serving: request cancelled by server shutdown     */
 
 #define GOCP_JW 0          /* Jordan-Wigner                                     */
 #define GOCP_BK 1          /* Bravyi-Kitaev (Fenwick-tree encoding)             */
@@ -273,6 +274,48 @@ int gocp_batch_result(gocp_batch *b, int32_t i, gocp_adapt_result *res);
  */
 int gocp_batch_time_kernel(gocp_batch *b, int32_t which, int32_t n_launch, double *avg_ms);
 int gocp_batch_destroy(gocp_batch *b);
+
+/* ---------------------------------------------------------------------
+ * Serving form: continuous batching of ADAPT solves on one device.
+ * Requests are queued from any thread.  A worker thread admits them in
+ * arrival order while a slot is free and the request's device footprint fits
+ * the HBM budget, starts each from its Hartree-Fock state, and advances all
+ * admitted requests together (iters_per_step iterations per step, one launch
+ * per kernel for all of them).  After every step it retires finished requests
+ * (converged or at max_iter), frees their memory and admits waiting ones, so
+ * requests arriving while others run join the running set.  Each request
+ * computes exactly what adapt_solve computes for it alone.
+ * ------------------------------------------------------------------- */
+typedef struct {
+    int32_t status;         /* GOCP_OK, GOCP_ENOMEM (never fits the budget),
+                               GOCP_ENUMERIC, GOCP_ECANCELED, GOCP_EDEVICE       */
+    int32_t n_qubits;
+    int64_t t_submit_ns;    /* steady-clock times of submission, admission and */
+    int64_t t_admit_ns;     /* completion (nanoseconds, one clock per process) */
+    int64_t t_done_ns;
+} gocp_request_info;
+
+/* Device bytes one request occupies while admitted (workspace + term tables). */
+int gocp_request_footprint(int n_qubits, int n_ops, int n_strings, int64_t n_terms, int n_classes,
+                           int max_iter, int dtype, int64_t *bytes);
+/* Start a server on ctx's device with its own stream and worker thread.
+ * Errors: EINVAL (non-positive budget, slots or iters_per_step). */
+int gocp_server_create(gocp_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_slots, int dtype,
+                       int32_t iters_per_step, gocp_server **out);
+/* Queue one solve: ham and pool (equal qubit counts) must stay alive until
+ * the request has been polled.  Stops at ||g||_2 < grad_tol or max_iter. */
+int gocp_server_submit(gocp_server *s, const gocp_ham *h, const gocp_pool *p, int32_t max_iter,
+                       double grad_tol, uint64_t *ticket);
+/* GOCP_EBUSY while the request is queued or running; otherwise the request's
+ * status, with its record in *res (arrays sized as for adapt_solve; may be
+ * NULL) and its times in *info (may be NULL).  A finished ticket is released
+ * by the poll that returns it. */
+int gocp_server_poll(gocp_server *s, uint64_t ticket, gocp_adapt_result *res, gocp_request_info *info);
+/* Running and queued requests, requests finished so far, admitted bytes, steps. */
+int gocp_server_stats(gocp_server *s, int32_t *active, int32_t *queued, int64_t *completed,
+                      int64_t *bytes_in_use, int64_t *steps);
+/* Stop the worker; unfinished requests end with GOCP_ECANCELED. */
+int gocp_server_destroy(gocp_server *s);
 
 #ifdef __cplusplus
 }

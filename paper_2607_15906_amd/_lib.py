@@ -10,7 +10,8 @@ LIB_PATH = os.path.join(_HERE, "libgocp.so")
 
 GOCP_OK = 0
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESHAPE",
-          -5: "ENOTSUP", -6: "EBUSY", -7: "ENUMERIC"}
+          -5: "ENOTSUP", -6: "EBUSY", -7: "ENUMERIC", -8: "ECANCELED"}
+GOCP_EBUSY = -6
 
 
 class GocpError(RuntimeError):
@@ -21,6 +22,11 @@ class GocpError(RuntimeError):
 
 class AdaptParams(C.Structure):
     _fields_ = [("grad_tol", C.c_double), ("max_iter", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_qubits", C.c_int32), ("t_submit_ns", C.c_int64),
+                ("t_admit_ns", C.c_int64), ("t_done_ns", C.c_int64)]
 
 
 class AdaptResult(C.Structure):
@@ -72,6 +78,12 @@ SIGNATURES = {
     "gocp_batch_result": [_P, C.c_int32, C.POINTER(AdaptResult)],
     "gocp_batch_time_kernel": [_P, C.c_int32, C.c_int32, _F64P],
     "gocp_batch_destroy": [_P],
+    "gocp_request_footprint": [C.c_int, C.c_int, C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int, _I64P],
+    "gocp_server_create": [_P, C.c_int64, C.c_int32, C.c_int, C.c_int32, _PP],
+    "gocp_server_submit": [_P, _P, _P, C.c_int32, C.c_double, _U64P],
+    "gocp_server_poll": [_P, C.c_uint64, C.POINTER(AdaptResult), C.POINTER(RequestInfo)],
+    "gocp_server_stats": [_P, _I32P, _I32P, _I64P, _I64P, _I64P],
+    "gocp_server_destroy": [_P],
 }
 
 _lib = None

@@ -12,12 +12,12 @@ import ctypes as C
 
 import numpy as np
 
-from ._lib import load, check, AdaptParams, AdaptResult
+from ._lib import load, check, AdaptParams, AdaptResult, RequestInfo, GOCP_EBUSY
 
 __all__ = ["MAPPINGS", "Hamiltonian", "Pool", "Context", "pauli_hamiltonian_load",
            "pauli_hamiltonian_load_terms", "pool_build", "gocp_partition", "hf_index",
            "state_basis", "energy", "apply_hamiltonian", "pool_gradients", "taylor5_apply",
-           "adapt_solve", "Batch", "version"]
+           "adapt_solve", "Batch", "Server", "request_footprint", "version"]
 
 MAPPINGS = {"jw": 0, "bk": 1, 0: 0, 1: 1}
 C128, C64 = 0, 1
@@ -338,6 +338,61 @@ class Batch:
         b, self._b = getattr(self, "_b", None), None
         if b:
             load().gocp_batch_destroy(b)
+
+    def __del__(self):
+        self.close()
+
+
+def request_footprint(ham: Hamiltonian, pool: Pool, max_iter: int, dtype: int = C64) -> int:
+    """Device bytes one serving request occupies while admitted."""
+    out = C.c_int64()
+    check(load().gocp_request_footprint(ham.n_qubits, pool.n_ops, pool.n_strings, ham.n_terms,
+                                        ham.n_classes, int(max_iter), int(dtype), C.byref(out)))
+    return out.value
+
+
+class Server:
+    """Continuous-batching ADAPT server (gocp_server_*): submit, then poll."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int, dtype: int = C64,
+                 iters_per_step: int = 4):
+        self._s = C.c_void_p()
+        check(load().gocp_server_create(ctx.handle, int(hbm_budget_bytes), int(max_slots), int(dtype),
+                                        int(iters_per_step), C.byref(self._s)))
+        self._keep = {}        # ticket -> (ham, pool, max_iter): alive until polled
+
+    def submit(self, ham: Hamiltonian, pool: Pool, max_iter: int, grad_tol: float) -> int:
+        t = C.c_uint64()
+        check(load().gocp_server_submit(self._s, ham.handle, pool.handle, int(max_iter),
+                                        float(grad_tol), C.byref(t)))
+        self._keep[t.value] = (ham, pool, int(max_iter))
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending; else (status, record dict or None, info dict)."""
+        ham, pool, max_iter = self._keep[ticket]
+        rec = _Record(max_iter)
+        info = RequestInfo()
+        st = load().gocp_server_poll(self._s, ticket, C.byref(rec.res), C.byref(info))
+        if st == GOCP_EBUSY:
+            return None
+        del self._keep[ticket]
+        inf = dict(status=info.status, n_qubits=info.n_qubits, t_submit_ns=info.t_submit_ns,
+                   t_admit_ns=info.t_admit_ns, t_done_ns=info.t_done_ns)
+        return st, (rec.as_dict() if st == 0 else None), inf
+
+    def stats(self):
+        a, q = C.c_int32(), C.c_int32()
+        c, b, n = C.c_int64(), C.c_int64(), C.c_int64()
+        check(load().gocp_server_stats(self._s, C.byref(a), C.byref(q), C.byref(c), C.byref(b),
+                                       C.byref(n)))
+        return dict(active=a.value, queued=q.value, completed=c.value, bytes_in_use=b.value,
+                    steps=n.value)
+
+    def close(self):
+        s, self._s = getattr(self, "_s", None), None
+        if s:
+            load().gocp_server_destroy(s)
 
     def __del__(self):
         self.close()

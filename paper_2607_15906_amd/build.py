@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgocp.so")
 
 HOST_SOURCES = ["host_mapping.cpp", "host_gocp.cpp", "capi_host.cpp"]
-HIP_SOURCES = ["kernels.hip", "runtime.hip", "adapt.hip"]
+HIP_SOURCES = ["kernels.hip", "runtime.hip", "adapt.hip", "serve.hip"]
 
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
@@ -59,7 +59,7 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
-          f"-L{ROCM}/lib", "-lamdhip64", f"-Wl,-rpath,{ROCM}/lib"])
+          f"-L{ROCM}/lib", "-lamdhip64", "-lpthread", f"-Wl,-rpath,{ROCM}/lib"])
     shutil.move(tmp, LIB)
     return LIB
 

@@ -1,0 +1,205 @@
+// Device-resident ADAPT instances and lock-step groups of them (shared by
+// the batched form and the serving runtime).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "runtime.h"
+
+namespace gocp {
+
+struct Instance {
+    const Ham *h = nullptr;
+    const Pool *p = nullptr;
+    void *psi = nullptr;
+    int dtype = 0;
+    int max_iter = 0;
+    double tol = 0.0;
+    InstPlan ip;
+    char *mem = nullptr;
+    InstDev desc;
+    bool finalized = false;
+    ~Instance() {
+        if (mem) (void)hipFree(mem);
+    }
+};
+
+// Validate, allocate and initialise one instance (state upload and counter
+// reset are stream-ordered on s).  With psi == nullptr the instance holds its
+// own state buffer, initialised to the Hartree-Fock basis state `hf`.
+inline Instance *instance_create(gocp_ctx *ctx, const Ham *h, const Pool *p, void *psi, int dtype,
+                          int max_iter, double tol, uint64_t hf, hipStream_t s) {
+    if (!h || !p) throw Error(GOCP_EINVAL, "null Hamiltonian or pool");
+    if (h->n_qubits != p->n_qubits)
+        throw Error(GOCP_ESHAPE, "Hamiltonian and pool act on different qubit counts");
+    check_dtype(dtype);
+    if (max_iter < 0) throw Error(GOCP_EINVAL, "negative max_iter");
+    std::unique_ptr<Instance> in(new Instance());
+    in->h = h;
+    in->p = p;
+    in->dtype = dtype;
+    in->max_iter = max_iter;
+    in->tol = tol;
+    const bool own = psi == nullptr;
+    in->ip = plan_instance(h->n_qubits, p->n_ops(), max_iter, dtype, own);
+    hip_check(hipMalloc(&in->mem, in->ip.bytes), "hipMalloc instance workspace");
+    in->psi = own ? in->mem + in->ip.o_psi : psi;
+    in->desc = make_desc(ctx->device, in->ip, in->mem, h, p, in->psi, nullptr);
+    const AdaptState st = make_state(in->ip, in->mem, max_iter, tol, true);
+    hip_check(hipMemsetAsync(in->mem + in->ip.o_cnt, 0, in->ip.n_counters * sizeof(int32_t), s),
+              "hipMemsetAsync");
+    hip_check(hipMemcpyAsync(in->mem + in->ip.o_st, &st, sizeof(st), hipMemcpyHostToDevice, s), "H2D");
+    if (own) launch_basis(dtype, in->psi, 1u << h->n_qubits, (uint32_t)hf, s);
+    return in.release();
+}
+
+struct Group {
+    gocp_ctx *ctx = nullptr;
+    int dtype = 0;
+    std::vector<Instance *> inst;
+    char *meta = nullptr;
+    size_t meta_cap = 0;
+    InstDev *desc = nullptr;
+    int2 *btile = nullptr, *bpair = nullptr, *bsub = nullptr;
+    int32_t *done = nullptr;   // n flags gathered on the device
+    int nt = 0, np = 0;
+    std::vector<int> tile0, pair0;
+    static constexpr int kChunk = 8;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+
+    ~Group() {
+        drop_graphs();
+        if (meta) (void)hipFree(meta);
+    }
+
+    void drop_graphs() {
+        for (int k = 0; k < 2; ++k) {
+            if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
+            if (graph[k]) (void)hipGraphDestroy(graph[k]);
+            exec[k] = nullptr;
+            graph[k] = nullptr;
+        }
+    }
+
+    // Upload descriptors and work tables of the current members.
+    void rebuild(hipStream_t s) {
+        drop_graphs();
+        std::vector<InstDev> d;
+        std::vector<int2> bt, bp;
+        tile0.clear();
+        pair0.clear();
+        for (size_t i = 0; i < inst.size(); ++i) {
+            d.push_back(inst[i]->desc);
+            tile0.push_back((int)bt.size());
+            pair0.push_back((int)bp.size());
+            for (int t = 0; t < inst[i]->ip.n_tiles; ++t) bt.push_back(make_int2((int)i, t));
+            for (int t = 0; t < inst[i]->ip.n_pblk; ++t) bp.push_back(make_int2((int)i, t));
+        }
+        nt = (int)bt.size();
+        np = (int)bp.size();
+        const size_t sub = std::max<size_t>({bt.size(), bp.size(), inst.size(), 1});
+        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        const size_t o_bt = al(d.size() * sizeof(InstDev));
+        const size_t o_bp = o_bt + al(bt.size() * sizeof(int2));
+        const size_t o_bs = o_bp + al(bp.size() * sizeof(int2));
+        const size_t o_dn = o_bs + al(sub * sizeof(int2));
+        const size_t need = o_dn + al(std::max<size_t>(inst.size(), 1) * sizeof(int32_t));
+        if (need > meta_cap) {
+            if (meta) {
+                hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+                hip_check(hipFree(meta), "hipFree");
+                meta = nullptr;
+            }
+            meta_cap = std::max(need, (size_t)1 << 16) * 2;
+            hip_check(hipMalloc(&meta, meta_cap), "hipMalloc group tables");
+        }
+        desc = reinterpret_cast<InstDev *>(meta);
+        btile = reinterpret_cast<int2 *>(meta + o_bt);
+        bpair = reinterpret_cast<int2 *>(meta + o_bp);
+        bsub = reinterpret_cast<int2 *>(meta + o_bs);
+        done = reinterpret_cast<int32_t *>(meta + o_dn);
+        if (!d.empty())
+            hip_check(hipMemcpyAsync(desc, d.data(), d.size() * sizeof(InstDev), hipMemcpyHostToDevice, s), "H2D");
+        if (!bt.empty())
+            hip_check(hipMemcpyAsync(btile, bt.data(), bt.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
+        if (!bp.empty())
+            hip_check(hipMemcpyAsync(bpair, bp.data(), bp.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
+    }
+
+    // One ADAPT iteration of every member (the screen and selection of the
+    // current state were done by the previous launch of k_energy_screen):
+    // line-search vectors, H v / H w and the angle, Taylor update, then the
+    // new state's energy together with its screen and selection.
+    void enqueue_iteration(hipStream_t s) const {
+        if (inst.empty()) return;
+        launch_kernel(K_LINE_VW, dtype, desc, bpair, np, 1, s);
+        launch_kernel(K_LINE_HVW, dtype, desc, btile, nt, 1, s);
+        launch_kernel(K_TAYLOR, dtype, desc, bpair, np, 1, s);
+        launch_kernel(K_ENERGY_SCREEN, dtype, desc, btile, nt, 2, s);
+    }
+
+    void capture() {
+        hipStream_t cs = ctx->own_stream;
+        const int iters[2] = {1, kChunk};
+        for (int k = 0; k < 2; ++k) {
+            hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            for (int i = 0; i < iters[k]; ++i) enqueue_iteration(cs);
+            hip_check(hipStreamEndCapture(cs, &graph[k]), "hipStreamEndCapture");
+            hip_check(hipGraphInstantiate(&exec[k], graph[k], nullptr, nullptr, 0), "hipGraphInstantiate");
+        }
+    }
+
+    // Enqueue n iterations on s (graph replays when use_graph).
+    void step(int n, hipStream_t s, bool use_graph) {
+        if (inst.empty() || n <= 0) return;
+        for (Instance *in : inst) in->finalized = false;
+        if (!use_graph) {
+            for (int i = 0; i < n; ++i) enqueue_iteration(s);
+            return;
+        }
+        if (!exec[0]) capture();
+        for (int i = 0; i < n / kChunk; ++i) hip_check(hipGraphLaunch(exec[1], s), "hipGraphLaunch");
+        for (int i = 0; i < n % kChunk; ++i) hip_check(hipGraphLaunch(exec[0], s), "hipGraphLaunch");
+    }
+
+    // Launch one kernel over the tile (or pair, or one-per-instance) rows of
+    // a subset of members.
+    void launch_subset(int which, int mode, const std::vector<int> &members, int table, hipStream_t s) {
+        std::vector<int2> rows;
+        for (int i : members) {
+            const int n = table == 0 ? inst[i]->ip.n_tiles : table == 1 ? inst[i]->ip.n_pblk : 1;
+            for (int t = 0; t < n; ++t) rows.push_back(make_int2(i, t));
+        }
+        if (rows.empty()) return;
+        hip_check(hipMemcpyAsync(bsub, rows.data(), rows.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
+        launch_kernel(which, dtype, desc, bsub, (int)rows.size(), mode, s);
+    }
+
+    // Energy, screen and selection of the starting state of the given members.
+    void start(const std::vector<int> &members, hipStream_t s) {
+        launch_subset(K_ENERGY_SCREEN, 1, members, 0, s);
+    }
+
+    // Scale the states of the given members to unit norm (their renormalisation
+    // is otherwise folded into the next Taylor update).
+    void finalize(const std::vector<int> &members, hipStream_t s) {
+        std::vector<int> todo;
+        for (int i : members)
+            if (!inst[i]->finalized) todo.push_back(i);
+        if (todo.empty()) return;
+        launch_subset(K_NORMALIZE, 1, todo, 1, s);
+        launch_subset(K_UNIT_NORM, 0, todo, 2, s);
+        for (int i : todo) inst[i]->finalized = true;
+    }
+};
+
+void read_result(Instance *in, hipStream_t s, gocp_adapt_result *res, AdaptState *out_state);
+void run_to_completion(Group &g, int max_iter, bool use_graph, hipStream_t s);
+
+}  // namespace gocp

@@ -21,11 +21,13 @@ constexpr int kStageCls = 1024;        // classes or operators (16 KiB)
 // Tiles per group in the two-level reduction of the gradient screen.
 constexpr int kGroup = 16;
 
-// A folded Pauli string as the kernels read it: 16 bytes, one scalar load.
+// A folded Pauli string as the kernels read it (16 bytes): the magnitude of
+// its coefficient, its Z mask, and the coefficient's sign bit, so that the
+// signed term at amplitude d is |c| with sign bit popcount(d & z) + sign.
 struct HTerm {
-    double c;
+    double c;        // |c|
     uint32_t z;
-    uint32_t pad;
+    uint32_t sign;   // 1 if c < 0
 };
 
 // An X-mask class of H (or a pool operator): its mask and string range.

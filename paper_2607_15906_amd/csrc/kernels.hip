@@ -94,14 +94,16 @@ __device__ __forceinline__ HTerm load_rec(const GOCP_AS4 HTerm *p, int i) {
     HTerm r;
     r.c = p[i].c;
     r.z = p[i].z;
-    r.pad = 0;
+    r.sign = p[i].sign;
     return r;
 }
 
-// c * (-1)^popcount(d & z): flip the sign bit by the parity of d & z.
-__device__ __forceinline__ double signed_coef(double c, uint32_t d, uint32_t z) {
-    const int flip = (int)((uint32_t)__popc(d & z) << 31);
-    return __hiloint2double(__double2hiint(c) ^ flip, __double2loint(c));
+// c (-1)^popcount(d & z) for c = (-1)^sign |c|: the sign bit of the result is
+// the low bit of popcount(d & z) + sign, placed over |c| (popcount-with-add
+// and shift-or, two instructions).
+__device__ __forceinline__ double signed_coef(const HTerm &t, uint32_t d) {
+    const uint32_t bit = ((uint32_t)__popc(d & t.z) + t.sign) << 31;
+    return __hiloint2double((int)(bit | (uint32_t)__double2hiint(t.c)), __double2loint(t.c));
 }
 
 // The same sum at two amplitudes d and e (the two members of a pair).
@@ -111,8 +113,8 @@ __device__ __forceinline__ void string_sum2(const GOCP_AS4 HTerm *t, int s0, int
     he = 0.0;
     for (int s = s0; s < s1; ++s) {
         const HTerm a = load_rec(t, s);
-        hd += signed_coef(a.c, d, a.z);
-        he += signed_coef(a.c, e, a.z);
+        hd += signed_coef(a, d);
+        he += signed_coef(a, e);
     }
 }
 
@@ -227,14 +229,14 @@ __device__ __forceinline__ double lds_string_sum(const HTerm *t, int s0, int s1,
     int s = s0;
     for (; s + 4 <= s1; s += 4) {
         const HTerm a = t[s], b = t[s + 1], c = t[s + 2], e = t[s + 3];
-        f0 += signed_coef(a.c, d, a.z);
-        f1 += signed_coef(b.c, d, b.z);
-        f0 += signed_coef(c.c, d, c.z);
-        f1 += signed_coef(e.c, d, e.z);
+        f0 += signed_coef(a, d);
+        f1 += signed_coef(b, d);
+        f0 += signed_coef(c, d);
+        f1 += signed_coef(e, d);
     }
     for (; s < s1; ++s) {
         const HTerm a = t[s];
-        f0 += signed_coef(a.c, d, a.z);
+        f0 += signed_coef(a, d);
     }
     return f0 + f1;
 }

@@ -31,6 +31,8 @@ T *dev_upload(const std::vector<T> &v) {
     return p;
 }
 
+HTerm make_term(double c, uint32_t z) { return HTerm{std::fabs(c), z, std::signbit(c) ? 1u : 0u}; }
+
 // Boundaries of consecutive record groups (classes or operators) such that
 // each group has at most kStageCls records and kStageTerms strings.
 std::vector<int32_t> stage_chunks(const std::vector<int32_t> &off) {
@@ -79,7 +81,7 @@ const DeviceHam *device_ham(const Ham &h, int dev) {
     std::vector<HClass> cls(h.n_classes());
     for (int c = 0; c < h.n_classes(); ++c) cls[c] = HClass{h.cls_x[c], h.cls_off[c], h.cls_off[c + 1], 0};
     std::vector<HTerm> terms(h.str_z.size());
-    for (size_t s = 0; s < terms.size(); ++s) terms[s] = HTerm{h.str_c[s], h.str_z[s], 0u};
+    for (size_t s = 0; s < terms.size(); ++s) terms[s] = make_term(h.str_c[s], h.str_z[s]);
     d->hcls = dev_upload(cls);
     d->hterm = dev_upload(terms);
     const std::vector<int32_t> ch = stage_chunks(h.cls_off);
@@ -98,7 +100,7 @@ const DevicePool *device_pool(const Pool &p, int dev) {
     std::vector<HClass> ops(p.n_ops());
     for (int k = 0; k < p.n_ops(); ++k) ops[k] = HClass{p.op_x[k], p.op_off[k], p.op_off[k + 1], p.kind[k]};
     std::vector<HTerm> terms(p.str_z.size());
-    for (size_t s = 0; s < terms.size(); ++s) terms[s] = HTerm{p.str_c[s], p.str_z[s], 0u};
+    for (size_t s = 0; s < terms.size(); ++s) terms[s] = make_term(p.str_c[s], p.str_z[s]);
     d->pop = dev_upload(ops);
     d->pterm = dev_upload(terms);
     d->op_norm1 = dev_upload(p.op_norm1);
@@ -110,7 +112,7 @@ const DevicePool *device_pool(const Pool &p, int dev) {
     std::vector<int32_t> soff{0};
     for (int32_t j : p.fam_members) {
         HClass r{p.op_x[j], (int32_t)sterm.size(), 0, j};
-        for (int s = p.op_off[j]; s < p.op_off[j + 1]; ++s) sterm.push_back(HTerm{p.str_c[s], p.str_z[s], 0u});
+        for (int s = p.op_off[j]; s < p.op_off[j + 1]; ++s) sterm.push_back(make_term(p.str_c[s], p.str_z[s]));
         r.s1 = (int32_t)sterm.size();
         sop.push_back(r);
         soff.push_back(r.s1);
