@@ -58,10 +58,10 @@ def _amp_updates(nq, T, S, off, ops, subs):
     return tot * (1 << nq)
 
 
-def run_adapt_timed(g, ctx, H, P, nq, ne, mapping, dtype, steps, warmup):
+def run_adapt_timed(g, ctx, H, P, nq, ne, mapping, dtype, steps, warmup, schedule=0):
     import torch
     psi = _hf_state(g, ctx, nq, ne, mapping, dtype)
-    b = g.Batch(ctx, [H], [P], [psi], max_iter=warmup + steps, use_graph=True)
+    b = g.Batch(ctx, [H], [P], [psi], max_iter=warmup + steps, use_graph=True, schedule=schedule)
     b.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -69,10 +69,11 @@ def run_adapt_timed(g, ctx, H, P, nq, ne, mapping, dtype, steps, warmup):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     r = b.result(0)
+    r["psi"] = psi
     return b, r, dt
 
 
-def serving_bench(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, load=0.7):
+def serving_bench(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, load=0.7, amps_per_lane=1):
     """Poisson stream of ADAPT solves (8-16 qubits, ||g|| < 1e-3, at most 300
     iterations), complex64 states.  Capacity is measured first with all
     requests submitted at once; the timed stream then arrives at `load` times
@@ -96,7 +97,8 @@ def serving_bench(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, load=0.7)
                 tickets.remove(t)
 
     # capacity: everything at once
-    srv = g.Server(ctx, budget, max_slots, dtype=1, iters_per_step=iters_per_step)
+    srv = g.Server(ctx, budget, max_slots, dtype=1, iters_per_step=iters_per_step,
+                   amps_per_lane=amps_per_lane)
     t0 = time.perf_counter()
     pend = [srv.submit(H, P, max_iter, tol) for (_, H, P) in reqs[warm:]]
     done = {}
@@ -108,7 +110,8 @@ def serving_bench(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, load=0.7)
 
     # timed Poisson stream at `load` x capacity (warm-up requests first)
     rate = load * cap
-    srv = g.Server(ctx, budget, max_slots, dtype=1, iters_per_step=iters_per_step)
+    srv = g.Server(ctx, budget, max_slots, dtype=1, iters_per_step=iters_per_step,
+                   amps_per_lane=amps_per_lane)
     arrivals = [d["arrival_s"] / rate for (d, _, _) in reqs]
     pend, done, meas = [], {}, []
     t0 = time.perf_counter()
@@ -143,7 +146,8 @@ def serving_bench(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, load=0.7)
     seq = nseq / (time.perf_counter() - t0)
     return {"requests": n_req, "warmup_requests": warm, "qubits": "uniform over {8,10,12,14,16}",
             "grad_tol": tol, "max_iter": max_iter, "state": "complex64", "max_slots": max_slots,
-            "iters_per_step": iters_per_step, "hbm_budget_bytes": budget,
+            "iters_per_step": iters_per_step, "amps_per_lane": amps_per_lane,
+            "hbm_budget_bytes": budget,
             "capacity_solves_per_s": round(cap, 2), "offered_rate_hz": round(rate, 2),
             "solves_per_s": round(n_req / ((t_end - t_sub) * 1e-9), 2),
             "p50_ms": round(float(np.percentile(lat, 50)), 3),
@@ -162,6 +166,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the c128 and batched extras")
     ap.add_argument("--serve-requests", type=int, default=96,
                     help="measured requests of the serving stream (after 16 warm-up requests)")
+    ap.add_argument("--schedule", type=int, default=0, choices=(0, 1, 2, 4),
+                    help="amplitudes per lane of the tile kernels (0: autotune)")
+    ap.add_argument("--serve-amps-per-lane", type=int, default=1, choices=(1, 2, 4))
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (a known-size "
                          "kernel that calibrates memory-traffic counters)")
@@ -197,7 +204,9 @@ def main():
     T, C, S, M = H.n_terms, H.n_classes, P.n_strings, P.n_ops
 
     _say(f"[bench] 14q c64: {args.warmup} warmup + {args.steps} timed ADAPT iterations")
-    b, r, dt = run_adapt_timed(g, ctx, H, P, nq, ne, mapping, torch.complex64, args.steps, args.warmup)
+    b, r, dt = run_adapt_timed(g, ctx, H, P, nq, ne, mapping, torch.complex64, args.steps, args.warmup,
+                               schedule=args.schedule)
+    sched = b.schedule
     w0, w1 = args.warmup, args.warmup + args.steps
     iters = r["n_iter"]
     if iters != w1:
@@ -234,7 +243,7 @@ def main():
                                "complex64 state with FP64 accumulation",
                    "n_qubits": nq, "n_electrons": ne, "mapping": mapping, "integral_seed": seed,
                    "pauli_terms": T, "xmask_classes": C, "pool_ops": M, "pool_strings": S,
-                   "state": "complex64", "graph_replay": True},
+                   "state": "complex64", "graph_replay": True, "amps_per_lane": sched},
         "amp_updates_per_s": float(f"{upd / dt:.6g}"),
         "final_energy": float(r["energies"][-1]),
         "roofline": roofline,
@@ -243,12 +252,22 @@ def main():
     if not args.no_forms:
         _say("[bench] 14q c128 path")
         b2, r2, dt2 = run_adapt_timed(g, ctx, H, P, nq, ne, mapping, torch.complex128,
-                                      args.steps, args.warmup)
+                                      args.steps, args.warmup, schedule=sched)
         b2.close()
         u2 = _amp_updates(nq, T, S, off, r2["ops"][w0:w1], r2["substeps"][w0:w1])
+        same_ops = r2["ops"] == r["ops"]
+        p64 = r["psi"].to(torch.complex128)
+        fid = float(torch.abs(torch.vdot(r2["psi"], p64)) ** 2)
+        # precision form: gradients of the final complex64 state against those of
+        # the complex128 state, both on the device with FP64 accumulation
+        g64 = g.pool_gradients(ctx, H, P, r["psi"])
+        g128 = g.pool_gradients(ctx, H, P, r2["psi"])
         out["complex128_state"] = {"iters_per_s": round(args.steps / dt2, 3),
                                    "amp_updates_per_s": float(f"{u2 / dt2:.6g}"),
-                                   "max_abs_dE_vs_c64": float(np.abs(r2["energies"] - r["energies"]).max())}
+                                   "same_operator_sequence": same_ops,
+                                   "max_abs_dE_vs_c64": float(np.abs(r2["energies"] - r["energies"]).max()),
+                                   "final_state_fidelity_c64": fid,
+                                   "max_abs_dg_final_c64": float(np.abs(g64 - g128).max())}
 
         _say("[bench] batched form: 64 instances x 30 iterations")
         insts = batched_instances()
@@ -259,12 +278,13 @@ def main():
             psis.append(_hf_state(g, ctx, d["n_qubits"], d["n_electrons"], d["mapping"], torch.complex64))
             meta.append((d["n_qubits"], Hi.n_terms, Pi.n_strings, Pi.strings()[0]))
         iters_b = 30
-        bb = g.Batch(ctx, hams, pools, psis, max_iter=iters_b, use_graph=True)
+        bb = g.Batch(ctx, hams, pools, psis, max_iter=iters_b, use_graph=True, schedule=args.schedule)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         bb.step(iters_b)
         torch.cuda.synchronize()
         dtb = time.perf_counter() - t0
+        sched_b = bb.schedule
         ub = 0
         for i in range(len(insts)):
             ri = bb.result(i)
@@ -272,12 +292,14 @@ def main():
             ub += _amp_updates(nqi, Ti, Si, offi, ri["ops"], ri["substeps"])
         bb.close()
         out["batched"] = {"instances": len(insts), "mix": "24x10q + 24x12q + 16x14q, JW/BK alternating",
-                          "iterations_each": iters_b, "seconds": round(dtb, 6),
+                          "iterations_each": iters_b, "amps_per_lane": sched_b,
+                          "seconds": round(dtb, 6),
                           "instance_iters_per_s": round(len(insts) * iters_b / dtb, 2),
                           "amp_updates_per_s": float(f"{ub / dtb:.6g}")}
 
         _say("[bench] serving form: Poisson stream of ADAPT solves")
-        out["serving"] = serving_bench(g, ctx, n_req=args.serve_requests, warm=16)
+        out["serving"] = serving_bench(g, ctx, n_req=args.serve_requests, warm=16,
+                                       amps_per_lane=args.serve_amps_per_lane)
 
     if args.cpu_sample_iters > 0:
         _say(f"[bench] CPU oracle baseline: {args.cpu_sample_iters} iterations at 14q")

@@ -213,7 +213,11 @@ int taylor5_apply(gocp_ctx *ctx, const gocp_pool *p, int32_t k, double theta, vo
 typedef struct {
     double grad_tol;        /* stop when ||g||_2 < grad_tol (0: never)               */
     int32_t max_iter;       /* operators appended at most                            */
-    int32_t use_graph;      /* 1: replay one captured hipGraph per iteration         */
+    int32_t use_graph;      /* 1: replay captured hipGraphs of the iteration         */
+    int32_t schedule;       /* amplitudes per lane of the tile kernels: 1, 2 or 4;
+                               0 = autotune (time each on the instances, keep the
+                               fastest; remembered per qubit-count mix)             */
+    int32_t reserved;
 } gocp_adapt_params;
 
 typedef struct {
@@ -273,6 +277,8 @@ int gocp_batch_result(gocp_batch *b, int32_t i, gocp_adapt_result *res);
  * from its current states and leave the iteration record untouched.
  */
 int gocp_batch_time_kernel(gocp_batch *b, int32_t which, int32_t n_launch, double *avg_ms);
+/* The schedule the batch runs with (amplitudes per lane; autotuned or given). */
+int gocp_batch_schedule(gocp_batch *b, int32_t *amps_per_lane);
 int gocp_batch_destroy(gocp_batch *b);
 
 /* ---------------------------------------------------------------------
@@ -298,10 +304,11 @@ typedef struct {
 /* Device bytes one request occupies while admitted (workspace + term tables). */
 int gocp_request_footprint(int n_qubits, int n_ops, int n_strings, int64_t n_terms, int n_classes,
                            int max_iter, int dtype, int64_t *bytes);
-/* Start a server on ctx's device with its own stream and worker thread.
- * Errors: EINVAL (non-positive budget, slots or iters_per_step). */
+/* Start a server on ctx's device with its own stream and worker thread; the
+ * tile kernels run with amps_per_lane (1, 2 or 4) amplitudes per lane.
+ * Errors: EINVAL (non-positive budget, slots or iters_per_step; bad schedule). */
 int gocp_server_create(gocp_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_slots, int dtype,
-                       int32_t iters_per_step, gocp_server **out);
+                       int32_t iters_per_step, int32_t amps_per_lane, gocp_server **out);
 /* Queue one solve: ham and pool (equal qubit counts) must stay alive until
  * the request has been polled.  Stops at ||g||_2 < grad_tol or max_iter. */
 int gocp_server_submit(gocp_server *s, const gocp_ham *h, const gocp_pool *p, int32_t max_iter,

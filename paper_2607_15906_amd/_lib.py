@@ -21,7 +21,8 @@ class GocpError(RuntimeError):
 
 
 class AdaptParams(C.Structure):
-    _fields_ = [("grad_tol", C.c_double), ("max_iter", C.c_int32), ("use_graph", C.c_int32)]
+    _fields_ = [("grad_tol", C.c_double), ("max_iter", C.c_int32), ("use_graph", C.c_int32),
+                ("schedule", C.c_int32), ("reserved", C.c_int32)]
 
 
 class RequestInfo(C.Structure):
@@ -77,9 +78,10 @@ SIGNATURES = {
     "gocp_batch_poll": [_P, _I32P],
     "gocp_batch_result": [_P, C.c_int32, C.POINTER(AdaptResult)],
     "gocp_batch_time_kernel": [_P, C.c_int32, C.c_int32, _F64P],
+    "gocp_batch_schedule": [_P, _I32P],
     "gocp_batch_destroy": [_P],
     "gocp_request_footprint": [C.c_int, C.c_int, C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int, _I64P],
-    "gocp_server_create": [_P, C.c_int64, C.c_int32, C.c_int, C.c_int32, _PP],
+    "gocp_server_create": [_P, C.c_int64, C.c_int32, C.c_int, C.c_int32, C.c_int32, _PP],
     "gocp_server_submit": [_P, _P, _P, C.c_int32, C.c_double, _U64P],
     "gocp_server_poll": [_P, C.c_uint64, C.POINTER(AdaptResult), C.POINTER(RequestInfo)],
     "gocp_server_stats": [_P, _I32P, _I32P, _I64P, _I64P, _I64P],

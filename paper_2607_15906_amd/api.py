@@ -274,11 +274,14 @@ class _Record:
 
 
 def adapt_solve(ctx: Context, ham: Hamiltonian, pool: Pool, psi, max_iter: int,
-                grad_tol: float = 0.0, use_graph: bool = True):
-    """Run ADAPT in place on psi; returns a dict of per-iteration records."""
+                grad_tol: float = 0.0, use_graph: bool = True, schedule: int = 1):
+    """Run ADAPT in place on psi; returns a dict of per-iteration records.
+
+    schedule: amplitudes per lane of the tile kernels (1, 2, 4) or 0 to autotune.
+    """
     p, dt = _state(psi)
     rec = _Record(max_iter)
-    prm = AdaptParams(float(grad_tol), int(max_iter), 1 if use_graph else 0)
+    prm = AdaptParams(float(grad_tol), int(max_iter), 1 if use_graph else 0, int(schedule), 0)
     check(load().adapt_solve(ctx.handle, ham.handle, pool.handle, p, dt, C.byref(prm),
                              C.byref(rec.res)))
     return rec.as_dict()
@@ -288,7 +291,7 @@ class Batch:
     """Lock-step batch of ADAPT instances (gocp_batch_*)."""
 
     def __init__(self, ctx: Context, hams, pools, psis, max_iter: int, grad_tol: float = 0.0,
-                 use_graph: bool = True):
+                 use_graph: bool = True, schedule: int = 0):
         n = len(psis)
         if not (len(hams) == len(pools) == n) or n == 0:
             raise ValueError("hams, pools and psis must have the same non-zero length")
@@ -307,7 +310,7 @@ class Batch:
         S = (C.c_void_p * n)(*ptrs)
         self.max_iter = max_iter
         self.n = n
-        prm = AdaptParams(float(grad_tol), int(max_iter), 1 if use_graph else 0)
+        prm = AdaptParams(float(grad_tol), int(max_iter), 1 if use_graph else 0, int(schedule), 0)
         self._b = C.c_void_p()
         check(load().gocp_batch_create(ctx.handle, n, H, P, S, self.dtype, C.byref(prm),
                                        C.byref(self._b)))
@@ -327,6 +330,12 @@ class Batch:
         rec = _Record(self.max_iter)
         check(load().gocp_batch_result(self._b, int(i), C.byref(rec.res)))
         return rec.as_dict()
+
+    @property
+    def schedule(self) -> int:
+        r = C.c_int32()
+        check(load().gocp_batch_schedule(self._b, C.byref(r)))
+        return r.value
 
     def time_kernel(self, which: int, n_launch: int) -> float:
         """Mean duration in ms of kernel `which` (0 H apply, 1 screen, 2 H v/H w)."""
@@ -355,10 +364,10 @@ class Server:
     """Continuous-batching ADAPT server (gocp_server_*): submit, then poll."""
 
     def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int, dtype: int = C64,
-                 iters_per_step: int = 4):
+                 iters_per_step: int = 4, amps_per_lane: int = 1):
         self._s = C.c_void_p()
         check(load().gocp_server_create(ctx.handle, int(hbm_budget_bytes), int(max_slots), int(dtype),
-                                        int(iters_per_step), C.byref(self._s)))
+                                        int(iters_per_step), int(amps_per_lane), C.byref(self._s)))
         self._keep = {}        # ticket -> (ham, pool, max_iter): alive until polled
 
     def submit(self, ham: Hamiltonian, pool: Pool, max_iter: int, grad_tol: float) -> int:

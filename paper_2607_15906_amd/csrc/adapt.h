@@ -53,14 +53,23 @@ inline Instance *instance_create(gocp_ctx *ctx, const Ham *h, const Pool *p, voi
     const AdaptState st = make_state(in->ip, in->mem, max_iter, tol, true);
     hip_check(hipMemsetAsync(in->mem + in->ip.o_cnt, 0, in->ip.n_counters * sizeof(int32_t), s),
               "hipMemsetAsync");
+    hip_check(hipMemsetAsync(in->mem + in->ip.o_v, 0, in->ip.o_pe - in->ip.o_v, s), "hipMemsetAsync");
     hip_check(hipMemcpyAsync(in->mem + in->ip.o_st, &st, sizeof(st), hipMemcpyHostToDevice, s), "H2D");
     if (own) launch_basis(dtype, in->psi, 1u << h->n_qubits, (uint32_t)hf, s);
     return in.release();
 }
 
+// Tiles of 64 R amplitudes covering a 2^n state.
+inline int tiles_for(int n_qubits, int R) {
+    const size_t dim = (size_t)1 << n_qubits, t = (size_t)kTile * R;
+    return (int)((dim + t - 1) / t);
+}
+
 struct Group {
     gocp_ctx *ctx = nullptr;
     int dtype = 0;
+    int R = 1;                 // amplitudes per lane of the tile kernels
+    std::vector<int> ntile;    // tiles of each member for R
     std::vector<Instance *> inst;
     char *meta = nullptr;
     size_t meta_cap = 0;
@@ -94,11 +103,16 @@ struct Group {
         std::vector<int2> bt, bp;
         tile0.clear();
         pair0.clear();
+        ntile.clear();
         for (size_t i = 0; i < inst.size(); ++i) {
-            d.push_back(inst[i]->desc);
+            InstDev di = inst[i]->desc;
+            di.n_tiles = tiles_for(di.n_qubits, R);
+            di.n_groups = (di.n_tiles + kGroup - 1) / kGroup;
+            d.push_back(di);
+            ntile.push_back(di.n_tiles);
             tile0.push_back((int)bt.size());
             pair0.push_back((int)bp.size());
-            for (int t = 0; t < inst[i]->ip.n_tiles; ++t) bt.push_back(make_int2((int)i, t));
+            for (int t = 0; t < di.n_tiles; ++t) bt.push_back(make_int2((int)i, t));
             for (int t = 0; t < inst[i]->ip.n_pblk; ++t) bp.push_back(make_int2((int)i, t));
         }
         nt = (int)bt.size();
@@ -138,10 +152,10 @@ struct Group {
     // new state's energy together with its screen and selection.
     void enqueue_iteration(hipStream_t s) const {
         if (inst.empty()) return;
-        launch_kernel(K_LINE_VW, dtype, desc, bpair, np, 1, s);
-        launch_kernel(K_LINE_HVW, dtype, desc, btile, nt, 1, s);
-        launch_kernel(K_TAYLOR, dtype, desc, bpair, np, 1, s);
-        launch_kernel(K_ENERGY_SCREEN, dtype, desc, btile, nt, 2, s);
+        launch_kernel(K_LINE_VW, dtype, R, desc, bpair, np, 1, s);
+        launch_kernel(K_LINE_HVW, dtype, R, desc, btile, nt, 1, s);
+        launch_kernel(K_TAYLOR, dtype, R, desc, bpair, np, 1, s);
+        launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 2, s);
     }
 
     void capture() {
@@ -173,13 +187,41 @@ struct Group {
     void launch_subset(int which, int mode, const std::vector<int> &members, int table, hipStream_t s) {
         std::vector<int2> rows;
         for (int i : members) {
-            const int n = table == 0 ? inst[i]->ip.n_tiles : table == 1 ? inst[i]->ip.n_pblk : 1;
+            const int n = table == 0 ? ntile[i] : table == 1 ? inst[i]->ip.n_pblk : 1;
             for (int t = 0; t < n; ++t) rows.push_back(make_int2(i, t));
         }
         if (rows.empty()) return;
         hip_check(hipMemcpyAsync(bsub, rows.data(), rows.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
-        launch_kernel(which, dtype, desc, bsub, (int)rows.size(), mode, s);
+        launch_kernel(which, dtype, R, desc, bsub, (int)rows.size(), mode, s);
     }
+
+    // Time one energy+screen launch and one line-search launch over the
+    // whole group (mode 0: no iteration record is touched); milliseconds.
+    double time_tile_kernels(hipStream_t s, int reps) {
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "hipEventCreate");
+        hip_check(hipEventCreate(&e1), "hipEventCreate");
+        launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 0, s);
+        launch_kernel(K_LINE_HVW, dtype, R, desc, btile, nt, 0, s);
+        hip_check(hipEventRecord(e0, s), "hipEventRecord");
+        for (int i = 0; i < reps; ++i) {
+            launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 0, s);
+            launch_kernel(K_LINE_HVW, dtype, R, desc, btile, nt, 0, s);
+        }
+        hip_check(hipEventRecord(e1, s), "hipEventRecord");
+        hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return (double)ms / reps;
+    }
+
+    // Choose the register blocking (schedule 1, 2 or 4 amplitudes per lane;
+    // 0 = autotune: time each on this group's members and keep the fastest,
+    // remembered per composition of qubit counts and precision).  Call before
+    // start(): the trial launches recompute values start() recomputes.
+    void choose_schedule(int schedule, hipStream_t s);
 
     // Energy, screen and selection of the starting state of the given members.
     void start(const std::vector<int> &members, hipStream_t s) {
@@ -200,6 +242,8 @@ struct Group {
 };
 
 void read_result(Instance *in, hipStream_t s, gocp_adapt_result *res, AdaptState *out_state);
+int autotune_cached(const std::vector<int> &qubits, int dtype);
+void autotune_store(const std::vector<int> &qubits, int dtype, int R);
 void run_to_completion(Group &g, int max_iter, bool use_graph, hipStream_t s);
 
 }  // namespace gocp

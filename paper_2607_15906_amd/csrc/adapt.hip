@@ -11,7 +11,61 @@
 
 #include "adapt.h"
 
+#include <map>
+#include <mutex>
+#include <string>
+
 namespace gocp {
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+
+std::string tune_key(std::vector<int> q, int dtype) {
+    std::sort(q.begin(), q.end());
+    std::string k = std::to_string(dtype) + ":";
+    for (int v : q) k += std::to_string(v) + ",";
+    return k;
+}
+}  // namespace
+
+int autotune_cached(const std::vector<int> &qubits, int dtype) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(qubits, dtype));
+    return it == g_tune.end() ? 0 : it->second;
+}
+
+void autotune_store(const std::vector<int> &qubits, int dtype, int R) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(qubits, dtype)] = R;
+}
+
+void Group::choose_schedule(int schedule, hipStream_t s) {
+    if (schedule == 1 || schedule == 2 || schedule == 4) {
+        R = schedule;
+        rebuild(s);
+        return;
+    }
+    if (schedule != 0) throw Error(GOCP_EINVAL, "schedule must be 0 (autotune), 1, 2 or 4");
+    std::vector<int> q;
+    for (Instance *in : inst) q.push_back(in->ip.n_qubits);
+    int best = autotune_cached(q, dtype);
+    if (best == 0) {
+        double best_ms = 0.0;
+        for (int cand : {1, 2, 4}) {
+            R = cand;
+            rebuild(s);
+            const double ms = time_tile_kernels(s, 3);
+            if (best == 0 || ms < best_ms) {
+                best = cand;
+                best_ms = ms;
+            }
+        }
+        autotune_store(q, dtype, best);
+    }
+    R = best;
+    rebuild(s);
+}
 
 // Copy one instance's iteration record to the caller's arrays (synchronises).
 void read_result(Instance *in, hipStream_t s, gocp_adapt_result *res, AdaptState *out_state) {
@@ -116,7 +170,7 @@ int adapt_solve(gocp_ctx *ctx, const gocp_ham *hh, const gocp_pool *pp, void *ps
     g.ctx = ctx;
     g.dtype = dtype;
     g.inst.push_back(in.get());
-    g.rebuild(s);
+    g.choose_schedule(params->schedule, s);
     g.start({0}, s);
     run_to_completion(g, params->max_iter, params->use_graph != 0, s);
     g.finalize({0}, s);
@@ -144,7 +198,7 @@ int gocp_batch_create(gocp_ctx *ctx, int32_t n, const gocp_ham *const *hams,
                                               dtype, params->max_iter, params->grad_tol, 0, s));
         b->group.inst.push_back(b->owned.back().get());
     }
-    b->group.rebuild(s);
+    b->group.choose_schedule(params->schedule, s);
     std::vector<int> all(n);
     for (int i = 0; i < n; ++i) all[i] = i;
     b->group.start(all, s);
@@ -215,9 +269,9 @@ int gocp_batch_time_kernel(gocp_batch *b, int32_t which, int32_t n_launch, doubl
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
-    launch_kernel(kid, g.dtype, g.desc, g.btile, g.nt, 0, s);     // warm
+    launch_kernel(kid, g.dtype, g.R, g.desc, g.btile, g.nt, 0, s);     // warm
     hip_check(hipEventRecord(e0, s), "hipEventRecord");
-    for (int i = 0; i < n_launch; ++i) launch_kernel(kid, g.dtype, g.desc, g.btile, g.nt, 0, s);
+    for (int i = 0; i < n_launch; ++i) launch_kernel(kid, g.dtype, g.R, g.desc, g.btile, g.nt, 0, s);
     hip_check(hipEventRecord(e1, s), "hipEventRecord");
     hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
     float ms = 0.f;
@@ -225,6 +279,14 @@ int gocp_batch_time_kernel(gocp_batch *b, int32_t which, int32_t n_launch, doubl
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *avg_ms = (double)ms / n_launch;
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
+int gocp_batch_schedule(gocp_batch *b, int32_t *amps_per_lane) {
+    GOCP_GUARD_BEGIN
+    if (!b || !amps_per_lane) throw Error(GOCP_EINVAL, "null argument");
+    *amps_per_lane = b->group.R;
     return GOCP_OK;
     GOCP_GUARD_END
 }

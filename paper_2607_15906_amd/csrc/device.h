@@ -30,6 +30,15 @@ struct HTerm {
     uint32_t sign;   // 1 if c < 0
 };
 
+// Start offsets (relative to the class's first string, 16 bits each) of the
+// eight sub-buckets of a class's strings.  Within a class the strings are
+// ordered by key = 4 z_6 + 2 z_7 + z_8 (bits 6-8 of the Z mask, the register
+// bits of a lane's amplitudes), so every grouping of the strings by z_6, or by
+// (z_6, z_7), is a union of consecutive sub-buckets.
+struct HSub {
+    uint32_t w[4];
+};
+
 // An X-mask class of H (or a pool operator): its mask and string range.
 struct HClass {
     uint32_t x;
@@ -70,6 +79,7 @@ struct InstDev {
     // Hamiltonian, grouped by X mask
     const HClass *hcls;
     const HTerm *hterm;
+    const HSub *hsub;
     const int32_t *hchunk;      // n_hchunks + 1 class boundaries of the LDS stages
     // pool, in pool order (pair kernels)
     const HClass *pop;          // one record per operator
@@ -78,6 +88,7 @@ struct InstDev {
     // pool in GOCP family order (gradient screen); HClass.pad = pool index
     const HClass *sop;
     const HTerm *sterm;
+    const HSub *psub;
     const int32_t *pchunk;      // n_pchunks + 1 operator boundaries of the LDS stages
     // buffers (psi, v, w in the state precision; sigma FP64)
     void *psi;
@@ -107,6 +118,7 @@ struct DeviceHam {
     int device = -1;
     HClass *hcls = nullptr;
     HTerm *hterm = nullptr;
+    HSub *hsub = nullptr;
     int32_t *hchunk = nullptr;
     int n_chunks = 0;
 };
@@ -118,6 +130,7 @@ struct DevicePool {
     double *op_norm1 = nullptr;
     HClass *sop = nullptr;
     HTerm *sterm = nullptr;
+    HSub *psub = nullptr;
     int32_t *pchunk = nullptr;
     int n_chunks = 0;
 };

@@ -197,10 +197,12 @@ __device__ double block_sum_coh(const double *src, int n, int stride, double *ld
 // ------------------------------------------------------------------ LDS staging of term tables
 
 // Shared memory of a tile kernel: one chunk of records (classes or
-// operators) and their strings; reused for the cross-wave reduction.
+// operators), their sub-bucket offsets and their strings; reused for the
+// cross-wave reduction.
 struct Stage {
     HTerm terms[kStageTerms];
     HClass cls[kStageCls];
+    HSub sub[kStageCls];
 };
 
 // Copy n 16-byte records from global memory to LDS with the whole workgroup
@@ -243,13 +245,76 @@ __device__ __forceinline__ double lds_string_sum(const HTerm *t, int s0, int s1,
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Apply the X-mask classes of H to NV vectors at the lane's amplitude dd:
-// acc[2k], acc[2k+1] += sum_classes f_class(dd) * vec_k[dd ^ x_class].  The
-// table is staged chunk by chunk; wave w takes classes w, w + kNW, ... of a
-// chunk, and the gather of its next class is issued before the current
+// Register blocking.  A lane of a tile kernel holds R amplitudes
+// d_r = d0 + 64 r (r < R, d0 with bits 6.. of r zero), so the sign of a string
+// at d_r is (-1)^popcount(d0 & z) times (-1)^popcount(r & u) with u the
+// string's register bits (z_6, z_7).  Strings are summed once at d0 into one
+// bucket per u, and f_r = sum_u (-1)^popcount(r & u) G_u is a Walsh-Hadamard
+// transform of the buckets: one signed term per string for all R amplitudes.
+//
+// Bucket i of R: value u and the range [k0, k1) of sub-buckets it spans
+// (sub-bucket key = 4 z_6 + 2 z_7 + z_8).
+template <int R>
+__device__ __forceinline__ void bucket(int i, int &u, int &k0, int &k1) {
+    if (R == 1) { u = 0; k0 = 0; k1 = 8; }
+    else if (R == 2) { u = i; k0 = 4 * i; k1 = 4 * i + 4; }
+    else { const int b6 = i >> 1, b7 = i & 1; u = b6 | (b7 << 1); k0 = 2 * i; k1 = 2 * i + 2; }
+}
+
+// In-place transform G_u -> f_r = sum_u (-1)^popcount(r & u) G_u.
+template <int R>
+__device__ __forceinline__ void wht(double *g) {
+#pragma unroll
+    for (int h = 1; h < R; h <<= 1)
+#pragma unroll
+        for (int i = 0; i < R; i += 2 * h)
+#pragma unroll
+            for (int j = i; j < i + h; ++j) {
+                const double a = g[j], b = g[j + h];
+                g[j] = a + b;
+                g[j + h] = a - b;
+            }
+}
+
+// Class (or operator) c of the staged chunk: f_r for the lane's R amplitudes.
+template <int R>
+__device__ __forceinline__ void class_coeffs(const Stage &S, int c, int sb, uint32_t d0, double *f) {
+    const int s0 = uni(S.cls[c].s0) - sb, s1 = uni(S.cls[c].s1) - sb;
+    if (R == 1) {
+        f[0] = lds_string_sum(S.terms, s0, s1, d0);
+        return;
+    }
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = (uint32_t)uni((int)S.sub[c].w[i]);
+    double g[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        int u, k0, k1;
+        bucket<R>(i, u, k0, k1);
+        const int a = (int)((w[k0 >> 1] >> (16 * (k0 & 1))) & 0xffffu);
+        const int e = k1 >= 8 ? s1 - s0 : (int)((w[k1 >> 1] >> (16 * (k1 & 1))) & 0xffffu);
+        g[u] = lds_string_sum(S.terms, s0 + a, s0 + e, d0);
+    }
+    wht<R>(g);
+#pragma unroll
+    for (int r = 0; r < R; ++r) f[r] = g[r];
+}
+
+// Index of the partner of amplitude r (d0 + 64 r) under X mask x, or of a
+// harmless in-range element when that amplitude lies beyond the state.
+__device__ __forceinline__ uint32_t partner(uint32_t d0, int r, uint32_t x, uint32_t dim) {
+    const uint32_t d = d0 | ((uint32_t)r << 6);
+    return d < dim ? d ^ x : x;
+}
+
+// Apply the X-mask classes of H to NV vectors at the lane's R amplitudes:
+// acc[(k R + r) 2 + {0,1}] += sum_classes f_class(d_r) vec_k[d_r ^ x_class].
+// The table is staged chunk by chunk; wave w takes classes w, w + kNW, ... of
+// a chunk, and the gathers of its next class are issued before the current
 // class's strings are summed.
-template <typename T, int NV>
-__device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32_t dd,
+template <typename T, int NV, int R>
+__device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32_t d0, uint32_t dim,
                                               const void *v0, const void *v1, double *acc) {
     const int wv = wave_id();
     const GOCP_AS4 int32_t *hch = cptr(I.hchunk);
@@ -259,34 +324,45 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
         const int sb = hcls[cb].s0, se = hcls[ce - 1].s1;
         __syncthreads();
         stage_copy(S.cls, I.hcls + cb, ce - cb);
+        stage_copy(S.sub, I.hsub + cb, ce - cb);
         stage_copy(S.terms, I.hterm + sb, se - sb);
         __syncthreads();
         const int nc = ce - cb;
         int c = wv;
-        typename Amp<T>::Raw rn0 = {}, rn1 = {};
+        typename Amp<T>::Raw rn[NV][R];
         if (c < nc) {
             const uint32_t xn = (uint32_t)uni((int)S.cls[c].x);
-            rn0 = Amp<T>::raw(v0, dd ^ xn);
-            if (NV == 2) rn1 = Amp<T>::raw(v1, dd ^ xn);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                rn[0][r] = Amp<T>::raw(v0, partner(d0, r, xn, dim));
+                if (NV == 2) rn[NV - 1][r] = Amp<T>::raw(v1, partner(d0, r, xn, dim));
+            }
         }
         for (; c < nc; c += kNW) {
-            const int s0 = uni(S.cls[c].s0) - sb, s1 = uni(S.cls[c].s1) - sb;
-            const typename Amp<T>::Raw r0 = rn0, r1 = rn1;
+            typename Amp<T>::Raw rc[NV][R];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int r = 0; r < R; ++r) rc[v][r] = rn[v][r];
             const int cn = c + kNW;
             if (cn < nc) {
                 const uint32_t xn = (uint32_t)uni((int)S.cls[cn].x);
-                rn0 = Amp<T>::raw(v0, dd ^ xn);
-                if (NV == 2) rn1 = Amp<T>::raw(v1, dd ^ xn);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    rn[0][r] = Amp<T>::raw(v0, partner(d0, r, xn, dim));
+                    if (NV == 2) rn[NV - 1][r] = Amp<T>::raw(v1, partner(d0, r, xn, dim));
+                }
             }
-            const double f = lds_string_sum(S.terms, s0, s1, dd);
-            const double2 p0 = Amp<T>::cvt(r0);
-            acc[0] = fma(f, p0.x, acc[0]);
-            acc[1] = fma(f, p0.y, acc[1]);
-            if (NV == 2) {
-                const double2 p1 = Amp<T>::cvt(r1);
-                acc[2] = fma(f, p1.x, acc[2]);
-                acc[3] = fma(f, p1.y, acc[3]);
-            }
+            double f[R];
+            class_coeffs<R>(S, c, sb, d0, f);
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double2 p = Amp<T>::cvt(rc[v][r]);
+                    acc[2 * (v * R + r)] = fma(f[r], p.x, acc[2 * (v * R + r)]);
+                    acc[2 * (v * R + r) + 1] = fma(f[r], p.y, acc[2 * (v * R + r) + 1]);
+                }
         }
     }
     __syncthreads();          // the stage may be reused by the caller
@@ -299,20 +375,21 @@ __device__ __forceinline__ uint32_t insert_zero_bit(uint32_t p, int hb) {
 
 // ------------------------------------------------------------------ energy + gradient screen
 
-// One launch per state, per 64-amplitude tile:
+// One launch per state, per tile of 64 R amplitudes (R per lane):
 //   1. sigma = H psi on the tile (FP64), and the tile's <psi|sigma>, <psi|psi>;
 //   2. when a screen is due, the tile's share of
 //      g_j = 2 Re <sigma | A_j psi> / <psi|psi> for every pool operator, with
 //      the tile's own sigma values taken from LDS.  Operators are visited in
 //      GOCP family order (the family-ordered table is staged in LDS; wave w
 //      takes operators w, w + kNW, ... of each stage);
-//   3. the last workgroup to finish forms the energy, the norm, the
+//   3. the last workgroup of each group of kGroup tiles sums the group's
+//      screen partials, and the last group forms the energy, the norm, the
 //      gradients, |g|max, ||g||_2 and the selected operator.
 // mode 0: one-shot (energy; gradients when the instance has a pool);
 // mode 1: starting state of an ADAPT run (E_0 and the first screen);
 // mode 2: state after an update: iteration counter + 1, its energy, and the
 //         next screen unless the iteration budget is spent.
-template <typename T>
+template <typename T, int R>
 __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__restrict__ insts,
                                                              const int2 *__restrict__ blk, int mode) {
     const int2 b = blk[blockIdx.x];
@@ -325,33 +402,44 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = wave_id();
     const uint32_t dim = 1u << I.n_qubits;
-    const uint32_t d = (uint32_t)b.y * kTile + lane;
-    const bool valid = d < dim;
-    const uint32_t dd = valid ? d : 0u;
+    const uint32_t d0 = (uint32_t)b.y * (kTile * R) + lane;
 
     __shared__ Stage S;
-    __shared__ double2 s_sig[kWave];
+    __shared__ double2 s_sig[R][kWave];
     __shared__ double gpart[kStageCls];
     __shared__ double lds[kNW * kWave];
 
     // 1. sigma on the tile
-    double acc[2] = {0.0, 0.0};
-    apply_classes<T, 1>(I, S, dd, I.psi, nullptr, acc);
-    double2 (*red)[kWave] = reinterpret_cast<double2 (*)[kWave]>(&S);
-    red[wv][lane] = make_double2(acc[0], acc[1]);
-    __syncthreads();
-    if (wv == 0) {
-        double ar = 0.0, ai = 0.0;
+    double acc[2 * R];
 #pragma unroll
-        for (int k = 0; k < kNW; ++k) {
-            ar += red[k][lane].x;
-            ai += red[k][lane].y;
+    for (int i = 0; i < 2 * R; ++i) acc[i] = 0.0;
+    apply_classes<T, 1, R>(I, S, d0, dim, I.psi, nullptr, acc);
+    double2 (*red)[kWave] = reinterpret_cast<double2 (*)[kWave]>(&S);
+    double pe = 0.0, pn = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        red[wv][lane] = make_double2(acc[2 * r], acc[2 * r + 1]);
+        __syncthreads();
+        if (wv == 0) {
+            double ar = 0.0, ai = 0.0;
+#pragma unroll
+            for (int k = 0; k < kNW; ++k) {
+                ar += red[k][lane].x;
+                ai += red[k][lane].y;
+            }
+            const uint32_t d = d0 | ((uint32_t)r << 6);
+            const bool valid = d < dim;
+            const double2 own = valid ? Amp<T>::load(I.psi, d) : make_double2(0.0, 0.0);
+            if (valid) {
+                pe += own.x * ar + own.y * ai;
+                pn += own.x * own.x + own.y * own.y;
+                I.sigma[d] = make_double2(ar, ai);
+            }
+            s_sig[r][lane] = valid ? make_double2(ar, ai) : make_double2(0.0, 0.0);
         }
-        const double2 own = Amp<T>::load(I.psi, dd);
-        double pe = valid ? own.x * ar + own.y * ai : 0.0;
-        double pn = valid ? own.x * own.x + own.y * own.y : 0.0;
-        if (valid) I.sigma[d] = make_double2(ar, ai);
-        s_sig[lane] = valid ? make_double2(ar, ai) : make_double2(0.0, 0.0);
+        __syncthreads();
+    }
+    if (wv == 0) {
         pe = wave_sum(pe);
         pn = wave_sum(pn);
         if (lane == 0) {
@@ -359,11 +447,12 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
             st_coh(&I.part_n[b.y], pn);
         }
     }
-    __syncthreads();
 
     // 2. gradient screen on the tile
     if (screen) {
-        const double2 sg = s_sig[lane];
+        double2 sg[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) sg[r] = s_sig[r][lane];
         const GOCP_AS4 int32_t *pch = cptr(I.pchunk);
         const GOCP_AS4 HClass *sop = cptr(I.sop);
         for (int k = 0; k < I.n_pchunks; ++k) {
@@ -371,20 +460,35 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
             const int sb = sop[ob].s0, se = sop[oe - 1].s1;
             __syncthreads();
             stage_copy(S.cls, I.sop + ob, oe - ob);
+            stage_copy(S.sub, I.psub + ob, oe - ob);
             stage_copy(S.terms, I.sterm + sb, se - sb);
             __syncthreads();
             const int no = oe - ob;
             int o = wv;
-            typename Amp<T>::Raw rn = {};
-            if (o < no) rn = Amp<T>::raw(I.psi, dd ^ (uint32_t)uni((int)S.cls[o].x));
+            typename Amp<T>::Raw rn[R];
+            if (o < no) {
+                const uint32_t xn = (uint32_t)uni((int)S.cls[o].x);
+#pragma unroll
+                for (int r = 0; r < R; ++r) rn[r] = Amp<T>::raw(I.psi, partner(d0, r, xn, dim));
+            }
             for (; o < no; o += kNW) {
-                const int s0 = uni(S.cls[o].s0) - sb, s1 = uni(S.cls[o].s1) - sb;
-                const typename Amp<T>::Raw r = rn;
+                typename Amp<T>::Raw rc[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) rc[r] = rn[r];
                 const int on = o + kNW;
-                if (on < no) rn = Amp<T>::raw(I.psi, dd ^ (uint32_t)uni((int)S.cls[on].x));
-                const double h = lds_string_sum(S.terms, s0, s1, dd);
-                const double2 p = Amp<T>::cvt(r);
-                double val = h * (sg.x * p.x + sg.y * p.y);
+                if (on < no) {
+                    const uint32_t xn = (uint32_t)uni((int)S.cls[on].x);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) rn[r] = Amp<T>::raw(I.psi, partner(d0, r, xn, dim));
+                }
+                double h[R];
+                class_coeffs<R>(S, o, sb, d0, h);
+                double val = 0.0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double2 p = Amp<T>::cvt(rc[r]);
+                    val += h[r] * (sg[r].x * p.x + sg[r].y * p.y);
+                }
                 val = wave_sum(val);
                 if (lane == 0) gpart[o] = val;
             }
@@ -394,6 +498,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                 for (int i = lane; i < no; i += kWave) st_coh(&I.part_g[(size_t)b.y * M + S.cls[i].pad], gpart[i]);
         }
     }
+
     // 3a. the last workgroup of each group of kGroup tiles sums the group's
     //     screen partials (fixed tile order) into part_g2
     const int grp = b.y / kGroup;
@@ -634,7 +739,7 @@ __device__ double line_search_wave(const Landscape &L, double g) {
 // H v, H w with shared class coefficients; partial Re<v|Hv>, Re<w|Hw>,
 // Re<v|Hw>; the last workgroup forms the landscape and picks the angle.
 // mode 1: ADAPT iteration; mode 0: the products and dots only (no angle).
-template <typename T>
+template <typename T, int R>
 __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restrict__ insts,
                                                         const int2 *__restrict__ blk, int mode) {
     const int2 b = blk[blockIdx.x];
@@ -644,31 +749,40 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = wave_id();
     const uint32_t dim = 1u << I.n_qubits;
-    const uint32_t d = (uint32_t)b.y * kTile + lane;
-    const bool valid = d < dim;
-    const uint32_t dd = valid ? d : 0u;
+    const uint32_t d0 = (uint32_t)b.y * (kTile * R) + lane;
 
     __shared__ Stage S;
-    __shared__ double lds[kNW * kWave];
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    apply_classes<T, 2>(I, S, dd, I.v, I.w, acc);
-    double4 (*red)[kWave] = reinterpret_cast<double4 (*)[kWave]>(&S);
-    red[wv][lane] = make_double4(acc[0], acc[1], acc[2], acc[3]);
-    __syncthreads();
-    if (wv == 0) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double acc[4 * R];
 #pragma unroll
-        for (int k = 0; k < kNW; ++k) {
-            const double4 r = red[k][lane];
-            a0 += r.x;
-            a1 += r.y;
-            a2 += r.z;
-            a3 += r.w;
+    for (int i = 0; i < 4 * R; ++i) acc[i] = 0.0;
+    apply_classes<T, 2, R>(I, S, d0, dim, I.v, I.w, acc);
+    double4 (*red)[kWave] = reinterpret_cast<double4 (*)[kWave]>(&S);
+    double p3 = 0.0, p5 = 0.0, p6 = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        red[wv][lane] = make_double4(acc[2 * r], acc[2 * r + 1], acc[2 * (R + r)], acc[2 * (R + r) + 1]);
+        __syncthreads();
+        if (wv == 0) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+            for (int k = 0; k < kNW; ++k) {
+                const double4 q = red[k][lane];
+                a0 += q.x;
+                a1 += q.y;
+                a2 += q.z;
+                a3 += q.w;
+            }
+            const uint32_t d = d0 | ((uint32_t)r << 6);
+            if (d < dim) {
+                const double2 ov = Amp<T>::load(I.v, d), ow = Amp<T>::load(I.w, d);
+                p3 += ov.x * a0 + ov.y * a1;
+                p5 += ow.x * a2 + ow.y * a3;
+                p6 += ov.x * a2 + ov.y * a3;
+            }
         }
-        const double2 ov = Amp<T>::load(I.v, dd), ow = Amp<T>::load(I.w, dd);
-        double p3 = valid ? ov.x * a0 + ov.y * a1 : 0.0;
-        double p5 = valid ? ow.x * a2 + ow.y * a3 : 0.0;
-        double p6 = valid ? ov.x * a2 + ov.y * a3 : 0.0;
+        __syncthreads();
+    }
+    if (wv == 0) {
         p3 = wave_sum(p3);
         p5 = wave_sum(p5);
         p6 = wave_sum(p6);
@@ -846,13 +960,27 @@ __global__ void k_basis(void *psi, uint32_t dim, uint32_t index) {
 
 // ------------------------------------------------------------------ launchers
 
+template <typename T, int R>
+static void launch_tile(int which, const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s) {
+    if (which == 0)
+        hipLaunchKernelGGL((k_energy_screen<T, R>), dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode);
+    else
+        hipLaunchKernelGGL((k_line_hvw<T, R>), dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode);
+}
+
 template <typename T>
-static void launch_all(int which, const InstDev *insts, const int2 *blk, int nblk, int mode,
-                       hipStream_t s, int j = 0, double th = 0.0, int ns = 0) {
+static void launch_all(int which, int R, const InstDev *insts, const int2 *blk, int nblk, int mode,
+                       hipStream_t s, int j, double th, int ns) {
     switch (which) {
-    case 0: hipLaunchKernelGGL(k_energy_screen<T>, dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode); break;
+    case 0:
+    case 3: {
+        const int w = which == 0 ? 0 : 1;
+        if (R == 4) launch_tile<T, 4>(w, insts, blk, nblk, mode, s);
+        else if (R == 2) launch_tile<T, 2>(w, insts, blk, nblk, mode, s);
+        else launch_tile<T, 1>(w, insts, blk, nblk, mode, s);
+        break;
+    }
     case 2: hipLaunchKernelGGL(k_line_vw<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk); break;
-    case 3: hipLaunchKernelGGL(k_line_hvw<T>, dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode); break;
     case 4: hipLaunchKernelGGL(k_taylor5<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode, j, th, ns); break;
     case 5: hipLaunchKernelGGL(k_normalize<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode); break;
     case 6: hipLaunchKernelGGL(k_state_unit_norm, dim3(nblk), dim3(64), 0, s, insts, blk); break;
@@ -860,13 +988,13 @@ static void launch_all(int which, const InstDev *insts, const int2 *blk, int nbl
     }
 }
 
-void launch_kernel(int which, int dtype, const InstDev *insts, const int2 *blk, int nblk, int mode,
+void launch_kernel(int which, int dtype, int R, const InstDev *insts, const int2 *blk, int nblk, int mode,
                    hipStream_t s, int j, double th, int ns) {
     if (nblk <= 0) return;
     if (dtype == GOCP_C64)
-        launch_all<float2>(which, insts, blk, nblk, mode, s, j, th, ns);
+        launch_all<float2>(which, R, insts, blk, nblk, mode, s, j, th, ns);
     else
-        launch_all<double2>(which, insts, blk, nblk, mode, s, j, th, ns);
+        launch_all<double2>(which, R, insts, blk, nblk, mode, s, j, th, ns);
     hip_check(hipGetLastError(), "kernel launch");
 }
 

@@ -33,6 +33,28 @@ T *dev_upload(const std::vector<T> &v) {
 
 HTerm make_term(double c, uint32_t z) { return HTerm{std::fabs(c), z, std::signbit(c) ? 1u : 0u}; }
 
+uint32_t sub_key(uint32_t z) { return ((z >> 6) & 1u) << 2 | ((z >> 7) & 1u) << 1 | ((z >> 8) & 1u); }
+
+// Append the strings [a, b) of (c, z) in sub-bucket order to `out` and return
+// the sub-bucket record of the group.
+HSub bucket_strings(const std::vector<double> &c, const std::vector<uint32_t> &z, int a, int b,
+                    std::vector<HTerm> &out) {
+    std::vector<int> idx;
+    for (int s = a; s < b; ++s) idx.push_back(s);
+    std::stable_sort(idx.begin(), idx.end(), [&](int p, int q) { return sub_key(z[p]) < sub_key(z[q]); });
+    if (b - a > 65535) throw Error(GOCP_ENOTSUP, "a class has more than 65535 strings");
+    uint16_t off[8];
+    int k = 0;
+    for (int key = 0; key < 8; ++key) {
+        off[key] = (uint16_t)k;
+        while (k < (int)idx.size() && (int)sub_key(z[idx[k]]) == key) ++k;
+    }
+    for (int s : idx) out.push_back(make_term(c[s], z[s]));
+    HSub r;
+    for (int i = 0; i < 4; ++i) r.w[i] = (uint32_t)off[2 * i] | ((uint32_t)off[2 * i + 1] << 16);
+    return r;
+}
+
 // Boundaries of consecutive record groups (classes or operators) such that
 // each group has at most kStageCls records and kStageTerms strings.
 std::vector<int32_t> stage_chunks(const std::vector<int32_t> &off) {
@@ -57,6 +79,7 @@ void release_device_ham(DeviceHam *d) {
     if (!d) return;
     (void)hipFree(d->hcls);
     (void)hipFree(d->hterm);
+    (void)hipFree(d->hsub);
     (void)hipFree(d->hchunk);
     delete d;
 }
@@ -68,6 +91,7 @@ void release_device_pool(DevicePool *d) {
     (void)hipFree(d->op_norm1);
     (void)hipFree(d->sop);
     (void)hipFree(d->sterm);
+    (void)hipFree(d->psub);
     (void)hipFree(d->pchunk);
     delete d;
 }
@@ -79,11 +103,15 @@ const DeviceHam *device_ham(const Ham &h, int dev) {
     std::unique_ptr<DeviceHam> d(new DeviceHam());
     d->device = dev;
     std::vector<HClass> cls(h.n_classes());
-    for (int c = 0; c < h.n_classes(); ++c) cls[c] = HClass{h.cls_x[c], h.cls_off[c], h.cls_off[c + 1], 0};
-    std::vector<HTerm> terms(h.str_z.size());
-    for (size_t s = 0; s < terms.size(); ++s) terms[s] = make_term(h.str_c[s], h.str_z[s]);
+    std::vector<HSub> sub(h.n_classes());
+    std::vector<HTerm> terms;
+    for (int c = 0; c < h.n_classes(); ++c) {
+        cls[c] = HClass{h.cls_x[c], h.cls_off[c], h.cls_off[c + 1], 0};
+        sub[c] = bucket_strings(h.str_c, h.str_z, h.cls_off[c], h.cls_off[c + 1], terms);
+    }
     d->hcls = dev_upload(cls);
     d->hterm = dev_upload(terms);
+    d->hsub = dev_upload(sub);
     const std::vector<int32_t> ch = stage_chunks(h.cls_off);
     d->hchunk = dev_upload(ch);
     d->n_chunks = (int)ch.size() - 1;
@@ -108,11 +136,12 @@ const DevicePool *device_pool(const Pool &p, int dev) {
     // GOCP family order (families in creation order, members in assignment
     // order); each record keeps its pool index
     std::vector<HClass> sop;
+    std::vector<HSub> psub;
     std::vector<HTerm> sterm;
     std::vector<int32_t> soff{0};
     for (int32_t j : p.fam_members) {
         HClass r{p.op_x[j], (int32_t)sterm.size(), 0, j};
-        for (int s = p.op_off[j]; s < p.op_off[j + 1]; ++s) sterm.push_back(make_term(p.str_c[s], p.str_z[s]));
+        psub.push_back(bucket_strings(p.str_c, p.str_z, p.op_off[j], p.op_off[j + 1], sterm));
         r.s1 = (int32_t)sterm.size();
         sop.push_back(r);
         soff.push_back(r.s1);
@@ -120,6 +149,7 @@ const DevicePool *device_pool(const Pool &p, int dev) {
     const std::vector<int32_t> pch = stage_chunks(soff);
     d->sop = dev_upload(sop);
     d->sterm = dev_upload(sterm);
+    d->psub = dev_upload(psub);
     d->pchunk = dev_upload(pch);
     d->n_chunks = (int)pch.size() - 1;
     p.dev[dev] = d.release();
@@ -185,6 +215,7 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
         const DeviceHam *dh = device_ham(*h, device);
         I.hcls = dh->hcls;
         I.hterm = dh->hterm;
+        I.hsub = dh->hsub;
         I.hchunk = dh->hchunk;
         I.n_hchunks = dh->n_chunks;
     }
@@ -195,6 +226,7 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
         I.op_norm1 = dp->op_norm1;
         I.sop = dp->sop;
         I.sterm = dp->sterm;
+        I.psub = dp->psub;
         I.pchunk = dp->pchunk;
         I.n_pchunks = dp->n_chunks;
     }
@@ -396,7 +428,7 @@ int energy(gocp_ctx *ctx, const gocp_ham *hh, const void *psi_dev, int dtype, do
     check_ctx(ctx);
     if (!e_out) throw Error(GOCP_EINVAL, "null output");
     OneShot o = one_shot(ctx, as_ham(hh), nullptr, psi_dev, dtype);
-    launch_kernel(K_ENERGY_SCREEN, dtype, o.desc, o.btile, o.nt, 0, ctx->user_stream);
+    launch_kernel(K_ENERGY_SCREEN, dtype, 1, o.desc, o.btile, o.nt, 0, ctx->user_stream);
     const AdaptState st = read_state(ctx, o);
     if (st.status) throw Error(st.status, "non-finite energy or zero norm");
     *e_out = st.energy;
@@ -410,7 +442,7 @@ int gocp_apply_hamiltonian(gocp_ctx *ctx, const gocp_ham *hh, const void *psi_de
     check_ctx(ctx);
     if (!sigma_dev) throw Error(GOCP_EINVAL, "null sigma pointer");
     OneShot o = one_shot(ctx, as_ham(hh), nullptr, psi_dev, dtype, static_cast<double2 *>(sigma_dev));
-    launch_kernel(K_ENERGY_SCREEN, dtype, o.desc, o.btile, o.nt, 0, ctx->user_stream);
+    launch_kernel(K_ENERGY_SCREEN, dtype, 1, o.desc, o.btile, o.nt, 0, ctx->user_stream);
     if (e_out) {
         const AdaptState st = read_state(ctx, o);
         if (st.status) throw Error(st.status, "non-finite energy or zero norm");
@@ -428,7 +460,7 @@ int pool_gradients(gocp_ctx *ctx, const gocp_ham *hh, const gocp_pool *pp, const
     const Ham *h = as_ham(hh);
     const Pool *p = as_pool(pp);
     OneShot o = one_shot(ctx, h, p, psi_dev, dtype);
-    launch_kernel(K_ENERGY_SCREEN, dtype, o.desc, o.btile, o.nt, 0, ctx->user_stream);
+    launch_kernel(K_ENERGY_SCREEN, dtype, 1, o.desc, o.btile, o.nt, 0, ctx->user_stream);
     const size_t gbytes = (size_t)p->n_ops() * sizeof(double);
     if (g_on_device) {
         hip_check(hipMemcpyAsync(g_out, o.base + o.ip.o_g, gbytes, hipMemcpyDeviceToDevice,
@@ -457,8 +489,8 @@ int taylor5_apply(gocp_ctx *ctx, const gocp_pool *pp, int32_t k, double theta, v
     }
     const int ns = std::max(1, (int)std::ceil(std::fabs(theta) * p->op_norm1[k] / 0.5));
     OneShot o = one_shot(ctx, nullptr, p, psi_dev, dtype);
-    launch_kernel(K_TAYLOR, dtype, o.desc, o.bpair, o.np, 0, ctx->user_stream, k, theta, ns);
-    launch_kernel(K_NORMALIZE, dtype, o.desc, o.bpair, o.np, 0, ctx->user_stream);
+    launch_kernel(K_TAYLOR, dtype, 1, o.desc, o.bpair, o.np, 0, ctx->user_stream, k, theta, ns);
+    launch_kernel(K_NORMALIZE, dtype, 1, o.desc, o.bpair, o.np, 0, ctx->user_stream);
     if (n_substeps_out) *n_substeps_out = ns;
     return GOCP_OK;
     GOCP_GUARD_END

@@ -231,12 +231,14 @@ int gocp_request_footprint(int n_qubits, int n_ops, int n_strings, int64_t n_ter
 }
 
 int gocp_server_create(gocp_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_slots, int dtype,
-                       int32_t iters_per_step, gocp_server **out) {
+                       int32_t iters_per_step, int32_t amps_per_lane, gocp_server **out) {
     GOCP_GUARD_BEGIN
     check_ctx(ctx);
     check_dtype(dtype);
     if (!out || hbm_budget_bytes <= 0 || max_slots <= 0 || iters_per_step <= 0)
         throw Error(GOCP_EINVAL, "invalid server parameters");
+    if (amps_per_lane != 1 && amps_per_lane != 2 && amps_per_lane != 4)
+        throw Error(GOCP_EINVAL, "amps_per_lane must be 1, 2 or 4");
     std::unique_ptr<gocp_server> s(new gocp_server());
     s->ctx = ctx;
     s->dtype = dtype;
@@ -246,6 +248,7 @@ int gocp_server_create(gocp_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_slot
     hip_check(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate");
     s->group.ctx = ctx;
     s->group.dtype = dtype;
+    s->group.R = amps_per_lane;
     gocp_server *raw = s.get();
     s->worker = std::thread([raw] { raw->run(); });
     *out = s.release();

@@ -43,21 +43,24 @@ def _psi(nq, hf, dtype):
     return t
 
 
+@pytest.mark.parametrize("schedule", [1, 2, 4])
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
-def test_batched_equals_solo(g, ctx, dtype):
-    _say(f"[batch] mixed sizes {dtype}")
-    specs = [(4, "jw", 1), (8, "bk", 2), (12, "jw", 3), (10, "bk", 4), (14, "jw", 5), (8, "jw", 6)]
+def test_batched_equals_solo(g, ctx, dtype, schedule):
+    _say(f"[batch] mixed sizes {dtype} schedule={schedule}")
+    specs = [(4, "jw", 1), (8, "bk", 2), (12, "jw", 3), (10, "bk", 4), (14, "jw", 5), (6, "jw", 6)]
     insts = [_inst(g, *s) for s in specs]
     iters = 12
     psis = [_psi(nq, hf, dtype) for (_, _, hf, nq) in insts]
-    b = g.Batch(ctx, [i[0] for i in insts], [i[1] for i in insts], psis, max_iter=iters)
+    b = g.Batch(ctx, [i[0] for i in insts], [i[1] for i in insts], psis, max_iter=iters,
+                schedule=schedule)
+    assert b.schedule == schedule
     b.step(5)
     b.step(iters - 5)
     assert b.poll() == 0
     for k, (H, P, hf, nq) in enumerate(insts):
         rb = b.result(k)
         solo = _psi(nq, hf, dtype)
-        rs = g.adapt_solve(ctx, H, P, solo, iters)
+        rs = g.adapt_solve(ctx, H, P, solo, iters, schedule=schedule)
         assert rb["ops"] == rs["ops"]
         assert np.array_equal(rb["energies"], rs["energies"])
         assert np.array_equal(rb["thetas"], rs["thetas"])
@@ -66,11 +69,33 @@ def test_batched_equals_solo(g, ctx, dtype):
     b.close()
 
 
+def test_autotuned_schedule_is_kept_and_matches_solo(g, ctx):
+    _say("[batch] autotune")
+    insts = [_inst(g, 12, "jw", 41 + k) for k in range(8)]
+    psis = [_psi(12, hf, torch.complex64) for (_, _, hf, _) in insts]
+    b = g.Batch(ctx, [i[0] for i in insts], [i[1] for i in insts], psis, max_iter=8, schedule=0)
+    R = b.schedule
+    assert R in (1, 2, 4)
+    b.run()
+    # the same composition reuses the remembered choice
+    psis2 = [_psi(12, hf, torch.complex64) for (_, _, hf, _) in insts]
+    b2 = g.Batch(ctx, [i[0] for i in insts], [i[1] for i in insts], psis2, max_iter=8, schedule=0)
+    assert b2.schedule == R
+    b2.close()
+    for k in (0, 5):
+        H, P, hf, nq = insts[k]
+        solo = _psi(nq, hf, torch.complex64)
+        rs = g.adapt_solve(ctx, H, P, solo, 8, schedule=R)
+        assert np.array_equal(b.result(k)["energies"], rs["energies"])
+        assert torch.equal(psis[k], solo)
+    b.close()
+
+
 def test_batch_run_stops_when_all_converged(g, ctx):
     insts = [_inst(g, 4, "jw", 11), _inst(g, 4, "bk", 12), _inst(g, 8, "jw", 13)]
     psis = [_psi(nq, hf, torch.complex128) for (_, _, hf, nq) in insts]
     b = g.Batch(ctx, [i[0] for i in insts], [i[1] for i in insts], psis, max_iter=400,
-                grad_tol=1e-3)
+                grad_tol=1e-3, schedule=1)
     b.run()
     assert b.poll() == 0
     for k in range(3):
@@ -93,13 +118,13 @@ def test_batch_graph_and_direct_launch_agree(g, ctx):
 def test_kernel_timing_hook_leaves_record_unchanged(g, ctx):
     H, P, hf, nq = _inst(g, 12, "bk", 31)
     psi = _psi(nq, hf, torch.complex128)
-    b = g.Batch(ctx, [H], [P], [psi], max_iter=10)
+    b = g.Batch(ctx, [H], [P], [psi], max_iter=10, schedule=2)
     b.step(4)
     for which in (0, 1):
         assert b.time_kernel(which, 3) > 0.0
     b.step(6)
     r = b.result(0)
     solo = _psi(nq, hf, torch.complex128)
-    rs = g.adapt_solve(ctx, H, P, solo, 10)
+    rs = g.adapt_solve(ctx, H, P, solo, 10, schedule=2)
     assert np.array_equal(r["energies"], rs["energies"]) and r["ops"] == rs["ops"]
     b.close()

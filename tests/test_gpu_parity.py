@@ -160,11 +160,12 @@ def test_shape_errors(g, ctx):
         g.taylor5_apply(ctx, s12["gP"], s12["gP"].n_ops, 0.1, d)
 
 
-def _adapt_gpu(g, ctx, s, nq, iters, dtype="c128", tol=0.0, use_graph=True):
+def _adapt_gpu(g, ctx, s, nq, iters, dtype="c128", tol=0.0, use_graph=True, schedule=1):
     psi = np.zeros(1 << nq, dtype=np.complex128)
     psi[s["hf"]] = 1.0
     d = to_dev(psi, dtype)
-    r = g.adapt_solve(ctx, s["gH"], s["gP"], d, iters, grad_tol=tol, use_graph=use_graph)
+    r = g.adapt_solve(ctx, s["gH"], s["gP"], d, iters, grad_tol=tol, use_graph=use_graph,
+                      schedule=schedule)
     return r, d.cpu().numpy().astype(np.complex128)
 
 
@@ -203,6 +204,25 @@ def test_adapt_12q_30_iterations(g, ctx, mapping):
     r, psi = _adapt_gpu(g, ctx, s, 12, 30)
     assert r["n_iter"] == 30
     _check_against_oracle(s, r, psi, 30)
+
+
+@pytest.mark.parametrize("schedule", [2, 4])
+@pytest.mark.parametrize("nq,mapping", [(12, "bk"), (6, "jw"), (4, "jw")])
+def test_adapt_register_blocked_schedules(g, ctx, schedule, nq, mapping):
+    """2 or 4 amplitudes per lane (tiles of 128 or 256, ragged when the state
+    is smaller than a tile) must follow the oracle like the 1-per-lane path."""
+    _say(f"[adapt] {nq}q {mapping} schedule={schedule}")
+    s = system(g, nq, mapping)
+    iters = 12 if nq >= 6 else 6
+    r, psi = _adapt_gpu(g, ctx, s, nq, iters, schedule=schedule)
+    _check_against_oracle(s, r, psi, iters)
+
+
+def test_adapt_bad_schedule_rejected(g, ctx):
+    s = system(g, 4, "jw")
+    with pytest.raises(g.GocpError) as e:
+        _adapt_gpu(g, ctx, s, 4, 2, schedule=3)
+    assert e.value.code == -1
 
 
 def test_adapt_12q_jw_equals_bk(g, ctx):

@@ -39,10 +39,10 @@ def _req(g, nq, mapping, seed):
                 hf=g.hf_index(nq, ne, mapping), nq=nq)
 
 
-def _solo(g, ctx, r, max_iter, tol, dtype):
+def _solo(g, ctx, r, max_iter, tol, dtype, schedule=1):
     psi = torch.zeros(1 << r["nq"], dtype=dtype, device="cuda")
     psi[r["hf"]] = 1.0
-    return g.adapt_solve(ctx, r["H"], r["P"], psi, max_iter, grad_tol=tol)
+    return g.adapt_solve(ctx, r["H"], r["P"], psi, max_iter, grad_tol=tol, schedule=schedule)
 
 
 def _drain(srv, tickets, timeout_s=60.0, watch=None):
@@ -70,12 +70,14 @@ def _same(a, b):
     assert np.array_equal(a["thetas"], b["thetas"])
 
 
-@pytest.mark.parametrize("dtype,code", [(torch.complex64, 1), (torch.complex128, 0)])
-def test_mix_equals_solo(g, ctx, dtype, code):
-    _say(f"[serve] mix {dtype}")
+@pytest.mark.parametrize("dtype,code,R", [(torch.complex64, 1, 1), (torch.complex128, 0, 1),
+                                          (torch.complex64, 1, 4)])
+def test_mix_equals_solo(g, ctx, dtype, code, R):
+    _say(f"[serve] mix {dtype} R={R}")
     reqs = [_req(g, *s) for s in [(8, "jw", 1), (10, "bk", 2), (12, "jw", 3), (8, "bk", 4),
                                   (10, "jw", 5), (12, "bk", 6)]]
-    srv = g.Server(ctx, hbm_budget_bytes=1 << 30, max_slots=16, dtype=code, iters_per_step=3)
+    srv = g.Server(ctx, hbm_budget_bytes=1 << 30, max_slots=16, dtype=code, iters_per_step=3,
+                   amps_per_lane=R)
     tickets = [srv.submit(r["H"], r["P"], 60, 1e-3) for r in reqs]
     res = _drain(srv, tickets)
     srv.close()
@@ -83,7 +85,7 @@ def test_mix_equals_solo(g, ctx, dtype, code):
         st, rec, info = res[t]
         assert st == 0 and info["status"] == 0 and info["n_qubits"] == r["nq"]
         assert info["t_submit_ns"] <= info["t_admit_ns"] <= info["t_done_ns"]
-        _same(rec, _solo(g, ctx, r, 60, 1e-3, dtype))
+        _same(rec, _solo(g, ctx, r, 60, 1e-3, dtype, schedule=R))
 
 
 def test_budget_forces_queueing_and_is_respected(g, ctx):
@@ -129,6 +131,11 @@ def test_late_arrivals_join_running_set(g, ctx):
         _same(res[t][1], _solo(g, ctx, r, 200, 1e-6, torch.complex64))
     for r, t in zip(late, t_late):
         _same(res[t][1], _solo(g, ctx, r, 200, 1e-3, torch.complex64))
+
+
+def test_bad_server_schedule_rejected(g, ctx):
+    with pytest.raises(g.GocpError):
+        g.Server(ctx, hbm_budget_bytes=1 << 30, max_slots=4, dtype=1, amps_per_lane=3)
 
 
 def test_request_larger_than_budget_is_rejected(g, ctx):
