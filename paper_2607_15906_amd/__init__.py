@@ -5,7 +5,14 @@ this package is its ctypes binding.  Importing the package loads the library
 and fails loudly if it has not been built.
 """
 
-from ._lib import load as _load, GocpError
+# torch first: libgocp then binds to the HIP runtime torch has loaded, the one
+# that owns the streams and device buffers handed to the library.
+try:
+    import torch as _torch  # noqa: F401
+except ImportError:          # host-only use (Hamiltonians, pools, partitions)
+    _torch = None
+
+from ._lib import load as _load, GocpError  # noqa: E402
 
 _load()
 

@@ -54,6 +54,8 @@ inline Instance *instance_create(gocp_ctx *ctx, const Ham *h, const Pool *p, voi
     hip_check(hipMemsetAsync(in->mem + in->ip.o_cnt, 0, in->ip.n_counters * sizeof(int32_t), s),
               "hipMemsetAsync");
     hip_check(hipMemsetAsync(in->mem + in->ip.o_v, 0, in->ip.o_pe - in->ip.o_v, s), "hipMemsetAsync");
+    if (in->ip.o_hv)
+        hip_check(hipMemsetAsync(in->mem + in->ip.o_hv, 0, in->ip.bytes - in->ip.o_hv, s), "hipMemsetAsync");
     hip_check(hipMemcpyAsync(in->mem + in->ip.o_st, &st, sizeof(st), hipMemcpyHostToDevice, s), "H2D");
     if (own) launch_basis(dtype, in->psi, 1u << h->n_qubits, (uint32_t)hf, s);
     return in.release();
@@ -196,16 +198,17 @@ struct Group {
     }
 
     // Time one energy+screen launch and one line-search launch over the
-    // whole group (mode 0: no iteration record is touched); milliseconds.
+    // whole group (dry modes: neither sigma nor the iteration record is
+    // written); milliseconds.
     double time_tile_kernels(hipStream_t s, int reps) {
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "hipEventCreate");
         hip_check(hipEventCreate(&e1), "hipEventCreate");
-        launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 0, s);
+        launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 3, s);
         launch_kernel(K_LINE_HVW, dtype, R, desc, btile, nt, 0, s);
         hip_check(hipEventRecord(e0, s), "hipEventRecord");
         for (int i = 0; i < reps; ++i) {
-            launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 0, s);
+            launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 3, s);
             launch_kernel(K_LINE_HVW, dtype, R, desc, btile, nt, 0, s);
         }
         hip_check(hipEventRecord(e1, s), "hipEventRecord");

@@ -63,6 +63,9 @@ struct AdaptState {
     double energy;         // e_num / nrm
     double gnorm, gmax;
     double pred;           // line-search landscape value at theta
+    // the update as a whole: T5(theta/s)^s = I + upd_alpha A + upd_beta A^2
+    // (A^3 = -A), applied to upd_scale * psi
+    double upd_alpha, upd_beta, upd_scale;
     // history (device arrays; may be null for one-shot calls)
     double *hist_e;        // max_iter + 1
     int32_t *hist_op;      // max_iter
@@ -95,6 +98,8 @@ struct InstDev {
     double2 *sigma;
     void *v;
     void *w;
+    double2 *hv;                // H v and H w (FP64), kept by the line search for the
+    double2 *hw;                // next sigma; null outside ADAPT runs
     double *part_e;             // n_tiles
     double *part_n;             // n_tiles
     double *part_g;             // n_tiles * M

@@ -42,6 +42,13 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // State element access: raw() loads the stored bits, cvt() widens to FP64.
+// Period (in ADAPT iterations) of the fresh H psi that resets the carried sigma:
+// the stored state is rounded to its precision at every update while the
+// carried sigma follows the unrounded update.
+template <typename T> struct Refresh;
+template <> struct Refresh<float2> { static constexpr int kPeriod = 8; };
+template <> struct Refresh<double2> { static constexpr int kPeriod = 32; };
+
 template <typename T> struct Amp;
 template <> struct Amp<double2> {
     using Raw = u32x4;
@@ -121,10 +128,33 @@ __device__ __forceinline__ void string_sum2(const GOCP_AS4 HTerm *t, int s0, int
 __device__ __forceinline__ int state_done(const AdaptState *st) { return cptr(&st->done)[0]; }
 
 // Sum over a wave with an xor butterfly: every lane ends with the same value.
+// DPP move of a double (as two 32-bit halves); lanes of rows outside ROW_MASK
+// receive 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sum over the 64 lanes of a full wave, returned to every lane: pairs and
+// quads, then halves of a row and whole rows by mirroring (every lane of a
+// row of 16 then holds the row sum), then rows 0+1 and 2+3 by broadcasting
+// lane 15 of a row into the next, and all four by broadcasting lane 31 into
+// rows 2 and 3; lane 63 ends with the total.  Register moves only, no LDS.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    v += dpp_f64<0xB1>(v);          // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);          // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);         // row_half_mirror
+    v += dpp_f64<0x140>(v);         // row_mirror
+    v += dpp_f64<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
+    return read_lane(v, kWave - 1);
 }
 
 __device__ __forceinline__ int wave_id() {
@@ -133,20 +163,25 @@ __device__ __forceinline__ int wave_id() {
 
 // Sum of `n` values at stride `stride` from `src`, in index order per thread
 // and a fixed tree over threads; the result is returned to every thread.
+// Sum of one value per thread over a block of NT threads: per-wave sums, then
+// the NT / 64 wave sums in wave order; returned to every thread.
+template <int NT>
+__device__ __forceinline__ double block_reduce(double acc, double *lds) {
+    const double w = wave_sum(acc);
+    if ((threadIdx.x & (kWave - 1)) == 0) lds[threadIdx.x >> 6] = w;
+    __syncthreads();
+    double r = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / kWave; ++k) r += lds[k];
+    __syncthreads();
+    return r;
+}
+
 template <int NT>
 __device__ double block_sum_strided(const double *src, int n, int stride, double *lds) {
     double acc = 0.0;
     for (int i = threadIdx.x; i < n; i += NT) acc += src[(size_t)i * stride];
-    lds[threadIdx.x] = acc;
-    __syncthreads();
-#pragma unroll
-    for (int h = NT / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) lds[threadIdx.x] += lds[threadIdx.x + h];
-        __syncthreads();
-    }
-    const double r = lds[0];
-    __syncthreads();
-    return r;
+    return block_reduce<NT>(acc, lds);
 }
 
 // Cross-workgroup partial results.  A workgroup's partials are written with
@@ -182,16 +217,7 @@ template <int NT>
 __device__ double block_sum_coh(const double *src, int n, int stride, double *lds) {
     double acc = 0.0;
     for (int i = threadIdx.x; i < n; i += NT) acc += ld_coh(src + (size_t)i * stride);
-    lds[threadIdx.x] = acc;
-    __syncthreads();
-#pragma unroll
-    for (int h = NT / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) lds[threadIdx.x] += lds[threadIdx.x + h];
-        __syncthreads();
-    }
-    const double r = lds[0];
-    __syncthreads();
-    return r;
+    return block_reduce<NT>(acc, lds);
 }
 
 // ------------------------------------------------------------------ LDS staging of term tables
@@ -388,17 +414,21 @@ __device__ __forceinline__ uint32_t insert_zero_bit(uint32_t p, int hb) {
 // mode 0: one-shot (energy; gradients when the instance has a pool);
 // mode 1: starting state of an ADAPT run (E_0 and the first screen);
 // mode 2: state after an update: iteration counter + 1, its energy, and the
-//         next screen unless the iteration budget is spent.
+//         next screen unless the iteration budget is spent;
+// mode 3: the work of mode 0 without writing sigma or the state record (kernel
+//         timing in the middle of a run); mode 4: likewise for the work of
+//         mode 2 when sigma is carried through the update.
 template <typename T, int R>
 __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__restrict__ insts,
                                                              const int2 *__restrict__ blk, int mode) {
     const int2 b = blk[blockIdx.x];
     const InstDev &I = insts[b.x];
     AdaptState *st = I.st;
-    if (mode != 0 && state_done(st)) return;
+    const bool oneshot = mode == 0 || mode >= 3, dry = mode >= 3;
+    if (!oneshot && state_done(st)) return;
     const int it = mode == 2 ? cptr(&st->iter)[0] + 1 : 0;
     const int M = I.M;
-    const bool screen = M > 0 && (mode == 0 || it < cptr(&st->max_iter)[0]);
+    const bool screen = M > 0 && (oneshot || it < cptr(&st->max_iter)[0]);
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = wave_id();
     const uint32_t dim = 1u << I.n_qubits;
@@ -409,33 +439,61 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
     __shared__ double gpart[kStageCls];
     __shared__ double lds[kNW * kWave];
 
-    // 1. sigma on the tile
-    double acc[2 * R];
-#pragma unroll
-    for (int i = 0; i < 2 * R; ++i) acc[i] = 0.0;
-    apply_classes<T, 1, R>(I, S, d0, dim, I.psi, nullptr, acc);
-    double2 (*red)[kWave] = reinterpret_cast<double2 (*)[kWave]>(&S);
+    // 1. sigma on the tile: H psi, or, after an update, sigma carried through
+    //    it (the update is I + al A + be A^2 on scale * psi, so
+    //    H psi' = scale (sigma + al H w - be H v) with the line search's H v,
+    //    H w).  Every Refresh<T>::kPeriod iterations H psi is applied afresh,
+    //    which bounds the drift from the rounding of the stored state.
+    const bool carry = I.hv != nullptr && (mode == 4 || (mode == 2 && (it % Refresh<T>::kPeriod) != 0));
     double pe = 0.0, pn = 0.0;
+    if (!carry) {
+        double acc[2 * R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        red[wv][lane] = make_double2(acc[2 * r], acc[2 * r + 1]);
-        __syncthreads();
+        for (int i = 0; i < 2 * R; ++i) acc[i] = 0.0;
+        apply_classes<T, 1, R>(I, S, d0, dim, I.psi, nullptr, acc);
+        double2 (*red)[kWave] = reinterpret_cast<double2 (*)[kWave]>(&S);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            red[wv][lane] = make_double2(acc[2 * r], acc[2 * r + 1]);
+            __syncthreads();
+            if (wv == 0) {
+                double ar = 0.0, ai = 0.0;
+#pragma unroll
+                for (int k = 0; k < kNW; ++k) {
+                    ar += red[k][lane].x;
+                    ai += red[k][lane].y;
+                }
+                const uint32_t d = d0 | ((uint32_t)r << 6);
+                const bool valid = d < dim;
+                const double2 own = valid ? Amp<T>::load(I.psi, d) : make_double2(0.0, 0.0);
+                if (valid) {
+                    pe += own.x * ar + own.y * ai;
+                    pn += own.x * own.x + own.y * own.y;
+                    if (!dry) I.sigma[d] = make_double2(ar, ai);
+                }
+                s_sig[r][lane] = valid ? make_double2(ar, ai) : make_double2(0.0, 0.0);
+            }
+            __syncthreads();
+        }
+    } else {
         if (wv == 0) {
-            double ar = 0.0, ai = 0.0;
+            const double al = cptr(&st->upd_alpha)[0], be = cptr(&st->upd_beta)[0];
+            const double sc = cptr(&st->upd_scale)[0];
 #pragma unroll
-            for (int k = 0; k < kNW; ++k) {
-                ar += red[k][lane].x;
-                ai += red[k][lane].y;
+            for (int r = 0; r < R; ++r) {
+                const uint32_t d = d0 | ((uint32_t)r << 6);
+                double2 sg = make_double2(0.0, 0.0);
+                if (d < dim) {
+                    const double2 s0 = I.sigma[d], hv = I.hv[d], hw = I.hw[d];
+                    sg.x = sc * (s0.x + al * hw.x - be * hv.x);
+                    sg.y = sc * (s0.y + al * hw.y - be * hv.y);
+                    const double2 own = Amp<T>::load(I.psi, d);
+                    pe += own.x * sg.x + own.y * sg.y;
+                    pn += own.x * own.x + own.y * own.y;
+                    if (!dry) I.sigma[d] = sg;
+                }
+                s_sig[r][lane] = sg;
             }
-            const uint32_t d = d0 | ((uint32_t)r << 6);
-            const bool valid = d < dim;
-            const double2 own = valid ? Amp<T>::load(I.psi, d) : make_double2(0.0, 0.0);
-            if (valid) {
-                pe += own.x * ar + own.y * ai;
-                pn += own.x * own.x + own.y * own.y;
-                I.sigma[d] = make_double2(ar, ai);
-            }
-            s_sig[r][lane] = valid ? make_double2(ar, ai) : make_double2(0.0, 0.0);
         }
         __syncthreads();
     }
@@ -542,14 +600,14 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                 double a = 0.0;
                 for (int w = 0; w < kNW; ++w) a += colsum[w * kWave + lane];
                 const double g = a * inv;
-                st->g[j] = g;
+                if (!dry) st->g[j] = g;
                 amax = fmax(amax, fabs(g));
                 sq += g * g;
             }
             __syncthreads();
         }
     }
-    if (wv != 0) return;
+    if (wv != 0 || dry) return;
     // wave 0 holds every g_j (lane l: j = l, l + 64, ...)
     double gmax = 0.0, gn = 0.0;
     int jmin = 0x7fffffff;
@@ -666,11 +724,14 @@ struct Landscape {
         sincos(th, &s, &c);
         return uu + 2.0 * uv * c + 2.0 * uw * s + vv * c * c + 2.0 * vw * s * c + ww * s * s;
     }
+    __device__ double deriv_sc(double s, double c) const {
+        return -2.0 * uv * s + 2.0 * uw * c - 2.0 * vv * s * c + 2.0 * vw * (c * c - s * s) +
+               2.0 * ww * s * c;
+    }
     __device__ double deriv(double th) const {
         double s, c;
         sincos(th, &s, &c);
-        return -2.0 * uv * s + 2.0 * uw * c - 2.0 * vv * s * c + 2.0 * vw * (c * c - s * s) +
-               2.0 * ww * s * c;
+        return deriv_sc(s, c);
     }
 };
 
@@ -716,20 +777,41 @@ __device__ double line_search_wave(const Landscape &L, double g) {
         return dir * bestk * step;
     }
     double lo = dir * (kfirst - 1) * step, hi = dir * kfirst * step;
+    // sin and cos at the sample points from those at the bracket's lower end:
+    // the offsets are at most one degree, where the series below are exact to
+    // rounding (next terms below 1e-20 relative); the new lower end is always
+    // one of the samples, whose sin and cos are taken from its lane
+    double s0, c0;
+    sincos(lo, &s0, &c0);
     for (int round = 0; round < 16; ++round) {
         const double t = lo + (hi - lo) * (double)(lane + 1) / (double)kWave;
-        const bool hit = lane < kWave - 1 && dir * L.deriv(t) >= 0.0;
+        const double dl = t - lo, d2 = dl * dl;
+        const double sd = dl * (1.0 - d2 / 6.0 * (1.0 - d2 / 20.0 * (1.0 - d2 / 42.0)));
+        const double cd = 1.0 - d2 / 2.0 * (1.0 - d2 / 12.0 * (1.0 - d2 / 30.0 * (1.0 - d2 / 56.0)));
+        const double st = s0 * cd + c0 * sd, ct = c0 * cd - s0 * sd;
+        const bool hit = lane < kWave - 1 && dir * L.deriv_sc(st, ct) >= 0.0;
         const unsigned long long mask = __ballot(hit);
         double nlo, nhi;
+        int src = -1;                       // lane whose sample becomes the lower end
         if (mask) {
             const int l = __ffsll((long long)mask) - 1;
             nhi = lo + (hi - lo) * (double)(l + 1) / (double)kWave;
-            nlo = l == 0 ? lo : lo + (hi - lo) * (double)l / (double)kWave;
+            if (l == 0) {
+                nlo = lo;
+            } else {
+                nlo = lo + (hi - lo) * (double)l / (double)kWave;
+                src = l - 1;
+            }
         } else {
             nlo = lo + (hi - lo) * (double)(kWave - 1) / (double)kWave;
             nhi = hi;
+            src = kWave - 2;
         }
         if (nlo == lo && nhi == hi) break;
+        if (src >= 0) {
+            s0 = read_lane(st, src);
+            c0 = read_lane(ct, src);
+        }
         lo = nlo;
         hi = nhi;
     }
@@ -778,6 +860,10 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
                 p3 += ov.x * a0 + ov.y * a1;
                 p5 += ow.x * a2 + ow.y * a3;
                 p6 += ov.x * a2 + ov.y * a3;
+                if (I.hv) {
+                    I.hv[d] = make_double2(a0, a1);
+                    I.hw[d] = make_double2(a2, a3);
+                }
             }
         }
         __syncthreads();
@@ -805,17 +891,20 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
         q[3] += ld_coh(&I.part_l[3 * I.n_tiles + 2 * i]);
         q[4] += ld_coh(&I.part_l[3 * I.n_tiles + 2 * i + 1]);
     }
-    double *tr = reinterpret_cast<double *>(&S);               // [5][NT]
+    double *tr = reinterpret_cast<double *>(&S);               // [5][kNW] wave sums
 #pragma unroll
-    for (int k = 0; k < 5; ++k) tr[k * NT + threadIdx.x] = q[k];
-    __syncthreads();
-    for (int h = NT / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h)
-#pragma unroll
-            for (int k = 0; k < 5; ++k) tr[k * NT + threadIdx.x] += tr[k * NT + threadIdx.x + h];
-        __syncthreads();
+    for (int k = 0; k < 5; ++k) {
+        const double v = wave_sum(q[k]);
+        if (lane == 0) tr[k * kNW + wv] = v;
     }
-    const double P3 = tr[0], P5 = tr[NT], P6 = tr[2 * NT], P2 = tr[3 * NT], P7 = tr[4 * NT];
+    __syncthreads();
+    double P[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        P[k] = 0.0;
+        for (int w = 0; w < kNW; ++w) P[k] += tr[k * kNW + w];
+    }
+    const double P3 = P[0], P5 = P[1], P6 = P[2], P2 = P[3], P7 = P[4];
     if (wv != 0 || mode == 0) return;
     const double inv = 1.0 / st->nrm;
     Landscape L;
@@ -829,6 +918,23 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
     const double th = line_search_wave(L, st->g[j]);
     if (lane == 0) {
         const int ns = th == 0.0 ? 0 : max(1, (int)ceil(fabs(th) * I.op_norm1[j] / 0.5));
+        // T5(h) = I + a A + b A^2 once A^3 = -A (and A^4 = -A^2); the product of
+        // two such factors stays in that span, so the whole chain is I + al A + be A^2
+        double al = 0.0, be = 0.0;
+        if (ns > 0) {
+            const double h = th / ns, h2 = h * h;
+            const double a = h * (1.0 - h2 / 6.0 * (1.0 - h2 / 20.0));   // h - h^3/6 + h^5/120
+            const double b = h2 * (0.5 - h2 / 24.0);                     // h^2/2 - h^4/24
+            for (int k = 0; k < ns; ++k) {
+                const double na = al + a - al * b - be * a;
+                const double nb = be + b + al * a - be * b;
+                al = na;
+                be = nb;
+            }
+        }
+        st->upd_alpha = al;
+        st->upd_beta = be;
+        st->upd_scale = 1.0 / sqrt(st->nrm);
         st->theta = th;
         st->nsub = ns;
         st->pred = L.value(th);

@@ -39,12 +39,13 @@ struct InstPlan {
     size_t n_counters = 0;
     size_t o_sigma = 0, o_v = 0, o_w = 0, o_pe = 0, o_pn = 0, o_pg = 0, o_pg2 = 0, o_pl = 0, o_pt = 0,
            o_cnt = 0, o_st = 0, o_he = 0, o_hop = 0, o_hth = 0, o_hgn = 0, o_hgm = 0, o_hns = 0,
-           o_hpr = 0, o_g = 0, o_psi = 0;
+           o_hpr = 0, o_g = 0, o_psi = 0, o_hv = 0, o_hw = 0;
     size_t bytes = 0;
 };
 
-// Lay out the workspace of one instance; own_psi reserves room for the state too.
-InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi);
+// Lay out the workspace of one instance; own_psi reserves room for the state
+// too, adapt the FP64 H v and H w an ADAPT iteration keeps.
+InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi, bool adapt = true);
 
 const DeviceHam *device_ham(const Ham &h, int dev);
 const DevicePool *device_pool(const Pool &p, int dev);

@@ -169,7 +169,7 @@ struct Bump {
 };
 }  // namespace
 
-InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi) {
+InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi, bool adapt) {
     InstPlan ip;
     Bump a;
     ip.n_qubits = nq;
@@ -203,6 +203,10 @@ InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi) {
     ip.o_hpr = a.take(hist * 8);
     ip.o_g = a.take((size_t)std::max(M, 1) * 8);
     if (own_psi) ip.o_psi = a.take(dim * es);
+    if (adapt) {
+        ip.o_hv = a.take(dim * 16);
+        ip.o_hw = a.take(dim * 16);
+    }
     ip.bytes = a.used;
     return ip;
 }
@@ -234,6 +238,8 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
     I.sigma = sigma_override ? sigma_override : reinterpret_cast<double2 *>(b + ip.o_sigma);
     I.v = b + ip.o_v;
     I.w = b + ip.o_w;
+    I.hv = ip.o_hv ? reinterpret_cast<double2 *>(b + ip.o_hv) : nullptr;
+    I.hw = ip.o_hw ? reinterpret_cast<double2 *>(b + ip.o_hw) : nullptr;
     I.part_e = reinterpret_cast<double *>(b + ip.o_pe);
     I.part_n = reinterpret_cast<double *>(b + ip.o_pn);
     I.part_g = reinterpret_cast<double *>(b + ip.o_pg);
@@ -306,7 +312,7 @@ OneShot one_shot(gocp_ctx *ctx, const Ham *h, const Pool *p, const void *psi, in
     if (h && p && h->n_qubits != p->n_qubits)
         throw Error(GOCP_ESHAPE, "Hamiltonian and pool act on different qubit counts");
     OneShot o;
-    o.ip = plan_instance(nq, p ? p->n_ops() : 0, 0, dtype, false);
+    o.ip = plan_instance(nq, p ? p->n_ops() : 0, 0, dtype, false, false);
     Bump a;
     a.used = o.ip.bytes;
     std::vector<int2> bt, bp;

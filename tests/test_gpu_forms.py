@@ -115,16 +115,20 @@ def test_batch_graph_and_direct_launch_agree(g, ctx):
     assert np.array_equal(r1["energies"], r2["energies"]) and r1["ops"] == r2["ops"]
 
 
-def test_kernel_timing_hook_leaves_record_unchanged(g, ctx):
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_kernel_timing_hook_leaves_record_unchanged(g, ctx, dtype):
     H, P, hf, nq = _inst(g, 12, "bk", 31)
-    psi = _psi(nq, hf, torch.complex128)
-    b = g.Batch(ctx, [H], [P], [psi], max_iter=10, schedule=2)
-    b.step(4)
-    for which in (0, 1):
+    psi = _psi(nq, hf, dtype)
+    b = g.Batch(ctx, [H], [P], [psi], max_iter=13, schedule=2)
+    b.step(5)
+    for which in (0, 1, 2):
         assert b.time_kernel(which, 3) > 0.0
-    b.step(6)
+    b.step(8)
     r = b.result(0)
-    solo = _psi(nq, hf, torch.complex128)
-    rs = g.adapt_solve(ctx, H, P, solo, 10, schedule=2)
+    solo = _psi(nq, hf, dtype)
+    rs = g.adapt_solve(ctx, H, P, solo, 13, schedule=2)
     assert np.array_equal(r["energies"], rs["energies"]) and r["ops"] == rs["ops"]
+    assert torch.equal(psi, solo)
+    with pytest.raises(g.GocpError):
+        b.time_kernel(3, 1)
     b.close()

@@ -247,6 +247,20 @@ def test_adapt_14q_first_iterations(g, ctx):
     _check_against_oracle(s, r, psi, 4)
 
 
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-12), ("c64", 2e-6)])
+@pytest.mark.parametrize("iters", [61, 64])
+def test_carried_sigma_energy_matches_fresh_energy(g, ctx, dtype, tol, iters):
+    """Between fresh H psi applications sigma is carried through each update;
+    the energy reported for the last iteration must match a fresh H psi on
+    the stored state (61: carried since the last refresh; 64: refreshed)."""
+    _say(f"[carry] 12q {dtype} {iters} iterations")
+    s = system(g, 12, "bk")
+    r, psi = _adapt_gpu(g, ctx, s, 12, iters, dtype)
+    e_fresh = g.energy(ctx, s["gH"], to_dev(psi, dtype))
+    assert r["n_iter"] == iters
+    assert abs(r["energies"][-1] - e_fresh) <= tol
+
+
 @pytest.mark.parametrize("mapping", ["jw", "bk"])
 def test_complex64_form_14q(g, ctx, mapping):
     """complex64 statevector with FP64 accumulation against the FP64 path."""

@@ -161,6 +161,33 @@ def test_taylor_chain_matches_closed_form(nq, j, theta):
     assert abs(np.vdot(out, out).real - (1 + (abs(zs) ** 2 - 1) * pn)) < 1e-14
 
 
+@pytest.mark.parametrize("theta", [0.3, -1.7, 2.9])
+def test_sigma_carried_through_the_update(theta):
+    """With A^3 = -A each substep is I + a A + b A^2 and products of such stay
+    in that span: (a1, b1) * (a2, b2) = (a1 + a2 - a1 b2 - b1 a2,
+    b1 + b2 + a1 a2 - b1 b2).  s such products give the closed form's
+    (Im z^s, 1 - Re z^s), and H psi' = sigma + al H w - be H v with
+    w = A psi, v = -A w (the sigma an ADAPT iteration carries forward)."""
+    nq = 10
+    h1, eri, ec, H, ops, hf, ne = _system(nq)
+    psi = _sector_state(nq, ne, np.random.default_rng(29))
+    A = ops[11]
+    out, s = taylor5(A, theta, psi, renormalize=False)
+    x = theta / s
+    a = x - x ** 3 / 6 + x ** 5 / 120
+    b = x ** 2 / 2 - x ** 4 / 24
+    al = be = 0.0
+    for _ in range(s):
+        al, be = al + a - al * b - be * a, be + b + al * a - be * b
+    _, _, zs = _closed_form_chain(A, theta, psi)
+    assert abs(al - zs.imag) < 1e-14 and abs(be - (1 - zs.real)) < 1e-14
+    w = apply_psum(A, psi)
+    v = -apply_psum(A, w)
+    sigma = apply_h(H, psi)
+    carried = sigma + al * apply_h(H, w) - be * apply_h(H, v)
+    assert np.abs(carried - apply_h(H, out)).max() < 1e-12
+
+
 @pytest.mark.parametrize("theta", [0.05, 0.5, -1.3, 3.0])
 def test_taylor_chain_versus_expm_within_truncation_bound(theta):
     h1, eri, ec, H, ops, hf, ne = _system(8)
