@@ -47,6 +47,7 @@ class Hamiltonian:
     def __init__(self, handle):
         self._h = handle
         lib = load()
+        self._free = lib.gocp_ham_free      # kept: module globals may be gone at exit
         nq, nt, nc = C.c_int32(), C.c_int64(), C.c_int32()
         check(lib.gocp_ham_info(self._h, C.byref(nq), C.byref(nt), C.byref(nc)))
         self.n_qubits, self.n_terms, self.n_classes = nq.value, nt.value, nc.value
@@ -68,7 +69,7 @@ class Hamiltonian:
     def __del__(self):
         h, self._h = getattr(self, "_h", None), None
         if h:
-            load().gocp_ham_free(h)
+            self._free(h)
 
 
 class Pool:
@@ -77,6 +78,7 @@ class Pool:
     def __init__(self, handle):
         self._h = handle
         lib = load()
+        self._free = lib.gocp_pool_free
         nq, m, s = C.c_int32(), C.c_int32(), C.c_int32()
         check(lib.gocp_pool_info(self._h, C.byref(nq), C.byref(m), C.byref(s)))
         self.n_qubits, self.n_ops, self.n_strings = nq.value, m.value, s.value
@@ -112,7 +114,7 @@ class Pool:
     def __del__(self):
         h, self._h = getattr(self, "_h", None), None
         if h:
-            load().gocp_pool_free(h)
+            self._free(h)
 
 
 def pauli_hamiltonian_load(h1, eri, e_core: float, mapping) -> Hamiltonian:
@@ -184,6 +186,7 @@ class Context:
             stream = torch.cuda.current_stream(device)
         sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
         self._c = C.c_void_p()
+        self._free = load().gocp_ctx_destroy
         check(load().gocp_ctx_create(device, C.c_void_p(sp), C.byref(self._c)))
         self.device = device
 
@@ -201,7 +204,7 @@ class Context:
     def close(self):
         c, self._c = getattr(self, "_c", None), None
         if c:
-            load().gocp_ctx_destroy(c)
+            self._free(c)
 
     def __del__(self):
         self.close()
@@ -312,6 +315,8 @@ class Batch:
         self.n = n
         prm = AdaptParams(float(grad_tol), int(max_iter), 1 if use_graph else 0, int(schedule), 0)
         self._b = C.c_void_p()
+        self._ctx = ctx                     # the context outlives the batch
+        self._free = load().gocp_batch_destroy
         check(load().gocp_batch_create(ctx.handle, n, H, P, S, self.dtype, C.byref(prm),
                                        C.byref(self._b)))
 
@@ -346,7 +351,7 @@ class Batch:
     def close(self):
         b, self._b = getattr(self, "_b", None), None
         if b:
-            load().gocp_batch_destroy(b)
+            self._free(b)
 
     def __del__(self):
         self.close()
@@ -366,6 +371,8 @@ class Server:
     def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int, dtype: int = C64,
                  iters_per_step: int = 4, amps_per_lane: int = 1):
         self._s = C.c_void_p()
+        self._ctx = ctx
+        self._free = load().gocp_server_destroy
         check(load().gocp_server_create(ctx.handle, int(hbm_budget_bytes), int(max_slots), int(dtype),
                                         int(iters_per_step), int(amps_per_lane), C.byref(self._s)))
         self._keep = {}        # ticket -> (ham, pool, max_iter): alive until polled
@@ -401,7 +408,7 @@ class Server:
     def close(self):
         s, self._s = getattr(self, "_s", None), None
         if s:
-            load().gocp_server_destroy(s)
+            self._free(s)
 
     def __del__(self):
         self.close()

@@ -99,7 +99,7 @@ struct InstDev {
     void *v;
     void *w;
     double2 *hv;                // H v and H w (FP64), kept by the line search for the
-    double2 *hw;                // next sigma; null outside ADAPT runs
+    double2 *hw;                // next sigma; null outside ADAPT runs of FP64 states
     double *part_e;             // n_tiles
     double *part_n;             // n_tiles
     double *part_g;             // n_tiles * M

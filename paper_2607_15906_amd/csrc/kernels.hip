@@ -44,9 +44,15 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // State element access: raw() loads the stored bits, cvt() widens to FP64.
 // Period (in ADAPT iterations) of the fresh H psi that resets the carried sigma:
 // the stored state is rounded to its precision at every update while the
-// carried sigma follows the unrounded update.
+// carried sigma follows the unrounded update, so the energy and gradients
+// formed with a carried sigma are off by a term of first order in that
+// rounding.  For FP64 states this is ~1e-15 and sigma is carried between
+// fresh applications every 32 iterations.  For complex64 states it is ~1e-7 Ha
+// at 14 qubits (against ~1e-10 with a fresh H psi, whose Rayleigh quotient is
+// second order in the rounding), so complex64 states apply H afresh every
+// iteration and do not keep H v, H w.
 template <typename T> struct Refresh;
-template <> struct Refresh<float2> { static constexpr int kPeriod = 8; };
+template <> struct Refresh<float2> { static constexpr int kPeriod = 1; };
 template <> struct Refresh<double2> { static constexpr int kPeriod = 32; };
 
 template <typename T> struct Amp;

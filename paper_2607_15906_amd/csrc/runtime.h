@@ -44,7 +44,7 @@ struct InstPlan {
 };
 
 // Lay out the workspace of one instance; own_psi reserves room for the state
-// too, adapt the FP64 H v and H w an ADAPT iteration keeps.
+// too, adapt (FP64 states only) the H v and H w an ADAPT iteration keeps.
 InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi, bool adapt = true);
 
 const DeviceHam *device_ham(const Ham &h, int dev);

@@ -203,7 +203,7 @@ InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi, boo
     ip.o_hpr = a.take(hist * 8);
     ip.o_g = a.take((size_t)std::max(M, 1) * 8);
     if (own_psi) ip.o_psi = a.take(dim * es);
-    if (adapt) {
+    if (adapt && dtype == GOCP_C128) {       // complex64 states never carry sigma
         ip.o_hv = a.take(dim * 16);
         ip.o_hw = a.take(dim * 16);
     }
