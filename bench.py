@@ -223,16 +223,18 @@ def main():
     # the other iterations; 1: the line search's H v and H w, every iteration)
     nl = 50
     rf = REFRESH["complex64"]
-    share = {0: 1.0 / rf, 1: 1.0, 2: 1.0 - 1.0 / rf}
-    ms = {which: b.time_kernel(which, nl) for which in (0, 1, 2) if share[which] > 0}
+    share = {0: 1.0 / rf, 1: 1.0, 2: 1.0 - 1.0 / rf, 3: 1.0}
+    ms = {which: b.time_kernel(which, nl) for which in (0, 1, 2, 3) if share[which] > 0}
     dim = 1 << nq
     # algorithmic FP64 flops per launch: one signed add per (string, amplitude),
     # a real-by-complex multiply-add (4 flops) per (class or operator, amplitude)
     # and the dot products; carrying sigma costs 8 flops per amplitude
     flops = {0: dim * (T + 4 * C + 4) + dim * (S + 4 * M),   # H psi + energy + screen
              1: dim * (T + 8 * C + 12),                      # H v and H w + three dots
-             2: dim * (8 + 4) + dim * (S + 4 * M)}           # carried sigma + energy + screen
-    names = {0: "k_energy_screen (fresh H psi)", 1: "k_line_hvw", 2: "k_energy_screen (carried sigma)"}
+             2: dim * (8 + 4) + dim * (S + 4 * M),           # carried sigma + energy + screen
+             3: (dim // 64) * (M + 2)}                       # sums of the tile partials
+    names = {0: "k_energy_screen (fresh H psi)", 1: "k_line_hvw", 2: "k_energy_screen (carried sigma)",
+             3: "k_screen_reduce"}
     dom = max(ms, key=lambda k: ms[k] * share[k])
     achieved = flops[dom] / (ms[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": names[dom], "achieved": round(achieved, 4),

@@ -271,11 +271,14 @@ int gocp_batch_result(gocp_batch *b, int32_t i, gocp_adapt_result *res);
 /*
  * Measurement hook: launch one kernel of the iteration n_launch times back to
  * back over the whole batch and return its mean duration from HIP events
- * recorded on the context stream.  which: 0 = energy + gradient screen with a
- * fresh H psi, 1 = H v / H w products of the line search, 2 = energy +
- * gradient screen with sigma carried through the last update (the form most
- * iterations run).  The launches write only scratch buffers (never sigma, the
- * states or the iteration record), so a run continues exactly as without them.
+ * recorded on the context stream.  which: 0 = per-tile energy and gradient
+ * screen partials with a fresh H psi, 1 = H v / H w products of the line
+ * search, 2 = the partials with sigma carried through the last update (the
+ * form most iterations of complex128 states run; complex64 states apply H
+ * afresh every iteration, and 2 then times the same work as 0), 3 = the
+ * reduction of the partials into energy, gradients and the selection.  The
+ * launches write only scratch buffers (never sigma, the states or the
+ * iteration record), so a run continues exactly as without them.
  */
 int gocp_batch_time_kernel(gocp_batch *b, int32_t which, int32_t n_launch, double *avg_ms);
 /* The schedule the batch runs with (amplitudes per lane; autotuned or given). */

@@ -72,11 +72,13 @@ struct Group {
     int dtype = 0;
     int R = 1;                 // amplitudes per lane of the tile kernels
     std::vector<int> ntile;    // tiles of each member for R
+    std::vector<int> ngroup;   // tile groups of each member (first reduction stage)
+    int ng = 0;
     std::vector<Instance *> inst;
     char *meta = nullptr;
     size_t meta_cap = 0;
     InstDev *desc = nullptr;
-    int2 *btile = nullptr, *bpair = nullptr, *bsub = nullptr;
+    int2 *btile = nullptr, *bpair = nullptr, *bsub = nullptr, *binst = nullptr, *bgrp = nullptr;
     int32_t *done = nullptr;   // n flags gathered on the device
     int nt = 0, np = 0;
     std::vector<int> tile0, pair0;
@@ -102,10 +104,11 @@ struct Group {
     void rebuild(hipStream_t s) {
         drop_graphs();
         std::vector<InstDev> d;
-        std::vector<int2> bt, bp;
+        std::vector<int2> bt, bp, bi, bg;
         tile0.clear();
         pair0.clear();
         ntile.clear();
+        ngroup.clear();
         for (size_t i = 0; i < inst.size(); ++i) {
             InstDev di = inst[i]->desc;
             di.n_tiles = tiles_for(di.n_qubits, R);
@@ -116,7 +119,11 @@ struct Group {
             pair0.push_back((int)bp.size());
             for (int t = 0; t < di.n_tiles; ++t) bt.push_back(make_int2((int)i, t));
             for (int t = 0; t < inst[i]->ip.n_pblk; ++t) bp.push_back(make_int2((int)i, t));
+            bi.push_back(make_int2((int)i, 0));
+            for (int gi = 0; gi < di.n_groups; ++gi) bg.push_back(make_int2((int)i, gi));
+            ngroup.push_back(di.n_groups);
         }
+        ng = (int)bg.size();
         nt = (int)bt.size();
         np = (int)bp.size();
         const size_t sub = std::max<size_t>({bt.size(), bp.size(), inst.size(), 1});
@@ -124,7 +131,9 @@ struct Group {
         const size_t o_bt = al(d.size() * sizeof(InstDev));
         const size_t o_bp = o_bt + al(bt.size() * sizeof(int2));
         const size_t o_bs = o_bp + al(bp.size() * sizeof(int2));
-        const size_t o_dn = o_bs + al(sub * sizeof(int2));
+        const size_t o_bi = o_bs + al(sub * sizeof(int2));
+        const size_t o_bg = o_bi + al(std::max<size_t>(inst.size(), 1) * sizeof(int2));
+        const size_t o_dn = o_bg + al(std::max<size_t>(bg.size(), 1) * sizeof(int2));
         const size_t need = o_dn + al(std::max<size_t>(inst.size(), 1) * sizeof(int32_t));
         if (need > meta_cap) {
             if (meta) {
@@ -139,6 +148,8 @@ struct Group {
         btile = reinterpret_cast<int2 *>(meta + o_bt);
         bpair = reinterpret_cast<int2 *>(meta + o_bp);
         bsub = reinterpret_cast<int2 *>(meta + o_bs);
+        binst = reinterpret_cast<int2 *>(meta + o_bi);
+        bgrp = reinterpret_cast<int2 *>(meta + o_bg);
         done = reinterpret_cast<int32_t *>(meta + o_dn);
         if (!d.empty())
             hip_check(hipMemcpyAsync(desc, d.data(), d.size() * sizeof(InstDev), hipMemcpyHostToDevice, s), "H2D");
@@ -146,18 +157,26 @@ struct Group {
             hip_check(hipMemcpyAsync(btile, bt.data(), bt.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
         if (!bp.empty())
             hip_check(hipMemcpyAsync(bpair, bp.data(), bp.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
+        if (!bi.empty())
+            hip_check(hipMemcpyAsync(binst, bi.data(), bi.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
+        if (!bg.empty())
+            hip_check(hipMemcpyAsync(bgrp, bg.data(), bg.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
     }
 
     // One ADAPT iteration of every member (the screen and selection of the
-    // current state were done by the previous launch of k_energy_screen):
+    // current state were done by the previous iteration or by start()):
     // line-search vectors, H v / H w and the angle, Taylor update, then the
-    // new state's energy together with its screen and selection.
+    // new state's energy and screen partials, and their reduction with the
+    // selection.
     void enqueue_iteration(hipStream_t s) const {
         if (inst.empty()) return;
+        const int n = (int)inst.size();
         launch_kernel(K_LINE_VW, dtype, R, desc, bpair, np, 1, s);
         launch_kernel(K_LINE_HVW, dtype, R, desc, btile, nt, 1, s);
         launch_kernel(K_TAYLOR, dtype, R, desc, bpair, np, 1, s);
         launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 2, s);
+        launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 2, s);
+        launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, n, 2, s);
     }
 
     void capture() {
@@ -184,12 +203,12 @@ struct Group {
         for (int i = 0; i < n % kChunk; ++i) hip_check(hipGraphLaunch(exec[0], s), "hipGraphLaunch");
     }
 
-    // Launch one kernel over the tile (or pair, or one-per-instance) rows of
-    // a subset of members.
+    // Launch one kernel over the tile (0), pair (1), instance (2) or tile-group
+    // (3) rows of a subset of members.
     void launch_subset(int which, int mode, const std::vector<int> &members, int table, hipStream_t s) {
         std::vector<int2> rows;
         for (int i : members) {
-            const int n = table == 0 ? ntile[i] : table == 1 ? inst[i]->ip.n_pblk : 1;
+            const int n = table == 0 ? ntile[i] : table == 1 ? inst[i]->ip.n_pblk : table == 3 ? ngroup[i] : 1;
             for (int t = 0; t < n; ++t) rows.push_back(make_int2(i, t));
         }
         if (rows.empty()) return;
@@ -204,11 +223,16 @@ struct Group {
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "hipEventCreate");
         hip_check(hipEventCreate(&e1), "hipEventCreate");
+        const int n = (int)inst.size();
         launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 3, s);
+        launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 3, s);
+        launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, n, 3, s);
         launch_kernel(K_LINE_HVW, dtype, R, desc, btile, nt, 0, s);
         hip_check(hipEventRecord(e0, s), "hipEventRecord");
         for (int i = 0; i < reps; ++i) {
             launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 3, s);
+            launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 3, s);
+            launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, n, 3, s);
             launch_kernel(K_LINE_HVW, dtype, R, desc, btile, nt, 0, s);
         }
         hip_check(hipEventRecord(e1, s), "hipEventRecord");
@@ -229,6 +253,8 @@ struct Group {
     // Energy, screen and selection of the starting state of the given members.
     void start(const std::vector<int> &members, hipStream_t s) {
         launch_subset(K_ENERGY_SCREEN, 1, members, 0, s);
+        launch_subset(K_SCREEN_SUM1, 1, members, 3, s);
+        launch_subset(K_SCREEN_REDUCE, 1, members, 2, s);
     }
 
     // Scale the states of the given members to unit norm (their renormalisation

@@ -261,18 +261,27 @@ int gocp_batch_result(gocp_batch *b, int32_t i, gocp_adapt_result *res) {
 int gocp_batch_time_kernel(gocp_batch *b, int32_t which, int32_t n_launch, double *avg_ms) {
     GOCP_GUARD_BEGIN
     if (!b || !avg_ms || n_launch <= 0) throw Error(GOCP_EINVAL, "null argument or no launches");
-    if (which < 0 || which > 2) throw Error(GOCP_EINVAL, "kernel id must be 0, 1 or 2");
+    if (which < 0 || which > 3) throw Error(GOCP_EINVAL, "kernel id must be 0, 1, 2 or 3");
     check_ctx(b->group.ctx);
     hipStream_t s = b->group.ctx->user_stream;
     Group &g = b->group;
     const int kid = which == 1 ? K_LINE_HVW : K_ENERGY_SCREEN;
-    const int mode = which == 0 ? 3 : which == 2 ? 4 : 0;                // dry modes
+    const int mode = which == 1 ? 0 : which == 2 ? 4 : 3;                // dry modes
+    // which 3: both reduction stages
+    auto launch = [&]() {
+        if (which == 3) {
+            launch_kernel(K_SCREEN_SUM1, g.dtype, g.R, g.desc, g.bgrp, g.ng, mode, s);
+            launch_kernel(K_SCREEN_REDUCE, g.dtype, g.R, g.desc, g.binst, (int)g.inst.size(), mode, s);
+        } else {
+            launch_kernel(kid, g.dtype, g.R, g.desc, g.btile, g.nt, mode, s);
+        }
+    };
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
-    launch_kernel(kid, g.dtype, g.R, g.desc, g.btile, g.nt, mode, s);     // warm
+    launch();     // warm
     hip_check(hipEventRecord(e0, s), "hipEventRecord");
-    for (int i = 0; i < n_launch; ++i) launch_kernel(kid, g.dtype, g.R, g.desc, g.btile, g.nt, mode, s);
+    for (int i = 0; i < n_launch; ++i) launch();
     hip_check(hipEventRecord(e1, s), "hipEventRecord");
     hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
     float ms = 0.f;

@@ -18,7 +18,15 @@ constexpr int kPairBlock = 256;        // threads (= amplitude pairs) per pair-k
 // Term tables are staged into LDS in chunks of at most this many records.
 constexpr int kStageTerms = 4096;      // strings (64 KiB)
 constexpr int kStageCls = 1024;        // classes or operators (16 KiB)
-// Tiles per group in the two-level reduction of the gradient screen.
+// Each class or operator of the staged tables is padded with zero strings to a
+// whole number of groups of this many strings (the tile kernels read and sum
+// strings a group at a time).
+constexpr int kStrGroup = 4;
+// Fixed per-record VALU cost estimates used to balance records over the waves
+// of a tile block (an H class; a screened operator, which adds a wave sum).
+constexpr int kClassCost = 10;
+constexpr int kOpCost = 36;
+// Tiles per group in the first stage of the screen reduction.
 constexpr int kGroup = 16;
 
 // A folded Pauli string as the kernels read it (16 bytes): the magnitude of
@@ -84,6 +92,7 @@ struct InstDev {
     const HTerm *hterm;
     const HSub *hsub;
     const int32_t *hchunk;      // n_hchunks + 1 class boundaries of the LDS stages
+    const int32_t *hseg;        // n_hchunks x (kNW + 1) class boundaries of the waves
     // pool, in pool order (pair kernels)
     const HClass *pop;          // one record per operator
     const HTerm *pterm;
@@ -93,6 +102,7 @@ struct InstDev {
     const HTerm *sterm;
     const HSub *psub;
     const int32_t *pchunk;      // n_pchunks + 1 operator boundaries of the LDS stages
+    const int32_t *pseg;        // n_pchunks x (kNW + 1) operator boundaries of the waves
     // buffers (psi, v, w in the state precision; sigma FP64)
     void *psi;
     double2 *sigma;
@@ -104,10 +114,11 @@ struct InstDev {
     double *part_n;             // n_tiles
     double *part_g;             // n_tiles * M
     double *part_g2;            // n_groups * M (sums over groups of kGroup tiles)
+    double *part_e2;            // n_groups
+    double *part_n2;            // n_groups
     double *part_l;             // 3 * n_tiles + 2 * n_pblk (line-search dots)
     double *part_t;             // n_pblk (Taylor norms)
-    int32_t *counters;          // arrival counters: [0] screen, [2] line search,
-                                // [4 + g] group g of the screen reduction
+    int32_t *counters;          // arrival counters: [2] line search (others spare)
     AdaptState *st;
     int32_t n_qubits;
     int32_t M;
@@ -125,6 +136,7 @@ struct DeviceHam {
     HTerm *hterm = nullptr;
     HSub *hsub = nullptr;
     int32_t *hchunk = nullptr;
+    int32_t *hseg = nullptr;     // per chunk, kNW + 1 wave boundaries of its classes
     int n_chunks = 0;
 };
 
@@ -137,6 +149,7 @@ struct DevicePool {
     HTerm *sterm = nullptr;
     HSub *psub = nullptr;
     int32_t *pchunk = nullptr;
+    int32_t *pseg = nullptr;     // per chunk, kNW + 1 wave boundaries of its operators
     int n_chunks = 0;
 };
 

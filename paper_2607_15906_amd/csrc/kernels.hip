@@ -340,6 +340,72 @@ __device__ __forceinline__ uint32_t partner(uint32_t d0, int r, uint32_t x, uint
     return d < dim ? d ^ x : x;
 }
 
+// One amplitude per lane: the wave's records [c0, c1) of the staged chunk
+// (classes or operators, each padded to whole groups of kStrGroup strings),
+// walked as a software pipeline over two register sets.  While record c is
+// summed, the first string group of record c + 1 and its gathered amplitudes
+// from v0 (and v1) are in flight, and the record after that is being read.
+// d must lie in the state (its bits feed the gather index directly).
+// fin(c, f_c(d), raw amplitudes at d ^ x_c) is called for every record in order.
+template <typename T, int NV, typename Fin>
+__device__ __forceinline__ void walk_classes_r1(const Stage &S, int c0, int c1, int sb, uint32_t d,
+                                                const void *v0, const void *v1, Fin &&fin) {
+    using Raw = typename Amp<T>::Raw;
+    struct Rec {
+        uint32_t x;
+        int s0, s1;
+    };
+    // start reading record r: its first string group and its gathered amplitudes
+    auto issue = [&](const HClass &r, HTerm (&g)[kStrGroup], Raw (&p)[NV]) {
+        const Rec k{(uint32_t)uni((int)r.x), uni(r.s0) - sb, uni(r.s1) - sb};
+#pragma unroll
+        for (int q = 0; q < kStrGroup; ++q) g[q] = S.terms[k.s0 + q];
+        p[0] = Amp<T>::raw(v0, d ^ k.x);
+        if (NV == 2) p[NV - 1] = Amp<T>::raw(v1, d ^ k.x);
+        return k;
+    };
+    // f(d) of a record whose first group is in registers; further groups are
+    // read here (the string range is uniform: scalar loop bounds)
+    auto coef = [&](const Rec &k, const HTerm (&g)[kStrGroup]) {
+        double f0 = signed_coef(g[0], d) + signed_coef(g[2], d);
+        double f1 = signed_coef(g[1], d) + signed_coef(g[3], d);
+        const int s1 = uni(k.s1);
+        for (int s = uni(k.s0) + kStrGroup; s < s1; s += kStrGroup) {
+            const HTerm a0 = S.terms[s], a1 = S.terms[s + 1], a2 = S.terms[s + 2], a3 = S.terms[s + 3];
+            f0 += signed_coef(a0, d) + signed_coef(a2, d);
+            f1 += signed_coef(a1, d) + signed_coef(a3, d);
+        }
+        return f0 + f1;
+    };
+    if (c0 >= c1) return;
+    HTerm gA[kStrGroup], gB[kStrGroup];
+    Raw pA[NV], pB[NV];
+    Rec kA = issue(S.cls[c0], gA, pA), kB = kA;
+    HClass rB = S.cls[c0 + 1 < c1 ? c0 + 1 : c0], rA = rB;
+    for (int c = c0;; c += 2) {
+        if (c + 1 < c1) {
+            kB = issue(rB, gB, pB);
+            if (c + 2 < c1) rA = S.cls[c + 2];
+        }
+        fin(c, coef(kA, gA), pA);
+        if (c + 1 >= c1) break;
+        if (c + 2 < c1) {
+            kA = issue(rA, gA, pA);
+            if (c + 3 < c1) rB = S.cls[c + 3];
+        }
+        fin(c + 1, coef(kB, gB), pB);
+        if (c + 2 >= c1) break;
+    }
+}
+
+// The wave's records [c0, c1) of stage chunk k (chunk-relative) from a
+// kNW + 1 boundary table per chunk.
+__device__ __forceinline__ void wave_range(const int32_t *seg, int k, int cb, int &c0, int &c1) {
+    const GOCP_AS4 int32_t *t = cptr(seg) + k * (kNW + 1) + wave_id();
+    c0 = t[0] - cb;
+    c1 = t[1] - cb;
+}
+
 // Apply the X-mask classes of H to NV vectors at the lane's R amplitudes:
 // acc[(k R + r) 2 + {0,1}] += sum_classes f_class(d_r) vec_k[d_r ^ x_class].
 // The table is staged chunk by chunk; wave w takes classes w, w + kNW, ... of
@@ -356,13 +422,27 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
         const int sb = hcls[cb].s0, se = hcls[ce - 1].s1;
         __syncthreads();
         stage_copy(S.cls, I.hcls + cb, ce - cb);
-        stage_copy(S.sub, I.hsub + cb, ce - cb);
+        if (R > 1) stage_copy(S.sub, I.hsub + cb, ce - cb);
         stage_copy(S.terms, I.hterm + sb, se - sb);
         __syncthreads();
-        const int nc = ce - cb;
-        int c = wv;
+        int c0, c1;
+        wave_range(I.hseg, k, cb, c0, c1);
+        if constexpr (R == 1) {
+            const uint32_t dd = d0 < dim ? d0 : 0u;
+            walk_classes_r1<T, NV>(S, c0, c1, sb, dd, v0, v1,
+                                   [&](int, double f, const typename Amp<T>::Raw (&p)[NV]) {
+#pragma unroll
+                                       for (int v = 0; v < NV; ++v) {
+                                           const double2 a = Amp<T>::cvt(p[v]);
+                                           acc[2 * v] = fma(f, a.x, acc[2 * v]);
+                                           acc[2 * v + 1] = fma(f, a.y, acc[2 * v + 1]);
+                                       }
+                                   });
+            continue;
+        }
+        int c = c0;
         typename Amp<T>::Raw rn[NV][R];
-        if (c < nc) {
+        if (c < c1) {
             const uint32_t xn = (uint32_t)uni((int)S.cls[c].x);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -370,14 +450,14 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
                 if (NV == 2) rn[NV - 1][r] = Amp<T>::raw(v1, partner(d0, r, xn, dim));
             }
         }
-        for (; c < nc; c += kNW) {
+        for (; c < c1; ++c) {
             typename Amp<T>::Raw rc[NV][R];
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
                 for (int r = 0; r < R; ++r) rc[v][r] = rn[v][r];
-            const int cn = c + kNW;
-            if (cn < nc) {
+            const int cn = c + 1;
+            if (cn < c1) {
                 const uint32_t xn = (uint32_t)uni((int)S.cls[cn].x);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -412,11 +492,10 @@ __device__ __forceinline__ uint32_t insert_zero_bit(uint32_t p, int hb) {
 //   2. when a screen is due, the tile's share of
 //      g_j = 2 Re <sigma | A_j psi> / <psi|psi> for every pool operator, with
 //      the tile's own sigma values taken from LDS.  Operators are visited in
-//      GOCP family order (the family-ordered table is staged in LDS; wave w
-//      takes operators w, w + kNW, ... of each stage);
-//   3. the last workgroup of each group of kGroup tiles sums the group's
-//      screen partials, and the last group forms the energy, the norm, the
-//      gradients, |g|max, ||g||_2 and the selected operator.
+//      GOCP family order (the family-ordered table is staged in LDS; each wave
+//      takes a contiguous, cost-balanced run of each stage's operators);
+// and writes the tile's partials; k_screen_reduce, launched next, forms the
+// energy, the norm, the gradients, |g|max, ||g||_2 and the selected operator.
 // mode 0: one-shot (energy; gradients when the instance has a pool);
 // mode 1: starting state of an ADAPT run (E_0 and the first screen);
 // mode 2: state after an update: iteration counter + 1, its energy, and the
@@ -443,7 +522,6 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
     __shared__ Stage S;
     __shared__ double2 s_sig[R][kWave];
     __shared__ double gpart[kStageCls];
-    __shared__ double lds[kNW * kWave];
 
     // 1. sigma on the tile: H psi, or, after an update, sigma carried through
     //    it (the update is I + al A + be A^2 on scale * psi, so
@@ -507,8 +585,8 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
         pe = wave_sum(pe);
         pn = wave_sum(pn);
         if (lane == 0) {
-            st_coh(&I.part_e[b.y], pe);
-            st_coh(&I.part_n[b.y], pn);
+            I.part_e[b.y] = pe;
+            I.part_n[b.y] = pn;
         }
     }
 
@@ -524,23 +602,33 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
             const int sb = sop[ob].s0, se = sop[oe - 1].s1;
             __syncthreads();
             stage_copy(S.cls, I.sop + ob, oe - ob);
-            stage_copy(S.sub, I.psub + ob, oe - ob);
+            if (R > 1) stage_copy(S.sub, I.psub + ob, oe - ob);
             stage_copy(S.terms, I.sterm + sb, se - sb);
             __syncthreads();
             const int no = oe - ob;
-            int o = wv;
+            int o0, o1;
+            wave_range(I.pseg, k, ob, o0, o1);
+            if constexpr (R == 1) {
+                walk_classes_r1<T, 1>(S, o0, o1, sb, d0 < dim ? d0 : 0u, I.psi, nullptr,
+                                      [&](int o, double h, const typename Amp<T>::Raw (&p)[1]) {
+                                          const double2 a = Amp<T>::cvt(p[0]);
+                                          const double val = wave_sum(h * (sg[0].x * a.x + sg[0].y * a.y));
+                                          if (lane == 0) gpart[o] = val;
+                                      });
+            } else {
+            int o = o0;
             typename Amp<T>::Raw rn[R];
-            if (o < no) {
+            if (o < o1) {
                 const uint32_t xn = (uint32_t)uni((int)S.cls[o].x);
 #pragma unroll
                 for (int r = 0; r < R; ++r) rn[r] = Amp<T>::raw(I.psi, partner(d0, r, xn, dim));
             }
-            for (; o < no; o += kNW) {
+            for (; o < o1; ++o) {
                 typename Amp<T>::Raw rc[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) rc[r] = rn[r];
-                const int on = o + kNW;
-                if (on < no) {
+                const int on = o + 1;
+                if (on < o1) {
                     const uint32_t xn = (uint32_t)uni((int)S.cls[on].x);
 #pragma unroll
                     for (int r = 0; r < R; ++r) rn[r] = Amp<T>::raw(I.psi, partner(d0, r, xn, dim));
@@ -556,59 +644,144 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                 val = wave_sum(val);
                 if (lane == 0) gpart[o] = val;
             }
+            }
             __syncthreads();
             // wave 0 writes this stage's per-operator partials (pool-indexed)
             if (wv == 0)
-                for (int i = lane; i < no; i += kWave) st_coh(&I.part_g[(size_t)b.y * M + S.cls[i].pad], gpart[i]);
+                for (int i = lane; i < no; i += kWave) I.part_g[(size_t)b.y * M + S.cls[i].pad] = gpart[i];
         }
     }
+}
 
-    // 3a. the last workgroup of each group of kGroup tiles sums the group's
-    //     screen partials (fixed tile order) into part_g2
-    const int grp = b.y / kGroup;
-    const int t0 = grp * kGroup, t1 = min(t0 + kGroup, I.n_tiles);
-    if (!arrive_last(&I.counters[4 + grp], t1 - t0)) return;
-    constexpr int NT = kNW * kWave;
-    if (screen) {
-        for (int j = threadIdx.x; j < M; j += NT) {
-            double a[kGroup];
+// The screen's partials are summed in two launches that follow
+// k_energy_screen on the same stream (each kernel boundary orders the stores
+// of one launch before the loads of the next); every sum runs in a fixed
+// order, so results do not depend on scheduling.
+//
+// First stage: workgroup (i, g) adds tiles g kGroup, ..., (g + 1) kGroup - 1
+// of instance i in tile order: the energy and norm partials, and every
+// operator's partial (thread = operator, all kGroup loads in flight).
+__global__ __launch_bounds__(kPairBlock) void k_screen_sum1(const InstDev *__restrict__ insts,
+                                                           const int2 *__restrict__ blk, int mode) {
+    const int2 b = blk[blockIdx.x];
+    const InstDev &I = insts[b.x];
+    AdaptState *st = I.st;
+    const bool oneshot = mode == 0 || mode >= 3;
+    if (!oneshot && state_done(st)) return;
+    const int it = mode == 2 ? cptr(&st->iter)[0] + 1 : 0;
+    const int M = I.M;
+    const bool screen = M > 0 && (oneshot || it < cptr(&st->max_iter)[0]);
+    const int t0 = b.y * kGroup, nt = min(kGroup, I.n_tiles - t0);
+    if (threadIdx.x < 2) {
+        const double *src = threadIdx.x == 0 ? I.part_e : I.part_n;
+        double x[kGroup];
 #pragma unroll
-            for (int t = 0; t < kGroup; ++t) a[t] = t0 + t < t1 ? ld_coh(&I.part_g[(size_t)(t0 + t) * M + j]) : 0.0;
-            double sum = 0.0;
+        for (int t = 0; t < kGroup; ++t) x[t] = t < nt ? src[t0 + t] : 0.0;
+        double a = 0.0;
 #pragma unroll
-            for (int t = 0; t < kGroup; ++t) sum += a[t];
-            st_coh(&I.part_g2[(size_t)grp * M + j], sum);
-        }
+        for (int t = 0; t < kGroup; ++t) a += x[t];
+        (threadIdx.x == 0 ? I.part_e2 : I.part_n2)[b.y] = a;
     }
-    // 3b. the last group to finish forms energy, norm, gradients, selection
-    if (!arrive_last(&I.counters[0], I.n_groups)) return;
-    const double e_num = block_sum_coh<NT>(I.part_e, I.n_tiles, 1, lds);
-    const double nrm = block_sum_coh<NT>(I.part_n, I.n_tiles, 1, lds);
+    if (!screen) return;
+    for (int j = threadIdx.x; j < M; j += kPairBlock) {
+        double x[kGroup];
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) x[t] = t < nt ? I.part_g[(size_t)(t0 + t) * M + j] : 0.0;
+        double a = 0.0;
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) a += x[t];
+        I.part_g2[(size_t)b.y * M + j] = a;
+    }
+}
+
+// Second stage, one workgroup per instance: energy, norm and gradients from
+// the group sums, then the operator selection and the iteration record (modes
+// as k_energy_screen).  Wave w adds group rows w, w + kNW, ... for up to
+// kRedCols 64-column blocks of operators at once (lane = column), and the kNW
+// wave sums are added in wave order.
+constexpr int kRedCols = 4;
+
+__global__ __launch_bounds__(kNW *kWave) void k_screen_reduce(const InstDev *__restrict__ insts,
+                                                             const int2 *__restrict__ blk, int mode) {
+    const InstDev &I = insts[blk[blockIdx.x].x];
+    AdaptState *st = I.st;
+    const bool oneshot = mode == 0 || mode >= 3, dry = mode >= 3;
+    if (!oneshot && state_done(st)) return;
+    const int it = mode == 2 ? cptr(&st->iter)[0] + 1 : 0;
+    const int M = I.M;
+    const bool screen = M > 0 && (oneshot || it < cptr(&st->max_iter)[0]);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = wave_id();
+    constexpr int NT = kNW * kWave;
+    __shared__ double lds[kRedCols * NT];
+    const int nt = I.n_groups;
+    // energy and norm: both group-sum arrays in one pass
+    double e_num, nrm;
+    {
+        double ae = 0.0, an = 0.0;
+        for (int t = threadIdx.x; t < nt; t += NT) {
+            ae += I.part_e2[t];
+            an += I.part_n2[t];
+        }
+        ae = wave_sum(ae);
+        an = wave_sum(an);
+        if (lane == 0) {
+            lds[wv] = ae;
+            lds[kNW + wv] = an;
+        }
+        __syncthreads();
+        e_num = 0.0;
+        nrm = 0.0;
+        for (int w = 0; w < kNW; ++w) {
+            e_num += lds[w];
+            nrm += lds[kNW + w];
+        }
+        __syncthreads();
+    }
     double amax = 0.0, sq = 0.0;
     if (screen) {
-        // column sums over groups: wave w takes groups w, w + kNW, ...; fixed order
         const double inv = 2.0 / nrm;
-        double *colsum = reinterpret_cast<double *>(&S);          // [kNW][kWave]
-        for (int jb = 0; jb < M; jb += kWave) {
-            const int j = jb + lane;
-            double a0 = 0.0, a1 = 0.0;
-            if (j < M) {
-                int t = wv;
-                for (; t + kNW < I.n_groups; t += 2 * kNW) {
-                    a0 += ld_coh(&I.part_g2[(size_t)t * M + j]);
-                    a1 += ld_coh(&I.part_g2[(size_t)(t + kNW) * M + j]);
-                }
-                if (t < I.n_groups) a0 += ld_coh(&I.part_g2[(size_t)t * M + j]);
+        for (int jb = 0; jb < M; jb += kRedCols * kWave) {
+            double acc[kRedCols];
+#pragma unroll
+            for (int c = 0; c < kRedCols; ++c) acc[c] = 0.0;
+            int t = wv;
+            for (; t + 3 * kNW < nt; t += 4 * kNW) {
+                double x[4][kRedCols];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < kRedCols; ++c) {
+                        const int j = jb + c * kWave + lane;
+                        x[r][c] = j < M ? I.part_g2[(size_t)(t + r * kNW) * M + j] : 0.0;
+                    }
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < kRedCols; ++c) acc[c] += x[r][c];
             }
-            colsum[wv * kWave + lane] = a0 + a1;
+            for (; t < nt; t += kNW)
+#pragma unroll
+                for (int c = 0; c < kRedCols; ++c) {
+                    const int j = jb + c * kWave + lane;
+                    acc[c] += j < M ? I.part_g2[(size_t)t * M + j] : 0.0;
+                }
+#pragma unroll
+            for (int c = 0; c < kRedCols; ++c) lds[(c * kNW + wv) * kWave + lane] = acc[c];
             __syncthreads();
-            if (wv == 0 && j < M) {
-                double a = 0.0;
-                for (int w = 0; w < kNW; ++w) a += colsum[w * kWave + lane];
-                const double g = a * inv;
-                if (!dry) st->g[j] = g;
-                amax = fmax(amax, fabs(g));
-                sq += g * g;
+            if (wv == 0) {
+#pragma unroll
+                for (int c = 0; c < kRedCols; ++c) {
+                    const int j = jb + c * kWave + lane;
+                    if (j < M) {
+                        double a = 0.0;
+                        for (int w = 0; w < kNW; ++w) a += lds[(c * kNW + w) * kWave + lane];
+                        const double g = a * inv;
+                        if (!dry) st->g[j] = g;
+                        amax = fmax(amax, fabs(g));
+                        sq += g * g;
+                    }
+                }
             }
             __syncthreads();
         }
@@ -824,9 +997,10 @@ __device__ double line_search_wave(const Landscape &L, double g) {
     return 0.5 * (lo + hi);
 }
 
-// H v, H w with shared class coefficients; partial Re<v|Hv>, Re<w|Hw>,
-// Re<v|Hw>; the last workgroup forms the landscape and picks the angle.
-// mode 1: ADAPT iteration; mode 0: the products and dots only (no angle).
+// H v, H w with shared class coefficients and the tile's partial Re<v|Hv>,
+// Re<w|Hw>, Re<v|Hw> (the angle is chosen from them by the Taylor launch
+// that follows).  mode 1: ADAPT iteration (instances already done are
+// skipped); mode 0: timing.
 template <typename T, int R>
 __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restrict__ insts,
                                                         const int2 *__restrict__ blk, int mode) {
@@ -879,86 +1053,104 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
         p5 = wave_sum(p5);
         p6 = wave_sum(p6);
         if (lane == 0) {
-            st_coh(&I.part_l[3 * b.y], p3);
-            st_coh(&I.part_l[3 * b.y + 1], p5);
-            st_coh(&I.part_l[3 * b.y + 2], p6);
+            I.part_l[3 * b.y] = p3;
+            I.part_l[3 * b.y + 1] = p5;
+            I.part_l[3 * b.y + 2] = p6;
         }
-    }
-    if (!arrive_last(&I.counters[2], I.n_tiles)) return;
-    // the five dot products, each summed in a fixed order (loads issued together)
-    constexpr int NT = kNW * kWave;
-    double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < I.n_tiles; i += NT) {
-        q[0] += ld_coh(&I.part_l[3 * i]);
-        q[1] += ld_coh(&I.part_l[3 * i + 1]);
-        q[2] += ld_coh(&I.part_l[3 * i + 2]);
-    }
-    for (int i = threadIdx.x; i < I.n_pblk; i += NT) {
-        q[3] += ld_coh(&I.part_l[3 * I.n_tiles + 2 * i]);
-        q[4] += ld_coh(&I.part_l[3 * I.n_tiles + 2 * i + 1]);
-    }
-    double *tr = reinterpret_cast<double *>(&S);               // [5][kNW] wave sums
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const double v = wave_sum(q[k]);
-        if (lane == 0) tr[k * kNW + wv] = v;
-    }
-    __syncthreads();
-    double P[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        P[k] = 0.0;
-        for (int w = 0; w < kNW; ++w) P[k] += tr[k * kNW + w];
-    }
-    const double P3 = P[0], P5 = P[1], P6 = P[2], P2 = P[3], P7 = P[4];
-    if (wv != 0 || mode == 0) return;
-    const double inv = 1.0 / st->nrm;
-    Landscape L;
-    L.uu = (st->e_num - 2.0 * P2 + P3) * inv;
-    L.uv = (P2 - P3) * inv;
-    L.uw = (P7 - P6) * inv;
-    L.vv = P3 * inv;
-    L.vw = P6 * inv;
-    L.ww = P5 * inv;
-    const int j = st->jsel;
-    const double th = line_search_wave(L, st->g[j]);
-    if (lane == 0) {
-        const int ns = th == 0.0 ? 0 : max(1, (int)ceil(fabs(th) * I.op_norm1[j] / 0.5));
-        // T5(h) = I + a A + b A^2 once A^3 = -A (and A^4 = -A^2); the product of
-        // two such factors stays in that span, so the whole chain is I + al A + be A^2
-        double al = 0.0, be = 0.0;
-        if (ns > 0) {
-            const double h = th / ns, h2 = h * h;
-            const double a = h * (1.0 - h2 / 6.0 * (1.0 - h2 / 20.0));   // h - h^3/6 + h^5/120
-            const double b = h2 * (0.5 - h2 / 24.0);                     // h^2/2 - h^4/24
-            for (int k = 0; k < ns; ++k) {
-                const double na = al + a - al * b - be * a;
-                const double nb = be + b + al * a - be * b;
-                al = na;
-                be = nb;
-            }
-        }
-        st->upd_alpha = al;
-        st->upd_beta = be;
-        st->upd_scale = 1.0 / sqrt(st->nrm);
-        st->theta = th;
-        st->nsub = ns;
-        st->pred = L.value(th);
-        const int it = st->iter;
-        if (st->hist_op) st->hist_op[it] = j;
-        if (st->hist_theta) st->hist_theta[it] = th;
-        if (st->hist_nsub) st->hist_nsub[it] = ns;
-        if (st->hist_pred) st->hist_pred[it] = st->pred;
     }
 }
 
 // ------------------------------------------------------------------ K3: O(5) Taylor update
 
+// The angle of an ADAPT iteration, computed by every workgroup of the Taylor
+// launch from the line-search partials (so no workgroup waits on another):
+// the five dot products, each summed in a fixed order, give the landscape, and
+// wave 0 searches it.  Returns theta and the substep count in every thread;
+// the workgroup of pair block 0 also writes the iteration record.
+__device__ void choose_angle(const InstDev &I, AdaptState *st, int j, bool writer, double &theta, int &ns) {
+    __shared__ double red[5][kPairBlock / kWave];
+    __shared__ double s_th;
+    __shared__ int s_ns;
+    const int lane = threadIdx.x & (kWave - 1), wv = wave_id();
+    double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < I.n_tiles; i += kPairBlock) {
+        q[0] += I.part_l[3 * i];
+        q[1] += I.part_l[3 * i + 1];
+        q[2] += I.part_l[3 * i + 2];
+    }
+    for (int i = threadIdx.x; i < I.n_pblk; i += kPairBlock) {
+        q[3] += I.part_l[3 * I.n_tiles + 2 * i];
+        q[4] += I.part_l[3 * I.n_tiles + 2 * i + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const double v = wave_sum(q[k]);
+        if (lane == 0) red[k][wv] = v;
+    }
+    __syncthreads();
+    if (wv == 0) {
+        double P[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            P[k] = 0.0;
+            for (int w = 0; w < kPairBlock / kWave; ++w) P[k] += red[k][w];
+        }
+        const double P3 = P[0], P5 = P[1], P6 = P[2], P2 = P[3], P7 = P[4];
+        const double nrm = cptr(&st->nrm)[0], e_num = cptr(&st->e_num)[0];
+        const double inv = 1.0 / nrm;
+        Landscape L;
+        L.uu = (e_num - 2.0 * P2 + P3) * inv;
+        L.uv = (P2 - P3) * inv;
+        L.uw = (P7 - P6) * inv;
+        L.vv = P3 * inv;
+        L.vw = P6 * inv;
+        L.ww = P5 * inv;
+        const double th = line_search_wave(L, st->g[j]);
+        if (lane == 0) {
+            const int n = th == 0.0 ? 0 : max(1, (int)ceil(fabs(th) * I.op_norm1[j] / 0.5));
+            s_th = th;
+            s_ns = n;
+            if (writer) {
+                // T5(h) = I + a A + b A^2 once A^3 = -A (and A^4 = -A^2); the product
+                // of two such factors stays in that span, so the whole chain is
+                // I + al A + be A^2
+                double al = 0.0, be = 0.0;
+                if (n > 0) {
+                    const double h = th / n, h2 = h * h;
+                    const double a = h * (1.0 - h2 / 6.0 * (1.0 - h2 / 20.0));   // h - h^3/6 + h^5/120
+                    const double b = h2 * (0.5 - h2 / 24.0);                     // h^2/2 - h^4/24
+                    for (int k = 0; k < n; ++k) {
+                        const double na = al + a - al * b - be * a;
+                        const double nb = be + b + al * a - be * b;
+                        al = na;
+                        be = nb;
+                    }
+                }
+                st->upd_alpha = al;
+                st->upd_beta = be;
+                st->upd_scale = 1.0 / sqrt(nrm);
+                st->theta = th;
+                st->nsub = n;
+                st->pred = L.value(th);
+                const int it = st->iter;
+                if (st->hist_op) st->hist_op[it] = j;
+                if (st->hist_theta) st->hist_theta[it] = th;
+                if (st->hist_nsub) st->hist_nsub[it] = n;
+                if (st->hist_pred) st->hist_pred[it] = st->pred;
+            }
+        }
+    }
+    __syncthreads();
+    theta = s_th;
+    ns = s_ns;
+}
+
 // psi <- T5(theta/s)^s (scale * psi) on the pairs of generator j.  In an ADAPT
-// iteration (adapt != 0) j, theta, s come from the device state and scale is
-// 1/sqrt(<psi|psi>) of the stored state (the renormalisation of the previous
-// update, applied here); one-shot calls pass them as arguments.  Writes the
-// per-workgroup |psi|^2 of the result to part_t.
+// iteration (adapt != 0) j comes from the device state, theta and s from the
+// line search done here, and scale is 1/sqrt(<psi|psi>) of the stored state
+// (the renormalisation of the previous update, applied here); one-shot calls
+// pass them as arguments.  Writes the per-workgroup |psi|^2 of the result to
+// part_t.
 template <typename T>
 __global__ __launch_bounds__(kPairBlock) void k_taylor5(const InstDev *__restrict__ insts,
                                                        const int2 *__restrict__ blk, int adapt,
@@ -968,8 +1160,9 @@ __global__ __launch_bounds__(kPairBlock) void k_taylor5(const InstDev *__restric
     AdaptState *st = I.st;
     if (adapt && state_done(st)) return;
     const int j = adapt ? cptr(&st->jsel)[0] : j_arg;
-    const double theta = adapt ? cptr(&st->theta)[0] : theta_arg;
-    const int ns = adapt ? cptr(&st->nsub)[0] : s_arg;
+    double theta = theta_arg;
+    int ns = s_arg;
+    if (adapt) choose_angle(I, st, j, b.y == 0, theta, ns);
     const double scale = adapt ? 1.0 / sqrt(cptr(&st->nrm)[0]) : 1.0;
     const HClass C = load_rec(cptr(I.pop), j);
     const uint32_t m = C.x;
@@ -1092,6 +1285,8 @@ static void launch_all(int which, int R, const InstDev *insts, const int2 *blk, 
         else launch_tile<T, 1>(w, insts, blk, nblk, mode, s);
         break;
     }
+    case 1: hipLaunchKernelGGL(k_screen_reduce, dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode); break;
+    case 7: hipLaunchKernelGGL(k_screen_sum1, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode); break;
     case 2: hipLaunchKernelGGL(k_line_vw<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk); break;
     case 4: hipLaunchKernelGGL(k_taylor5<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode, j, th, ns); break;
     case 5: hipLaunchKernelGGL(k_normalize<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode); break;

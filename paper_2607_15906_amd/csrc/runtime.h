@@ -21,8 +21,8 @@ struct gocp_ctx {
 namespace gocp {
 
 enum {
-    K_ENERGY_SCREEN = 0, K_LINE_VW = 2, K_LINE_HVW = 3, K_TAYLOR = 4, K_NORMALIZE = 5,
-    K_UNIT_NORM = 6
+    K_ENERGY_SCREEN = 0, K_SCREEN_REDUCE = 1, K_LINE_VW = 2, K_LINE_HVW = 3, K_TAYLOR = 4,
+    K_NORMALIZE = 5, K_UNIT_NORM = 6, K_SCREEN_SUM1 = 7
 };
 
 // R = amplitudes per lane of the tile kernels (1, 2 or 4); the pair kernels ignore it.
@@ -37,7 +37,7 @@ struct InstPlan {
     int n_tiles = 0, n_pblk = 0;
     int n_groups = 0;
     size_t n_counters = 0;
-    size_t o_sigma = 0, o_v = 0, o_w = 0, o_pe = 0, o_pn = 0, o_pg = 0, o_pg2 = 0, o_pl = 0, o_pt = 0,
+    size_t o_sigma = 0, o_v = 0, o_w = 0, o_pe = 0, o_pn = 0, o_pg = 0, o_pg2 = 0, o_pe2 = 0, o_pn2 = 0, o_pl = 0, o_pt = 0,
            o_cnt = 0, o_st = 0, o_he = 0, o_hop = 0, o_hth = 0, o_hgn = 0, o_hgm = 0, o_hns = 0,
            o_hpr = 0, o_g = 0, o_psi = 0, o_hv = 0, o_hw = 0;
     size_t bytes = 0;

@@ -35,8 +35,9 @@ HTerm make_term(double c, uint32_t z) { return HTerm{std::fabs(c), z, std::signb
 
 uint32_t sub_key(uint32_t z) { return ((z >> 6) & 1u) << 2 | ((z >> 7) & 1u) << 1 | ((z >> 8) & 1u); }
 
-// Append the strings [a, b) of (c, z) in sub-bucket order to `out` and return
-// the sub-bucket record of the group.
+// Append the strings [a, b) of (c, z) in sub-bucket order to `out`, then zero
+// strings up to a whole number of groups of kStrGroup, and return the
+// sub-bucket record of the group (the padding sits after the last sub-bucket).
 HSub bucket_strings(const std::vector<double> &c, const std::vector<uint32_t> &z, int a, int b,
                     std::vector<HTerm> &out) {
     std::vector<int> idx;
@@ -49,7 +50,9 @@ HSub bucket_strings(const std::vector<double> &c, const std::vector<uint32_t> &z
         off[key] = (uint16_t)k;
         while (k < (int)idx.size() && (int)sub_key(z[idx[k]]) == key) ++k;
     }
+    const size_t start = out.size();
     for (int s : idx) out.push_back(make_term(c[s], z[s]));
+    while ((out.size() - start) % kStrGroup) out.push_back(HTerm{0.0, 0u, 0u});
     HSub r;
     for (int i = 0; i < 4; ++i) r.w[i] = (uint32_t)off[2 * i] | ((uint32_t)off[2 * i + 1] << 16);
     return r;
@@ -73,6 +76,51 @@ std::vector<int32_t> stage_chunks(const std::vector<int32_t> &off) {
     return b;
 }
 
+// Estimated VALU instructions of one class or operator in a tile kernel: a
+// fixed cost per record (gather, conversion, multiply-add; for the screen also
+// the wave reduction) plus four per string of its padded group.
+int record_cost(int n_strings, int fixed) {
+    return fixed + 4 * ((n_strings + kStrGroup - 1) / kStrGroup * kStrGroup);
+}
+
+// Order the records [b, e) of one LDS stage chunk for the kNW waves of a tile
+// block: each record, most expensive first (ties by position), goes to the
+// wave with the least work so far (lowest wave on ties); every wave keeps its
+// records in their original relative order.  Appends the records to `order`
+// and the kNW + 1 wave boundaries (positions in `order`) to `seg`.
+void wave_split(const std::vector<int> &cost, int b, int e, std::vector<int32_t> &order,
+                std::vector<int32_t> &seg) {
+    std::vector<int> idx;
+    for (int i = b; i < e; ++i) idx.push_back(i);
+    std::stable_sort(idx.begin(), idx.end(), [&](int u, int v) { return cost[u] > cost[v]; });
+    std::vector<std::vector<int>> lists(kNW);
+    std::vector<long long> load(kNW, 0);
+    for (int i : idx) {
+        int w = 0;
+        for (int k = 1; k < kNW; ++k)
+            if (load[k] < load[w]) w = k;
+        lists[w].push_back(i);
+        load[w] += cost[i];
+    }
+    for (int w = 0; w < kNW; ++w) {
+        std::sort(lists[w].begin(), lists[w].end());
+        seg.push_back((int32_t)order.size());
+        for (int i : lists[w]) order.push_back(i);
+    }
+    seg.push_back((int32_t)order.size());
+}
+
+// Padded string offsets of records taken in the order `rec` with `count(r)` strings.
+template <typename F>
+std::vector<int32_t> padded_offsets(int n, F count) {
+    std::vector<int32_t> off{0};
+    for (int r = 0; r < n; ++r) {
+        const int c = count(r);
+        off.push_back(off.back() + (c + kStrGroup - 1) / kStrGroup * kStrGroup);
+    }
+    return off;
+}
+
 }  // namespace
 
 void release_device_ham(DeviceHam *d) {
@@ -81,6 +129,7 @@ void release_device_ham(DeviceHam *d) {
     (void)hipFree(d->hterm);
     (void)hipFree(d->hsub);
     (void)hipFree(d->hchunk);
+    (void)hipFree(d->hseg);
     delete d;
 }
 
@@ -93,6 +142,7 @@ void release_device_pool(DevicePool *d) {
     (void)hipFree(d->sterm);
     (void)hipFree(d->psub);
     (void)hipFree(d->pchunk);
+    (void)hipFree(d->pseg);
     delete d;
 }
 
@@ -102,18 +152,29 @@ const DeviceHam *device_ham(const Ham &h, int dev) {
     if (h.dev[dev]) return h.dev[dev];
     std::unique_ptr<DeviceHam> d(new DeviceHam());
     d->device = dev;
-    std::vector<HClass> cls(h.n_classes());
-    std::vector<HSub> sub(h.n_classes());
+    // LDS stage chunks over the classes, then within each chunk the classes
+    // re-laid out wave by wave (a chunk keeps the same classes, so its string
+    // total and boundaries are unchanged)
+    const int nc = h.n_classes();
+    auto count = [&](int c) { return h.cls_off[c + 1] - h.cls_off[c]; };
+    const std::vector<int32_t> ch = stage_chunks(padded_offsets(nc, count));
+    std::vector<int> cost(nc);
+    for (int c = 0; c < nc; ++c) cost[c] = record_cost(count(c), kClassCost);
+    std::vector<int32_t> order, seg;
+    for (size_t k = 0; k + 1 < ch.size(); ++k) wave_split(cost, ch[k], ch[k + 1], order, seg);
+    std::vector<HClass> cls;
+    std::vector<HSub> sub;
     std::vector<HTerm> terms;
-    for (int c = 0; c < h.n_classes(); ++c) {
-        cls[c] = HClass{h.cls_x[c], h.cls_off[c], h.cls_off[c + 1], 0};
-        sub[c] = bucket_strings(h.str_c, h.str_z, h.cls_off[c], h.cls_off[c + 1], terms);
+    for (int32_t c : order) {
+        const int32_t s0 = (int32_t)terms.size();
+        sub.push_back(bucket_strings(h.str_c, h.str_z, h.cls_off[c], h.cls_off[c + 1], terms));
+        cls.push_back(HClass{h.cls_x[c], s0, (int32_t)terms.size(), 0});
     }
     d->hcls = dev_upload(cls);
     d->hterm = dev_upload(terms);
     d->hsub = dev_upload(sub);
-    const std::vector<int32_t> ch = stage_chunks(h.cls_off);
     d->hchunk = dev_upload(ch);
+    d->hseg = dev_upload(seg);
     d->n_chunks = (int)ch.size() - 1;
     h.dev[dev] = d.release();
     return h.dev[dev];
@@ -135,22 +196,30 @@ const DevicePool *device_pool(const Pool &p, int dev) {
     // gradient screen schedule: operators and their strings re-laid out in
     // GOCP family order (families in creation order, members in assignment
     // order); each record keeps its pool index
+    // (within each LDS stage chunk, re-laid out wave by wave as for H, every
+    // wave keeping family order)
+    const int m = p.n_ops();
+    auto count = [&](int r) { const int j = p.fam_members[r]; return p.op_off[j + 1] - p.op_off[j]; };
+    const std::vector<int32_t> pch = stage_chunks(padded_offsets(m, count));
+    std::vector<int> cost(m);
+    for (int r = 0; r < m; ++r) cost[r] = record_cost(count(r), kOpCost);
+    std::vector<int32_t> order, seg;
+    for (size_t k = 0; k + 1 < pch.size(); ++k) wave_split(cost, pch[k], pch[k + 1], order, seg);
     std::vector<HClass> sop;
     std::vector<HSub> psub;
     std::vector<HTerm> sterm;
-    std::vector<int32_t> soff{0};
-    for (int32_t j : p.fam_members) {
-        HClass r{p.op_x[j], (int32_t)sterm.size(), 0, j};
+    for (int32_t r : order) {
+        const int32_t j = p.fam_members[r];
+        HClass rec{p.op_x[j], (int32_t)sterm.size(), 0, j};
         psub.push_back(bucket_strings(p.str_c, p.str_z, p.op_off[j], p.op_off[j + 1], sterm));
-        r.s1 = (int32_t)sterm.size();
-        sop.push_back(r);
-        soff.push_back(r.s1);
+        rec.s1 = (int32_t)sterm.size();
+        sop.push_back(rec);
     }
-    const std::vector<int32_t> pch = stage_chunks(soff);
     d->sop = dev_upload(sop);
     d->sterm = dev_upload(sterm);
     d->psub = dev_upload(psub);
     d->pchunk = dev_upload(pch);
+    d->pseg = dev_upload(seg);
     d->n_chunks = (int)pch.size() - 1;
     p.dev[dev] = d.release();
     return p.dev[dev];
@@ -189,7 +258,9 @@ InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi, boo
     ip.o_pg = a.take((size_t)ip.n_tiles * std::max(M, 1) * 8);
     ip.n_groups = (ip.n_tiles + kGroup - 1) / kGroup;
     ip.o_pg2 = a.take((size_t)ip.n_groups * std::max(M, 1) * 8);
-    ip.n_counters = 4 + (size_t)ip.n_groups;
+    ip.o_pe2 = a.take((size_t)ip.n_groups * 8);
+    ip.o_pn2 = a.take((size_t)ip.n_groups * 8);
+    ip.n_counters = 4;
     ip.o_pl = a.take((3 * (size_t)ip.n_tiles + 2 * (size_t)ip.n_pblk) * 8);
     ip.o_pt = a.take((size_t)ip.n_pblk * 8);
     ip.o_cnt = a.take(ip.n_counters * sizeof(int32_t));
@@ -221,6 +292,7 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
         I.hterm = dh->hterm;
         I.hsub = dh->hsub;
         I.hchunk = dh->hchunk;
+        I.hseg = dh->hseg;
         I.n_hchunks = dh->n_chunks;
     }
     if (p) {
@@ -232,6 +304,7 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
         I.sterm = dp->sterm;
         I.psub = dp->psub;
         I.pchunk = dp->pchunk;
+        I.pseg = dp->pseg;
         I.n_pchunks = dp->n_chunks;
     }
     I.psi = psi;
@@ -244,6 +317,8 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
     I.part_n = reinterpret_cast<double *>(b + ip.o_pn);
     I.part_g = reinterpret_cast<double *>(b + ip.o_pg);
     I.part_g2 = reinterpret_cast<double *>(b + ip.o_pg2);
+    I.part_e2 = reinterpret_cast<double *>(b + ip.o_pe2);
+    I.part_n2 = reinterpret_cast<double *>(b + ip.o_pn2);
     I.n_groups = ip.n_groups;
     I.part_l = reinterpret_cast<double *>(b + ip.o_pl);
     I.part_t = reinterpret_cast<double *>(b + ip.o_pt);
@@ -316,7 +391,7 @@ OneShot one_shot(gocp_ctx *ctx, const Ham *h, const Pool *p, const void *psi, in
     Bump a;
     a.used = o.ip.bytes;
     std::vector<int2> bt, bp;
-    for (int t = 0; t < o.ip.n_tiles; ++t) bt.push_back(make_int2(0, t));
+    for (int t = 0; t < o.ip.n_tiles; ++t) bt.push_back(make_int2(0, t));   // rows (0, g) double as group rows
     for (int t = 0; t < o.ip.n_pblk; ++t) bp.push_back(make_int2(0, t));
     o.o_desc = a.take(sizeof(InstDev));
     o.o_btile = a.take(bt.size() * sizeof(int2));
@@ -435,6 +510,8 @@ int energy(gocp_ctx *ctx, const gocp_ham *hh, const void *psi_dev, int dtype, do
     if (!e_out) throw Error(GOCP_EINVAL, "null output");
     OneShot o = one_shot(ctx, as_ham(hh), nullptr, psi_dev, dtype);
     launch_kernel(K_ENERGY_SCREEN, dtype, 1, o.desc, o.btile, o.nt, 0, ctx->user_stream);
+    launch_kernel(K_SCREEN_SUM1, dtype, 1, o.desc, o.btile, o.ip.n_groups, 0, ctx->user_stream);
+    launch_kernel(K_SCREEN_REDUCE, dtype, 1, o.desc, o.btile, 1, 0, ctx->user_stream);
     const AdaptState st = read_state(ctx, o);
     if (st.status) throw Error(st.status, "non-finite energy or zero norm");
     *e_out = st.energy;
@@ -449,6 +526,8 @@ int gocp_apply_hamiltonian(gocp_ctx *ctx, const gocp_ham *hh, const void *psi_de
     if (!sigma_dev) throw Error(GOCP_EINVAL, "null sigma pointer");
     OneShot o = one_shot(ctx, as_ham(hh), nullptr, psi_dev, dtype, static_cast<double2 *>(sigma_dev));
     launch_kernel(K_ENERGY_SCREEN, dtype, 1, o.desc, o.btile, o.nt, 0, ctx->user_stream);
+    launch_kernel(K_SCREEN_SUM1, dtype, 1, o.desc, o.btile, o.ip.n_groups, 0, ctx->user_stream);
+    launch_kernel(K_SCREEN_REDUCE, dtype, 1, o.desc, o.btile, 1, 0, ctx->user_stream);
     if (e_out) {
         const AdaptState st = read_state(ctx, o);
         if (st.status) throw Error(st.status, "non-finite energy or zero norm");
@@ -467,6 +546,8 @@ int pool_gradients(gocp_ctx *ctx, const gocp_ham *hh, const gocp_pool *pp, const
     const Pool *p = as_pool(pp);
     OneShot o = one_shot(ctx, h, p, psi_dev, dtype);
     launch_kernel(K_ENERGY_SCREEN, dtype, 1, o.desc, o.btile, o.nt, 0, ctx->user_stream);
+    launch_kernel(K_SCREEN_SUM1, dtype, 1, o.desc, o.btile, o.ip.n_groups, 0, ctx->user_stream);
+    launch_kernel(K_SCREEN_REDUCE, dtype, 1, o.desc, o.btile, 1, 0, ctx->user_stream);
     const size_t gbytes = (size_t)p->n_ops() * sizeof(double);
     if (g_on_device) {
         hip_check(hipMemcpyAsync(g_out, o.base + o.ip.o_g, gbytes, hipMemcpyDeviceToDevice,

@@ -49,10 +49,17 @@ struct Request {
     std::vector<int32_t> ops, substeps;
 };
 
+// Device tables of a request (an upper bound: staged tables carry up to
+// kStrGroup - 1 zero strings per class or operator).
 size_t table_bytes(const Ham *h, const Pool *p) {
-    return (size_t)h->n_terms() * sizeof(HTerm) + (size_t)h->n_classes() * sizeof(HClass) +
-           2 * ((size_t)p->str_z.size() * sizeof(HTerm) + (size_t)p->n_ops() * sizeof(HClass)) +
-           (size_t)p->n_ops() * sizeof(double);
+    const size_t nc = (size_t)h->n_classes(), m = (size_t)p->n_ops(), ps = p->str_z.size();
+    const size_t ham = ((size_t)h->n_terms() + (kStrGroup - 1) * nc) * sizeof(HTerm) +
+                       nc * (sizeof(HClass) + sizeof(HSub)) + (nc + 1) * sizeof(int32_t);
+    const size_t pool = ps * sizeof(HTerm) + m * sizeof(HClass) +                       // pair tables
+                        (ps + (kStrGroup - 1) * m) * sizeof(HTerm) +                      // screen tables
+                        m * (sizeof(HClass) + sizeof(HSub)) + (m + 1) * sizeof(int32_t) +
+                        m * sizeof(double);
+    return ham + pool;
 }
 
 }  // namespace
