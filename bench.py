@@ -27,9 +27,14 @@ if ROOT not in sys.path:
 
 METRIC = "ADAPT iters/s + Pauli-term amp-updates/s at 14q; p50/p99 solve latency"
 FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector peak (FMA = 2 flops)
-# iterations between fresh H psi applications: complex64 states apply H afresh
-# every iteration, complex128 states carry sigma in between
-REFRESH = {"complex64": 1, "complex128": 32}
+# HBM bytes per launch of the dominant kernel (FETCH_SIZE and WRITE_SIZE,
+# scaled by a 256 MiB copy), from the rocprofv3 counter runs summarised under
+# profiles/; keyed by (kernel, amplitudes per lane).  An entry is removed when
+# the kernel changes, until the counters are taken again.
+TRAFFIC_BYTES = {("k_energy_screen", 1): 2679555}
+# the dominant kernel is bracketed by HIP events in every 8th timed iteration
+# (events around every launch would slow the loop by several per cent)
+LIVE_SAMPLE_EVERY = 8
 
 
 def _say(msg):
@@ -61,19 +66,30 @@ def _amp_updates(nq, T, S, off, ops, subs):
     return tot * (1 << nq)
 
 
-def run_adapt_timed(g, ctx, H, P, nq, ne, mapping, dtype, steps, warmup, schedule=0):
+def run_adapt_timed(g, ctx, H, P, nq, ne, mapping, dtype, steps, warmup, schedule=0, timed_kernel=None):
+    """Warm-up iterations (graph replays), then the timed iterations.  With
+    timed_kernel (an index of Batch.STEP_KERNELS) the timed iterations are
+    launched directly with HIP events around every launch of that kernel, and
+    its mean duration over the timed region is returned as well."""
     import torch
     psi = _hf_state(g, ctx, nq, ne, mapping, dtype)
     b = g.Batch(ctx, [H], [P], [psi], max_iter=warmup + steps, use_graph=True, schedule=schedule)
+    pre = {w: b.time_kernel(w, 20) for w in (0, 1)}   # dry launches: which tile kernel dominates
     b.step(warmup)
     torch.cuda.synchronize()
+    kernel_ms = None
     t0 = time.perf_counter()
-    b.step(steps)
+    if timed_kernel is None:
+        b.step(steps)
+    else:
+        k = timed_kernel(pre) if callable(timed_kernel) else timed_kernel
+        _, kernel_ms = b.step_timed(steps, k, LIVE_SAMPLE_EVERY)
+        kernel_ms = (k, kernel_ms)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     r = b.result(0)
     r["psi"] = psi
-    return b, r, dt
+    return b, r, dt, kernel_ms
 
 
 def serving_bench(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, load=0.7, amps_per_lane=1):
@@ -207,8 +223,12 @@ def main():
     T, C, S, M = H.n_terms, H.n_classes, P.n_strings, P.n_ops
 
     _say(f"[bench] 14q c64: {args.warmup} warmup + {args.steps} timed ADAPT iterations")
-    b, r, dt = run_adapt_timed(g, ctx, H, P, nq, ne, mapping, torch.complex64, args.steps, args.warmup,
-                               schedule=args.schedule)
+    # the dominant tile kernel (k_energy_screen: STEP_KERNELS[3], or k_line_hvw:
+    # [1]) from dry timing-hook launches; its live duration over the timed
+    # region then feeds the roofline
+    b, r, dt, live = run_adapt_timed(g, ctx, H, P, nq, ne, mapping, torch.complex64, args.steps,
+                                     args.warmup, schedule=args.schedule,
+                                     timed_kernel=lambda pre: 3 if pre[0] >= pre[1] else 1)
     sched = b.schedule
     w0, w1 = args.warmup, args.warmup + args.steps
     iters = r["n_iter"]
@@ -217,33 +237,26 @@ def main():
     ips = args.steps / dt
     upd = _amp_updates(nq, T, S, off, r["ops"][w0:w1], r["substeps"][w0:w1])
 
-    # dominant kernel: HIP-event timing of the tile kernels on the stream they
-    # run on (0: energy + screen with a fresh H psi, once every REFRESH
-    # iterations; 2: energy + screen with sigma carried through the update,
-    # the other iterations; 1: the line search's H v and H w, every iteration)
-    nl = 50
-    rf = REFRESH["complex64"]
-    share = {0: 1.0 / rf, 1: 1.0, 2: 1.0 - 1.0 / rf, 3: 1.0}
-    ms = {which: b.time_kernel(which, nl) for which in (0, 1, 2, 3) if share[which] > 0}
+    # roofline of the dominant kernel: algorithmic FP64 flops per launch (one
+    # signed add per (string, amplitude), a real-by-complex multiply-add (4
+    # flops) per (class or operator, amplitude), and the dot products) over its
+    # mean launch duration, measured live with HIP events over the timed region
     dim = 1 << nq
-    # algorithmic FP64 flops per launch: one signed add per (string, amplitude),
-    # a real-by-complex multiply-add (4 flops) per (class or operator, amplitude)
-    # and the dot products; carrying sigma costs 8 flops per amplitude
-    flops = {0: dim * (T + 4 * C + 4) + dim * (S + 4 * M),   # H psi + energy + screen
-             1: dim * (T + 8 * C + 12),                      # H v and H w + three dots
-             2: dim * (8 + 4) + dim * (S + 4 * M),           # carried sigma + energy + screen
-             3: (dim // 64) * (M + 2)}                       # sums of the tile partials
-    names = {0: "k_energy_screen (fresh H psi)", 1: "k_line_hvw", 2: "k_energy_screen (carried sigma)",
-             3: "k_screen_reduce"}
-    dom = max(ms, key=lambda k: ms[k] * share[k])
-    achieved = flops[dom] / (ms[dom] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": names[dom], "achieved": round(achieved, 4),
+    flops = {3: dim * (T + 4 * C + 4) + dim * (S + 4 * M),   # H psi + energy + screen partials
+             1: dim * (T + 8 * C + 12)}                      # H v and H w + three dots
+    dom, kms = live
+    name = g.Batch.STEP_KERNELS[dom]
+    achieved = flops[dom] / (kms * 1e-3) / 1e12
+    traffic = TRAFFIC_BYTES.get((name, sched))
+    hook = {"k_energy_screen (fresh H psi)": b.time_kernel(0, 50), "k_line_hvw": b.time_kernel(1, 50),
+            "k_screen_sum1 + k_screen_reduce": b.time_kernel(3, 50)}
+    roofline = {"bound": "alu", "kernel": name, "achieved": round(achieved, 4),
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": None,
-                "avg_launch_us": round(ms[dom] * 1e3, 3),
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": traffic,
+                "avg_launch_us": round(kms * 1e3, 3),
+                "launches_sampled": (args.steps + LIVE_SAMPLE_EVERY - 1) // LIVE_SAMPLE_EVERY,
                 "algorithmic_flops_per_launch": int(flops[dom]),
-                "kernel_avg_us": {names[k]: round(v * 1e3, 3) for k, v in ms.items()},
-                "launches_per_iteration": {names[k]: share[k] for k in ms}}
+                "dry_launch_avg_us": {k: round(v * 1e3, 3) for k, v in hook.items()}}
     b.close()
 
     out = {
@@ -263,8 +276,8 @@ def main():
 
     if not args.no_forms:
         _say("[bench] 14q c128 path")
-        b2, r2, dt2 = run_adapt_timed(g, ctx, H, P, nq, ne, mapping, torch.complex128,
-                                      args.steps, args.warmup, schedule=sched)
+        b2, r2, dt2, _ = run_adapt_timed(g, ctx, H, P, nq, ne, mapping, torch.complex128,
+                                         args.steps, args.warmup, schedule=sched)
         b2.close()
         u2 = _amp_updates(nq, T, S, off, r2["ops"][w0:w1], r2["substeps"][w0:w1])
         same_ops = r2["ops"] == r["ops"]

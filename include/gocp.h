@@ -261,6 +261,18 @@ int gocp_batch_create(gocp_ctx *ctx, int32_t n, const gocp_ham *const *hams,
 /* Enqueue n_iter iterations for every instance (asynchronous).  Instances that
  * converged or reached max_iter skip their work. */
 int gocp_batch_step(gocp_batch *b, int32_t n_iter);
+/*
+ * Measurement form of gocp_batch_step: n_iter iterations launched directly
+ * (no graph) on the context stream, with HIP events recorded around the
+ * launch of one kernel of the iteration (kernel: 0 line-search vectors, 1 H v
+ * / H w, 2 Taylor update, 3 energy and screen partials, 4 and 5 the two
+ * reduction stages) in iterations 0, every, 2 every, ...  Waits for the work;
+ * returns the elapsed time of all n_iter iterations and the mean duration of
+ * the sampled launches (ms).  The iterations are the same as
+ * gocp_batch_step's.  Errors: EINVAL.
+ */
+int gocp_batch_step_timed(gocp_batch *b, int32_t n_iter, int32_t kernel, int32_t every,
+                          double *total_ms, double *kernel_ms);
 /* Run the remaining iterations, stopping early once every instance is done. */
 int gocp_batch_run(gocp_batch *b);
 /* Synchronise and count the instances still running. */

@@ -74,6 +74,7 @@ SIGNATURES = {
     "gocp_batch_create": [_P, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                           C.POINTER(C.c_void_p), C.c_int, C.POINTER(AdaptParams), _PP],
     "gocp_batch_step": [_P, C.c_int32],
+    "gocp_batch_step_timed": [_P, C.c_int32, C.c_int32, C.c_int32, _F64P, _F64P],
     "gocp_batch_run": [_P],
     "gocp_batch_poll": [_P, _I32P],
     "gocp_batch_result": [_P, C.c_int32, C.POINTER(AdaptResult)],

@@ -323,6 +323,18 @@ class Batch:
     def step(self, n_iter: int):
         check(load().gocp_batch_step(self._b, int(n_iter)))
 
+    STEP_KERNELS = ("k_line_vw", "k_line_hvw", "k_taylor5", "k_energy_screen", "k_screen_sum1",
+                    "k_screen_reduce")
+
+    def step_timed(self, n_iter: int, kernel: int, every: int = 1):
+        """n_iter iterations with HIP events around the launch of one of
+        STEP_KERNELS in every `every`-th iteration; returns (total ms, mean ms
+        of the sampled launches)."""
+        tot, k = C.c_double(), C.c_double()
+        check(load().gocp_batch_step_timed(self._b, int(n_iter), int(kernel), int(every), C.byref(tot),
+                                           C.byref(k)))
+        return tot.value, k.value
+
     def run(self):
         check(load().gocp_batch_run(self._b))
 

@@ -168,15 +168,25 @@ struct Group {
     // line-search vectors, H v / H w and the angle, Taylor update, then the
     // new state's energy and screen partials, and their reduction with the
     // selection.
-    void enqueue_iteration(hipStream_t s) const {
+    // With `timed` set, HIP events ev[0] and ev[1] are recorded on s right
+    // before and after the launch of kernel id `timed_kid`.
+    void enqueue_iteration(hipStream_t s, int timed_kid = -1, const hipEvent_t *ev = nullptr) const {
         if (inst.empty()) return;
         const int n = (int)inst.size();
-        launch_kernel(K_LINE_VW, dtype, R, desc, bpair, np, 1, s);
-        launch_kernel(K_LINE_HVW, dtype, R, desc, btile, nt, 1, s);
-        launch_kernel(K_TAYLOR, dtype, R, desc, bpair, np, 1, s);
-        launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 2, s);
-        launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 2, s);
-        launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, n, 2, s);
+        struct L {
+            int kid, mode;
+            const int2 *rows;
+            int nrows;
+        };
+        const L seq[6] = {{K_LINE_VW, 1, bpair, np},       {K_LINE_HVW, 1, btile, nt},
+                          {K_TAYLOR, 1, bpair, np},        {K_ENERGY_SCREEN, 2, btile, nt},
+                          {K_SCREEN_SUM1, 2, bgrp, ng},    {K_SCREEN_REDUCE, 2, binst, n}};
+        for (const L &l : seq) {
+            const bool t = ev && l.kid == timed_kid;
+            if (t) hip_check(hipEventRecord(ev[0], s), "hipEventRecord");
+            launch_kernel(l.kid, dtype, R, desc, l.rows, l.nrows, l.mode, s);
+            if (t) hip_check(hipEventRecord(ev[1], s), "hipEventRecord");
+        }
     }
 
     void capture() {

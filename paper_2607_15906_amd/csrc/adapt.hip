@@ -51,12 +51,16 @@ void Group::choose_schedule(int schedule, hipStream_t s) {
     for (Instance *in : inst) q.push_back(in->ip.n_qubits);
     int best = autotune_cached(q, dtype);
     if (best == 0) {
+        // each candidate: one warm-up pass, then the fastest of three timed
+        // passes; a larger blocking must beat the best so far by 2 %
         double best_ms = 0.0;
         for (int cand : {1, 2, 4}) {
             R = cand;
             rebuild(s);
-            const double ms = time_tile_kernels(s, 3);
-            if (best == 0 || ms < best_ms) {
+            (void)time_tile_kernels(s, 1);
+            double ms = time_tile_kernels(s, 5);
+            for (int trial = 1; trial < 3; ++trial) ms = std::min(ms, time_tile_kernels(s, 5));
+            if (best == 0 || ms < 0.98 * best_ms) {
                 best = cand;
                 best_ms = ms;
             }
@@ -214,6 +218,47 @@ int gocp_batch_step(gocp_batch *b, int32_t n_iter) {
     if (n_iter < 0) throw Error(GOCP_EINVAL, "negative iteration count");
     b->group.step(n_iter, b->group.ctx->user_stream, b->use_graph);
     b->issued += n_iter;
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
+int gocp_batch_step_timed(gocp_batch *b, int32_t n_iter, int32_t kernel, int32_t every,
+                          double *total_ms, double *kernel_ms) {
+    GOCP_GUARD_BEGIN
+    if (!b || !total_ms || !kernel_ms) throw Error(GOCP_EINVAL, "null argument");
+    check_ctx(b->group.ctx);
+    if (n_iter <= 0 || every <= 0) throw Error(GOCP_EINVAL, "need at least one iteration and every >= 1");
+    static const int kids[6] = {K_LINE_VW, K_LINE_HVW, K_TAYLOR, K_ENERGY_SCREEN, K_SCREEN_SUM1,
+                                K_SCREEN_REDUCE};
+    if (kernel < 0 || kernel > 5) throw Error(GOCP_EINVAL, "kernel must be 0..5");
+    hipStream_t s = b->group.ctx->user_stream;
+    std::vector<hipEvent_t> ev(2 * (size_t)n_iter + 2);
+    for (hipEvent_t &e : ev) hip_check(hipEventCreate(&e), "hipEventCreate");
+    hip_check(hipEventRecord(ev[2 * n_iter], s), "hipEventRecord");
+    int sampled = 0;
+    for (int i = 0; i < n_iter; ++i) {
+        for (Instance *in : b->group.inst) in->finalized = false;
+        if (i % every == 0) {
+            b->group.enqueue_iteration(s, kids[kernel], &ev[2 * sampled]);
+            ++sampled;
+        } else {
+            b->group.enqueue_iteration(s);
+        }
+    }
+    hip_check(hipEventRecord(ev[2 * n_iter + 1], s), "hipEventRecord");
+    hip_check(hipEventSynchronize(ev[2 * n_iter + 1]), "hipEventSynchronize");
+    double k = 0.0;
+    for (int i = 0; i < sampled; ++i) {
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]), "hipEventElapsedTime");
+        k += ms;
+    }
+    float tot = 0.f;
+    hip_check(hipEventElapsedTime(&tot, ev[2 * n_iter], ev[2 * n_iter + 1]), "hipEventElapsedTime");
+    for (hipEvent_t &e : ev) (void)hipEventDestroy(e);
+    b->issued += n_iter;
+    *total_ms = tot;
+    *kernel_ms = k / sampled;
     return GOCP_OK;
     GOCP_GUARD_END
 }

@@ -132,3 +132,26 @@ def test_kernel_timing_hook_leaves_record_unchanged(g, ctx, dtype):
     with pytest.raises(g.GocpError):
         b.time_kernel(4, 1)
     b.close()
+
+
+@pytest.mark.parametrize("kernel", [1, 3, 5])
+def test_step_timed_matches_step(g, ctx, kernel):
+    """Event-instrumented iterations compute exactly what plain steps compute."""
+    H, P, hf, nq = _inst(g, 12, "jw", 51)
+    p1, p2 = _psi(nq, hf, torch.complex64), _psi(nq, hf, torch.complex64)
+    b1 = g.Batch(ctx, [H], [P], [p1], max_iter=12, schedule=1)
+    b2 = g.Batch(ctx, [H], [P], [p2], max_iter=12, schedule=1)
+    b1.step(2)
+    b1.step(10)
+    b2.step(2)
+    tot, k = b2.step_timed(10, kernel, 3)
+    assert tot > 0.0 and 0.0 < k < tot
+    r1, r2 = b1.result(0), b2.result(0)
+    assert np.array_equal(r1["energies"], r2["energies"]) and r1["ops"] == r2["ops"]
+    assert torch.equal(p1, p2)
+    with pytest.raises(g.GocpError):
+        b2.step_timed(1, 6)
+    with pytest.raises(g.GocpError):
+        b2.step_timed(1, 0, 0)
+    b1.close()
+    b2.close()
