@@ -92,9 +92,10 @@ def run_adapt_timed(g, ctx, H, P, nq, ne, mapping, dtype, steps, warmup, schedul
     return b, r, dt, kernel_ms
 
 
-def serving_bench(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, load=0.7, amps_per_lane=1):
+def serving_bench(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, load=0.7, amps_per_lane=0,
+                  state="complex128"):
     """Poisson stream of ADAPT solves (8-16 qubits, ||g|| < 1e-3, at most 300
-    iterations), complex64 states.  Capacity is measured first with all
+    iterations), states of the given precision.  Capacity is measured first with all
     requests submitted at once; the timed stream then arrives at `load` times
     that capacity.  Latency is submission to completion (library clock)."""
     import numpy as np
@@ -116,7 +117,8 @@ def serving_bench(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, load=0.7,
                 tickets.remove(t)
 
     # capacity: everything at once
-    srv = g.Server(ctx, budget, max_slots, dtype=1, iters_per_step=iters_per_step,
+    code = 1 if state == "complex64" else 0
+    srv = g.Server(ctx, budget, max_slots, dtype=code, iters_per_step=iters_per_step,
                    amps_per_lane=amps_per_lane)
     t0 = time.perf_counter()
     pend = [srv.submit(H, P, max_iter, tol) for (_, H, P) in reqs[warm:]]
@@ -129,7 +131,7 @@ def serving_bench(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, load=0.7,
 
     # timed Poisson stream at `load` x capacity (warm-up requests first)
     rate = load * cap
-    srv = g.Server(ctx, budget, max_slots, dtype=1, iters_per_step=iters_per_step,
+    srv = g.Server(ctx, budget, max_slots, dtype=code, iters_per_step=iters_per_step,
                    amps_per_lane=amps_per_lane)
     arrivals = [d["arrival_s"] / rate for (d, _, _) in reqs]
     pend, done, meas = [], {}, []
@@ -164,8 +166,9 @@ def serving_bench(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, load=0.7,
     torch.cuda.synchronize()
     seq = nseq / (time.perf_counter() - t0)
     return {"requests": n_req, "warmup_requests": warm, "qubits": "uniform over {8,10,12,14,16}",
-            "grad_tol": tol, "max_iter": max_iter, "state": "complex64", "max_slots": max_slots,
-            "iters_per_step": iters_per_step, "amps_per_lane": amps_per_lane,
+            "grad_tol": tol, "max_iter": max_iter, "state": state, "max_slots": max_slots,
+            "iters_per_step": iters_per_step,
+            "amps_per_lane": amps_per_lane if amps_per_lane else "adaptive",
             "hbm_budget_bytes": budget,
             "capacity_solves_per_s": round(cap, 2), "offered_rate_hz": round(rate, 2),
             "solves_per_s": round(n_req / ((t_end - t_sub) * 1e-9), 2),
@@ -187,7 +190,9 @@ def main():
                     help="measured requests of the serving stream (after 16 warm-up requests)")
     ap.add_argument("--schedule", type=int, default=0, choices=(0, 1, 2, 4),
                     help="amplitudes per lane of the tile kernels (0: autotune)")
-    ap.add_argument("--serve-amps-per-lane", type=int, default=1, choices=(1, 2, 4))
+    ap.add_argument("--serve-amps-per-lane", type=int, default=0, choices=(0, 1, 2, 4),
+                    help="server schedule (0: chosen from the active set)")
+    ap.add_argument("--serve-state", default="complex128", choices=("complex64", "complex128"))
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (a known-size "
                          "kernel that calibrates memory-traffic counters)")
@@ -325,7 +330,7 @@ def main():
 
         _say("[bench] serving form: Poisson stream of ADAPT solves")
         out["serving"] = serving_bench(g, ctx, n_req=args.serve_requests, warm=16,
-                                       amps_per_lane=args.serve_amps_per_lane)
+                                       amps_per_lane=args.serve_amps_per_lane, state=args.serve_state)
 
     if args.cpu_sample_iters > 0:
         _say(f"[bench] CPU oracle baseline: {args.cpu_sample_iters} iterations at 14q")

@@ -321,7 +321,12 @@ typedef struct {
 int gocp_request_footprint(int n_qubits, int n_ops, int n_strings, int64_t n_terms, int n_classes,
                            int max_iter, int dtype, int64_t *bytes);
 /* Start a server on ctx's device with its own stream and worker thread; the
- * tile kernels run with amps_per_lane (1, 2 or 4) amplitudes per lane.
+ * tile kernels run with amps_per_lane (1, 2 or 4) amplitudes per lane, or with
+ * 0 a schedule chosen whenever the active set changes: 1 while the set has
+ * fewer than four 64-amplitude tiles per compute unit, else 2 (GOCP_C128) or
+ * 4 (GOCP_C64).  A request's result is bit-identical to adapt_solve with the
+ * same schedule; under the adaptive schedule it can change between steps, so
+ * results agree with adapt_solve to rounding.
  * Errors: EINVAL (non-positive budget, slots or iters_per_step; bad schedule). */
 int gocp_server_create(gocp_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_slots, int dtype,
                        int32_t iters_per_step, int32_t amps_per_lane, gocp_server **out);

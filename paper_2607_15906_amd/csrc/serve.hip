@@ -69,6 +69,7 @@ struct gocp_server {
     gocp_ctx *ctx = nullptr;
     hipStream_t stream = nullptr;
     int dtype = 0, max_slots = 1, iters_per_step = 1;
+    int schedule = 1;     // amplitudes per lane, or 0: chosen from the active set
     size_t budget = 0;
     std::mutex mu;
     std::condition_variable cv;
@@ -83,6 +84,7 @@ struct gocp_server {
     std::string worker_error;
     gocp::Group group;
     std::thread worker;
+    void choose_schedule();
 
     void finish(gocp::Request *r, int status) {   // caller holds mu
         r->status = status;
@@ -114,6 +116,18 @@ void copy_record(Request *r, hipStream_t s) {
 
 }  // namespace
 }  // namespace gocp
+
+// Adaptive schedule: one amplitude per lane while the active set has fewer
+// than four tiles of 64 amplitudes per compute unit (the launches are then
+// latency-bound and more tiles keep more units busy); otherwise wider blocking,
+// which cuts the work per amplitude (2 for complex128 states, whose widest
+// blocking runs short of registers; 4 for complex64).
+void gocp_server::choose_schedule() {
+    if (schedule != 0) return;
+    long tiles = 0;
+    for (gocp::Request *r : active) tiles += gocp::tiles_for(r->inst->ip.n_qubits, 1);
+    group.R = tiles < 4L * ctx->n_cu ? 1 : (dtype == GOCP_C128 ? 2 : 4);
+}
 
 void gocp_server::run() {
     using namespace gocp;
@@ -158,6 +172,7 @@ void gocp_server::run() {
             if (!admitted.empty()) {
                 group.inst.clear();
                 for (Request *r : active) group.inst.push_back(r->inst.get());
+                choose_schedule();
                 group.rebuild(stream);
                 group.start(fresh, stream);
             }
@@ -195,6 +210,7 @@ void gocp_server::run() {
                 }
                 group.inst.clear();
                 for (Request *r : active) group.inst.push_back(r->inst.get());
+                choose_schedule();
                 group.rebuild(stream);
                 cv.notify_all();
             }
@@ -244,8 +260,8 @@ int gocp_server_create(gocp_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_slot
     check_dtype(dtype);
     if (!out || hbm_budget_bytes <= 0 || max_slots <= 0 || iters_per_step <= 0)
         throw Error(GOCP_EINVAL, "invalid server parameters");
-    if (amps_per_lane != 1 && amps_per_lane != 2 && amps_per_lane != 4)
-        throw Error(GOCP_EINVAL, "amps_per_lane must be 1, 2 or 4");
+    if (amps_per_lane != 0 && amps_per_lane != 1 && amps_per_lane != 2 && amps_per_lane != 4)
+        throw Error(GOCP_EINVAL, "amps_per_lane must be 0 (adaptive), 1, 2 or 4");
     std::unique_ptr<gocp_server> s(new gocp_server());
     s->ctx = ctx;
     s->dtype = dtype;
@@ -255,7 +271,8 @@ int gocp_server_create(gocp_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_slot
     hip_check(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate");
     s->group.ctx = ctx;
     s->group.dtype = dtype;
-    s->group.R = amps_per_lane;
+    s->schedule = amps_per_lane;
+    s->group.R = amps_per_lane ? amps_per_lane : 1;
     gocp_server *raw = s.get();
     s->worker = std::thread([raw] { raw->run(); });
     *out = s.release();

@@ -133,6 +133,25 @@ def test_late_arrivals_join_running_set(g, ctx):
         _same(res[t][1], _solo(g, ctx, r, 200, 1e-3, torch.complex64))
 
 
+def test_adaptive_schedule_agrees_with_solo(g, ctx):
+    """amps_per_lane=0 picks the blocking from the active set (six 14-qubit
+    requests give 1536 tiles: wider blocking); results agree with solo runs to
+    rounding."""
+    _say("[serve] adaptive schedule")
+    reqs = [_req(g, 14, "jw" if i % 2 else "bk", 90 + i) for i in range(6)] + [_req(g, 8, "jw", 96)]
+    srv = g.Server(ctx, hbm_budget_bytes=1 << 31, max_slots=16, dtype=0, iters_per_step=4, amps_per_lane=0)
+    tickets = [srv.submit(r["H"], r["P"], 24, 1e-4) for r in reqs]
+    res = _drain(srv, tickets)
+    srv.close()
+    for r, t in zip(reqs, tickets):
+        st, rec, info = res[t]
+        assert st == 0
+        solo = _solo(g, ctx, r, 24, 1e-4, torch.complex128)
+        assert rec["ops"] == solo["ops"] and rec["n_iter"] == solo["n_iter"]
+        assert np.abs(rec["energies"] - solo["energies"]).max() <= 1e-10
+        assert np.abs(rec["gnorms"] - solo["gnorms"]).max() <= 1e-9
+
+
 def test_bad_server_schedule_rejected(g, ctx):
     with pytest.raises(g.GocpError):
         g.Server(ctx, hbm_budget_bytes=1 << 30, max_slots=4, dtype=1, amps_per_lane=3)
