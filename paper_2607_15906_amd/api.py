@@ -323,8 +323,7 @@ class Batch:
     def step(self, n_iter: int):
         check(load().gocp_batch_step(self._b, int(n_iter)))
 
-    STEP_KERNELS = ("k_line_vw", "k_line_hvw", "k_taylor5", "k_energy_screen", "k_screen_sum1",
-                    "k_screen_reduce")
+    STEP_KERNELS = ("k_line_vw", "k_line_hvw", "k_taylor5", "k_energy_screen", "k_screen_sum1")
 
     def step_timed(self, n_iter: int, kernel: int, every: int = 1):
         """n_iter iterations with HIP events around the launch of one of

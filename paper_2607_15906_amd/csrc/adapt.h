@@ -163,11 +163,12 @@ struct Group {
             hip_check(hipMemcpyAsync(bgrp, bg.data(), bg.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
     }
 
-    // One ADAPT iteration of every member (the screen and selection of the
-    // current state were done by the previous iteration or by start()):
-    // line-search vectors, H v / H w and the angle, Taylor update, then the
-    // new state's energy and screen partials, and their reduction with the
-    // selection.
+    // One ADAPT iteration of every member: the selection from the pending
+    // screen partials (in every workgroup of the line-search-vector launch)
+    // and the line-search vectors, H v / H w, the angle and the Taylor update,
+    // then the new state's energy and screen partials and their group sums.
+    // The new state's selection is pending until the next iteration or
+    // select_pending().
     // With `timed` set, HIP events ev[0] and ev[1] are recorded on s right
     // before and after the launch of kernel id `timed_kid`.
     void enqueue_iteration(hipStream_t s, int timed_kid = -1, const hipEvent_t *ev = nullptr) const {
@@ -178,9 +179,10 @@ struct Group {
             const int2 *rows;
             int nrows;
         };
-        const L seq[6] = {{K_LINE_VW, 1, bpair, np},       {K_LINE_HVW, 1, btile, nt},
+        (void)n;
+        const L seq[5] = {{K_LINE_VW, 1, bpair, np},       {K_LINE_HVW, 1, btile, nt},
                           {K_TAYLOR, 1, bpair, np},        {K_ENERGY_SCREEN, 2, btile, nt},
-                          {K_SCREEN_SUM1, 2, bgrp, ng},    {K_SCREEN_REDUCE, 2, binst, n}};
+                          {K_SCREEN_SUM1, 2, bgrp, ng}};
         for (const L &l : seq) {
             const bool t = ev && l.kid == timed_kid;
             if (t) hip_check(hipEventRecord(ev[0], s), "hipEventRecord");
@@ -189,12 +191,20 @@ struct Group {
         }
     }
 
+    // Selection (energy, gradients, operator, record) of every member's
+    // pending partials; selecting them again later writes the same record.
+    void select_pending(hipStream_t s) const {
+        if (inst.empty()) return;
+        launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, (int)inst.size(), kModePending, s);
+    }
+
     void capture() {
         hipStream_t cs = ctx->own_stream;
         const int iters[2] = {1, kChunk};
         for (int k = 0; k < 2; ++k) {
             hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
             for (int i = 0; i < iters[k]; ++i) enqueue_iteration(cs);
+            select_pending(cs);
             hip_check(hipStreamEndCapture(cs, &graph[k]), "hipStreamEndCapture");
             hip_check(hipGraphInstantiate(&exec[k], graph[k], nullptr, nullptr, 0), "hipGraphInstantiate");
         }
@@ -206,6 +216,7 @@ struct Group {
         for (Instance *in : inst) in->finalized = false;
         if (!use_graph) {
             for (int i = 0; i < n; ++i) enqueue_iteration(s);
+            select_pending(s);
             return;
         }
         if (!exec[0]) capture();
@@ -264,7 +275,7 @@ struct Group {
     void start(const std::vector<int> &members, hipStream_t s) {
         launch_subset(K_ENERGY_SCREEN, 1, members, 0, s);
         launch_subset(K_SCREEN_SUM1, 1, members, 3, s);
-        launch_subset(K_SCREEN_REDUCE, 1, members, 2, s);
+        launch_subset(K_SCREEN_REDUCE, kModePending, members, 2, s);
     }
 
     // Scale the states of the given members to unit norm (their renormalisation

@@ -228,9 +228,8 @@ int gocp_batch_step_timed(gocp_batch *b, int32_t n_iter, int32_t kernel, int32_t
     if (!b || !total_ms || !kernel_ms) throw Error(GOCP_EINVAL, "null argument");
     check_ctx(b->group.ctx);
     if (n_iter <= 0 || every <= 0) throw Error(GOCP_EINVAL, "need at least one iteration and every >= 1");
-    static const int kids[6] = {K_LINE_VW, K_LINE_HVW, K_TAYLOR, K_ENERGY_SCREEN, K_SCREEN_SUM1,
-                                K_SCREEN_REDUCE};
-    if (kernel < 0 || kernel > 5) throw Error(GOCP_EINVAL, "kernel must be 0..5");
+    static const int kids[5] = {K_LINE_VW, K_LINE_HVW, K_TAYLOR, K_ENERGY_SCREEN, K_SCREEN_SUM1};
+    if (kernel < 0 || kernel > 4) throw Error(GOCP_EINVAL, "kernel must be 0..4");
     hipStream_t s = b->group.ctx->user_stream;
     std::vector<hipEvent_t> ev(2 * (size_t)n_iter + 2);
     for (hipEvent_t &e : ev) hip_check(hipEventCreate(&e), "hipEventCreate");
@@ -245,6 +244,7 @@ int gocp_batch_step_timed(gocp_batch *b, int32_t n_iter, int32_t kernel, int32_t
             b->group.enqueue_iteration(s);
         }
     }
+    b->group.select_pending(s);
     hip_check(hipEventRecord(ev[2 * n_iter + 1], s), "hipEventRecord");
     hip_check(hipEventSynchronize(ev[2 * n_iter + 1]), "hipEventSynchronize");
     double k = 0.0;

@@ -28,6 +28,9 @@ constexpr int kClassCost = 10;
 constexpr int kOpCost = 36;
 // Tiles per group in the first stage of the screen reduction.
 constexpr int kGroup = 16;
+// Launch mode of k_screen_reduce that selects the pending partials of an
+// ADAPT run (the iteration and mode k_energy_screen recorded with them).
+constexpr int kModePending = 5;
 
 // A folded Pauli string as the kernels read it (16 bytes): the magnitude of
 // its coefficient, its Z mask, and the coefficient's sign bit, so that the
@@ -64,6 +67,10 @@ struct AdaptState {
     int32_t nsub;          // Taylor substeps of the current update
     int32_t status;        // 0 ok, else a GOCP_E* code raised on the device
     int32_t pad0;
+    int32_t pend_it;       // iteration and mode of the screen partials awaiting
+    int32_t pend_mode;     // selection (written by k_energy_screen)
+    int32_t sel_it;        // iteration and mode of the partials the standalone
+    int32_t sel_mode;      // selection last recorded (k_screen_reduce)
     double grad_tol;
     double theta;          // angle of the current update
     double e_num;          // sum Re<psi|sigma> of the stored state

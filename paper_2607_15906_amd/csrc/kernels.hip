@@ -529,6 +529,10 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
     //    H w).  Every Refresh<T>::kPeriod iterations H psi is applied afresh,
     //    which bounds the drift from the rounding of the stored state.
     const bool carry = I.hv != nullptr && (mode == 4 || (mode == 2 && (it % Refresh<T>::kPeriod) != 0));
+    if ((mode == 1 || mode == 2) && b.y == 0 && threadIdx.x == 0) {
+        st->pend_it = it;
+        st->pend_mode = mode;
+    }
     double pe = 0.0, pn = 0.0;
     if (!carry) {
         double acc[2 * R];
@@ -694,155 +698,148 @@ __global__ __launch_bounds__(kPairBlock) void k_screen_sum1(const InstDev *__res
     }
 }
 
-// Second stage, one workgroup per instance: energy, norm and gradients from
-// the group sums, then the operator selection and the iteration record (modes
-// as k_energy_screen).  Wave w adds group rows w, w + kNW, ... for up to
-// kRedCols 64-column blocks of operators at once (lane = column), and the kNW
-// wave sums are added in wave order.
-constexpr int kRedCols = 4;
-
-__global__ __launch_bounds__(kNW *kWave) void k_screen_reduce(const InstDev *__restrict__ insts,
-                                                             const int2 *__restrict__ blk, int mode) {
-    const InstDev &I = insts[blk[blockIdx.x].x];
-    AdaptState *st = I.st;
-    const bool oneshot = mode == 0 || mode >= 3, dry = mode >= 3;
-    if (!oneshot && state_done(st)) return;
-    const int it = mode == 2 ? cptr(&st->iter)[0] + 1 : 0;
-    const int M = I.M;
-    const bool screen = M > 0 && (oneshot || it < cptr(&st->max_iter)[0]);
+// Second stage: energy, norm and gradients of an instance from the group sums,
+// then the operator selection and whether the run ends (modes as
+// k_energy_screen).  Every workgroup that calls it computes the same values in
+// the same order: thread k adds operator columns k, k + NT, ... over the groups
+// in group order, per-thread results meet by wave sums in wave order, and the
+// tie band is searched in a second pass over the same sums.  `writer`
+// workgroups also write the record.  Returns the selected operator and
+// whether the run is over, in every thread.
+template <int NT>
+__device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it, bool writer, int &jsel,
+                             bool &done) {
+    __shared__ double red[2][NT / kWave];
+    __shared__ int redi[NT / kWave];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wv = wave_id();
-    constexpr int NT = kNW * kWave;
-    __shared__ double lds[kRedCols * NT];
-    const int nt = I.n_groups;
-    // energy and norm: both group-sum arrays in one pass
-    double e_num, nrm;
-    {
-        double ae = 0.0, an = 0.0;
-        for (int t = threadIdx.x; t < nt; t += NT) {
-            ae += I.part_e2[t];
-            an += I.part_n2[t];
-        }
-        ae = wave_sum(ae);
-        an = wave_sum(an);
-        if (lane == 0) {
-            lds[wv] = ae;
-            lds[kNW + wv] = an;
-        }
-        __syncthreads();
-        e_num = 0.0;
-        nrm = 0.0;
-        for (int w = 0; w < kNW; ++w) {
-            e_num += lds[w];
-            nrm += lds[kNW + w];
-        }
-        __syncthreads();
+    const int wv = threadIdx.x >> 6;
+    const bool oneshot = mode == 0 || mode >= 3, dry = mode >= 3;
+    const int M = I.M, ng = I.n_groups;
+    const int max_iter = cptr(&st->max_iter)[0];
+    const bool screen = M > 0 && (oneshot || it < max_iter);
+    double e_num = 0.0, nrm = 0.0;
+    for (int t = 0; t < ng; ++t) {
+        e_num += I.part_e2[t];
+        nrm += I.part_n2[t];
     }
-    double amax = 0.0, sq = 0.0;
-    if (screen) {
-        const double inv = 2.0 / nrm;
-        for (int jb = 0; jb < M; jb += kRedCols * kWave) {
-            double acc[kRedCols];
+    const double inv = 2.0 / nrm;
+    auto grad = [&](int j) {
+        double a = 0.0;
+        int t = 0;
+        for (; t + 8 <= ng; t += 8) {
+            double x[8];
 #pragma unroll
-            for (int c = 0; c < kRedCols; ++c) acc[c] = 0.0;
-            int t = wv;
-            for (; t + 3 * kNW < nt; t += 4 * kNW) {
-                double x[4][kRedCols];
+            for (int u = 0; u < 8; ++u) x[u] = I.part_g2[(size_t)(t + u) * M + j];
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int c = 0; c < kRedCols; ++c) {
-                        const int j = jb + c * kWave + lane;
-                        x[r][c] = j < M ? I.part_g2[(size_t)(t + r * kNW) * M + j] : 0.0;
-                    }
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int c = 0; c < kRedCols; ++c) acc[c] += x[r][c];
-            }
-            for (; t < nt; t += kNW)
-#pragma unroll
-                for (int c = 0; c < kRedCols; ++c) {
-                    const int j = jb + c * kWave + lane;
-                    acc[c] += j < M ? I.part_g2[(size_t)t * M + j] : 0.0;
-                }
-#pragma unroll
-            for (int c = 0; c < kRedCols; ++c) lds[(c * kNW + wv) * kWave + lane] = acc[c];
-            __syncthreads();
-            if (wv == 0) {
-#pragma unroll
-                for (int c = 0; c < kRedCols; ++c) {
-                    const int j = jb + c * kWave + lane;
-                    if (j < M) {
-                        double a = 0.0;
-                        for (int w = 0; w < kNW; ++w) a += lds[(c * kNW + w) * kWave + lane];
-                        const double g = a * inv;
-                        if (!dry) st->g[j] = g;
-                        amax = fmax(amax, fabs(g));
-                        sq += g * g;
-                    }
-                }
-            }
-            __syncthreads();
+            for (int u = 0; u < 8; ++u) a += x[u];
         }
-    }
-    if (wv != 0 || dry) return;
-    // wave 0 holds every g_j (lane l: j = l, l + 64, ...)
+        for (; t < ng; ++t) a += I.part_g2[(size_t)t * M + j];
+        return a * inv;
+    };
     double gmax = 0.0, gn = 0.0;
     int jmin = 0x7fffffff;
     if (screen) {
+        double amax = 0.0, sq = 0.0;
+        for (int j = threadIdx.x; j < M; j += NT) {
+            const double g = grad(j);
+            if (writer && !dry) st->g[j] = g;
+            amax = fmax(amax, fabs(g));
+            sq += g * g;
+        }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, kWave));
-        gmax = amax;
-        gn = sqrt(wave_sum(sq));
+        sq = wave_sum(sq);
+        if (lane == 0) {
+            red[0][wv] = amax;
+            red[1][wv] = sq;
+        }
+        __syncthreads();
+        for (int w = 0; w < NT / kWave; ++w) {
+            gmax = fmax(gmax, red[0][w]);
+            gn += red[1][w];
+        }
+        gn = sqrt(gn);
         // lowest index within the tie band of the largest magnitude
         const double thresh = gmax * (1.0 - 1e-12);
-        for (int j = lane; j < M; j += kWave)
-            if (fabs(st->g[j]) >= thresh) {
-                jmin = j;
+        int jm = 0x7fffffff;
+        for (int j = threadIdx.x; j < M; j += NT)
+            if (fabs(grad(j)) >= thresh) {
+                jm = j;
                 break;
             }
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) jmin = min(jmin, __shfl_xor(jmin, off, kWave));
+        for (int off = 32; off > 0; off >>= 1) jm = min(jm, __shfl_xor(jm, off, kWave));
+        if (lane == 0) redi[wv] = jm;
+        __syncthreads();
+        for (int w = 0; w < NT / kWave; ++w) jmin = min(jmin, redi[w]);
+        __syncthreads();
     }
-    if (lane != 0) return;
     const double e = e_num / nrm;
+    bool bad = !(nrm > 0.0) || !isfinite(e) || (screen && !isfinite(gn));
+    bool end = bad;
+    if (mode == 1 && max_iter <= 0) end = true;
+    if (mode == 2 && it >= max_iter) end = true;
+    const bool conv = screen && mode != 0 && !oneshot && gn < cptr(&st->grad_tol)[0];
+    if (conv) end = true;
+    jsel = jmin < M ? jmin : 0;
+    done = end;
+    if (!writer || dry || threadIdx.x != 0) return;
     st->e_num = e_num;
     st->nrm = nrm;
     st->energy = e;
-    bool bad = !(nrm > 0.0) || !isfinite(e);
     if (mode == 1) {
         if (st->hist_e) st->hist_e[0] = e;
-        if (st->max_iter <= 0) st->done = 1;
     } else if (mode == 2) {
         st->iter = it;
         if (st->hist_e) st->hist_e[it] = e;
-        if (it >= st->max_iter) st->done = 1;
     }
     if (screen) {
         st->gmax = gmax;
         st->gnorm = gn;
-        st->jsel = jmin < M ? jmin : 0;
-        bad = bad || !isfinite(gn);
+        st->jsel = jsel;
         if (mode != 0) {
             if (st->hist_gnorm) st->hist_gnorm[it] = gn;
             if (st->hist_gmax) st->hist_gmax[it] = gmax;
-            if (gn < st->grad_tol) {
-                st->converged = 1;
-                st->done = 1;
-            }
         }
     }
-    if (bad) {
-        st->status = GOCP_ENUMERIC;
-        st->done = 1;
+    if (conv) st->converged = 1;
+    if (bad) st->status = GOCP_ENUMERIC;
+    if (end && mode != 0) st->done = 1;
+    if (bad) st->done = 1;
+}
+
+// Standalone selection, one workgroup per instance: modes as k_energy_screen,
+// or kModePending to select the partials the last k_energy_screen of an ADAPT
+// run left (their iteration and mode recorded by it; selecting the same
+// partials again writes the same record).
+__global__ __launch_bounds__(kPairBlock) void k_screen_reduce(const InstDev *__restrict__ insts,
+                                                             const int2 *__restrict__ blk, int mode) {
+    const InstDev &I = insts[blk[blockIdx.x].x];
+    AdaptState *st = I.st;
+    int it = 0;
+    if (mode == kModePending) {
+        if (state_done(st)) return;
+        it = cptr(&st->pend_it)[0];
+    }
+    int j;
+    bool done;
+    const bool pending = mode == kModePending;
+    if (pending) {
+        const int m = cptr(&st->pend_mode)[0];
+        select_state<kPairBlock>(I, st, m, it, true, j, done);
+        if (threadIdx.x == 0) {
+            st->sel_it = it;
+            st->sel_mode = m;
+        }
+    } else {
+        select_state<kPairBlock>(I, st, mode, it, true, j, done);
     }
 }
 
 // ------------------------------------------------------------------ line search vectors
 
-// w = A psi and v = -A w on the pairs of the selected generator, and the
-// partial dot products Re<v|sigma>, Re<sigma|w>.
+// Selection of the generator (see select_state), then w = A psi and
+// v = -A w on its pairs and the partial dot products Re<v|sigma>, Re<sigma|w>.
 template <typename T>
 __global__ __launch_bounds__(kPairBlock) void k_line_vw(const InstDev *__restrict__ insts,
                                                        const int2 *__restrict__ blk) {
@@ -850,7 +847,18 @@ __global__ __launch_bounds__(kPairBlock) void k_line_vw(const InstDev *__restric
     const InstDev &I = insts[b.x];
     AdaptState *st = I.st;
     if (state_done(st)) return;
-    const int j = cptr(&st->jsel)[0];
+    // selection of the partials the last k_energy_screen left, done by every
+    // workgroup (the same sums in the same order) and recorded by pair block 0,
+    // unless a standalone selection already recorded it
+    const int pit = cptr(&st->pend_it)[0], pmode = cptr(&st->pend_mode)[0];
+    int j;
+    if (cptr(&st->sel_it)[0] == pit && cptr(&st->sel_mode)[0] == pmode) {
+        j = cptr(&st->jsel)[0];
+    } else {
+        bool over;
+        select_state<kPairBlock>(I, st, pmode, pit, b.y == 0, j, over);
+        if (over) return;
+    }
     const HClass C = load_rec(cptr(I.pop), j);
     const uint32_t m = C.x;
     const int hb = 31 - __clz(m);
@@ -1285,7 +1293,7 @@ static void launch_all(int which, int R, const InstDev *insts, const int2 *blk, 
         else launch_tile<T, 1>(w, insts, blk, nblk, mode, s);
         break;
     }
-    case 1: hipLaunchKernelGGL(k_screen_reduce, dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode); break;
+    case 1: hipLaunchKernelGGL(k_screen_reduce, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode); break;
     case 7: hipLaunchKernelGGL(k_screen_sum1, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode); break;
     case 2: hipLaunchKernelGGL(k_line_vw<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk); break;
     case 4: hipLaunchKernelGGL(k_taylor5<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode, j, th, ns); break;

@@ -337,6 +337,8 @@ AdaptState make_state(const InstPlan &ip, char *b, int max_iter, double grad_tol
     s.max_iter = max_iter;
     s.grad_tol = grad_tol;
     s.nrm = 1.0;
+    s.pend_it = s.sel_it = -1;
+    s.pend_mode = s.sel_mode = -1;
     if (hist) {
         s.hist_e = reinterpret_cast<double *>(b + ip.o_he);
         s.hist_op = reinterpret_cast<int32_t *>(b + ip.o_hop);

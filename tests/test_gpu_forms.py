@@ -134,7 +134,7 @@ def test_kernel_timing_hook_leaves_record_unchanged(g, ctx, dtype):
     b.close()
 
 
-@pytest.mark.parametrize("kernel", [1, 3, 5])
+@pytest.mark.parametrize("kernel", [0, 1, 3, 4])
 def test_step_timed_matches_step(g, ctx, kernel):
     """Event-instrumented iterations compute exactly what plain steps compute."""
     H, P, hf, nq = _inst(g, 12, "jw", 51)
@@ -150,7 +150,7 @@ def test_step_timed_matches_step(g, ctx, kernel):
     assert np.array_equal(r1["energies"], r2["energies"]) and r1["ops"] == r2["ops"]
     assert torch.equal(p1, p2)
     with pytest.raises(g.GocpError):
-        b2.step_timed(1, 6)
+        b2.step_timed(1, 5)
     with pytest.raises(g.GocpError):
         b2.step_timed(1, 0, 0)
     b1.close()
