@@ -920,6 +920,9 @@ struct Landscape {
         sincos(th, &s, &c);
         return deriv_sc(s, c);
     }
+    __device__ double deriv2_sc(double s, double c) const {
+        return -2.0 * uv * c - 2.0 * uw * s + 2.0 * (ww - vv) * (c * c - s * s) - 8.0 * vw * s * c;
+    }
 };
 
 // First local minimum of E from 0 in the descent direction -sign(g), found by
@@ -970,12 +973,19 @@ __device__ double line_search_wave(const Landscape &L, double g) {
     // one of the samples, whose sin and cos are taken from its lane
     double s0, c0;
     sincos(lo, &s0, &c0);
-    for (int round = 0; round < 16; ++round) {
-        const double t = lo + (hi - lo) * (double)(lane + 1) / (double)kWave;
-        const double dl = t - lo, d2 = dl * dl;
+    auto sc_at = [&](double dl, double &st, double &ct) {
+        const double d2 = dl * dl;
         const double sd = dl * (1.0 - d2 / 6.0 * (1.0 - d2 / 20.0 * (1.0 - d2 / 42.0)));
         const double cd = 1.0 - d2 / 2.0 * (1.0 - d2 / 12.0 * (1.0 - d2 / 30.0 * (1.0 - d2 / 56.0)));
-        const double st = s0 * cd + c0 * sd, ct = c0 * cd - s0 * sd;
+        st = s0 * cd + c0 * sd;
+        ct = c0 * cd - s0 * sd;
+    };
+    // 64-way sections while the bracket is wider than 1e-9 rad (three rounds
+    // from one degree)
+    for (int round = 0; round < 16 && fabs(hi - lo) > 1e-9; ++round) {
+        const double t = lo + (hi - lo) * (double)(lane + 1) / (double)kWave;
+        double st, ct;
+        sc_at(t - lo, st, ct);
         const bool hit = lane < kWave - 1 && dir * L.deriv_sc(st, ct) >= 0.0;
         const unsigned long long mask = __ballot(hit);
         double nlo, nhi;
@@ -1002,7 +1012,22 @@ __device__ double line_search_wave(const Landscape &L, double g) {
         lo = nlo;
         hi = nhi;
     }
-    return 0.5 * (lo + hi);
+    // then Newton steps on E' from the midpoint (E'' analytic), each kept
+    // inside the bracket (a step that would leave it halves the bracket
+    // instead); the root is the one the sections were closing in on
+    const double ref = lo;                  // s0, c0 are sin, cos at ref
+    double x = 0.5 * (lo + hi);
+    for (int it = 0; it < 4; ++it) {
+        double st, ct;
+        sc_at(x - ref, st, ct);
+        const double d1 = L.deriv_sc(st, ct), d2v = L.deriv2_sc(st, ct);
+        if (dir * d1 >= 0.0) hi = x; else lo = x;
+        double xn = d2v != 0.0 ? x - d1 / d2v : 0.5 * (lo + hi);
+        if (!(xn > fmin(lo, hi) && xn < fmax(lo, hi))) xn = 0.5 * (lo + hi);
+        if (xn == x) break;
+        x = xn;
+    }
+    return x;
 }
 
 // H v, H w with shared class coefficients and the tile's partial Re<v|Hv>,
@@ -1020,6 +1045,31 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
     const int wv = wave_id();
     const uint32_t dim = 1u << I.n_qubits;
     const uint32_t d0 = (uint32_t)b.y * (kTile * R) + lane;
+
+    // The three dots have v* or w* as left factor, and v, w vanish wherever
+    // the selected generator does: a tile with v = w = 0 on all its amplitudes
+    // contributes nothing.  Unless H v and H w are kept for the carried sigma
+    // (FP64 states), such a tile only writes zero partials.  Every wave reads
+    // the same amplitudes, so all waves of the tile take the same branch.
+    if (I.hv == nullptr) {
+        bool act = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t d = d0 | ((uint32_t)r << 6);
+            if (d < dim) {
+                const double2 a = Amp<T>::load(I.v, d), c = Amp<T>::load(I.w, d);
+                act = act || a.x != 0.0 || a.y != 0.0 || c.x != 0.0 || c.y != 0.0;
+            }
+        }
+        if (__ballot(act) == 0ull) {
+            if (wv == 0 && lane == 0) {
+                I.part_l[3 * b.y] = 0.0;
+                I.part_l[3 * b.y + 1] = 0.0;
+                I.part_l[3 * b.y + 2] = 0.0;
+            }
+            return;
+        }
+    }
 
     __shared__ Stage S;
     double acc[4 * R];
@@ -1080,6 +1130,10 @@ __device__ void choose_angle(const InstDev &I, AdaptState *st, int j, bool write
     __shared__ double s_th;
     __shared__ int s_ns;
     const int lane = threadIdx.x & (kWave - 1), wv = wave_id();
+    // scalar inputs of the landscape, loaded before the partial sums so that
+    // their latency overlaps
+    const double nrm = cptr(&st->nrm)[0], e_num = cptr(&st->e_num)[0];
+    const double gj = cptr(st->g)[j], onorm = cptr(I.op_norm1)[j];
     double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int i = threadIdx.x; i < I.n_tiles; i += kPairBlock) {
         q[0] += I.part_l[3 * i];
@@ -1104,7 +1158,6 @@ __device__ void choose_angle(const InstDev &I, AdaptState *st, int j, bool write
             for (int w = 0; w < kPairBlock / kWave; ++w) P[k] += red[k][w];
         }
         const double P3 = P[0], P5 = P[1], P6 = P[2], P2 = P[3], P7 = P[4];
-        const double nrm = cptr(&st->nrm)[0], e_num = cptr(&st->e_num)[0];
         const double inv = 1.0 / nrm;
         Landscape L;
         L.uu = (e_num - 2.0 * P2 + P3) * inv;
@@ -1113,9 +1166,9 @@ __device__ void choose_angle(const InstDev &I, AdaptState *st, int j, bool write
         L.vv = P3 * inv;
         L.vw = P6 * inv;
         L.ww = P5 * inv;
-        const double th = line_search_wave(L, st->g[j]);
+        const double th = line_search_wave(L, gj);
         if (lane == 0) {
-            const int n = th == 0.0 ? 0 : max(1, (int)ceil(fabs(th) * I.op_norm1[j] / 0.5));
+            const int n = th == 0.0 ? 0 : max(1, (int)ceil(fabs(th) * onorm / 0.5));
             s_th = th;
             s_ns = n;
             if (writer) {
