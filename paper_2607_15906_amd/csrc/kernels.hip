@@ -58,8 +58,13 @@ template <> struct Refresh<double2> { static constexpr int kPeriod = 32; };
 template <typename T> struct Amp;
 template <> struct Amp<double2> {
     using Raw = u32x4;
+    static constexpr int kShift = 4;       // log2 of the element size
     static __device__ __forceinline__ Raw raw(const void *p, uint32_t i) {
         return ((const GOCP_AS1 u32x4 *)(uintptr_t)p)[i];
+    }
+    // element at byte offset `off` (a multiple of the element size)
+    static __device__ __forceinline__ Raw raw_at(const void *p, uint32_t off) {
+        return *(const GOCP_AS1 u32x4 *)((const GOCP_AS1 char *)(uintptr_t)p + off);
     }
     static __device__ __forceinline__ double2 cvt(Raw r) {
         return make_double2(__hiloint2double((int)r.y, (int)r.x), __hiloint2double((int)r.w, (int)r.z));
@@ -72,8 +77,12 @@ template <> struct Amp<double2> {
 };
 template <> struct Amp<float2> {
     using Raw = u32x2;
+    static constexpr int kShift = 3;
     static __device__ __forceinline__ Raw raw(const void *p, uint32_t i) {
         return ((const GOCP_AS1 u32x2 *)(uintptr_t)p)[i];
+    }
+    static __device__ __forceinline__ Raw raw_at(const void *p, uint32_t off) {
+        return *(const GOCP_AS1 u32x2 *)((const GOCP_AS1 char *)(uintptr_t)p + off);
     }
     static __device__ __forceinline__ double2 cvt(Raw r) {
         return make_double2((double)__uint_as_float(r.x), (double)__uint_as_float(r.y));
@@ -333,11 +342,18 @@ __device__ __forceinline__ void class_coeffs(const Stage &S, int c, int sb, uint
     for (int r = 0; r < R; ++r) f[r] = g[r];
 }
 
-// Index of the partner of amplitude r (d0 + 64 r) under X mask x, or of a
-// harmless in-range element when that amplitude lies beyond the state.
-__device__ __forceinline__ uint32_t partner(uint32_t d0, int r, uint32_t x, uint32_t dim) {
-    const uint32_t d = d0 | ((uint32_t)r << 6);
-    return d < dim ? d ^ x : x;
+// Byte offsets of the lane's R amplitudes d0 + 64 r in a vector of elements
+// of 2^SH bytes, 0 for an amplitude beyond the state; the partner of
+// amplitude r under X mask x is then at byte offset off[r] ^ (x << SH)
+// (element x, in range, for an amplitude beyond the state).
+template <int R, int SH>
+__device__ __forceinline__ void lane_offsets(uint32_t d0, uint32_t dim, uint32_t (&off)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t d = d0 | ((uint32_t)r << 6);
+        off[r] = d < dim ? d << SH : 0u;
+        asm volatile("" : "+v"(off[r]));  // keep the shifted offsets: one XOR per gather
+    }
 }
 
 // One amplitude per lane: the wave's records [c0, c1) of the staged chunk
@@ -355,13 +371,16 @@ __device__ __forceinline__ void walk_classes_r1(const Stage &S, int c0, int c1, 
         uint32_t x;
         int s0, s1;
     };
+    uint32_t doff = d << Amp<T>::kShift;
+    asm volatile("" : "+v"(doff));      // keep the shifted offset: one XOR per gather
     // start reading record r: its first string group and its gathered amplitudes
     auto issue = [&](const HClass &r, HTerm (&g)[kStrGroup], Raw (&p)[NV]) {
         const Rec k{(uint32_t)uni((int)r.x), uni(r.s0) - sb, uni(r.s1) - sb};
 #pragma unroll
         for (int q = 0; q < kStrGroup; ++q) g[q] = S.terms[k.s0 + q];
-        p[0] = Amp<T>::raw(v0, d ^ k.x);
-        if (NV == 2) p[NV - 1] = Amp<T>::raw(v1, d ^ k.x);
+        const uint32_t o = doff ^ (k.x << Amp<T>::kShift);
+        p[0] = Amp<T>::raw_at(v0, o);
+        if (NV == 2) p[NV - 1] = Amp<T>::raw_at(v1, o);
         return k;
     };
     // f(d) of a record whose first group is in registers; further groups are
@@ -441,13 +460,15 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
             continue;
         }
         int c = c0;
+        uint32_t off[R];
+        lane_offsets<R, Amp<T>::kShift>(d0, dim, off);
         typename Amp<T>::Raw rn[NV][R];
         if (c < c1) {
-            const uint32_t xn = (uint32_t)uni((int)S.cls[c].x);
+            const uint32_t xn = (uint32_t)uni((int)S.cls[c].x) << Amp<T>::kShift;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                rn[0][r] = Amp<T>::raw(v0, partner(d0, r, xn, dim));
-                if (NV == 2) rn[NV - 1][r] = Amp<T>::raw(v1, partner(d0, r, xn, dim));
+                rn[0][r] = Amp<T>::raw_at(v0, off[r] ^ xn);
+                if (NV == 2) rn[NV - 1][r] = Amp<T>::raw_at(v1, off[r] ^ xn);
             }
         }
         for (; c < c1; ++c) {
@@ -458,11 +479,11 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
                 for (int r = 0; r < R; ++r) rc[v][r] = rn[v][r];
             const int cn = c + 1;
             if (cn < c1) {
-                const uint32_t xn = (uint32_t)uni((int)S.cls[cn].x);
+                const uint32_t xn = (uint32_t)uni((int)S.cls[cn].x) << Amp<T>::kShift;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    rn[0][r] = Amp<T>::raw(v0, partner(d0, r, xn, dim));
-                    if (NV == 2) rn[NV - 1][r] = Amp<T>::raw(v1, partner(d0, r, xn, dim));
+                    rn[0][r] = Amp<T>::raw_at(v0, off[r] ^ xn);
+                    if (NV == 2) rn[NV - 1][r] = Amp<T>::raw_at(v1, off[r] ^ xn);
                 }
             }
             double f[R];
@@ -621,11 +642,13 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                                       });
             } else {
             int o = o0;
+            uint32_t off[R];
+            lane_offsets<R, Amp<T>::kShift>(d0, dim, off);
             typename Amp<T>::Raw rn[R];
             if (o < o1) {
-                const uint32_t xn = (uint32_t)uni((int)S.cls[o].x);
+                const uint32_t xn = (uint32_t)uni((int)S.cls[o].x) << Amp<T>::kShift;
 #pragma unroll
-                for (int r = 0; r < R; ++r) rn[r] = Amp<T>::raw(I.psi, partner(d0, r, xn, dim));
+                for (int r = 0; r < R; ++r) rn[r] = Amp<T>::raw_at(I.psi, off[r] ^ xn);
             }
             for (; o < o1; ++o) {
                 typename Amp<T>::Raw rc[R];
@@ -633,9 +656,9 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                 for (int r = 0; r < R; ++r) rc[r] = rn[r];
                 const int on = o + 1;
                 if (on < o1) {
-                    const uint32_t xn = (uint32_t)uni((int)S.cls[on].x);
+                    const uint32_t xn = (uint32_t)uni((int)S.cls[on].x) << Amp<T>::kShift;
 #pragma unroll
-                    for (int r = 0; r < R; ++r) rn[r] = Amp<T>::raw(I.psi, partner(d0, r, xn, dim));
+                    for (int r = 0; r < R; ++r) rn[r] = Amp<T>::raw_at(I.psi, off[r] ^ xn);
                 }
                 double h[R];
                 class_coeffs<R>(S, o, sb, d0, h);
@@ -926,21 +949,34 @@ struct Landscape {
 };
 
 // First local minimum of E from 0 in the descent direction -sign(g), found by
-// one wave: 1-degree steps (64 at a time) until d E' >= 0, then the bracket is
-// cut into 64 parts per round until it stops shrinking.  Without a sign
-// change within a full turn, the best sampled angle.  Called by all 64 lanes
-// of one wave; returns the angle in every lane.
+// one wave: 1-degree steps (64 at a time) until d E' >= 0, then inside that
+// one-degree bracket Newton steps on E' (E'' analytic) from the secant point
+// of the bracket's ends, each kept inside the bracket (a step that would
+// leave it goes to the bracket's midpoint instead) until the step no longer
+// moves the point.  Without a sign change within a full turn, the best
+// sampled angle.  Called by all 64 lanes of one wave; returns the angle in
+// every lane.
 __device__ double line_search_wave(const Landscape &L, double g) {
     if (g == 0.0) return 0.0;
     const int lane = threadIdx.x & (kWave - 1);
     const double dir = g > 0.0 ? -1.0 : 1.0;
     const double step = M_PI / 180.0;
     int kfirst = 0;
+    double s_hi = 0.0, c_hi = 1.0, e_hi = 0.0;
     for (int base = 0; base < 360 && kfirst == 0; base += kWave) {
         const int k = base + lane + 1;
-        const bool hit = k <= 360 && dir * L.deriv(dir * k * step) >= 0.0;
+        double sk, ck;
+        sincos(dir * k * step, &sk, &ck);
+        const double ek = L.deriv_sc(sk, ck);
+        const bool hit = k <= 360 && dir * ek >= 0.0;
         const unsigned long long mask = __ballot(hit);
-        if (mask) kfirst = base + __ffsll((long long)mask);
+        if (mask) {
+            const int l = __ffsll((long long)mask) - 1;
+            kfirst = base + l + 1;
+            s_hi = read_lane(sk, l);
+            c_hi = read_lane(ck, l);
+            e_hi = read_lane(ek, l);
+        }
     }
     if (kfirst == 0) {
         // no sign change: argmin over the 360 sampled angles (first on ties)
@@ -966,66 +1002,38 @@ __device__ double line_search_wave(const Landscape &L, double g) {
         }
         return dir * bestk * step;
     }
-    double lo = dir * (kfirst - 1) * step, hi = dir * kfirst * step;
-    // sin and cos at the sample points from those at the bracket's lower end:
-    // the offsets are at most one degree, where the series below are exact to
-    // rounding (next terms below 1e-20 relative); the new lower end is always
-    // one of the samples, whose sin and cos are taken from its lane
-    double s0, c0;
-    sincos(lo, &s0, &c0);
-    auto sc_at = [&](double dl, double &st, double &ct) {
-        const double d2 = dl * dl;
+    // bracket: lo (E' not yet past zero) and hi = the first sample that is;
+    // sin and cos inside it from those at hi, by the angle-addition formulas
+    // with series for the offset (at most one degree, where the series below
+    // are exact to rounding: next terms below 1e-20 relative)
+    const double ref = dir * kfirst * step;
+    double lo = dir * (kfirst - 1) * step, hi = ref;
+    auto sc_at = [&](double x, double &st, double &ct) {
+        const double dl = x - ref, d2 = dl * dl;
         const double sd = dl * (1.0 - d2 / 6.0 * (1.0 - d2 / 20.0 * (1.0 - d2 / 42.0)));
         const double cd = 1.0 - d2 / 2.0 * (1.0 - d2 / 12.0 * (1.0 - d2 / 30.0 * (1.0 - d2 / 56.0)));
-        st = s0 * cd + c0 * sd;
-        ct = c0 * cd - s0 * sd;
+        st = s_hi * cd + c_hi * sd;
+        ct = c_hi * cd - s_hi * sd;
     };
-    // 64-way sections while the bracket is wider than 1e-9 rad (three rounds
-    // from one degree)
-    for (int round = 0; round < 16 && fabs(hi - lo) > 1e-9; ++round) {
-        const double t = lo + (hi - lo) * (double)(lane + 1) / (double)kWave;
-        double st, ct;
-        sc_at(t - lo, st, ct);
-        const bool hit = lane < kWave - 1 && dir * L.deriv_sc(st, ct) >= 0.0;
-        const unsigned long long mask = __ballot(hit);
-        double nlo, nhi;
-        int src = -1;                       // lane whose sample becomes the lower end
-        if (mask) {
-            const int l = __ffsll((long long)mask) - 1;
-            nhi = lo + (hi - lo) * (double)(l + 1) / (double)kWave;
-            if (l == 0) {
-                nlo = lo;
-            } else {
-                nlo = lo + (hi - lo) * (double)l / (double)kWave;
-                src = l - 1;
-            }
-        } else {
-            nlo = lo + (hi - lo) * (double)(kWave - 1) / (double)kWave;
-            nhi = hi;
-            src = kWave - 2;
-        }
-        if (nlo == lo && nhi == hi) break;
-        if (src >= 0) {
-            s0 = read_lane(st, src);
-            c0 = read_lane(ct, src);
-        }
-        lo = nlo;
-        hi = nhi;
-    }
-    // then Newton steps on E' from the midpoint (E'' analytic), each kept
-    // inside the bracket (a step that would leave it halves the bracket
-    // instead); the root is the one the sections were closing in on
-    const double ref = lo;                  // s0, c0 are sin, cos at ref
+    double st, ct;
+    sc_at(lo, st, ct);
+    const double e_lo = L.deriv_sc(st, ct);
     double x = 0.5 * (lo + hi);
-    for (int it = 0; it < 4; ++it) {
-        double st, ct;
-        sc_at(x - ref, st, ct);
+    if (e_lo != e_hi) {
+        const double xs = lo + (hi - lo) * (e_lo / (e_lo - e_hi));
+        if (xs > fmin(lo, hi) && xs < fmax(lo, hi)) x = xs;
+    }
+    // (a run of midpoint steps alone halves the bracket each time, so the
+    // cap is reached only if Newton keeps failing)
+    for (int it = 0; it < 48; ++it) {
+        sc_at(x, st, ct);
         const double d1 = L.deriv_sc(st, ct), d2v = L.deriv2_sc(st, ct);
         if (dir * d1 >= 0.0) hi = x; else lo = x;
         double xn = d2v != 0.0 ? x - d1 / d2v : 0.5 * (lo + hi);
         if (!(xn > fmin(lo, hi) && xn < fmax(lo, hi))) xn = 0.5 * (lo + hi);
-        if (xn == x) break;
+        const bool done = fabs(xn - x) <= 1e-15 * fabs(x);
         x = xn;
+        if (done) break;
     }
     return x;
 }
@@ -1221,21 +1229,28 @@ __global__ __launch_bounds__(kPairBlock) void k_taylor5(const InstDev *__restric
     AdaptState *st = I.st;
     if (adapt && state_done(st)) return;
     const int j = adapt ? cptr(&st->jsel)[0] : j_arg;
-    double theta = theta_arg;
-    int ns = s_arg;
-    if (adapt) choose_angle(I, st, j, b.y == 0, theta, ns);
-    const double scale = adapt ? 1.0 / sqrt(cptr(&st->nrm)[0]) : 1.0;
+    // the pair, its generator coefficients and amplitudes do not depend on
+    // the angle: they are read before the angle is chosen
     const HClass C = load_rec(cptr(I.pop), j);
     const uint32_t m = C.x;
     const int hb = 31 - __clz(m);
     const uint32_t half = 1u << (I.n_qubits - 1);
     const uint32_t p = (uint32_t)b.y * kPairBlock + threadIdx.x;
-    double nn = 0.0;
-    if (p < half) {
-        const uint32_t d = insert_zero_bit(p, hb), e = d ^ m;
-        double hd, he;
+    const bool own = p < half;
+    const uint32_t d = own ? insert_zero_bit(p, hb) : 0u, e = d ^ m;
+    double hd = 0.0, he = 0.0;
+    double2 a = make_double2(0.0, 0.0), c = a;
+    if (own) {
         string_sum2(cptr(I.pterm), C.s0, C.s1, d, e, hd, he);
-        double2 a = Amp<T>::load(I.psi, d), c = Amp<T>::load(I.psi, e);
+        a = Amp<T>::load(I.psi, d);
+        c = Amp<T>::load(I.psi, e);
+    }
+    double theta = theta_arg;
+    int ns = s_arg;
+    if (adapt) choose_angle(I, st, j, b.y == 0, theta, ns);
+    const double scale = adapt ? 1.0 / sqrt(cptr(&st->nrm)[0]) : 1.0;
+    double nn = 0.0;
+    if (own) {
         a.x *= scale; a.y *= scale;
         c.x *= scale; c.y *= scale;
         if (ns > 0) {
