@@ -99,7 +99,7 @@ struct InstDev {
     const HTerm *hterm;
     const HSub *hsub;
     const int32_t *hchunk;      // n_hchunks + 1 class boundaries of the LDS stages
-    const int32_t *hseg;        // n_hchunks x (kNW + 1) class boundaries of the waves
+    const int32_t *hseg;        // n_hchunks x (4 kNW + 1) class boundaries of quarter wave segments
     // pool, in pool order (pair kernels)
     const HClass *pop;          // one record per operator
     const HTerm *pterm;
@@ -123,7 +123,7 @@ struct InstDev {
     double *part_g2;            // n_groups * M (sums over groups of kGroup tiles)
     double *part_e2;            // n_groups
     double *part_n2;            // n_groups
-    double *part_l;             // 3 * n_tiles + 2 * n_pblk (line-search dots)
+    double *part_l;             // 2 * n_pblk + 3 * n_lpart (line-search dots)
     double *part_t;             // n_pblk (Taylor norms)
     int32_t *counters;          // arrival counters: [2] line search (others spare)
     AdaptState *st;
@@ -134,7 +134,7 @@ struct InstDev {
     int32_t n_hchunks;
     int32_t n_pchunks;
     int32_t n_groups;
-    int32_t pad1;
+    int32_t n_lpart;            // workgroups of the H v, H w launch (partial triples)
 };
 
 struct DeviceHam {
@@ -143,7 +143,7 @@ struct DeviceHam {
     HTerm *hterm = nullptr;
     HSub *hsub = nullptr;
     int32_t *hchunk = nullptr;
-    int32_t *hseg = nullptr;     // per chunk, kNW + 1 wave boundaries of its classes
+    int32_t *hseg = nullptr;     // per chunk, 4 kNW + 1 quarter-segment boundaries of its classes
     int n_chunks = 0;
 };
 
