@@ -27,11 +27,19 @@ if ROOT not in sys.path:
 
 METRIC = "ADAPT iters/s + Pauli-term amp-updates/s at 14q; p50/p99 solve latency"
 FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector peak (FMA = 2 flops)
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane operations per
+# second (a wave64 instruction occupies a SIMD for four cycles; FP64 adds and
+# FMAs issue at this rate too)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# algorithmic lane operations per string-amplitude of a Pauli-string
+# application: AND with the Z mask, popcount, sign, accumulate, and the
+# multiply-add by the gathered amplitude
+LANE_OPS_PER_STRING_AMP = 5
 # HBM bytes per launch of the dominant kernel (FETCH_SIZE and WRITE_SIZE,
 # scaled by a 256 MiB copy), from the rocprofv3 counter runs summarised under
 # profiles/; keyed by (kernel, amplitudes per lane).  An entry is removed when
 # the kernel changes, until the counters are taken again.
-TRAFFIC_BYTES = {("k_energy_screen", 1): 2679555}
+TRAFFIC_BYTES = {}
 # the dominant kernel is bracketed by HIP events in every 8th timed iteration
 # (events around every launch would slow the loop by several per cent)
 LIVE_SAMPLE_EVERY = 8
@@ -242,25 +250,35 @@ def main():
     ips = args.steps / dt
     upd = _amp_updates(nq, T, S, off, r["ops"][w0:w1], r["substeps"][w0:w1])
 
-    # roofline of the dominant kernel: algorithmic FP64 flops per launch (one
-    # signed add per (string, amplitude), a real-by-complex multiply-add (4
-    # flops) per (class or operator, amplitude), and the dot products) over its
-    # mean launch duration, measured live with HIP events over the timed region
+    # roofline of the dominant kernel, which is bound by VALU issue: the
+    # algorithmic lane operations per launch (LANE_OPS_PER_STRING_AMP per
+    # string-amplitude: H psi and the screen for k_energy_screen, two H
+    # applications for k_line_hvw) over its mean launch duration, measured
+    # live with HIP events over the timed region; beside it the FP64 view (one
+    # signed add per string-amplitude, a real-by-complex multiply-add (4
+    # flops) per (class or operator, amplitude), and the dot products)
     dim = 1 << nq
+    string_amps = {3: dim * (T + S), 1: 2 * dim * T}
     flops = {3: dim * (T + 4 * C + 4) + dim * (S + 4 * M),   # H psi + energy + screen partials
              1: dim * (T + 8 * C + 12)}                      # H v and H w + three dots
     dom, kms = live
     name = g.Batch.STEP_KERNELS[dom]
-    achieved = flops[dom] / (kms * 1e-3) / 1e12
+    lane_ops = LANE_OPS_PER_STRING_AMP * string_amps[dom]
+    achieved = lane_ops / (kms * 1e-3) / 1e12
+    achieved_fp64 = flops[dom] / (kms * 1e-3) / 1e12
     traffic = TRAFFIC_BYTES.get((name, sched))
     hook = {"k_energy_screen (fresh H psi)": b.time_kernel(0, 50), "k_line_hvw": b.time_kernel(1, 50),
             "k_screen_sum1 + k_screen_reduce": b.time_kernel(3, 50)}
     roofline = {"bound": "alu", "kernel": name, "achieved": round(achieved, 4),
-                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": traffic,
+                "peak": round(VALU_PEAK_TOPS, 4), "unit": "Tlane-op/s",
+                "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": traffic,
                 "avg_launch_us": round(kms * 1e3, 3),
                 "launches_sampled": (args.steps + LIVE_SAMPLE_EVERY - 1) // LIVE_SAMPLE_EVERY,
-                "algorithmic_flops_per_launch": int(flops[dom]),
+                "algorithmic_string_amps_per_launch": int(string_amps[dom]),
+                "algorithmic_lane_ops_per_launch": int(lane_ops),
+                "fp64_view": {"achieved_tflops": round(achieved_fp64, 4), "peak_tflops": FP64_PEAK_TFLOPS,
+                              "frac": round(achieved_fp64 / FP64_PEAK_TFLOPS, 5),
+                              "algorithmic_flops_per_launch": int(flops[dom])},
                 "dry_launch_avg_us": {k: round(v * 1e3, 3) for k, v in hook.items()}}
     b.close()
 

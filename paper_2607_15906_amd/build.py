@@ -27,9 +27,12 @@ HIPCC = os.path.join(ROCM, "bin", "hipcc")
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}"]
-# Packed FP32 instructions stay disabled in every HIP compilation.
+# Packed FP32 instructions stay disabled in every HIP compilation.  Kernel
+# arguments are preloaded into scalar registers at wave launch (the code
+# object keeps the fallback that loads them when the firmware does not).
 HIP_FLAGS = COMMON + [f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
-                      "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
+                      "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-kernarg-preload-count=8",
+                      "-Wno-unused-command-line-argument"]
 
 
 def _run(cmd):
