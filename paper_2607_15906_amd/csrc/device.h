@@ -32,9 +32,13 @@ constexpr int kGroup = 16;
 // ADAPT run (the iteration and mode k_energy_screen recorded with them).
 constexpr int kModePending = 5;
 
-// A folded Pauli string as the kernels read it (16 bytes): the magnitude of
-// its coefficient, its Z mask, and the coefficient's sign bit, so that the
+// A folded Pauli string as the pair kernels read it (16 bytes): the magnitude
+// of its coefficient, its Z mask, and the coefficient's sign bit, so that the
 // signed term at amplitude d is |c| with sign bit popcount(d & z) + sign.
+// The tile kernels read the same data from two arrays instead: the
+// magnitudes (FP64; staged in LDS and read by broadcast) and the Z masks with
+// the sign in bit 31 (`zs`, read through the scalar cache), so that only
+// eight bytes per string cross the LDS into the vector registers.
 struct HTerm {
     double c;        // |c|
     uint32_t z;
@@ -96,7 +100,8 @@ struct AdaptState {
 struct InstDev {
     // Hamiltonian, grouped by X mask
     const HClass *hcls;
-    const HTerm *hterm;
+    const double *hcoef;        // |c| of H's strings, class by class
+    const uint32_t *hzs;        // z | sign << 31 of the same strings
     const HSub *hsub;
     const int32_t *hchunk;      // n_hchunks + 1 class boundaries of the LDS stages
     const int32_t *hseg;        // n_hchunks x (4 kNW + 1) class boundaries of quarter wave segments
@@ -106,7 +111,8 @@ struct InstDev {
     const double *op_norm1;
     // pool in GOCP family order (gradient screen); HClass.pad = pool index
     const HClass *sop;
-    const HTerm *sterm;
+    const double *scoef;        // |c| and z | sign << 31 of the screen's strings
+    const uint32_t *szs;
     const HSub *psub;
     const int32_t *pchunk;      // n_pchunks + 1 operator boundaries of the LDS stages
     const int32_t *pseg;        // n_pchunks x (kNW + 1) operator boundaries of the waves
@@ -140,7 +146,8 @@ struct InstDev {
 struct DeviceHam {
     int device = -1;
     HClass *hcls = nullptr;
-    HTerm *hterm = nullptr;
+    double *hcoef = nullptr;
+    uint32_t *hzs = nullptr;
     HSub *hsub = nullptr;
     int32_t *hchunk = nullptr;
     int32_t *hseg = nullptr;     // per chunk, 4 kNW + 1 quarter-segment boundaries of its classes
@@ -153,7 +160,8 @@ struct DevicePool {
     HTerm *pterm = nullptr;
     double *op_norm1 = nullptr;
     HClass *sop = nullptr;
-    HTerm *sterm = nullptr;
+    double *scoef = nullptr;
+    uint32_t *szs = nullptr;
     HSub *psub = nullptr;
     int32_t *pchunk = nullptr;
     int32_t *pseg = nullptr;     // per chunk, kNW + 1 wave boundaries of its operators

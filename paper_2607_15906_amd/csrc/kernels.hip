@@ -157,16 +157,22 @@ __device__ __forceinline__ double read_lane(double v, int l) {
                             __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
-// Sum over the 64 lanes of a full wave, returned to every lane: pairs and
-// quads, then halves of a row and whole rows by mirroring (every lane of a
-// row of 16 then holds the row sum), then rows 0+1 and 2+3 by broadcasting
-// lane 15 of a row into the next, and all four by broadcasting lane 31 into
-// rows 2 and 3; lane 63 ends with the total.  Register moves only, no LDS.
-__device__ __forceinline__ double wave_sum(double v) {
+// row_sum: sum over each row of 16 lanes, returned to every lane of the row:
+// pairs and quads, then halves of a row and whole rows by mirroring.
+// wave_sum: sum over the 64 lanes of a full wave: row sums, then rows 0+1 and
+// 2+3 by broadcasting lane 15 of a row into the next, and all four by
+// broadcasting lane 31 into rows 2 and 3; lane 63 ends with the total.
+// Register moves only, no LDS.
+__device__ __forceinline__ double row_sum(double v) {
     v += dpp_f64<0xB1>(v);          // quad_perm [1,0,3,2]
     v += dpp_f64<0x4E>(v);          // quad_perm [2,3,0,1]
     v += dpp_f64<0x141>(v);         // row_half_mirror
     v += dpp_f64<0x140>(v);         // row_mirror
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    v = row_sum(v);
     v += dpp_f64<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
     v += dpp_f64<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
     return read_lane(v, kWave - 1);
@@ -238,13 +244,18 @@ __device__ double block_sum_coh(const double *src, int n, int stride, double *ld
 // ------------------------------------------------------------------ LDS staging of term tables
 
 // Shared memory of a tile kernel: one chunk of records (classes or
-// operators), their sub-bucket offsets and their strings; reused for the
-// cross-wave reduction.
+// operators), their sub-bucket offsets and their strings' coefficient
+// magnitudes (the strings' Z masks are read through the scalar cache); reused
+// for the cross-wave reduction.
 struct Stage {
-    HTerm terms[kStageTerms];
+    double coef[kStageTerms];
     HClass cls[kStageCls];
     HSub sub[kStageCls];
 };
+
+// Stage the coefficient magnitudes [sb, se) of a chunk (sb and se are
+// multiples of kStrGroup, so whole 16-byte pairs are copied).
+__device__ __forceinline__ void stage_coef(Stage &S, const double *co, int sb, int se);
 
 // Copy n 16-byte records from global memory to LDS with the whole workgroup
 // (kNW * kWave threads), four loads in flight per thread.
@@ -265,22 +276,35 @@ __device__ __forceinline__ void stage_copy(R *dst, const R *src, int n) {
     for (; i < n; i += NT) d[i] = s[i];
 }
 
-// sum_s c_s (-1)^popcount(d & z_s) over LDS strings [s0, s1): every lane
-// reads the same record (a broadcast), four strings per step.
-__device__ __forceinline__ double lds_string_sum(const HTerm *t, int s0, int s1, uint32_t d) {
+__device__ __forceinline__ void stage_coef(Stage &S, const double *co, int sb, int se) {
+    stage_copy(reinterpret_cast<u32x4 *>(S.coef), reinterpret_cast<const u32x4 *>(co + sb), (se - sb) / 2);
+}
+
+// |c| with sign bit popcount(d & z) + sign, for zs = z | sign << 31 and
+// dz = d | 1 << 31 (d < 2^31): popcount(dz & zs) counts the sign bit with
+// the Z bits (and, popcount, shift-or).
+__device__ __forceinline__ double signed_cz(double c, uint32_t zs, uint32_t dz) {
+    const uint32_t bit = (uint32_t)__popc(dz & zs) << 31;
+    return __hiloint2double((int)(bit | (uint32_t)__double2hiint(c)), __double2loint(c));
+}
+__device__ __forceinline__ uint32_t with_sign_bit(uint32_t d) { return d | 0x80000000u; }
+
+// sum_s c_s (-1)^popcount(d & z_s) over the chunk's strings [s0, s1): every
+// lane reads the same magnitude from LDS (a broadcast) and the same Z mask
+// through the scalar cache (zs = the chunk's masks), four strings per step;
+// d = with_sign_bit(amplitude).
+__device__ __forceinline__ double lds_string_sum(const double *co, const GOCP_AS4 uint32_t *zs, int s0, int s1,
+                                                 uint32_t d) {
     double f0 = 0.0, f1 = 0.0;
     int s = s0;
     for (; s + 4 <= s1; s += 4) {
-        const HTerm a = t[s], b = t[s + 1], c = t[s + 2], e = t[s + 3];
-        f0 += signed_coef(a, d);
-        f1 += signed_coef(b, d);
-        f0 += signed_coef(c, d);
-        f1 += signed_coef(e, d);
+        const double a = co[s], b = co[s + 1], c = co[s + 2], e = co[s + 3];
+        f0 += signed_cz(a, zs[s], d);
+        f1 += signed_cz(b, zs[s + 1], d);
+        f0 += signed_cz(c, zs[s + 2], d);
+        f1 += signed_cz(e, zs[s + 3], d);
     }
-    for (; s < s1; ++s) {
-        const HTerm a = t[s];
-        f0 += signed_coef(a, d);
-    }
+    for (; s < s1; ++s) f0 += signed_cz(co[s], zs[s], d);
     return f0 + f1;
 }
 
@@ -317,12 +341,15 @@ __device__ __forceinline__ void wht(double *g) {
             }
 }
 
-// Class (or operator) c of the staged chunk: f_r for the lane's R amplitudes.
+// Class (or operator) c of the staged chunk: f_r for the lane's R amplitudes
+// (zs = the chunk's Z masks).
 template <int R>
-__device__ __forceinline__ void class_coeffs(const Stage &S, int c, int sb, uint32_t d0, double *f) {
+__device__ __forceinline__ void class_coeffs(const Stage &S, const GOCP_AS4 uint32_t *zs, int c, int sb, uint32_t d0,
+                                             double *f) {
     const int s0 = uni(S.cls[c].s0) - sb, s1 = uni(S.cls[c].s1) - sb;
+    const uint32_t dz = with_sign_bit(d0);
     if (R == 1) {
-        f[0] = lds_string_sum(S.terms, s0, s1, d0);
+        f[0] = lds_string_sum(S.coef, zs, s0, s1, dz);
         return;
     }
     uint32_t w[4];
@@ -335,7 +362,7 @@ __device__ __forceinline__ void class_coeffs(const Stage &S, int c, int sb, uint
         bucket<R>(i, u, k0, k1);
         const int a = (int)((w[k0 >> 1] >> (16 * (k0 & 1))) & 0xffffu);
         const int e = k1 >= 8 ? s1 - s0 : (int)((w[k1 >> 1] >> (16 * (k1 & 1))) & 0xffffu);
-        g[u] = lds_string_sum(S.terms, s0 + a, s0 + e, d0);
+        g[u] = lds_string_sum(S.coef, zs, s0 + a, s0 + e, dz);
     }
     wht<R>(g);
 #pragma unroll
@@ -364,20 +391,28 @@ __device__ __forceinline__ void lane_offsets(uint32_t d0, uint32_t dim, uint32_t
 // d must lie in the state (its bits feed the gather index directly).
 // fin(c, f_c(d), raw amplitudes at d ^ x_c) is called for every record in order.
 template <typename T, int NV, typename Fin>
-__device__ __forceinline__ void walk_classes_r1(const Stage &S, int c0, int c1, int sb, uint32_t d,
-                                                const void *v0, const void *v1, Fin &&fin) {
+__device__ __forceinline__ void walk_classes_r1(const Stage &S, const GOCP_AS4 uint32_t *zs, int c0, int c1, int sb,
+                                                uint32_t d, const void *v0, const void *v1, Fin &&fin) {
     using Raw = typename Amp<T>::Raw;
     struct Rec {
         uint32_t x;
         int s0, s1;
     };
+    struct Grp {                        // one group of strings: magnitudes and Z masks
+        double c[kStrGroup];
+        uint32_t z[kStrGroup];
+    };
     uint32_t doff = d << Amp<T>::kShift;
     asm volatile("" : "+v"(doff));      // keep the shifted offset: one XOR per gather
+    const uint32_t dz = with_sign_bit(d);
     // start reading record r: its first string group and its gathered amplitudes
-    auto issue = [&](const HClass &r, HTerm (&g)[kStrGroup], Raw (&p)[NV]) {
+    auto issue = [&](const HClass &r, Grp &g, Raw (&p)[NV]) {
         const Rec k{(uint32_t)uni((int)r.x), uni(r.s0) - sb, uni(r.s1) - sb};
 #pragma unroll
-        for (int q = 0; q < kStrGroup; ++q) g[q] = S.terms[k.s0 + q];
+        for (int q = 0; q < kStrGroup; ++q) {
+            g.c[q] = S.coef[k.s0 + q];
+            g.z[q] = zs[k.s0 + q];
+        }
         const uint32_t o = doff ^ (k.x << Amp<T>::kShift);
         p[0] = Amp<T>::raw_at(v0, o);
         if (NV == 2) p[NV - 1] = Amp<T>::raw_at(v1, o);
@@ -385,33 +420,33 @@ __device__ __forceinline__ void walk_classes_r1(const Stage &S, int c0, int c1, 
     };
     // f(d) of a record whose first group is in registers; further groups are
     // read here (the string range is uniform: scalar loop bounds)
-    auto coef = [&](const Rec &k, const HTerm (&g)[kStrGroup]) {
-        double f0 = signed_coef(g[0], d) + signed_coef(g[2], d);
-        double f1 = signed_coef(g[1], d) + signed_coef(g[3], d);
+    auto coef = [&](const Rec &k, const Grp &g) {
+        double f0 = signed_cz(g.c[0], g.z[0], dz) + signed_cz(g.c[2], g.z[2], dz);
+        double f1 = signed_cz(g.c[1], g.z[1], dz) + signed_cz(g.c[3], g.z[3], dz);
         const int s1 = uni(k.s1);
         for (int s = uni(k.s0) + kStrGroup; s < s1; s += kStrGroup) {
-            const HTerm a0 = S.terms[s], a1 = S.terms[s + 1], a2 = S.terms[s + 2], a3 = S.terms[s + 3];
-            f0 += signed_coef(a0, d) + signed_coef(a2, d);
-            f1 += signed_coef(a1, d) + signed_coef(a3, d);
+            const double a0 = S.coef[s], a1 = S.coef[s + 1], a2 = S.coef[s + 2], a3 = S.coef[s + 3];
+            f0 += signed_cz(a0, zs[s], dz) + signed_cz(a2, zs[s + 2], dz);
+            f1 += signed_cz(a1, zs[s + 1], dz) + signed_cz(a3, zs[s + 3], dz);
         }
         return f0 + f1;
     };
+    // Reads ahead are issued unconditionally (past the end of the run they
+    // re-read its last record, harmlessly), so every pass issues the same
+    // loads in the same order.
     if (c0 >= c1) return;
-    HTerm gA[kStrGroup], gB[kStrGroup];
+    const int cl = c1 - 1;
+    Grp gA, gB;
     Raw pA[NV], pB[NV];
-    Rec kA = issue(S.cls[c0], gA, pA), kB = kA;
-    HClass rB = S.cls[c0 + 1 < c1 ? c0 + 1 : c0], rA = rB;
+    Rec kA = issue(S.cls[c0], gA, pA);
+    HClass rB = S.cls[min(c0 + 1, cl)];
     for (int c = c0;; c += 2) {
-        if (c + 1 < c1) {
-            kB = issue(rB, gB, pB);
-            if (c + 2 < c1) rA = S.cls[c + 2];
-        }
+        const Rec kB = issue(rB, gB, pB);
+        const HClass rA = S.cls[min(c + 2, cl)];
         fin(c, coef(kA, gA), pA);
         if (c + 1 >= c1) break;
-        if (c + 2 < c1) {
-            kA = issue(rA, gA, pA);
-            if (c + 3 < c1) rB = S.cls[c + 3];
-        }
+        kA = issue(rA, gA, pA);
+        rB = S.cls[min(c + 3, cl)];
         fin(c + 1, coef(kB, gB), pB);
         if (c + 2 >= c1) break;
     }
@@ -449,12 +484,13 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
         __syncthreads();
         stage_copy(S.cls, I.hcls + cb, ce - cb);
         if (R > 1) stage_copy(S.sub, I.hsub + cb, ce - cb);
-        stage_copy(S.terms, I.hterm + sb, se - sb);
+        stage_coef(S, I.hcoef, sb, se);
+        const GOCP_AS4 uint32_t *zs = cptr(I.hzs) + sb;
         __syncthreads();
         const int c0 = seg[wv * kStep] - cb, c1 = seg[(wv + 1) * kStep] - cb;
         if constexpr (R == 1) {
             const uint32_t dd = d0 < dim ? d0 : 0u;
-            walk_classes_r1<T, NV>(S, c0, c1, sb, dd, v0, v1,
+            walk_classes_r1<T, NV>(S, zs, c0, c1, sb, dd, v0, v1,
                                    [&](int, double f, const typename Amp<T>::Raw (&p)[NV]) {
 #pragma unroll
                                        for (int v = 0; v < NV; ++v) {
@@ -493,7 +529,7 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
                 }
             }
             double f[R];
-            class_coeffs<R>(S, c, sb, d0, f);
+            class_coeffs<R>(S, zs, c, sb, d0, f);
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -549,6 +585,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
     __shared__ Stage S;
     __shared__ double2 s_sig[R][kWave];
     __shared__ double gpart[kStageCls];
+    __shared__ double opbuf[kNW][4][kWave];   // per wave: lane contributions of up to four operators
 
     // 1. sigma on the tile: H psi, or, after an update, sigma carried through
     //    it (the update is I + al A + be A^2 on scale * psi, so
@@ -634,17 +671,38 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
             __syncthreads();
             stage_copy(S.cls, I.sop + ob, oe - ob);
             if (R > 1) stage_copy(S.sub, I.psub + ob, oe - ob);
-            stage_copy(S.terms, I.sterm + sb, se - sb);
+            stage_coef(S, I.scoef, sb, se);
+            const GOCP_AS4 uint32_t *zs = cptr(I.szs) + sb;
             __syncthreads();
             const int no = oe - ob;
             int o0, o1;
             wave_range(I.pseg, k, ob, o0, o1);
+            // Per-operator sums over the wave's 64 amplitudes, four operators
+            // at a time: every lane stores its contribution to the wave's
+            // buffer; after every fourth operator of the wave's run (and after
+            // its last) row r of the wave adds the buffer's operator r (four
+            // contributions per lane, then a 16-lane row sum) -- one row
+            // reduction per four operators instead of one wave reduction each.
+            // The buffer is private to the wave, whose LDS accesses complete
+            // in order.
+            int nbuf = 0, obase = 0;
+            auto flush = [&]() {
+                const int r = lane >> 4, q = (lane & 15) * 4;
+                const double t4 = (opbuf[wv][r][q] + opbuf[wv][r][q + 1]) + (opbuf[wv][r][q + 2] + opbuf[wv][r][q + 3]);
+                const double t = row_sum(r < nbuf ? t4 : 0.0);
+                if ((lane & 15) == 0 && r < nbuf) gpart[obase + r] = t;
+                nbuf = 0;
+            };
+            auto push = [&](int o, double v) {
+                if (nbuf == 0) obase = o;
+                opbuf[wv][nbuf][lane] = v;
+                if (++nbuf == 4) flush();
+            };
             if constexpr (R == 1) {
-                walk_classes_r1<T, 1>(S, o0, o1, sb, d0 < dim ? d0 : 0u, I.psi, nullptr,
+                walk_classes_r1<T, 1>(S, zs, o0, o1, sb, d0 < dim ? d0 : 0u, I.psi, nullptr,
                                       [&](int o, double h, const typename Amp<T>::Raw (&p)[1]) {
                                           const double2 a = Amp<T>::cvt(p[0]);
-                                          const double val = wave_sum(h * (sg[0].x * a.x + sg[0].y * a.y));
-                                          if (lane == 0) gpart[o] = val;
+                                          push(o, h * (sg[0].x * a.x + sg[0].y * a.y));
                                       });
             } else {
             int o = o0;
@@ -667,17 +725,17 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                     for (int r = 0; r < R; ++r) rn[r] = Amp<T>::raw_at(I.psi, off[r] ^ xn);
                 }
                 double h[R];
-                class_coeffs<R>(S, o, sb, d0, h);
+                class_coeffs<R>(S, zs, o, sb, d0, h);
                 double val = 0.0;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const double2 p = Amp<T>::cvt(rc[r]);
                     val += h[r] * (sg[r].x * p.x + sg[r].y * p.y);
                 }
-                val = wave_sum(val);
-                if (lane == 0) gpart[o] = val;
+                push(o, val);
             }
             }
+            if (nbuf > 0) flush();
             __syncthreads();
             // wave 0 writes this stage's per-operator partials (pool-indexed)
             if (wv == 0)

@@ -35,11 +35,12 @@ HTerm make_term(double c, uint32_t z) { return HTerm{std::fabs(c), z, std::signb
 
 uint32_t sub_key(uint32_t z) { return ((z >> 6) & 1u) << 2 | ((z >> 7) & 1u) << 1 | ((z >> 8) & 1u); }
 
-// Append the strings [a, b) of (c, z) in sub-bucket order to `out`, then zero
-// strings up to a whole number of groups of kStrGroup, and return the
-// sub-bucket record of the group (the padding sits after the last sub-bucket).
+// Append the strings [a, b) of (c, z) in sub-bucket order to the magnitude
+// and Z-mask-with-sign arrays, then zero strings up to a whole number of
+// groups of kStrGroup, and return the sub-bucket record of the group (the
+// padding sits after the last sub-bucket).
 HSub bucket_strings(const std::vector<double> &c, const std::vector<uint32_t> &z, int a, int b,
-                    std::vector<HTerm> &out) {
+                    std::vector<double> &co, std::vector<uint32_t> &zs) {
     std::vector<int> idx;
     for (int s = a; s < b; ++s) idx.push_back(s);
     std::stable_sort(idx.begin(), idx.end(), [&](int p, int q) { return sub_key(z[p]) < sub_key(z[q]); });
@@ -50,9 +51,16 @@ HSub bucket_strings(const std::vector<double> &c, const std::vector<uint32_t> &z
         off[key] = (uint16_t)k;
         while (k < (int)idx.size() && (int)sub_key(z[idx[k]]) == key) ++k;
     }
-    const size_t start = out.size();
-    for (int s : idx) out.push_back(make_term(c[s], z[s]));
-    while ((out.size() - start) % kStrGroup) out.push_back(HTerm{0.0, 0u, 0u});
+    const size_t start = co.size();
+    for (int s : idx) {
+        if (z[s] >> 31) throw Error(GOCP_ENOTSUP, "Z mask beyond 31 qubits");
+        co.push_back(std::fabs(c[s]));
+        zs.push_back(z[s] | (std::signbit(c[s]) ? 1u << 31 : 0u));
+    }
+    while ((co.size() - start) % kStrGroup) {
+        co.push_back(0.0);
+        zs.push_back(0u);
+    }
     HSub r;
     for (int i = 0; i < 4; ++i) r.w[i] = (uint32_t)off[2 * i] | ((uint32_t)off[2 * i + 1] << 16);
     return r;
@@ -161,7 +169,8 @@ std::vector<int32_t> padded_offsets(int n, F count) {
 void release_device_ham(DeviceHam *d) {
     if (!d) return;
     (void)hipFree(d->hcls);
-    (void)hipFree(d->hterm);
+    (void)hipFree(d->hcoef);
+    (void)hipFree(d->hzs);
     (void)hipFree(d->hsub);
     (void)hipFree(d->hchunk);
     (void)hipFree(d->hseg);
@@ -174,7 +183,8 @@ void release_device_pool(DevicePool *d) {
     (void)hipFree(d->pterm);
     (void)hipFree(d->op_norm1);
     (void)hipFree(d->sop);
-    (void)hipFree(d->sterm);
+    (void)hipFree(d->scoef);
+    (void)hipFree(d->szs);
     (void)hipFree(d->psub);
     (void)hipFree(d->pchunk);
     (void)hipFree(d->pseg);
@@ -207,14 +217,16 @@ const DeviceHam *device_ham(const Ham &h, int dev) {
     }
     std::vector<HClass> cls;
     std::vector<HSub> sub;
-    std::vector<HTerm> terms;
+    std::vector<double> co;
+    std::vector<uint32_t> zs;
     for (int32_t c : order) {
-        const int32_t s0 = (int32_t)terms.size();
-        sub.push_back(bucket_strings(h.str_c, h.str_z, h.cls_off[c], h.cls_off[c + 1], terms));
-        cls.push_back(HClass{h.cls_x[c], s0, (int32_t)terms.size(), 0});
+        const int32_t s0 = (int32_t)co.size();
+        sub.push_back(bucket_strings(h.str_c, h.str_z, h.cls_off[c], h.cls_off[c + 1], co, zs));
+        cls.push_back(HClass{h.cls_x[c], s0, (int32_t)co.size(), 0});
     }
     d->hcls = dev_upload(cls);
-    d->hterm = dev_upload(terms);
+    d->hcoef = dev_upload(co);
+    d->hzs = dev_upload(zs);
     d->hsub = dev_upload(sub);
     d->hchunk = dev_upload(ch);
     d->hseg = dev_upload(quarter);
@@ -250,16 +262,18 @@ const DevicePool *device_pool(const Pool &p, int dev) {
     for (size_t k = 0; k + 1 < pch.size(); ++k) wave_split(cost, pch[k], pch[k + 1], order, seg);
     std::vector<HClass> sop;
     std::vector<HSub> psub;
-    std::vector<HTerm> sterm;
+    std::vector<double> co;
+    std::vector<uint32_t> zs;
     for (int32_t r : order) {
         const int32_t j = p.fam_members[r];
-        HClass rec{p.op_x[j], (int32_t)sterm.size(), 0, j};
-        psub.push_back(bucket_strings(p.str_c, p.str_z, p.op_off[j], p.op_off[j + 1], sterm));
-        rec.s1 = (int32_t)sterm.size();
+        HClass rec{p.op_x[j], (int32_t)co.size(), 0, j};
+        psub.push_back(bucket_strings(p.str_c, p.str_z, p.op_off[j], p.op_off[j + 1], co, zs));
+        rec.s1 = (int32_t)co.size();
         sop.push_back(rec);
     }
     d->sop = dev_upload(sop);
-    d->sterm = dev_upload(sterm);
+    d->scoef = dev_upload(co);
+    d->szs = dev_upload(zs);
     d->psub = dev_upload(psub);
     d->pchunk = dev_upload(pch);
     d->pseg = dev_upload(seg);
@@ -334,7 +348,8 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
     if (h) {
         const DeviceHam *dh = device_ham(*h, device);
         I.hcls = dh->hcls;
-        I.hterm = dh->hterm;
+        I.hcoef = dh->hcoef;
+        I.hzs = dh->hzs;
         I.hsub = dh->hsub;
         I.hchunk = dh->hchunk;
         I.hseg = dh->hseg;
@@ -346,7 +361,8 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
         I.pterm = dp->pterm;
         I.op_norm1 = dp->op_norm1;
         I.sop = dp->sop;
-        I.sterm = dp->sterm;
+        I.scoef = dp->scoef;
+        I.szs = dp->szs;
         I.psub = dp->psub;
         I.pchunk = dp->pchunk;
         I.pseg = dp->pseg;
