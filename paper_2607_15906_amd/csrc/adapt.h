@@ -67,16 +67,10 @@ inline int tiles_for(int n_qubits, int R) {
     return (int)((dim + t - 1) / t);
 }
 
-// Workgroups per tile of the H v, H w launch for complex64 groups too small
-// to fill the GPU (their tiles then take kHvwSplit amplitudes per lane and
-// each workgroup a 1 / kHvwSplit share of H's classes).
-constexpr int kHvwSplit = 2;
-
 struct Group {
     gocp_ctx *ctx = nullptr;
     int dtype = 0;
     int R = 1;                 // amplitudes per lane of the tile kernels
-    int RH = 1, SH = 1;        // amplitudes per lane and workgroups per tile of the H v, H w launch
     std::vector<int> ntile;    // tiles of each member for R
     std::vector<int> ngroup;   // tile groups of each member (first reduction stage)
     int ng = 0;
@@ -85,9 +79,8 @@ struct Group {
     size_t meta_cap = 0;
     InstDev *desc = nullptr;
     int2 *btile = nullptr, *bpair = nullptr, *bsub = nullptr, *binst = nullptr, *bgrp = nullptr;
-    int2 *bhvw = nullptr;      // rows of the H v, H w launch (tiles of 64 RH amplitudes)
     int32_t *done = nullptr;   // n flags gathered on the device
-    int nt = 0, np = 0, nh = 0;
+    int nt = 0, np = 0;
     std::vector<int> tile0, pair0;
     static constexpr int kChunk = 8;
     hipGraph_t graph[2] = {nullptr, nullptr};
@@ -111,28 +104,15 @@ struct Group {
     void rebuild(hipStream_t s) {
         drop_graphs();
         std::vector<InstDev> d;
-        std::vector<int2> bt, bp, bi, bg, bh;
+        std::vector<int2> bt, bp, bi, bg;
         tile0.clear();
         pair0.clear();
         ntile.clear();
         ngroup.clear();
-        // complex64 states keep no H v, H w, so a group that leaves most of
-        // the GPU idle spreads each tile of that launch over kHvwSplit
-        // workgroups (more amplitudes per lane, fewer classes per wave)
-        RH = R;
-        SH = 1;
-        if (dtype == GOCP_C64 && kHvwSplit > 1) {
-            long long t = 0;
-            for (Instance *in : inst) t += tiles_for(in->ip.n_qubits, kHvwSplit);
-            if (t * kHvwSplit <= 2LL * std::max(ctx->n_cu, 1)) RH = SH = kHvwSplit;
-        }
         for (size_t i = 0; i < inst.size(); ++i) {
             InstDev di = inst[i]->desc;
             di.n_tiles = tiles_for(di.n_qubits, R);
             di.n_groups = (di.n_tiles + kGroup - 1) / kGroup;
-            const int th = tiles_for(di.n_qubits, RH);
-            di.n_lpart = th * SH;
-            for (int t = 0; t < th; ++t) bh.push_back(make_int2((int)i, t));
             d.push_back(di);
             ntile.push_back(di.n_tiles);
             tile0.push_back((int)bt.size());
@@ -146,7 +126,6 @@ struct Group {
         ng = (int)bg.size();
         nt = (int)bt.size();
         np = (int)bp.size();
-        nh = (int)bh.size();
         const size_t sub = std::max<size_t>({bt.size(), bp.size(), inst.size(), 1});
         auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
         const size_t o_bt = al(d.size() * sizeof(InstDev));
@@ -154,8 +133,7 @@ struct Group {
         const size_t o_bs = o_bp + al(bp.size() * sizeof(int2));
         const size_t o_bi = o_bs + al(sub * sizeof(int2));
         const size_t o_bg = o_bi + al(std::max<size_t>(inst.size(), 1) * sizeof(int2));
-        const size_t o_bh = o_bg + al(std::max<size_t>(bg.size(), 1) * sizeof(int2));
-        const size_t o_dn = o_bh + al(std::max<size_t>(bh.size(), 1) * sizeof(int2));
+        const size_t o_dn = o_bg + al(std::max<size_t>(bg.size(), 1) * sizeof(int2));
         const size_t need = o_dn + al(std::max<size_t>(inst.size(), 1) * sizeof(int32_t));
         if (need > meta_cap) {
             if (meta) {
@@ -172,7 +150,6 @@ struct Group {
         bsub = reinterpret_cast<int2 *>(meta + o_bs);
         binst = reinterpret_cast<int2 *>(meta + o_bi);
         bgrp = reinterpret_cast<int2 *>(meta + o_bg);
-        bhvw = reinterpret_cast<int2 *>(meta + o_bh);
         done = reinterpret_cast<int32_t *>(meta + o_dn);
         if (!d.empty())
             hip_check(hipMemcpyAsync(desc, d.data(), d.size() * sizeof(InstDev), hipMemcpyHostToDevice, s), "H2D");
@@ -184,8 +161,6 @@ struct Group {
             hip_check(hipMemcpyAsync(binst, bi.data(), bi.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
         if (!bg.empty())
             hip_check(hipMemcpyAsync(bgrp, bg.data(), bg.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
-        if (!bh.empty())
-            hip_check(hipMemcpyAsync(bhvw, bh.data(), bh.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
     }
 
     // One ADAPT iteration of every member: the selection from the pending
@@ -205,21 +180,15 @@ struct Group {
             int nrows;
         };
         (void)n;
-        const L seq[5] = {{K_LINE_VW, 1, bpair, np},       {K_LINE_HVW, 1, bhvw, nh},
+        const L seq[5] = {{K_LINE_VW, 1, bpair, np},       {K_LINE_HVW, 1, btile, nt},
                           {K_TAYLOR, 1, bpair, np},        {K_ENERGY_SCREEN, 2, btile, nt},
                           {K_SCREEN_SUM1, 2, bgrp, ng}};
         for (const L &l : seq) {
             const bool t = ev && l.kid == timed_kid;
             if (t) hip_check(hipEventRecord(ev[0], s), "hipEventRecord");
-            if (l.kid == K_LINE_HVW) launch_hvw(l.mode, s);
-            else launch_kernel(l.kid, dtype, R, desc, l.rows, l.nrows, l.mode, s);
+            launch_kernel(l.kid, dtype, R, desc, l.rows, l.nrows, l.mode, s);
             if (t) hip_check(hipEventRecord(ev[1], s), "hipEventRecord");
         }
-    }
-
-    // The H v, H w launch over the whole group (mode as k_line_hvw).
-    void launch_hvw(int mode, hipStream_t s) const {
-        gocp::launch_hvw(dtype, RH, SH, desc, bhvw, nh, mode, s);
     }
 
     // Selection (energy, gradients, operator, record) of every member's
@@ -279,13 +248,13 @@ struct Group {
         launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 3, s);
         launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 3, s);
         launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, n, 3, s);
-        launch_hvw(0, s);
+        launch_kernel(K_LINE_HVW, dtype, R, desc, btile, nt, 0, s);
         hip_check(hipEventRecord(e0, s), "hipEventRecord");
         for (int i = 0; i < reps; ++i) {
             launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 3, s);
             launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 3, s);
             launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, n, 3, s);
-            launch_hvw(0, s);
+            launch_kernel(K_LINE_HVW, dtype, R, desc, btile, nt, 0, s);
         }
         hip_check(hipEventRecord(e1, s), "hipEventRecord");
         hip_check(hipEventSynchronize(e1), "hipEventSynchronize");

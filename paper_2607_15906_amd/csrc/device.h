@@ -104,7 +104,7 @@ struct InstDev {
     const uint32_t *hzs;        // z | sign << 31 of the same strings
     const HSub *hsub;
     const int32_t *hchunk;      // n_hchunks + 1 class boundaries of the LDS stages
-    const int32_t *hseg;        // n_hchunks x (4 kNW + 1) class boundaries of quarter wave segments
+    const int32_t *hseg;        // n_hchunks x (kNW + 1) class boundaries of the waves
     // pool, in pool order (pair kernels)
     const HClass *pop;          // one record per operator
     const HTerm *pterm;
@@ -129,7 +129,7 @@ struct InstDev {
     double *part_g2;            // n_groups * M (sums over groups of kGroup tiles)
     double *part_e2;            // n_groups
     double *part_n2;            // n_groups
-    double *part_l;             // 2 * n_pblk + 3 * n_lpart (line-search dots)
+    double *part_l;             // 3 * n_tiles + 2 * n_pblk (line-search dots)
     double *part_t;             // n_pblk (Taylor norms)
     int32_t *counters;          // arrival counters: [2] line search (others spare)
     AdaptState *st;
@@ -140,7 +140,7 @@ struct InstDev {
     int32_t n_hchunks;
     int32_t n_pchunks;
     int32_t n_groups;
-    int32_t n_lpart;            // workgroups of the H v, H w launch (partial triples)
+    int32_t pad1;
 };
 
 struct DeviceHam {
@@ -150,7 +150,7 @@ struct DeviceHam {
     uint32_t *hzs = nullptr;
     HSub *hsub = nullptr;
     int32_t *hchunk = nullptr;
-    int32_t *hseg = nullptr;     // per chunk, 4 kNW + 1 quarter-segment boundaries of its classes
+    int32_t *hseg = nullptr;     // per chunk, kNW + 1 wave boundaries of its classes
     int n_chunks = 0;
 };
 

@@ -462,24 +462,17 @@ __device__ __forceinline__ void wave_range(const int32_t *seg, int k, int cb, in
 
 // Apply the X-mask classes of H to NV vectors at the lane's R amplitudes:
 // acc[(k R + r) 2 + {0,1}] += sum_classes f_class(d_r) vec_k[d_r ^ x_class].
-// The table is staged chunk by chunk.  Each chunk's classes are laid out in
-// kNW contiguous, cost-balanced wave segments, each cut into four runs of
-// nearly equal cost.  With SPLIT = 1 wave w takes segment w (runs 4w .. 4w + 3);
-// with SPLIT = 2 or 4 a tile is covered by SPLIT workgroups, wave w of part p
-// takes the 4 / SPLIT runs starting at (p kNW + w) 4 / SPLIT, and each part
-// stages only its own classes.  Within its range a wave issues the gathers of
-// its next class before the current class's strings are summed.
-template <typename T, int NV, int R, int SPLIT = 1>
+// The table is staged chunk by chunk; wave w takes classes w, w + kNW, ... of
+// a chunk, and the gathers of its next class are issued before the current
+// class's strings are summed.
+template <typename T, int NV, int R>
 __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32_t d0, uint32_t dim,
-                                              const void *v0, const void *v1, double *acc, int part = 0) {
-    static_assert(SPLIT == 1 || SPLIT == 2 || SPLIT == 4, "a tile is split over 1, 2 or 4 workgroups");
-    constexpr int kStep = 4 / SPLIT;         // runs per wave
+                                              const void *v0, const void *v1, double *acc) {
     const int wv = wave_id();
+    const GOCP_AS4 int32_t *hch = cptr(I.hchunk);
     const GOCP_AS4 HClass *hcls = cptr(I.hcls);
     for (int k = 0; k < I.n_hchunks; ++k) {
-        const GOCP_AS4 int32_t *seg = cptr(I.hseg) + k * (4 * kNW + 1) + part * kNW * kStep;
-        const int cb = seg[0], ce = seg[kNW * kStep];
-        if (cb == ce) continue;              // same for the whole workgroup
+        const int cb = hch[k], ce = hch[k + 1];
         const int sb = hcls[cb].s0, se = hcls[ce - 1].s1;
         __syncthreads();
         stage_copy(S.cls, I.hcls + cb, ce - cb);
@@ -487,7 +480,8 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
         stage_coef(S, I.hcoef, sb, se);
         const GOCP_AS4 uint32_t *zs = cptr(I.hzs) + sb;
         __syncthreads();
-        const int c0 = seg[wv * kStep] - cb, c1 = seg[(wv + 1) * kStep] - cb;
+        int c0, c1;
+        wave_range(I.hseg, k, cb, c0, c1);
         if constexpr (R == 1) {
             const uint32_t dd = d0 < dim ? d0 : 0u;
             walk_classes_r1<T, NV>(S, zs, c0, c1, sb, dd, v0, v1,
@@ -985,8 +979,8 @@ __global__ __launch_bounds__(kPairBlock) void k_line_vw(const InstDev *__restric
             a2 += r2[k];
             a7 += r7[k];
         }
-        I.part_l[2 * b.y] = a2;
-        I.part_l[2 * b.y + 1] = a7;
+        I.part_l[3 * I.n_tiles + 2 * b.y] = a2;
+        I.part_l[3 * I.n_tiles + 2 * b.y + 1] = a7;
     }
 }
 
@@ -1102,19 +1096,14 @@ __device__ double line_search_wave(const Landscape &L, double g) {
     return x;
 }
 
-// H v, H w with shared class coefficients and the workgroup's partial
-// Re<v|Hv>, Re<w|Hw>, Re<v|Hw> (the angle is chosen from them by the Taylor
-// launch that follows).  A tile of 64 R amplitudes is covered by SPLIT
-// workgroups (grid = rows x SPLIT), each applying its share of H's classes;
-// partial triple p = tile SPLIT + part.  H v and H w themselves are stored
-// only by whole-tile workgroups (SPLIT = 1).
-// mode 1: ADAPT iteration (instances already done are skipped); mode 0:
-// timing.
-template <typename T, int R, int SPLIT>
+// H v, H w with shared class coefficients and the tile's partial Re<v|Hv>,
+// Re<w|Hw>, Re<v|Hw> (the angle is chosen from them by the Taylor launch
+// that follows).  mode 1: ADAPT iteration (instances already done are
+// skipped); mode 0: timing.
+template <typename T, int R>
 __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restrict__ insts,
                                                         const int2 *__restrict__ blk, int mode) {
-    const int2 b = blk[blockIdx.x / SPLIT];
-    const int part = blockIdx.x % SPLIT;
+    const int2 b = blk[blockIdx.x];
     const InstDev &I = insts[b.x];
     AdaptState *st = I.st;
     if (mode != 0 && state_done(st)) return;
@@ -1122,16 +1111,13 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
     const int wv = wave_id();
     const uint32_t dim = 1u << I.n_qubits;
     const uint32_t d0 = (uint32_t)b.y * (kTile * R) + lane;
-    double *const pl = I.part_l + 2 * I.n_pblk + 3 * (b.y * SPLIT + part);
-    double2 *const hv = SPLIT == 1 ? I.hv : nullptr;
-    double2 *const hw = SPLIT == 1 ? I.hw : nullptr;
 
     // The three dots have v* or w* as left factor, and v, w vanish wherever
     // the selected generator does: a tile with v = w = 0 on all its amplitudes
     // contributes nothing.  Unless H v and H w are kept for the carried sigma
     // (FP64 states), such a tile only writes zero partials.  Every wave reads
     // the same amplitudes, so all waves of the tile take the same branch.
-    if (hv == nullptr) {
+    if (I.hv == nullptr) {
         bool act = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -1143,9 +1129,9 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
         }
         if (__ballot(act) == 0ull) {
             if (wv == 0 && lane == 0) {
-                pl[0] = 0.0;
-                pl[1] = 0.0;
-                pl[2] = 0.0;
+                I.part_l[3 * b.y] = 0.0;
+                I.part_l[3 * b.y + 1] = 0.0;
+                I.part_l[3 * b.y + 2] = 0.0;
             }
             return;
         }
@@ -1155,7 +1141,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
     double acc[4 * R];
 #pragma unroll
     for (int i = 0; i < 4 * R; ++i) acc[i] = 0.0;
-    apply_classes<T, 2, R, SPLIT>(I, S, d0, dim, I.v, I.w, acc, part);
+    apply_classes<T, 2, R>(I, S, d0, dim, I.v, I.w, acc);
     double4 (*red)[kWave] = reinterpret_cast<double4 (*)[kWave]>(&S);
     double p3 = 0.0, p5 = 0.0, p6 = 0.0;
 #pragma unroll
@@ -1178,9 +1164,9 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
                 p3 += ov.x * a0 + ov.y * a1;
                 p5 += ow.x * a2 + ow.y * a3;
                 p6 += ov.x * a2 + ov.y * a3;
-                if (hv) {
-                    hv[d] = make_double2(a0, a1);
-                    hw[d] = make_double2(a2, a3);
+                if (I.hv) {
+                    I.hv[d] = make_double2(a0, a1);
+                    I.hw[d] = make_double2(a2, a3);
                 }
             }
         }
@@ -1191,9 +1177,9 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
         p5 = wave_sum(p5);
         p6 = wave_sum(p6);
         if (lane == 0) {
-            pl[0] = p3;
-            pl[1] = p5;
-            pl[2] = p6;
+            I.part_l[3 * b.y] = p3;
+            I.part_l[3 * b.y + 1] = p5;
+            I.part_l[3 * b.y + 2] = p6;
         }
     }
 }
@@ -1215,15 +1201,14 @@ __device__ void choose_angle(const InstDev &I, AdaptState *st, int j, bool write
     const double nrm = cptr(&st->nrm)[0], e_num = cptr(&st->e_num)[0];
     const double gj = cptr(st->g)[j], onorm = cptr(I.op_norm1)[j];
     double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const double *pl = I.part_l + 2 * I.n_pblk;
-    for (int i = threadIdx.x; i < I.n_lpart; i += kPairBlock) {
-        q[0] += pl[3 * i];
-        q[1] += pl[3 * i + 1];
-        q[2] += pl[3 * i + 2];
+    for (int i = threadIdx.x; i < I.n_tiles; i += kPairBlock) {
+        q[0] += I.part_l[3 * i];
+        q[1] += I.part_l[3 * i + 1];
+        q[2] += I.part_l[3 * i + 2];
     }
     for (int i = threadIdx.x; i < I.n_pblk; i += kPairBlock) {
-        q[3] += I.part_l[2 * i];
-        q[4] += I.part_l[2 * i + 1];
+        q[3] += I.part_l[3 * I.n_tiles + 2 * i];
+        q[4] += I.part_l[3 * I.n_tiles + 2 * i + 1];
     }
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -1419,7 +1404,7 @@ static void launch_tile(int which, const InstDev *insts, const int2 *blk, int nb
     if (which == 0)
         hipLaunchKernelGGL((k_energy_screen<T, R>), dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode);
     else
-        hipLaunchKernelGGL((k_line_hvw<T, R, 1>), dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode);
+        hipLaunchKernelGGL((k_line_hvw<T, R>), dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode);
 }
 
 template <typename T>
@@ -1451,23 +1436,6 @@ void launch_kernel(int which, int dtype, int R, const InstDev *insts, const int2
         launch_all<float2>(which, R, insts, blk, nblk, mode, s, j, th, ns);
     else
         launch_all<double2>(which, R, insts, blk, nblk, mode, s, j, th, ns);
-    hip_check(hipGetLastError(), "kernel launch");
-}
-
-void launch_hvw(int dtype, int R, int split, const InstDev *insts, const int2 *blk, int nblk, int mode,
-                hipStream_t s) {
-    if (nblk <= 0) return;
-    if (split == 1) {
-        launch_kernel(3, dtype, R, insts, blk, nblk, mode, s, 0, 0.0, 0);   // whole-tile H v, H w launch
-        return;
-    }
-    // split launches keep no H v, H w: complex64 states only, R = split
-    if (dtype != GOCP_C64 || R != split || (split != 2 && split != 4))
-        throw Error(GOCP_EINVAL, "unsupported split of the H v, H w launch");
-    if (split == 2)
-        hipLaunchKernelGGL((k_line_hvw<float2, 2, 2>), dim3(2 * nblk), dim3(kNW * kWave), 0, s, insts, blk, mode);
-    else
-        hipLaunchKernelGGL((k_line_hvw<float2, 4, 4>), dim3(4 * nblk), dim3(kNW * kWave), 0, s, insts, blk, mode);
     hip_check(hipGetLastError(), "kernel launch");
 }
 

@@ -28,10 +28,6 @@ enum {
 // R = amplitudes per lane of the tile kernels (1, 2 or 4); the pair kernels ignore it.
 void launch_kernel(int which, int dtype, int R, const InstDev *insts, const int2 *blk, int nblk, int mode,
                    hipStream_t s, int j = 0, double th = 0.0, int ns = 0);
-// H v, H w launch over rows (instance, tile of 64 R amplitudes), `split`
-// workgroups per tile (1; or 2 or 4 with R = split for complex64 states).
-void launch_hvw(int dtype, int R, int split, const InstDev *insts, const int2 *blk, int nblk, int mode,
-                hipStream_t s);
 void launch_basis(int dtype, void *psi, uint32_t dim, uint32_t index, hipStream_t s);
 void launch_gather_done(const InstDev *insts, int n, int32_t *out, hipStream_t s);
 

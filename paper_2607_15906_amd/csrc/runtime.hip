@@ -118,41 +118,6 @@ void wave_split(const std::vector<int> &cost, int b, int e, std::vector<int32_t>
     seg.push_back((int32_t)order.size());
 }
 
-// Cut the records order[a, b) of one wave into four contiguous runs whose
-// largest cost is as small as possible (binary search on that cost with
-// greedy packing); appends the run starts a = b0 <= b1 <= b2 <= b3.
-void quarter_cuts(const std::vector<int> &cost, const std::vector<int32_t> &order, int a, int b,
-                  std::vector<int32_t> &out) {
-    long long lo = 0, hi = 0;
-    for (int i = a; i < b; ++i) {
-        lo = std::max<long long>(lo, cost[order[i]]);
-        hi += cost[order[i]];
-    }
-    auto pack = [&](long long cap, std::vector<int32_t> *cuts) {
-        int runs = 1;
-        long long cur = 0;
-        if (cuts) cuts->push_back(a);
-        for (int i = a; i < b; ++i) {
-            const int c = cost[order[i]];
-            if (cur + c > cap) {
-                ++runs;
-                cur = 0;
-                if (cuts) cuts->push_back(i);
-            }
-            cur += c;
-        }
-        return runs;
-    };
-    while (lo < hi) {
-        const long long mid = (lo + hi) / 2;
-        if (pack(mid, nullptr) <= 4) hi = mid; else lo = mid + 1;
-    }
-    std::vector<int32_t> cuts;
-    pack(lo, &cuts);
-    while (cuts.size() < 4) cuts.push_back(b);
-    for (int k = 0; k < 4; ++k) out.push_back(cuts[k]);
-}
-
 // Padded string offsets of records taken in the order `rec` with `count(r)` strings.
 template <typename F>
 std::vector<int32_t> padded_offsets(int n, F count) {
@@ -205,16 +170,8 @@ const DeviceHam *device_ham(const Ham &h, int dev) {
     const std::vector<int32_t> ch = stage_chunks(padded_offsets(nc, count));
     std::vector<int> cost(nc);
     for (int c = 0; c < nc; ++c) cost[c] = record_cost(count(c), kClassCost);
-    // each wave's classes are further cut into four runs of nearly equal cost
-    // (4 kNW + 1 boundaries per chunk), for launches that spread a tile over
-    // two or four workgroups
-    std::vector<int32_t> order, seg, quarter;
-    for (size_t k = 0; k + 1 < ch.size(); ++k) {
-        const size_t s0 = seg.size();
-        wave_split(cost, ch[k], ch[k + 1], order, seg);
-        for (int w = 0; w < kNW; ++w) quarter_cuts(cost, order, seg[s0 + w], seg[s0 + w + 1], quarter);
-        quarter.push_back(seg[s0 + kNW]);
-    }
+    std::vector<int32_t> order, seg;
+    for (size_t k = 0; k + 1 < ch.size(); ++k) wave_split(cost, ch[k], ch[k + 1], order, seg);
     std::vector<HClass> cls;
     std::vector<HSub> sub;
     std::vector<double> co;
@@ -229,7 +186,7 @@ const DeviceHam *device_ham(const Ham &h, int dev) {
     d->hzs = dev_upload(zs);
     d->hsub = dev_upload(sub);
     d->hchunk = dev_upload(ch);
-    d->hseg = dev_upload(quarter);
+    d->hseg = dev_upload(seg);
     d->n_chunks = (int)ch.size() - 1;
     h.dev[dev] = d.release();
     return h.dev[dev];
@@ -318,9 +275,7 @@ InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi, boo
     ip.o_pe2 = a.take((size_t)ip.n_groups * 8);
     ip.o_pn2 = a.take((size_t)ip.n_groups * 8);
     ip.n_counters = 4;
-    // line-search partials: two per pair block, then three per H v, H w
-    // workgroup (at most four per tile of 64 amplitudes)
-    ip.o_pl = a.take((2 * (size_t)ip.n_pblk + 12 * (size_t)ip.n_tiles) * 8);
+    ip.o_pl = a.take((3 * (size_t)ip.n_tiles + 2 * (size_t)ip.n_pblk) * 8);
     ip.o_pt = a.take((size_t)ip.n_pblk * 8);
     ip.o_cnt = a.take(ip.n_counters * sizeof(int32_t));
     ip.o_st = a.take(sizeof(AdaptState));
@@ -389,7 +344,6 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
     I.M = ip.M;
     I.n_tiles = ip.n_tiles;
     I.n_pblk = ip.n_pblk;
-    I.n_lpart = ip.n_tiles;
     return I;
 }
 
