@@ -56,6 +56,8 @@ inline Instance *instance_create(gocp_ctx *ctx, const Ham *h, const Pool *p, voi
     hip_check(hipMemsetAsync(in->mem + in->ip.o_v, 0, in->ip.o_pe - in->ip.o_v, s), "hipMemsetAsync");
     if (in->ip.o_hv)
         hip_check(hipMemsetAsync(in->mem + in->ip.o_hv, 0, in->ip.bytes - in->ip.o_hv, s), "hipMemsetAsync");
+    if (in->ip.o_actn)
+        hip_check(hipMemsetAsync(in->mem + in->ip.o_actn, 0, (size_t)in->ip.n_pblk * 4, s), "hipMemsetAsync");
     hip_check(hipMemcpyAsync(in->mem + in->ip.o_st, &st, sizeof(st), hipMemcpyHostToDevice, s), "H2D");
     if (own) launch_basis(dtype, in->psi, 1u << h->n_qubits, (uint32_t)hf, s);
     return in.release();
@@ -79,8 +81,10 @@ struct Group {
     size_t meta_cap = 0;
     InstDev *desc = nullptr;
     int2 *btile = nullptr, *bpair = nullptr, *bsub = nullptr, *binst = nullptr, *bgrp = nullptr;
+    int2 *bact = nullptr;      // rows of the compacted H v, H w launch (members with lists)
+    int2 *bhvw = nullptr;      // tile rows of the whole-state H v, H w launch (the others)
     int32_t *done = nullptr;   // n flags gathered on the device
-    int nt = 0, np = 0;
+    int nt = 0, np = 0, na = 0, nh = 0;
     std::vector<int> tile0, pair0;
     static constexpr int kChunk = 8;
     hipGraph_t graph[2] = {nullptr, nullptr};
@@ -104,7 +108,7 @@ struct Group {
     void rebuild(hipStream_t s) {
         drop_graphs();
         std::vector<InstDev> d;
-        std::vector<int2> bt, bp, bi, bg;
+        std::vector<int2> bt, bp, bi, bg, ba, bh;
         tile0.clear();
         pair0.clear();
         ntile.clear();
@@ -113,6 +117,18 @@ struct Group {
             InstDev di = inst[i]->desc;
             di.n_tiles = tiles_for(di.n_qubits, R);
             di.n_groups = (di.n_tiles + kGroup - 1) / kGroup;
+            // members that keep a list of the amplitudes where v or w is
+            // nonzero (complex64 states) take the compacted H v, H w launch:
+            // kHvwSlots tile slots (fewer for small states) of kHvwParts
+            // workgroups, a function of the member alone, so its results do
+            // not depend on the group it runs in
+            if (di.act) {
+                di.n_lpart = std::min(kHvwSlots, tiles_for(di.n_qubits, 1)) * kHvwParts;
+                for (int y = 0; y < di.n_lpart; ++y) ba.push_back(make_int2((int)i, y));
+            } else {
+                di.n_lpart = di.n_tiles;
+                for (int t = 0; t < di.n_tiles; ++t) bh.push_back(make_int2((int)i, t));
+            }
             d.push_back(di);
             ntile.push_back(di.n_tiles);
             tile0.push_back((int)bt.size());
@@ -126,6 +142,8 @@ struct Group {
         ng = (int)bg.size();
         nt = (int)bt.size();
         np = (int)bp.size();
+        na = (int)ba.size();
+        nh = (int)bh.size();
         const size_t sub = std::max<size_t>({bt.size(), bp.size(), inst.size(), 1});
         auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
         const size_t o_bt = al(d.size() * sizeof(InstDev));
@@ -133,7 +151,9 @@ struct Group {
         const size_t o_bs = o_bp + al(bp.size() * sizeof(int2));
         const size_t o_bi = o_bs + al(sub * sizeof(int2));
         const size_t o_bg = o_bi + al(std::max<size_t>(inst.size(), 1) * sizeof(int2));
-        const size_t o_dn = o_bg + al(std::max<size_t>(bg.size(), 1) * sizeof(int2));
+        const size_t o_ba = o_bg + al(std::max<size_t>(bg.size(), 1) * sizeof(int2));
+        const size_t o_bh = o_ba + al(std::max<size_t>(ba.size(), 1) * sizeof(int2));
+        const size_t o_dn = o_bh + al(std::max<size_t>(bh.size(), 1) * sizeof(int2));
         const size_t need = o_dn + al(std::max<size_t>(inst.size(), 1) * sizeof(int32_t));
         if (need > meta_cap) {
             if (meta) {
@@ -150,6 +170,8 @@ struct Group {
         bsub = reinterpret_cast<int2 *>(meta + o_bs);
         binst = reinterpret_cast<int2 *>(meta + o_bi);
         bgrp = reinterpret_cast<int2 *>(meta + o_bg);
+        bact = reinterpret_cast<int2 *>(meta + o_ba);
+        bhvw = reinterpret_cast<int2 *>(meta + o_bh);
         done = reinterpret_cast<int32_t *>(meta + o_dn);
         if (!d.empty())
             hip_check(hipMemcpyAsync(desc, d.data(), d.size() * sizeof(InstDev), hipMemcpyHostToDevice, s), "H2D");
@@ -161,6 +183,10 @@ struct Group {
             hip_check(hipMemcpyAsync(binst, bi.data(), bi.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
         if (!bg.empty())
             hip_check(hipMemcpyAsync(bgrp, bg.data(), bg.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
+        if (!ba.empty())
+            hip_check(hipMemcpyAsync(bact, ba.data(), ba.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
+        if (!bh.empty())
+            hip_check(hipMemcpyAsync(bhvw, bh.data(), bh.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
     }
 
     // One ADAPT iteration of every member: the selection from the pending
@@ -180,15 +206,23 @@ struct Group {
             int nrows;
         };
         (void)n;
-        const L seq[5] = {{K_LINE_VW, 1, bpair, np},       {K_LINE_HVW, 1, btile, nt},
+        const L seq[5] = {{K_LINE_VW, 1, bpair, np},       {K_LINE_HVW, 1, bhvw, nh},
                           {K_TAYLOR, 1, bpair, np},        {K_ENERGY_SCREEN, 2, btile, nt},
                           {K_SCREEN_SUM1, 2, bgrp, ng}};
         for (const L &l : seq) {
             const bool t = ev && l.kid == timed_kid;
             if (t) hip_check(hipEventRecord(ev[0], s), "hipEventRecord");
-            launch_kernel(l.kid, dtype, R, desc, l.rows, l.nrows, l.mode, s);
+            if (l.kid == K_LINE_HVW) launch_hvw(l.mode, s);
+            else launch_kernel(l.kid, dtype, R, desc, l.rows, l.nrows, l.mode, s);
             if (t) hip_check(hipEventRecord(ev[1], s), "hipEventRecord");
         }
+    }
+
+    // The H v, H w launches over the whole group (mode as k_line_hvw):
+    // compacted for members with lists, whole-state for the others.
+    void launch_hvw(int mode, hipStream_t s) const {
+        launch_hvw_act(desc, bact, na, mode, s);
+        launch_kernel(K_LINE_HVW, dtype, R, desc, bhvw, nh, mode, s);
     }
 
     // Selection (energy, gradients, operator, record) of every member's
@@ -248,13 +282,13 @@ struct Group {
         launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 3, s);
         launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 3, s);
         launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, n, 3, s);
-        launch_kernel(K_LINE_HVW, dtype, R, desc, btile, nt, 0, s);
+        launch_hvw(0, s);
         hip_check(hipEventRecord(e0, s), "hipEventRecord");
         for (int i = 0; i < reps; ++i) {
             launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 3, s);
             launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 3, s);
             launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, n, 3, s);
-            launch_kernel(K_LINE_HVW, dtype, R, desc, btile, nt, 0, s);
+            launch_hvw(0, s);
         }
         hip_check(hipEventRecord(e1, s), "hipEventRecord");
         hip_check(hipEventSynchronize(e1), "hipEventSynchronize");

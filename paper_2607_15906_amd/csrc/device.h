@@ -28,6 +28,14 @@ constexpr int kClassCost = 10;
 constexpr int kOpCost = 36;
 // Tiles per group in the first stage of the screen reduction.
 constexpr int kGroup = 16;
+// Compacted H v, H w launch (complex64 states): each tile of 64 active
+// amplitudes is spread over kHvwParts workgroups, each applying 1 / kHvwParts
+// of H's classes; an instance gets at most kHvwSlots tile slots (its
+// workgroups loop over further tiles), and states whose pair blocks number
+// more than kActMaxBlocks use the whole-state launch.
+constexpr int kHvwParts = 8;
+constexpr int kHvwSlots = 32;
+constexpr int kActMaxBlocks = 1024;
 // Launch mode of k_screen_reduce that selects the pending partials of an
 // ADAPT run (the iteration and mode k_energy_screen recorded with them).
 constexpr int kModePending = 5;
@@ -105,6 +113,7 @@ struct InstDev {
     const HSub *hsub;
     const int32_t *hchunk;      // n_hchunks + 1 class boundaries of the LDS stages
     const int32_t *hseg;        // n_hchunks x (kNW + 1) class boundaries of the waves
+    const int32_t *hsegp;       // n_hchunks x (kNW kHvwParts + 1): each wave's run cut into kHvwParts
     // pool, in pool order (pair kernels)
     const HClass *pop;          // one record per operator
     const HTerm *pterm;
@@ -123,13 +132,15 @@ struct InstDev {
     void *w;
     double2 *hv;                // H v and H w (FP64), kept by the line search for the
     double2 *hw;                // next sigma; null outside ADAPT runs of FP64 states
+    uint32_t *act;              // per pair block, the amplitudes where v or w is nonzero
+    int32_t *act_n;             // (compacted by k_line_vw; null unless compacted)
     double *part_e;             // n_tiles
     double *part_n;             // n_tiles
     double *part_g;             // n_tiles * M
     double *part_g2;            // n_groups * M (sums over groups of kGroup tiles)
     double *part_e2;            // n_groups
     double *part_n2;            // n_groups
-    double *part_l;             // 3 * n_tiles + 2 * n_pblk (line-search dots)
+    double *part_l;             // 2 * n_pblk + 3 * n_lpart (line-search dots)
     double *part_t;             // n_pblk (Taylor norms)
     int32_t *counters;          // arrival counters: [2] line search (others spare)
     AdaptState *st;
@@ -140,7 +151,7 @@ struct InstDev {
     int32_t n_hchunks;
     int32_t n_pchunks;
     int32_t n_groups;
-    int32_t pad1;
+    int32_t n_lpart;            // workgroups of the H v, H w launch (partial triples)
 };
 
 struct DeviceHam {
@@ -151,6 +162,7 @@ struct DeviceHam {
     HSub *hsub = nullptr;
     int32_t *hchunk = nullptr;
     int32_t *hseg = nullptr;     // per chunk, kNW + 1 wave boundaries of its classes
+    int32_t *hsegp = nullptr;    // per chunk, kNW kHvwParts + 1 boundaries of the waves' runs
     int n_chunks = 0;
 };
 

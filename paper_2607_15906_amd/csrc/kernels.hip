@@ -946,6 +946,8 @@ __global__ __launch_bounds__(kPairBlock) void k_line_vw(const InstDev *__restric
     const uint32_t half = 1u << (I.n_qubits - 1);
     const uint32_t p = (uint32_t)b.y * kPairBlock + threadIdx.x;
     double p2 = 0.0, p7 = 0.0;
+    bool fd = false, fe = false;
+    uint32_t ad = 0, ae = 0;
     if (p < half) {
         const uint32_t d = insert_zero_bit(p, hb), e = d ^ m;
         double hd, he;
@@ -963,11 +965,38 @@ __global__ __launch_bounds__(kPairBlock) void k_line_vw(const InstDev *__restric
         const double2 sd = I.sigma[d], se = I.sigma[e];
         p2 = vd.x * sd.x + vd.y * sd.y + ve.x * se.x + ve.y * se.y;
         p7 = sd.x * wd.x + sd.y * wd.y + se.x * we.x + se.y * we.y;
+        // the amplitudes where the stored v or w is nonzero
+        const double2 rvd = Amp<T>::rounded(vd), rwd = Amp<T>::rounded(wd);
+        const double2 rve = Amp<T>::rounded(ve), rwe = Amp<T>::rounded(we);
+        fd = rvd.x != 0.0 || rvd.y != 0.0 || rwd.x != 0.0 || rwd.y != 0.0;
+        fe = rve.x != 0.0 || rve.y != 0.0 || rwe.x != 0.0 || rwe.y != 0.0;
+        ad = d;
+        ae = e;
     }
     __shared__ double r2[kPairBlock / kWave], r7[kPairBlock / kWave];
+    const int wv = wave_id(), lane = threadIdx.x & (kWave - 1);
+    if (I.act) {
+        // compaction for the H v, H w launch: this block's active amplitudes
+        // in a fixed order (wave by wave; within a wave the first members of
+        // the pairs in lane order, then the second members)
+        __shared__ int wcnt[kPairBlock / kWave];
+        const unsigned long long bd = __ballot(fd), be = __ballot(fe);
+        const unsigned long long lt = (1ull << lane) - 1ull;
+        const int nd = __popcll(bd), ne = __popcll(be);
+        if (lane == 0) wcnt[wv] = nd + ne;
+        __syncthreads();
+        int base = 0, tot = 0;
+        for (int k = 0; k < kPairBlock / kWave; ++k) {
+            base += k < wv ? wcnt[k] : 0;
+            tot += wcnt[k];
+        }
+        uint32_t *out = I.act + (size_t)b.y * 2 * kPairBlock;
+        if (fd) out[base + __popcll(bd & lt)] = ad;
+        if (fe) out[base + nd + __popcll(be & lt)] = ae;
+        if (threadIdx.x == 0) I.act_n[b.y] = tot;
+    }
     p2 = wave_sum(p2);
     p7 = wave_sum(p7);
-    const int wv = wave_id(), lane = threadIdx.x & (kWave - 1);
     if (lane == 0) {
         r2[wv] = p2;
         r7[wv] = p7;
@@ -979,8 +1008,8 @@ __global__ __launch_bounds__(kPairBlock) void k_line_vw(const InstDev *__restric
             a2 += r2[k];
             a7 += r7[k];
         }
-        I.part_l[3 * I.n_tiles + 2 * b.y] = a2;
-        I.part_l[3 * I.n_tiles + 2 * b.y + 1] = a7;
+        I.part_l[2 * b.y] = a2;
+        I.part_l[2 * b.y + 1] = a7;
     }
 }
 
@@ -1129,9 +1158,10 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
         }
         if (__ballot(act) == 0ull) {
             if (wv == 0 && lane == 0) {
-                I.part_l[3 * b.y] = 0.0;
-                I.part_l[3 * b.y + 1] = 0.0;
-                I.part_l[3 * b.y + 2] = 0.0;
+                double *pl = I.part_l + 2 * I.n_pblk + 3 * b.y;
+                pl[0] = 0.0;
+                pl[1] = 0.0;
+                pl[2] = 0.0;
             }
             return;
         }
@@ -1177,10 +1207,109 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
         p5 = wave_sum(p5);
         p6 = wave_sum(p6);
         if (lane == 0) {
-            I.part_l[3 * b.y] = p3;
-            I.part_l[3 * b.y + 1] = p5;
-            I.part_l[3 * b.y + 2] = p6;
+            double *pl = I.part_l + 2 * I.n_pblk + 3 * b.y;
+            pl[0] = p3;
+            pl[1] = p5;
+            pl[2] = p6;
         }
+    }
+}
+
+// H v, H w dots over the compacted active amplitudes (complex64 states, whose
+// line search keeps no H v, H w).  The three dots have v* or w* as left
+// factor, so only amplitudes where v or w is nonzero contribute; k_line_vw
+// lists them per pair block.  Row (instance, slot kHvwParts + part): the
+// workgroup takes tiles slot, slot + kHvwSlots, ... of 64 listed amplitudes
+// (lane l of tile t has list entry 64 t + l, in pair-block order) and applies
+// the classes of run `part` of each wave segment (a 1 / kHvwParts share of H);
+// since the dots are linear in H v and H w, each (chunk, tile) adds
+// v* (H_part v) etc. at once.  Writes its partial triple to row y of the
+// line-search partials.  mode 1: ADAPT iteration; mode 0: timing.
+template <typename T>
+__global__ __launch_bounds__(kNW *kWave) void k_line_hvw_act(const InstDev *__restrict__ insts,
+                                                            const int2 *__restrict__ blk, int mode) {
+    const int2 b = blk[blockIdx.x];
+    const InstDev &I = insts[b.x];
+    AdaptState *st = I.st;
+    if (mode != 0 && state_done(st)) return;
+    const int slot = b.y / kHvwParts, part = b.y % kHvwParts;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = wave_id();
+    const uint32_t dim = 1u << I.n_qubits;
+    const int nb = I.n_pblk;
+    __shared__ int pre[kActMaxBlocks + 1];
+    __shared__ Stage S;
+    __shared__ double rsum[3][kNW];
+    // exclusive prefix of the blocks' counts (each at most 2 kPairBlock)
+    if (threadIdx.x == 0) {
+        int a = 0;
+        for (int i = 0; i < nb; ++i) {
+            pre[i] = a;
+            a += min(max(cptr(I.act_n)[i], 0), 2 * kPairBlock);
+        }
+        pre[nb] = a;
+    }
+    __syncthreads();
+    const int n_act = pre[nb];
+    double p3 = 0.0, p5 = 0.0, p6 = 0.0;
+    if (slot * kWave < n_act) {
+        const GOCP_AS4 HClass *hcls = cptr(I.hcls);
+        for (int k = 0; k < I.n_hchunks; ++k) {
+            const GOCP_AS4 int32_t *seg = cptr(I.hsegp) + k * (kNW * kHvwParts + 1);
+            const int cb = cptr(I.hchunk)[k], ce = cptr(I.hchunk)[k + 1];
+            const int sb = hcls[cb].s0, se = hcls[ce - 1].s1;
+            __syncthreads();
+            stage_copy(S.cls, I.hcls + cb, ce - cb);
+            stage_coef(S, I.hcoef, sb, se);
+            const GOCP_AS4 uint32_t *zs = cptr(I.hzs) + sb;
+            __syncthreads();
+            const int c0 = seg[wv * kHvwParts + part] - cb, c1 = seg[wv * kHvwParts + part + 1] - cb;
+            for (int t = slot; t * kWave < n_act; t += kHvwSlots) {
+                // this lane's amplitude: list entry g, found in the block prefix
+                const int g = t * kWave + lane;
+                const bool on = g < n_act;
+                uint32_t d = 0;
+                if (on) {
+                    int lo = 0, hi = nb;                  // pre[lo] <= g < pre[hi]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (pre[mid] <= g) lo = mid; else hi = mid;
+                    }
+                    d = I.act[(size_t)lo * 2 * kPairBlock + (g - pre[lo])] & (dim - 1u);
+                }
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                walk_classes_r1<T, 2>(S, zs, c0, c1, sb, d, I.v, I.w,
+                                      [&](int, double f, const typename Amp<T>::Raw (&p)[2]) {
+#pragma unroll
+                                          for (int v = 0; v < 2; ++v) {
+                                              const double2 a = Amp<T>::cvt(p[v]);
+                                              acc[2 * v] = fma(f, a.x, acc[2 * v]);
+                                              acc[2 * v + 1] = fma(f, a.y, acc[2 * v + 1]);
+                                          }
+                                      });
+                if (on) {
+                    const double2 ov = Amp<T>::load(I.v, d), ow = Amp<T>::load(I.w, d);
+                    p3 += ov.x * acc[0] + ov.y * acc[1];
+                    p5 += ow.x * acc[2] + ow.y * acc[3];
+                    p6 += ov.x * acc[2] + ov.y * acc[3];
+                }
+            }
+        }
+    }
+    // the workgroup's triple: wave sums, then waves in order
+    p3 = wave_sum(p3);
+    p5 = wave_sum(p5);
+    p6 = wave_sum(p6);
+    if (lane == 0) {
+        rsum[0][wv] = p3;
+        rsum[1][wv] = p5;
+        rsum[2][wv] = p6;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double a = 0.0;
+        for (int k = 0; k < kNW; ++k) a += rsum[threadIdx.x][k];
+        I.part_l[2 * I.n_pblk + 3 * b.y + threadIdx.x] = a;
     }
 }
 
@@ -1201,14 +1330,15 @@ __device__ void choose_angle(const InstDev &I, AdaptState *st, int j, bool write
     const double nrm = cptr(&st->nrm)[0], e_num = cptr(&st->e_num)[0];
     const double gj = cptr(st->g)[j], onorm = cptr(I.op_norm1)[j];
     double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < I.n_tiles; i += kPairBlock) {
-        q[0] += I.part_l[3 * i];
-        q[1] += I.part_l[3 * i + 1];
-        q[2] += I.part_l[3 * i + 2];
+    const double *pl = I.part_l + 2 * I.n_pblk;
+    for (int i = threadIdx.x; i < I.n_lpart; i += kPairBlock) {
+        q[0] += pl[3 * i];
+        q[1] += pl[3 * i + 1];
+        q[2] += pl[3 * i + 2];
     }
     for (int i = threadIdx.x; i < I.n_pblk; i += kPairBlock) {
-        q[3] += I.part_l[3 * I.n_tiles + 2 * i];
-        q[4] += I.part_l[3 * I.n_tiles + 2 * i + 1];
+        q[3] += I.part_l[2 * i];
+        q[4] += I.part_l[2 * i + 1];
     }
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -1436,6 +1566,12 @@ void launch_kernel(int which, int dtype, int R, const InstDev *insts, const int2
         launch_all<float2>(which, R, insts, blk, nblk, mode, s, j, th, ns);
     else
         launch_all<double2>(which, R, insts, blk, nblk, mode, s, j, th, ns);
+    hip_check(hipGetLastError(), "kernel launch");
+}
+
+void launch_hvw_act(const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s) {
+    if (nblk <= 0) return;
+    hipLaunchKernelGGL(k_line_hvw_act<float2>, dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode);
     hip_check(hipGetLastError(), "kernel launch");
 }
 

@@ -28,6 +28,9 @@ enum {
 // R = amplitudes per lane of the tile kernels (1, 2 or 4); the pair kernels ignore it.
 void launch_kernel(int which, int dtype, int R, const InstDev *insts, const int2 *blk, int nblk, int mode,
                    hipStream_t s, int j = 0, double th = 0.0, int ns = 0);
+// Compacted H v, H w launch (complex64 states with a compaction list): rows
+// (instance, slot kHvwParts + part).
+void launch_hvw_act(const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s);
 void launch_basis(int dtype, void *psi, uint32_t dim, uint32_t index, hipStream_t s);
 void launch_gather_done(const InstDev *insts, int n, int32_t *out, hipStream_t s);
 
@@ -39,7 +42,7 @@ struct InstPlan {
     size_t n_counters = 0;
     size_t o_sigma = 0, o_v = 0, o_w = 0, o_pe = 0, o_pn = 0, o_pg = 0, o_pg2 = 0, o_pe2 = 0, o_pn2 = 0, o_pl = 0, o_pt = 0,
            o_cnt = 0, o_st = 0, o_he = 0, o_hop = 0, o_hth = 0, o_hgn = 0, o_hgm = 0, o_hns = 0,
-           o_hpr = 0, o_g = 0, o_psi = 0, o_hv = 0, o_hw = 0;
+           o_hpr = 0, o_g = 0, o_psi = 0, o_hv = 0, o_hw = 0, o_act = 0, o_actn = 0;
     size_t bytes = 0;
 };
 

@@ -118,6 +118,41 @@ void wave_split(const std::vector<int> &cost, int b, int e, std::vector<int32_t>
     seg.push_back((int32_t)order.size());
 }
 
+// Cut the records order[a, b) of one wave into `parts` contiguous runs whose
+// largest cost is as small as possible (binary search on that cost with
+// greedy packing); appends the run starts a = b_0 <= ... <= b_{parts-1}.
+void cut_runs(const std::vector<int> &cost, const std::vector<int32_t> &order, int a, int b, int parts,
+              std::vector<int32_t> &out) {
+    long long lo = 0, hi = 0;
+    for (int i = a; i < b; ++i) {
+        lo = std::max<long long>(lo, cost[order[i]]);
+        hi += cost[order[i]];
+    }
+    auto pack = [&](long long cap, std::vector<int32_t> *cuts) {
+        int runs = 1;
+        long long cur = 0;
+        if (cuts) cuts->push_back(a);
+        for (int i = a; i < b; ++i) {
+            const int c = cost[order[i]];
+            if (cur + c > cap) {
+                ++runs;
+                cur = 0;
+                if (cuts) cuts->push_back(i);
+            }
+            cur += c;
+        }
+        return runs;
+    };
+    while (lo < hi) {
+        const long long mid = (lo + hi) / 2;
+        if (pack(mid, nullptr) <= parts) hi = mid; else lo = mid + 1;
+    }
+    std::vector<int32_t> cuts;
+    pack(lo, &cuts);
+    while ((int)cuts.size() < parts) cuts.push_back(b);
+    for (int k = 0; k < parts; ++k) out.push_back(cuts[k]);
+}
+
 // Padded string offsets of records taken in the order `rec` with `count(r)` strings.
 template <typename F>
 std::vector<int32_t> padded_offsets(int n, F count) {
@@ -139,6 +174,7 @@ void release_device_ham(DeviceHam *d) {
     (void)hipFree(d->hsub);
     (void)hipFree(d->hchunk);
     (void)hipFree(d->hseg);
+    (void)hipFree(d->hsegp);
     delete d;
 }
 
@@ -170,8 +206,15 @@ const DeviceHam *device_ham(const Ham &h, int dev) {
     const std::vector<int32_t> ch = stage_chunks(padded_offsets(nc, count));
     std::vector<int> cost(nc);
     for (int c = 0; c < nc; ++c) cost[c] = record_cost(count(c), kClassCost);
-    std::vector<int32_t> order, seg;
-    for (size_t k = 0; k + 1 < ch.size(); ++k) wave_split(cost, ch[k], ch[k + 1], order, seg);
+    // each wave's run is further cut into kHvwParts runs of nearly equal cost
+    // (the compacted H v, H w launch spreads a tile's classes over workgroups)
+    std::vector<int32_t> order, seg, segp;
+    for (size_t k = 0; k + 1 < ch.size(); ++k) {
+        const size_t s0 = seg.size();
+        wave_split(cost, ch[k], ch[k + 1], order, seg);
+        for (int w = 0; w < kNW; ++w) cut_runs(cost, order, seg[s0 + w], seg[s0 + w + 1], kHvwParts, segp);
+        segp.push_back(seg[s0 + kNW]);
+    }
     std::vector<HClass> cls;
     std::vector<HSub> sub;
     std::vector<double> co;
@@ -187,6 +230,7 @@ const DeviceHam *device_ham(const Ham &h, int dev) {
     d->hsub = dev_upload(sub);
     d->hchunk = dev_upload(ch);
     d->hseg = dev_upload(seg);
+    d->hsegp = dev_upload(segp);
     d->n_chunks = (int)ch.size() - 1;
     h.dev[dev] = d.release();
     return h.dev[dev];
@@ -275,7 +319,10 @@ InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi, boo
     ip.o_pe2 = a.take((size_t)ip.n_groups * 8);
     ip.o_pn2 = a.take((size_t)ip.n_groups * 8);
     ip.n_counters = 4;
-    ip.o_pl = a.take((3 * (size_t)ip.n_tiles + 2 * (size_t)ip.n_pblk) * 8);
+    // line-search partials: two per pair block, then three per H v, H w
+    // workgroup (one per tile, or kHvwParts per compacted tile slot)
+    const size_t n_lpart = std::max<size_t>(ip.n_tiles, (size_t)kHvwSlots * kHvwParts);
+    ip.o_pl = a.take((2 * (size_t)ip.n_pblk + 3 * n_lpart) * 8);
     ip.o_pt = a.take((size_t)ip.n_pblk * 8);
     ip.o_cnt = a.take(ip.n_counters * sizeof(int32_t));
     ip.o_st = a.take(sizeof(AdaptState));
@@ -291,6 +338,10 @@ InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi, boo
     if (adapt && dtype == GOCP_C128) {       // complex64 states never carry sigma
         ip.o_hv = a.take(dim * 16);
         ip.o_hw = a.take(dim * 16);
+    }
+    if (adapt && dtype == GOCP_C64 && ip.n_pblk <= kActMaxBlocks) {   // compacted H v, H w
+        ip.o_act = a.take((size_t)ip.n_pblk * 2 * kPairBlock * 4);
+        ip.o_actn = a.take((size_t)ip.n_pblk * 4);
     }
     ip.bytes = a.used;
     return ip;
@@ -308,6 +359,7 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
         I.hsub = dh->hsub;
         I.hchunk = dh->hchunk;
         I.hseg = dh->hseg;
+        I.hsegp = dh->hsegp;
         I.n_hchunks = dh->n_chunks;
     }
     if (p) {
@@ -329,6 +381,8 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
     I.w = b + ip.o_w;
     I.hv = ip.o_hv ? reinterpret_cast<double2 *>(b + ip.o_hv) : nullptr;
     I.hw = ip.o_hw ? reinterpret_cast<double2 *>(b + ip.o_hw) : nullptr;
+    I.act = ip.o_act ? reinterpret_cast<uint32_t *>(b + ip.o_act) : nullptr;
+    I.act_n = ip.o_actn ? reinterpret_cast<int32_t *>(b + ip.o_actn) : nullptr;
     I.part_e = reinterpret_cast<double *>(b + ip.o_pe);
     I.part_n = reinterpret_cast<double *>(b + ip.o_pn);
     I.part_g = reinterpret_cast<double *>(b + ip.o_pg);
@@ -344,6 +398,7 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
     I.M = ip.M;
     I.n_tiles = ip.n_tiles;
     I.n_pblk = ip.n_pblk;
+    I.n_lpart = ip.n_tiles;
     return I;
 }
 
