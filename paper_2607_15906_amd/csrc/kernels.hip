@@ -820,9 +820,13 @@ __device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it,
     double gmax = 0.0, gn = 0.0;
     int jmin = 0x7fffffff;
     if (screen) {
+        // a thread's first kCache gradients are kept for the tie-band pass
+        constexpr int kCache = 4;
+        double gc[kCache];
         double amax = 0.0, sq = 0.0;
-        for (int j = threadIdx.x; j < M; j += NT) {
+        for (int j = threadIdx.x, i = 0; j < M; j += NT, ++i) {
             const double g = grad(j);
+            if (i < kCache) gc[i] = g;
             if (writer && !dry) st->g[j] = g;
             amax = fmax(amax, fabs(g));
             sq += g * g;
@@ -843,8 +847,8 @@ __device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it,
         // lowest index within the tie band of the largest magnitude
         const double thresh = gmax * (1.0 - 1e-12);
         int jm = 0x7fffffff;
-        for (int j = threadIdx.x; j < M; j += NT)
-            if (fabs(grad(j)) >= thresh) {
+        for (int j = threadIdx.x, i = 0; j < M; j += NT, ++i)
+            if (fabs(i < kCache ? gc[i] : grad(j)) >= thresh) {
                 jm = j;
                 break;
             }
