@@ -51,8 +51,6 @@ inline Instance *instance_create(gocp_ctx *ctx, const Ham *h, const Pool *p, voi
     in->psi = own ? in->mem + in->ip.o_psi : psi;
     in->desc = make_desc(ctx->device, in->ip, in->mem, h, p, in->psi, nullptr);
     const AdaptState st = make_state(in->ip, in->mem, max_iter, tol, true);
-    hip_check(hipMemsetAsync(in->mem + in->ip.o_cnt, 0, in->ip.n_counters * sizeof(int32_t), s),
-              "hipMemsetAsync");
     hip_check(hipMemsetAsync(in->mem + in->ip.o_v, 0, in->ip.o_pe - in->ip.o_v, s), "hipMemsetAsync");
     if (in->ip.o_hv)
         hip_check(hipMemsetAsync(in->mem + in->ip.o_hv, 0, in->ip.bytes - in->ip.o_hv, s), "hipMemsetAsync");

@@ -142,7 +142,6 @@ struct InstDev {
     double *part_n2;            // n_groups
     double *part_l;             // 2 * n_pblk + 3 * n_lpart (line-search dots)
     double *part_t;             // n_pblk (Taylor norms)
-    int32_t *counters;          // arrival counters: [2] line search (others spare)
     AdaptState *st;
     int32_t n_qubits;
     int32_t M;

@@ -99,6 +99,12 @@ template <> struct Amp<float2> {
 // Read-only tables are read through the constant address space: with a wave
 // uniform index the load becomes a scalar (SMEM) load broadcast to all lanes.
 #define GOCP_AS4 __attribute__((address_space(4)))
+// Global-memory view of a pointer (vector loads without the flat path).
+template <typename T>
+__device__ __forceinline__ const GOCP_AS1 T *gptr(const T *p) {
+    return (const GOCP_AS1 T *)(uintptr_t)p;
+}
+
 template <typename T>
 __device__ __forceinline__ const GOCP_AS4 T *cptr(const T *p) {
     return (const GOCP_AS4 T *)(uintptr_t)p;
@@ -128,15 +134,24 @@ __device__ __forceinline__ double signed_coef(const HTerm &t, uint32_t d) {
     return __hiloint2double((int)(bit | (uint32_t)__double2hiint(t.c)), __double2loint(t.c));
 }
 
-// The same sum at two amplitudes d and e (the two members of a pair).
+// The same sum at two amplitudes d and e (the two members of a pair), in
+// string order.  The strings' scalar loads go out eight at a time (indices
+// clamped into the range, surplus strings skipped), so a generator of up to
+// eight strings waits once.
 __device__ __forceinline__ void string_sum2(const GOCP_AS4 HTerm *t, int s0, int s1, uint32_t d,
                                             uint32_t e, double &hd, double &he) {
     hd = 0.0;
     he = 0.0;
-    for (int s = s0; s < s1; ++s) {
-        const HTerm a = load_rec(t, s);
-        hd += signed_coef(a, d);
-        he += signed_coef(a, e);
+    for (int s = s0; s < s1; s += 8) {
+        HTerm a[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] = load_rec(t, min(s + q, s1 - 1));
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (s + q < s1) {
+                hd += signed_coef(a[q], d);
+                he += signed_coef(a[q], e);
+            }
     }
 }
 
@@ -205,41 +220,6 @@ __device__ double block_sum_strided(const double *src, int n, int stride, double
     return block_reduce<NT>(acc, lds);
 }
 
-// Cross-workgroup partial results.  A workgroup's partials are written with
-// device-coherent stores (they bypass the per-XCD L2), each writer waits for
-// its stores to complete, and only then is the arrival counter incremented;
-// the last workgroup to arrive reads the partials with device-coherent loads.
-// This needs no L2 writeback or invalidation, which would otherwise stall the
-// workgroups still running on the same XCD.
-__device__ __forceinline__ void st_coh(double *p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double ld_coh(const double *p) {
-    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Returns true (in every thread) in the workgroup that arrives last.
-__device__ bool arrive_last(int32_t *counter, int total) {
-    __shared__ int s_last;
-    __builtin_amdgcn_s_waitcnt(0);       // this wave's coherent stores have completed
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int prev = __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == total - 1);
-        if (s_last) __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    return s_last != 0;
-}
-
-// Sum of n coherent partials at stride `stride`, in index order per thread
-// and a fixed tree over threads; the result is returned to every thread.
-template <int NT>
-__device__ double block_sum_coh(const double *src, int n, int stride, double *lds) {
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += NT) acc += ld_coh(src + (size_t)i * stride);
-    return block_reduce<NT>(acc, lds);
-}
 
 // ------------------------------------------------------------------ LDS staging of term tables
 
@@ -756,25 +736,28 @@ __global__ __launch_bounds__(kPairBlock) void k_screen_sum1(const InstDev *__res
     const int it = mode == 2 ? cptr(&st->iter)[0] + 1 : 0;
     const int M = I.M;
     const bool screen = M > 0 && (oneshot || it < cptr(&st->max_iter)[0]);
+    // the group's kGroup loads go out together (indices clamped into the
+    // group, surplus values masked), then are added in tile order
     const int t0 = b.y * kGroup, nt = min(kGroup, I.n_tiles - t0);
     if (threadIdx.x < 2) {
-        const double *src = threadIdx.x == 0 ? I.part_e : I.part_n;
+        const GOCP_AS1 double *src = gptr(threadIdx.x == 0 ? I.part_e : I.part_n) + t0;
         double x[kGroup];
 #pragma unroll
-        for (int t = 0; t < kGroup; ++t) x[t] = t < nt ? src[t0 + t] : 0.0;
+        for (int t = 0; t < kGroup; ++t) x[t] = src[min(t, nt - 1)];
         double a = 0.0;
 #pragma unroll
-        for (int t = 0; t < kGroup; ++t) a += x[t];
+        for (int t = 0; t < kGroup; ++t) a += t < nt ? x[t] : 0.0;
         (threadIdx.x == 0 ? I.part_e2 : I.part_n2)[b.y] = a;
     }
     if (!screen) return;
+    const GOCP_AS1 double *pg = gptr(I.part_g) + (size_t)t0 * M;
     for (int j = threadIdx.x; j < M; j += kPairBlock) {
         double x[kGroup];
 #pragma unroll
-        for (int t = 0; t < kGroup; ++t) x[t] = t < nt ? I.part_g[(size_t)(t0 + t) * M + j] : 0.0;
+        for (int t = 0; t < kGroup; ++t) x[t] = pg[(size_t)min(t, nt - 1) * M + j];
         double a = 0.0;
 #pragma unroll
-        for (int t = 0; t < kGroup; ++t) a += x[t];
+        for (int t = 0; t < kGroup; ++t) a += t < nt ? x[t] : 0.0;
         I.part_g2[(size_t)b.y * M + j] = a;
     }
 }
@@ -798,23 +781,37 @@ __device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it,
     const int M = I.M, ng = I.n_groups;
     const int max_iter = cptr(&st->max_iter)[0];
     const bool screen = M > 0 && (oneshot || it < max_iter);
+    // sums over the groups in group order; loads go out kGroup at a time
+    // (indices clamped into range, surplus values masked), so a sum waits
+    // once per kGroup groups instead of once per group
+    const GOCP_AS1 double *pe2 = gptr(I.part_e2), *pn2 = gptr(I.part_n2), *pg2 = gptr(I.part_g2);
     double e_num = 0.0, nrm = 0.0;
-    for (int t = 0; t < ng; ++t) {
-        e_num += I.part_e2[t];
-        nrm += I.part_n2[t];
+    for (int t0 = 0; t0 < ng; t0 += kGroup) {
+        double xe[kGroup], xn[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            const int t = min(t0 + u, ng - 1);
+            xe[u] = pe2[t];
+            xn[u] = pn2[t];
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u)
+            if (t0 + u < ng) {
+                e_num += xe[u];
+                nrm += xn[u];
+            }
     }
     const double inv = 2.0 / nrm;
     auto grad = [&](int j) {
         double a = 0.0;
-        int t = 0;
-        for (; t + 8 <= ng; t += 8) {
-            double x[8];
+        for (int t0 = 0; t0 < ng; t0 += kGroup) {
+            double x[kGroup];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = I.part_g2[(size_t)(t + u) * M + j];
+            for (int u = 0; u < kGroup; ++u) x[u] = pg2[(size_t)min(t0 + u, ng - 1) * M + j];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a += x[u];
+            for (int u = 0; u < kGroup; ++u)
+                if (t0 + u < ng) a += x[u];
         }
-        for (; t < ng; ++t) a += I.part_g2[(size_t)t * M + j];
         return a * inv;
     };
     double gmax = 0.0, gn = 0.0;
@@ -954,9 +951,10 @@ __global__ __launch_bounds__(kPairBlock) void k_line_vw(const InstDev *__restric
     uint32_t ad = 0, ae = 0;
     if (p < half) {
         const uint32_t d = insert_zero_bit(p, hb), e = d ^ m;
+        const double2 a = Amp<T>::load(I.psi, d), c = Amp<T>::load(I.psi, e);
+        const double2 sd = I.sigma[d], se = I.sigma[e];
         double hd, he;
         string_sum2(cptr(I.pterm), C.s0, C.s1, d, e, hd, he);
-        const double2 a = Amp<T>::load(I.psi, d), c = Amp<T>::load(I.psi, e);
         const double2 wd = make_double2(hd * c.x, hd * c.y);
         const double2 we = make_double2(he * a.x, he * a.y);
         const double hh = -hd * he;
@@ -966,7 +964,6 @@ __global__ __launch_bounds__(kPairBlock) void k_line_vw(const InstDev *__restric
         Amp<T>::store(I.w, e, we);
         Amp<T>::store(I.v, d, vd);
         Amp<T>::store(I.v, e, ve);
-        const double2 sd = I.sigma[d], se = I.sigma[e];
         p2 = vd.x * sd.x + vd.y * sd.y + ve.x * se.x + ve.y * se.y;
         p7 = sd.x * wd.x + sd.y * wd.y + se.x * we.x + se.y * we.y;
         // the amplitudes where the stored v or w is nonzero
@@ -1244,14 +1241,25 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw_act(const InstDev *__re
     __shared__ int pre[kActMaxBlocks + 1];
     __shared__ Stage S;
     __shared__ double rsum[3][kNW];
-    // exclusive prefix of the blocks' counts (each at most 2 kPairBlock)
-    if (threadIdx.x == 0) {
-        int a = 0;
-        for (int i = 0; i < nb; ++i) {
-            pre[i] = a;
-            a += min(max(cptr(I.act_n)[i], 0), 2 * kPairBlock);
+    // exclusive prefix of the blocks' counts (each at most 2 kPairBlock): the
+    // counts are loaded by all threads at once, then scanned by wave 0, 64 at
+    // a time
+    for (int i = threadIdx.x; i < nb; i += kNW * kWave) pre[i + 1] = min(max(gptr(I.act_n)[i], 0), 2 * kPairBlock);
+    __syncthreads();
+    if (wv == 0) {
+        int carry = 0;
+        for (int base = 0; base < nb; base += kWave) {
+            const int i = base + lane;
+            int v = i < nb ? pre[i + 1] : 0;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int u = __shfl_up(v, off, kWave);
+                if (lane >= off) v += u;
+            }
+            if (i < nb) pre[i + 1] = carry + v;
+            carry += __shfl(v, kWave - 1, kWave);
         }
-        pre[nb] = a;
+        if (lane == 0) pre[0] = 0;
     }
     __syncthreads();
     const int n_act = pre[nb];
@@ -1334,15 +1342,15 @@ __device__ void choose_angle(const InstDev &I, AdaptState *st, int j, bool write
     const double nrm = cptr(&st->nrm)[0], e_num = cptr(&st->e_num)[0];
     const double gj = cptr(st->g)[j], onorm = cptr(I.op_norm1)[j];
     double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const double *pl = I.part_l + 2 * I.n_pblk;
+    const GOCP_AS1 double *pp = gptr(I.part_l), *pl = pp + 2 * I.n_pblk;
     for (int i = threadIdx.x; i < I.n_lpart; i += kPairBlock) {
         q[0] += pl[3 * i];
         q[1] += pl[3 * i + 1];
         q[2] += pl[3 * i + 2];
     }
     for (int i = threadIdx.x; i < I.n_pblk; i += kPairBlock) {
-        q[3] += I.part_l[2 * i];
-        q[4] += I.part_l[2 * i + 1];
+        q[3] += pp[2 * i];
+        q[4] += pp[2 * i + 1];
     }
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -1433,9 +1441,9 @@ __global__ __launch_bounds__(kPairBlock) void k_taylor5(const InstDev *__restric
     double hd = 0.0, he = 0.0;
     double2 a = make_double2(0.0, 0.0), c = a;
     if (own) {
-        string_sum2(cptr(I.pterm), C.s0, C.s1, d, e, hd, he);
         a = Amp<T>::load(I.psi, d);
         c = Amp<T>::load(I.psi, e);
+        string_sum2(cptr(I.pterm), C.s0, C.s1, d, e, hd, he);
     }
     double theta = theta_arg;
     int ns = s_arg;

@@ -39,9 +39,8 @@ struct InstPlan {
     int n_qubits = 0, M = 0, max_iter = 0, dtype = 0;
     int n_tiles = 0, n_pblk = 0;
     int n_groups = 0;
-    size_t n_counters = 0;
     size_t o_sigma = 0, o_v = 0, o_w = 0, o_pe = 0, o_pn = 0, o_pg = 0, o_pg2 = 0, o_pe2 = 0, o_pn2 = 0, o_pl = 0, o_pt = 0,
-           o_cnt = 0, o_st = 0, o_he = 0, o_hop = 0, o_hth = 0, o_hgn = 0, o_hgm = 0, o_hns = 0,
+           o_st = 0, o_he = 0, o_hop = 0, o_hth = 0, o_hgn = 0, o_hgm = 0, o_hns = 0,
            o_hpr = 0, o_g = 0, o_psi = 0, o_hv = 0, o_hw = 0, o_act = 0, o_actn = 0;
     size_t bytes = 0;
 };

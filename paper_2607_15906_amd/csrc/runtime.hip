@@ -318,13 +318,11 @@ InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi, boo
     ip.o_pg2 = a.take((size_t)ip.n_groups * std::max(M, 1) * 8);
     ip.o_pe2 = a.take((size_t)ip.n_groups * 8);
     ip.o_pn2 = a.take((size_t)ip.n_groups * 8);
-    ip.n_counters = 4;
     // line-search partials: two per pair block, then three per H v, H w
     // workgroup (one per tile, or kHvwParts per compacted tile slot)
     const size_t n_lpart = std::max<size_t>(ip.n_tiles, (size_t)kHvwSlots * kHvwParts);
     ip.o_pl = a.take((2 * (size_t)ip.n_pblk + 3 * n_lpart) * 8);
     ip.o_pt = a.take((size_t)ip.n_pblk * 8);
-    ip.o_cnt = a.take(ip.n_counters * sizeof(int32_t));
     ip.o_st = a.take(sizeof(AdaptState));
     ip.o_he = a.take(hist * 8);
     ip.o_hop = a.take(hist * 4);
@@ -392,7 +390,6 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
     I.n_groups = ip.n_groups;
     I.part_l = reinterpret_cast<double *>(b + ip.o_pl);
     I.part_t = reinterpret_cast<double *>(b + ip.o_pt);
-    I.counters = reinterpret_cast<int32_t *>(b + ip.o_cnt);
     I.st = reinterpret_cast<AdaptState *>(b + ip.o_st);
     I.n_qubits = ip.n_qubits;
     I.M = ip.M;
@@ -483,7 +480,6 @@ OneShot one_shot(gocp_ctx *ctx, const Ham *h, const Pool *p, const void *psi, in
     char *b = ctx->arena;
     o.base = b;
     hipStream_t s = ctx->user_stream;
-    hip_check(hipMemsetAsync(b + o.ip.o_cnt, 0, o.ip.n_counters * sizeof(int32_t), s), "hipMemsetAsync");
     InstDev I = make_desc(ctx->device, o.ip, b, h, p, const_cast<void *>(psi), sigma_override);
     AdaptState st = make_state(o.ip, b, 0, 0.0, false);
     hip_check(hipMemcpyAsync(b + o.ip.o_st, &st, sizeof(st), hipMemcpyHostToDevice, s), "H2D");

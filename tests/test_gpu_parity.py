@@ -288,3 +288,22 @@ def test_complex64_form_14q(g, ctx, mapping):
     fid = abs(np.vdot(psi64, psi32)) ** 2 / (np.vdot(psi32, psi32).real)
     assert fid >= 1 - 1e-6
     assert r32["ops"] == r64["ops"]
+
+
+def test_complex64_compacted_line_search_dense_state(g, ctx):
+    """From a dense random state every amplitude is active in the line search,
+    so the compacted H v / H w dots of complex64 states run two 64-amplitude
+    tiles per workgroup slot at 12 qubits; the trajectory must follow the
+    FP64 path (whole-state H v / H w) from the same starting state."""
+    _say("[c64] 12q dense start, compacted line search")
+    s = system(g, 12, "jw")
+    start = rand_state(12, 77).astype(np.complex64).astype(np.complex128)
+    start /= np.linalg.norm(start)
+    runs = {}
+    for dtype in ("c128", "c64"):
+        d = to_dev(start, dtype)
+        runs[dtype] = g.adapt_solve(ctx, s["gH"], s["gP"], d, 10, grad_tol=0.0, schedule=1)
+    r64, r32 = runs["c128"], runs["c64"]
+    assert r32["ops"] == r64["ops"]
+    assert np.abs(r32["energies"] - r64["energies"]).max() <= 1e-6
+    assert np.abs(np.array(r32["thetas"]) - np.array(r64["thetas"])).max() <= 1e-5
