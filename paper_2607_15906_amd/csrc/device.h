@@ -26,6 +26,9 @@ constexpr int kStrGroup = 4;
 // of a tile block (an H class; a screened operator, which adds a wave sum).
 constexpr int kClassCost = 10;
 constexpr int kOpCost = 36;
+// Strings a pair kernel reads at once; each pool operator's strings are padded
+// to a multiple of it (zero strings) in pool order.
+constexpr int kPairGroup = 8;
 // Tiles per group in the first stage of the screen reduction.
 constexpr int kGroup = 16;
 // Compacted H v, H w launch (complex64 states): each tile of 64 active

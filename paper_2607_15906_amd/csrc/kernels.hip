@@ -135,23 +135,22 @@ __device__ __forceinline__ double signed_coef(const HTerm &t, uint32_t d) {
 }
 
 // The same sum at two amplitudes d and e (the two members of a pair), in
-// string order.  The strings' scalar loads go out eight at a time (indices
-// clamped into the range, surplus strings skipped), so a generator of up to
-// eight strings waits once.
+// string order.  A pool operator's strings are padded with zero strings to a
+// multiple of kPairGroup, so its scalar loads go out kPairGroup at a time and
+// a generator of up to kPairGroup strings waits once.
 __device__ __forceinline__ void string_sum2(const GOCP_AS4 HTerm *t, int s0, int s1, uint32_t d,
                                             uint32_t e, double &hd, double &he) {
     hd = 0.0;
     he = 0.0;
-    for (int s = s0; s < s1; s += 8) {
-        HTerm a[8];
+    for (int s = s0; s < s1; s += kPairGroup) {
+        HTerm a[kPairGroup];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) a[q] = load_rec(t, min(s + q, s1 - 1));
+        for (int q = 0; q < kPairGroup; ++q) a[q] = load_rec(t, s + q);
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (s + q < s1) {
-                hd += signed_coef(a[q], d);
-                he += signed_coef(a[q], e);
-            }
+        for (int q = 0; q < kPairGroup; ++q) {
+            hd += signed_coef(a[q], d);
+            he += signed_coef(a[q], e);
+        }
     }
 }
 

@@ -242,10 +242,16 @@ const DevicePool *device_pool(const Pool &p, int dev) {
     if (p.dev[dev]) return p.dev[dev];
     std::unique_ptr<DevicePool> d(new DevicePool());
     d->device = dev;
+    // pool order (pair kernels): each operator's strings padded with zero
+    // strings to a multiple of kPairGroup, read kPairGroup at a time
     std::vector<HClass> ops(p.n_ops());
-    for (int k = 0; k < p.n_ops(); ++k) ops[k] = HClass{p.op_x[k], p.op_off[k], p.op_off[k + 1], p.kind[k]};
-    std::vector<HTerm> terms(p.str_z.size());
-    for (size_t s = 0; s < terms.size(); ++s) terms[s] = make_term(p.str_c[s], p.str_z[s]);
+    std::vector<HTerm> terms;
+    for (int k = 0; k < p.n_ops(); ++k) {
+        const int32_t s0 = (int32_t)terms.size();
+        for (int s = p.op_off[k]; s < p.op_off[k + 1]; ++s) terms.push_back(make_term(p.str_c[s], p.str_z[s]));
+        while ((terms.size() - s0) % kPairGroup) terms.push_back(HTerm{0.0, 0u, 0u});
+        ops[k] = HClass{p.op_x[k], s0, (int32_t)terms.size(), p.kind[k]};
+    }
     d->pop = dev_upload(ops);
     d->pterm = dev_upload(terms);
     d->op_norm1 = dev_upload(p.op_norm1);
