@@ -114,7 +114,7 @@ struct InstDev {
     const double *hcoef;        // |c| of H's strings, class by class
     const uint32_t *hzs;        // z | sign << 31 of the same strings
     const HSub *hsub;
-    const int32_t *hchunk;      // n_hchunks + 1 class boundaries of the LDS stages
+    const int4 *hchunk;         // per LDS stage: class range [x, y), string range [z, w)
     const int32_t *hseg;        // n_hchunks x (kNW + 1) class boundaries of the waves
     const int32_t *hsegp;       // n_hchunks x (kNW kHvwParts + 1): each wave's run cut into kHvwParts
     // pool, in pool order (pair kernels)
@@ -126,7 +126,7 @@ struct InstDev {
     const double *scoef;        // |c| and z | sign << 31 of the screen's strings
     const uint32_t *szs;
     const HSub *psub;
-    const int32_t *pchunk;      // n_pchunks + 1 operator boundaries of the LDS stages
+    const int4 *pchunk;         // per LDS stage: operator range [x, y), string range [z, w)
     const int32_t *pseg;        // n_pchunks x (kNW + 1) operator boundaries of the waves
     // buffers (psi, v, w in the state precision; sigma FP64)
     void *psi;
@@ -162,7 +162,7 @@ struct DeviceHam {
     double *hcoef = nullptr;
     uint32_t *hzs = nullptr;
     HSub *hsub = nullptr;
-    int32_t *hchunk = nullptr;
+    int4 *hchunk = nullptr;
     int32_t *hseg = nullptr;     // per chunk, kNW + 1 wave boundaries of its classes
     int32_t *hsegp = nullptr;    // per chunk, kNW kHvwParts + 1 boundaries of the waves' runs
     int n_chunks = 0;
@@ -177,7 +177,7 @@ struct DevicePool {
     double *scoef = nullptr;
     uint32_t *szs = nullptr;
     HSub *psub = nullptr;
-    int32_t *pchunk = nullptr;
+    int4 *pchunk = nullptr;
     int32_t *pseg = nullptr;     // per chunk, kNW + 1 wave boundaries of its operators
     int n_chunks = 0;
 };

@@ -118,6 +118,9 @@ __device__ __forceinline__ HClass load_rec(const GOCP_AS4 HClass *p, int i) {
     r.pad = p[i].pad;
     return r;
 }
+__device__ __forceinline__ int4 load_rec(const GOCP_AS4 int4 *p, int i) {
+    return make_int4(p[i].x, p[i].y, p[i].z, p[i].w);
+}
 __device__ __forceinline__ HTerm load_rec(const GOCP_AS4 HTerm *p, int i) {
     HTerm r;
     r.c = p[i].c;
@@ -155,6 +158,28 @@ __device__ __forceinline__ void string_sum2(const GOCP_AS4 HTerm *t, int s0, int
 }
 
 __device__ __forceinline__ int state_done(const AdaptState *st) { return cptr(&st->done)[0]; }
+
+// The leading fields of an instance's state record, read in one scalar load.
+struct StHead {
+    int32_t iter, max_iter, done, converged, jsel, nsub, status, pad0, pend_it, pend_mode, sel_it, sel_mode;
+};
+__device__ __forceinline__ StHead load_head(const AdaptState *st) {
+    const GOCP_AS4 int32_t *p = cptr(reinterpret_cast<const int32_t *>(st));
+    StHead h;
+    h.iter = p[0];
+    h.max_iter = p[1];
+    h.done = p[2];
+    h.converged = p[3];
+    h.jsel = p[4];
+    h.nsub = p[5];
+    h.status = p[6];
+    h.pad0 = p[7];
+    h.pend_it = p[8];
+    h.pend_mode = p[9];
+    h.sel_it = p[10];
+    h.sel_mode = p[11];
+    return h;
+}
 
 // Sum over a wave with an xor butterfly: every lane ends with the same value.
 // DPP move of a double (as two 32-bit halves); lanes of rows outside ROW_MASK
@@ -448,11 +473,10 @@ template <typename T, int NV, int R>
 __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32_t d0, uint32_t dim,
                                               const void *v0, const void *v1, double *acc) {
     const int wv = wave_id();
-    const GOCP_AS4 int32_t *hch = cptr(I.hchunk);
-    const GOCP_AS4 HClass *hcls = cptr(I.hcls);
+    const GOCP_AS4 int4 *hch = cptr(I.hchunk);
     for (int k = 0; k < I.n_hchunks; ++k) {
-        const int cb = hch[k], ce = hch[k + 1];
-        const int sb = hcls[cb].s0, se = hcls[ce - 1].s1;
+        const int4 bd = load_rec(hch, k);
+        const int cb = bd.x, ce = bd.y, sb = bd.z, se = bd.w;
         __syncthreads();
         stage_copy(S.cls, I.hcls + cb, ce - cb);
         if (R > 1) stage_copy(S.sub, I.hsub + cb, ce - cb);
@@ -545,14 +569,23 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
     const int2 b = blk[blockIdx.x];
     const InstDev &I = insts[b.x];
     AdaptState *st = I.st;
+    // the descriptor fields and the state record's head are each loaded in
+    // one batch ahead of every test that uses them (a chain of one load per
+    // field otherwise)
+    const int M = I.M, nq = I.n_qubits, nhc = I.n_hchunks;
+    const double2 *hvp = I.hv;
+    const GOCP_AS4 int4 *hch = cptr(I.hchunk);
+    asm volatile("" ::"s"(st), "s"(M), "s"(nq), "s"(nhc), "s"(hvp), "s"(hch));
+    const StHead h = load_head(st);
+    const int4 bd0 = load_rec(hch, 0);
+    asm volatile("" ::"s"(h.done), "s"(h.iter), "s"(h.max_iter), "s"(bd0.x), "s"(bd0.y), "s"(bd0.z), "s"(bd0.w));
     const bool oneshot = mode == 0 || mode >= 3, dry = mode >= 3;
-    if (!oneshot && state_done(st)) return;
-    const int it = mode == 2 ? cptr(&st->iter)[0] + 1 : 0;
-    const int M = I.M;
-    const bool screen = M > 0 && (oneshot || it < cptr(&st->max_iter)[0]);
+    if (!oneshot && h.done) return;
+    const int it = mode == 2 ? h.iter + 1 : 0;
+    const bool screen = M > 0 && (oneshot || it < h.max_iter);
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = wave_id();
-    const uint32_t dim = 1u << I.n_qubits;
+    const uint32_t dim = 1u << nq;
     const uint32_t d0 = (uint32_t)b.y * (kTile * R) + lane;
 
     __shared__ Stage S;
@@ -636,11 +669,10 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
         double2 sg[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) sg[r] = s_sig[r][lane];
-        const GOCP_AS4 int32_t *pch = cptr(I.pchunk);
-        const GOCP_AS4 HClass *sop = cptr(I.sop);
+        const GOCP_AS4 int4 *pch = cptr(I.pchunk);
         for (int k = 0; k < I.n_pchunks; ++k) {
-            const int ob = pch[k], oe = pch[k + 1];
-            const int sb = sop[ob].s0, se = sop[oe - 1].s1;
+            const int4 bd = load_rec(pch, k);
+            const int ob = bd.x, oe = bd.y, sb = bd.z, se = bd.w;
             __syncthreads();
             stage_copy(S.cls, I.sop + ob, oe - ob);
             if (R > 1) stage_copy(S.sub, I.psub + ob, oe - ob);
@@ -1264,11 +1296,10 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw_act(const InstDev *__re
     const int n_act = pre[nb];
     double p3 = 0.0, p5 = 0.0, p6 = 0.0;
     if (slot * kWave < n_act) {
-        const GOCP_AS4 HClass *hcls = cptr(I.hcls);
         for (int k = 0; k < I.n_hchunks; ++k) {
             const GOCP_AS4 int32_t *seg = cptr(I.hsegp) + k * (kNW * kHvwParts + 1);
-            const int cb = cptr(I.hchunk)[k], ce = cptr(I.hchunk)[k + 1];
-            const int sb = hcls[cb].s0, se = hcls[ce - 1].s1;
+            const int4 bd = load_rec(cptr(I.hchunk), k);
+            const int cb = bd.x, ce = bd.y, sb = bd.z, se = bd.w;
             __syncthreads();
             stage_copy(S.cls, I.hcls + cb, ce - cb);
             stage_coef(S, I.hcoef, sb, se);

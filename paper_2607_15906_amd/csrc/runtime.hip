@@ -153,6 +153,15 @@ void cut_runs(const std::vector<int> &cost, const std::vector<int32_t> &order, i
     for (int k = 0; k < parts; ++k) out.push_back(cuts[k]);
 }
 
+// Per LDS stage chunk (record boundaries b): its record range and the string
+// range of those records in the laid-out table.
+std::vector<int4> stage_bounds(const std::vector<int32_t> &b, const std::vector<HClass> &recs) {
+    std::vector<int4> out;
+    for (size_t k = 0; k + 1 < b.size(); ++k)
+        out.push_back(make_int4(b[k], b[k + 1], recs[b[k]].s0, recs[b[k + 1] - 1].s1));
+    return out;
+}
+
 // Padded string offsets of records taken in the order `rec` with `count(r)` strings.
 template <typename F>
 std::vector<int32_t> padded_offsets(int n, F count) {
@@ -228,7 +237,7 @@ const DeviceHam *device_ham(const Ham &h, int dev) {
     d->hcoef = dev_upload(co);
     d->hzs = dev_upload(zs);
     d->hsub = dev_upload(sub);
-    d->hchunk = dev_upload(ch);
+    d->hchunk = dev_upload(stage_bounds(ch, cls));
     d->hseg = dev_upload(seg);
     d->hsegp = dev_upload(segp);
     d->n_chunks = (int)ch.size() - 1;
@@ -282,7 +291,7 @@ const DevicePool *device_pool(const Pool &p, int dev) {
     d->scoef = dev_upload(co);
     d->szs = dev_upload(zs);
     d->psub = dev_upload(psub);
-    d->pchunk = dev_upload(pch);
+    d->pchunk = dev_upload(stage_bounds(pch, sop));
     d->pseg = dev_upload(seg);
     d->n_chunks = (int)pch.size() - 1;
     p.dev[dev] = d.release();
