@@ -105,6 +105,13 @@ __device__ __forceinline__ const GOCP_AS1 T *gptr(const T *p) {
     return (const GOCP_AS1 T *)(uintptr_t)p;
 }
 
+// Writable global-memory view (stores without the flat path: a flat store
+// still in flight makes every later wait on vector loads a full wait).
+template <typename T>
+__device__ __forceinline__ GOCP_AS1 T *gmut(T *p) {
+    return (GOCP_AS1 T *)(uintptr_t)p;
+}
+
 template <typename T>
 __device__ __forceinline__ const GOCP_AS4 T *cptr(const T *p) {
     return (const GOCP_AS4 T *)(uintptr_t)p;
@@ -252,7 +259,7 @@ __device__ double block_sum_strided(const double *src, int n, int stride, double
 // magnitudes (the strings' Z masks are read through the scalar cache); reused
 // for the cross-wave reduction.
 struct Stage {
-    double coef[kStageTerms];
+    double coef[kStageTerms + kStrGroup];   // the chunk's magnitudes, then one zero group
     HClass cls[kStageCls];
     HSub sub[kStageCls];
 };
@@ -282,6 +289,7 @@ __device__ __forceinline__ void stage_copy(R *dst, const R *src, int n) {
 
 __device__ __forceinline__ void stage_coef(Stage &S, const double *co, int sb, int se) {
     stage_copy(reinterpret_cast<u32x4 *>(S.coef), reinterpret_cast<const u32x4 *>(co + sb), (se - sb) / 2);
+    if (threadIdx.x < kStrGroup) S.coef[kStageTerms + threadIdx.x] = 0.0;
 }
 
 // |c| with sign bit popcount(d & z) + sign, for zs = z | sign << 31 and
@@ -456,6 +464,124 @@ __device__ __forceinline__ void walk_classes_r1(const Stage &S, const GOCP_AS4 u
     }
 }
 
+// One amplitude per lane, for operators linear in the per-group sums (H
+// applied to NV vectors): acc[2 v + {0,1}] += sum over the groups [g0, g1) of
+// the staged chunk (chunk-relative) of f_g(d) vec_v[d ^ x_g], with f_g the
+// signed sum of group g's kStrGroup strings and x_g its class's X mask.  The
+// groups are walked K at a time as a two-stage pipeline, 2 K per pass.  Z masks and X masks
+// come through the scalar cache and magnitudes from LDS; scalar loads return
+// out of order, so every use of one waits for all outstanding scalar and LDS
+// loads.  Each step therefore first waits for the data of its own K groups
+// (issued one step earlier), and only then issues the next step's loads:
+// Z masks and magnitudes of the next K groups, their gathers (with X masks
+// read two steps ahead), and the X masks of the step after.  Groups past g1
+// take their magnitudes from the stage's zero group; their Z and X masks are
+// read from the tables' zero padding or from the following groups (a run reads
+// up to 4 K - 1 groups past its end).
+// d must lie in the state.
+template <typename T, int NV, int K>
+__device__ __forceinline__ void walk_groups_r1(const Stage &S, const GOCP_AS4 uint32_t *zs,
+                                               const GOCP_AS4 uint32_t *gx, int g0, int g1, uint32_t d,
+                                               const void *v0, const void *v1, double *acc) {
+    using Raw = typename Amp<T>::Raw;
+    struct Bat {
+        double c[K][kStrGroup];
+        uint32_t z[K][kStrGroup];
+        Raw p[K][NV];
+    };
+    if (g0 >= g1) return;
+    uint32_t doff = d << Amp<T>::kShift;
+    asm volatile("" : "+v"(doff));      // keep the shifted offset: one XOR per gather
+    const uint32_t dz = with_sign_bit(d);
+    // the pointer and index laundering below ties each load to the wait
+    // before it (the loads are not hoisted above it)
+    auto load_x = [&](uint32_t (&x)[K], int g) {
+        const GOCP_AS4 uint32_t *p = gx + g;
+        asm volatile("" : "+s"(p));
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = p[k];
+    };
+    auto load_zc = [&](Bat &b, int g) {
+        const GOCP_AS4 uint32_t *zp = zs + kStrGroup * g;
+        asm volatile("" : "+s"(zp));
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < kStrGroup; ++q) b.z[k][q] = zp[kStrGroup * k + q];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            int ci = g + k < g1 ? kStrGroup * (g + k) : kStageTerms;
+            asm volatile("" : "+s"(ci));
+#pragma unroll
+            for (int q = 0; q < kStrGroup; ++q) b.c[k][q] = S.coef[ci + q];
+        }
+    };
+    auto gather = [&](Bat &b, const uint32_t (&x)[K]) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t o = doff ^ (x[k] << Amp<T>::kShift);
+            b.p[k][0] = Amp<T>::raw_at(v0, o);
+            if (NV == 2) b.p[k][NV - 1] = Amp<T>::raw_at(v1, o);
+        }
+    };
+    // (a use of scalar-loaded data waits for every outstanding scalar and LDS
+    // load, so the Z masks and X masks stand for the magnitudes too)
+    auto ready = [&](const Bat &b, const uint32_t (&x)[K]) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int q = 0; q < kStrGroup; ++q) asm volatile("" ::"s"(b.z[k][q]));
+            asm volatile("" ::"s"(x[k]));
+        }
+    };
+    auto compute = [&](const Bat &b) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double f0 = signed_cz(b.c[k][0], b.z[k][0], dz) + signed_cz(b.c[k][2], b.z[k][2], dz);
+            const double f1 = signed_cz(b.c[k][1], b.z[k][1], dz) + signed_cz(b.c[k][3], b.z[k][3], dz);
+            const double f = f0 + f1;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double2 a = Amp<T>::cvt(b.p[k][v]);
+                acc[2 * v] = fma(f, a.x, acc[2 * v]);
+                acc[2 * v + 1] = fma(f, a.y, acc[2 * v + 1]);
+            }
+        }
+    };
+    Bat A, B;
+    uint32_t xa[K], xb[K];
+    load_x(xa, g0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) asm volatile("" ::"s"(xa[k]));
+    gather(A, xa);
+    load_zc(A, g0);
+    load_x(xb, g0 + K);
+    // One exit, after both steps: every load issued is consumed on every
+    // path (a load used only past a branch would be sunk into it, next to its
+    // use).  A step that starts past g1 sums zero magnitudes; the last pass
+    // reads ahead into the tables' zero padding and leaves those loads unused.
+    // Scheduling barriers keep each step in the order wait, issue, compute.
+    for (int g = g0;; g += 2 * K) {
+        ready(A, xb);
+        __builtin_amdgcn_sched_barrier(0);
+        gather(B, xb);
+        load_zc(B, g + K);
+        load_x(xa, g + 2 * K);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(A);
+        __builtin_amdgcn_sched_barrier(0);
+        ready(B, xa);
+        __builtin_amdgcn_sched_barrier(0);
+        gather(A, xa);
+        load_zc(A, g + 2 * K);
+        load_x(xb, g + 3 * K);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(B);
+        __builtin_amdgcn_sched_barrier(0);
+        if (g + 2 * K >= g1) break;
+    }
+}
+
 // The wave's records [c0, c1) of stage chunk k (chunk-relative) from a
 // kNW + 1 boundary table per chunk.
 __device__ __forceinline__ void wave_range(const int32_t *seg, int k, int cb, int &c0, int &c1) {
@@ -478,26 +604,23 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
         const int4 bd = load_rec(hch, k);
         const int cb = bd.x, ce = bd.y, sb = bd.z, se = bd.w;
         __syncthreads();
-        stage_copy(S.cls, I.hcls + cb, ce - cb);
-        if (R > 1) stage_copy(S.sub, I.hsub + cb, ce - cb);
+        if (R > 1) {
+            stage_copy(S.cls, I.hcls + cb, ce - cb);
+            stage_copy(S.sub, I.hsub + cb, ce - cb);
+        }
         stage_coef(S, I.hcoef, sb, se);
         const GOCP_AS4 uint32_t *zs = cptr(I.hzs) + sb;
         __syncthreads();
-        int c0, c1;
-        wave_range(I.hseg, k, cb, c0, c1);
         if constexpr (R == 1) {
-            const uint32_t dd = d0 < dim ? d0 : 0u;
-            walk_classes_r1<T, NV>(S, zs, c0, c1, sb, dd, v0, v1,
-                                   [&](int, double f, const typename Amp<T>::Raw (&p)[NV]) {
-#pragma unroll
-                                       for (int v = 0; v < NV; ++v) {
-                                           const double2 a = Amp<T>::cvt(p[v]);
-                                           acc[2 * v] = fma(f, a.x, acc[2 * v]);
-                                           acc[2 * v + 1] = fma(f, a.y, acc[2 * v + 1]);
-                                       }
-                                   });
+            // the wave's run of string groups
+            const int gb = sb / kStrGroup;
+            const GOCP_AS4 int32_t *t = cptr(I.hgseg) + k * (kNW + 1) + wv;
+            walk_groups_r1<T, NV, kWalkBatch>(S, zs, cptr(I.hgx) + gb, t[0] - gb, t[1] - gb,
+                                              d0 < dim ? d0 : 0u, v0, v1, acc);
             continue;
         }
+        int c0, c1;
+        wave_range(I.hseg, k, cb, c0, c1);
         int c = c0;
         uint32_t off[R];
         lane_offsets<R, Amp<T>::kShift>(d0, dim, off);
@@ -600,8 +723,9 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
     //    which bounds the drift from the rounding of the stored state.
     const bool carry = I.hv != nullptr && (mode == 4 || (mode == 2 && (it % Refresh<T>::kPeriod) != 0));
     if ((mode == 1 || mode == 2) && b.y == 0 && threadIdx.x == 0) {
-        st->pend_it = it;
-        st->pend_mode = mode;
+        GOCP_AS1 AdaptState *gs = gmut(st);
+        gs->pend_it = it;
+        gs->pend_mode = mode;
     }
     double pe = 0.0, pn = 0.0;
     if (!carry) {
@@ -761,36 +885,41 @@ __global__ __launch_bounds__(kPairBlock) void k_screen_sum1(const InstDev *__res
                                                            const int2 *__restrict__ blk, int mode) {
     const int2 b = blk[blockIdx.x];
     const InstDev &I = insts[b.x];
-    AdaptState *st = I.st;
-    const bool oneshot = mode == 0 || mode >= 3;
-    if (!oneshot && state_done(st)) return;
-    const int it = mode == 2 ? cptr(&st->iter)[0] + 1 : 0;
-    const int M = I.M;
-    const bool screen = M > 0 && (oneshot || it < cptr(&st->max_iter)[0]);
+    // The descriptor fields are loaded in one batch; then the state record's
+    // head and the group's partials are loaded together: the sums are formed
+    // whatever the state says and stored only when it asks for them, so no
+    // load waits on the state's test (nor is moved behind it).
+    const AdaptState *st = I.st;
+    const int M = I.M, n_tiles = I.n_tiles;
+    const double *pe = I.part_e, *pn = I.part_n, *pg = I.part_g;
+    double *pe2 = I.part_e2, *pn2 = I.part_n2, *pg2 = I.part_g2;
+    asm volatile("" ::"s"(st), "s"(M), "s"(n_tiles), "s"(pe), "s"(pn), "s"(pg), "s"(pe2), "s"(pn2), "s"(pg2));
+    const StHead h = load_head(st);
     // the group's kGroup loads go out together (indices clamped into the
     // group, surplus values masked), then are added in tile order
-    const int t0 = b.y * kGroup, nt = min(kGroup, I.n_tiles - t0);
-    if (threadIdx.x < 2) {
-        const GOCP_AS1 double *src = gptr(threadIdx.x == 0 ? I.part_e : I.part_n) + t0;
+    const int t0 = b.y * kGroup, nt = min(kGroup, n_tiles - t0);
+    auto group_sum = [&](const GOCP_AS1 double *src, size_t stride) {
         double x[kGroup];
 #pragma unroll
-        for (int t = 0; t < kGroup; ++t) x[t] = src[min(t, nt - 1)];
+        for (int t = 0; t < kGroup; ++t) x[t] = src[(size_t)min(t, nt - 1) * stride];
         double a = 0.0;
 #pragma unroll
         for (int t = 0; t < kGroup; ++t) a += t < nt ? x[t] : 0.0;
-        (threadIdx.x == 0 ? I.part_e2 : I.part_n2)[b.y] = a;
-    }
+        return a;
+    };
+    const int j0 = threadIdx.x;
+    double ae = 0.0, ag = 0.0;
+    if (j0 < 2) ae = group_sum(gptr(j0 == 0 ? pe : pn) + t0, 1);
+    if (j0 < M) ag = group_sum(gptr(pg) + (size_t)t0 * M + j0, (size_t)M);
+    const bool oneshot = mode == 0 || mode >= 3;
+    const bool live = oneshot || !h.done;
+    const int it = mode == 2 ? h.iter + 1 : 0;
+    const bool screen = live && M > 0 && (oneshot || it < h.max_iter);
+    if (live && j0 < 2) (j0 == 0 ? pe2 : pn2)[b.y] = ae;
     if (!screen) return;
-    const GOCP_AS1 double *pg = gptr(I.part_g) + (size_t)t0 * M;
-    for (int j = threadIdx.x; j < M; j += kPairBlock) {
-        double x[kGroup];
-#pragma unroll
-        for (int t = 0; t < kGroup; ++t) x[t] = pg[(size_t)min(t, nt - 1) * M + j];
-        double a = 0.0;
-#pragma unroll
-        for (int t = 0; t < kGroup; ++t) a += t < nt ? x[t] : 0.0;
-        I.part_g2[(size_t)b.y * M + j] = a;
-    }
+    if (j0 < M) pg2[(size_t)b.y * M + j0] = ag;
+    for (int j = j0 + kPairBlock; j < M; j += kPairBlock)
+        pg2[(size_t)b.y * M + j] = group_sum(gptr(pg) + (size_t)t0 * M + j, (size_t)M);
 }
 
 // Second stage: energy, norm and gradients of an instance from the group sums,
@@ -852,10 +981,11 @@ __device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it,
         constexpr int kCache = 4;
         double gc[kCache];
         double amax = 0.0, sq = 0.0;
+        GOCP_AS1 double *gout = gmut(cptr(&st->g)[0]);
         for (int j = threadIdx.x, i = 0; j < M; j += NT, ++i) {
             const double g = grad(j);
             if (i < kCache) gc[i] = g;
-            if (writer && !dry) st->g[j] = g;
+            if (writer && !dry) gout[j] = g;
             amax = fmax(amax, fabs(g));
             sq += g * g;
         }
@@ -897,28 +1027,32 @@ __device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it,
     jsel = jmin < M ? jmin : 0;
     done = end;
     if (!writer || dry || threadIdx.x != 0) return;
-    st->e_num = e_num;
-    st->nrm = nrm;
-    st->energy = e;
+    // the record is written through global (not flat) stores; its history
+    // pointers are never written by a kernel
+    GOCP_AS1 AdaptState *gs = gmut(st);
+    double *hist_e = cptr(&st->hist_e)[0], *hist_gn = cptr(&st->hist_gnorm)[0], *hist_gm = cptr(&st->hist_gmax)[0];
+    gs->e_num = e_num;
+    gs->nrm = nrm;
+    gs->energy = e;
     if (mode == 1) {
-        if (st->hist_e) st->hist_e[0] = e;
+        if (hist_e) gmut(hist_e)[0] = e;
     } else if (mode == 2) {
-        st->iter = it;
-        if (st->hist_e) st->hist_e[it] = e;
+        gs->iter = it;
+        if (hist_e) gmut(hist_e)[it] = e;
     }
     if (screen) {
-        st->gmax = gmax;
-        st->gnorm = gn;
-        st->jsel = jsel;
+        gs->gmax = gmax;
+        gs->gnorm = gn;
+        gs->jsel = jsel;
         if (mode != 0) {
-            if (st->hist_gnorm) st->hist_gnorm[it] = gn;
-            if (st->hist_gmax) st->hist_gmax[it] = gmax;
+            if (hist_gn) gmut(hist_gn)[it] = gn;
+            if (hist_gm) gmut(hist_gm)[it] = gmax;
         }
     }
-    if (conv) st->converged = 1;
-    if (bad) st->status = GOCP_ENUMERIC;
-    if (end && mode != 0) st->done = 1;
-    if (bad) st->done = 1;
+    if (conv) gs->converged = 1;
+    if (bad) gs->status = GOCP_ENUMERIC;
+    if (end && mode != 0) gs->done = 1;
+    if (bad) gs->done = 1;
 }
 
 // Standalone selection, one workgroup per instance: modes as k_energy_screen,
@@ -958,18 +1092,33 @@ __global__ __launch_bounds__(kPairBlock) void k_line_vw(const InstDev *__restric
                                                        const int2 *__restrict__ blk) {
     const int2 b = blk[blockIdx.x];
     const InstDev &I = insts[b.x];
+    // the descriptor fields used by the selection and the pair work, then the
+    // state record's head, are each loaded in one batch ahead of their uses
+    // (a chain of one load per field otherwise)
     AdaptState *st = I.st;
-    if (state_done(st)) return;
+    {
+        const int M = I.M, ng = I.n_groups, nq = I.n_qubits;
+        const double *pe2 = I.part_e2, *pn2 = I.part_n2, *pg2 = I.part_g2;
+        const HClass *pop = I.pop;
+        const HTerm *pterm = I.pterm;
+        const void *psi = I.psi;
+        const double2 *sigma = I.sigma;
+        asm volatile("" ::"s"(st), "s"(M), "s"(ng), "s"(nq), "s"(pe2), "s"(pn2), "s"(pg2), "s"(pop), "s"(pterm),
+                     "s"(psi), "s"(sigma));
+    }
+    const StHead h = load_head(st);
+    asm volatile("" ::"s"(h.done), "s"(h.pend_it), "s"(h.pend_mode), "s"(h.sel_it), "s"(h.sel_mode), "s"(h.jsel),
+                 "s"(h.max_iter));
+    if (h.done) return;
     // selection of the partials the last k_energy_screen left, done by every
     // workgroup (the same sums in the same order) and recorded by pair block 0,
     // unless a standalone selection already recorded it
-    const int pit = cptr(&st->pend_it)[0], pmode = cptr(&st->pend_mode)[0];
     int j;
-    if (cptr(&st->sel_it)[0] == pit && cptr(&st->sel_mode)[0] == pmode) {
-        j = cptr(&st->jsel)[0];
+    if (h.sel_it == h.pend_it && h.sel_mode == h.pend_mode) {
+        j = h.jsel;
     } else {
         bool over;
-        select_state<kPairBlock>(I, st, pmode, pit, b.y == 0, j, over);
+        select_state<kPairBlock>(I, st, h.pend_mode, h.pend_it, b.y == 0, j, over);
         if (over) return;
     }
     const HClass C = load_rec(cptr(I.pop), j);
@@ -1262,20 +1411,63 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw_act(const InstDev *__re
                                                             const int2 *__restrict__ blk, int mode) {
     const int2 b = blk[blockIdx.x];
     const InstDev &I = insts[b.x];
-    AdaptState *st = I.st;
-    if (mode != 0 && state_done(st)) return;
     const int slot = b.y / kHvwParts, part = b.y % kHvwParts;
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = wave_id();
-    const uint32_t dim = 1u << I.n_qubits;
-    const int nb = I.n_pblk;
+    // the descriptor fields, then the state record's flag and the wave's
+    // chunk-0 run bounds, are each loaded in one batch ahead of their uses
+    // (a chain of one load per field otherwise)
+    const AdaptState *st = I.st;
+    const int nq = I.n_qubits, nb = I.n_pblk, loc = I.hvw_local;
+    const int32_t *hsegp = I.hsegp, *hsegps = I.hsegps, *act_n = I.act_n;
+    const void *vv = I.v, *vw = I.w;
+    const uint32_t *act = I.act, *hzs = I.hzs;
+    const HClass *hcls = I.hcls;
+    const double *hcoef = I.hcoef;
+    asm volatile("" ::"s"(st), "s"(nq), "s"(nb), "s"(loc), "s"(hsegp), "s"(hsegps), "s"(act_n), "s"(vv), "s"(vw),
+                 "s"(act), "s"(hzs), "s"(hcls), "s"(hcoef));
+    const int r0 = wv * kHvwParts + part;
+    const int done = cptr(&st->done)[0];
+    const int ra = cptr(hsegp)[r0], rb = cptr(hsegp)[r0 + 1], sa0 = cptr(hsegps)[r0], sb0 = cptr(hsegps)[r0 + 1];
+    asm volatile("" ::"s"(done), "s"(ra), "s"(rb), "s"(sa0), "s"(sb0));
+    if (mode != 0 && done) return;
+    const uint32_t dim = 1u << nq;
     __shared__ int pre[kActMaxBlocks + 1];
     __shared__ Stage S;
     __shared__ double rsum[3][kNW];
-    // exclusive prefix of the blocks' counts (each at most 2 kPairBlock): the
-    // counts are loaded by all threads at once, then scanned by wave 0, 64 at
-    // a time
-    for (int i = threadIdx.x; i < nb; i += kNW * kWave) pre[i + 1] = min(max(gptr(I.act_n)[i], 0), 2 * kPairBlock);
+    // When every run fits a wave's slice of the stage, each wave copies only
+    // its own run of chunk k (records, magnitudes) into its slice: no
+    // workgroup barrier, as the slice is the wave's alone and a wave's LDS
+    // accesses complete in order.  Chunk 0's copy is issued first, so that its
+    // loads overlap those of the counts below.
+    static_assert(kHvwWaveCls <= kWave && kActMaxBlocks <= kNW * kWave, "one record and one count per thread");
+    constexpr int kPer = kHvwWaveStr / kWave;
+    HClass rec{};
+    double cv[kPer];
+    auto load_run = [&](int a, int n, int sa, int sz) {
+        if (lane < n) rec = load_rec(cptr(hcls), a + lane);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int i = lane + j * kWave;
+            cv[j] = i < sz ? gptr(hcoef)[sa + i] : 0.0;
+        }
+    };
+    auto store_run = [&](int n, int sz) {
+        if (lane < n) S.cls[wv * kHvwWaveCls + lane] = rec;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int i = lane + j * kWave;
+            if (i < sz) S.coef[wv * kHvwWaveStr + i] = cv[j];
+        }
+    };
+    // chunk 0's run and the blocks' counts: every load is issued before the
+    // first LDS write
+    if (loc) load_run(ra, rb - ra, sa0, sb0 - sa0);
+    const int cnt = threadIdx.x < nb ? min(max(gptr(act_n)[threadIdx.x], 0), 2 * kPairBlock) : 0;
+    if (loc) store_run(rb - ra, sb0 - sa0);
+    // exclusive prefix of the blocks' counts (each at most 2 kPairBlock),
+    // scanned by wave 0, 64 at a time
+    if (threadIdx.x < nb) pre[threadIdx.x + 1] = cnt;
     __syncthreads();
     if (wv == 0) {
         int carry = 0;
@@ -1297,15 +1489,36 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw_act(const InstDev *__re
     double p3 = 0.0, p5 = 0.0, p6 = 0.0;
     if (slot * kWave < n_act) {
         for (int k = 0; k < I.n_hchunks; ++k) {
-            const GOCP_AS4 int32_t *seg = cptr(I.hsegp) + k * (kNW * kHvwParts + 1);
-            const int4 bd = load_rec(cptr(I.hchunk), k);
-            const int cb = bd.x, ce = bd.y, sb = bd.z, se = bd.w;
-            __syncthreads();
-            stage_copy(S.cls, I.hcls + cb, ce - cb);
-            stage_coef(S, I.hcoef, sb, se);
-            const GOCP_AS4 uint32_t *zs = cptr(I.hzs) + sb;
-            __syncthreads();
-            const int c0 = seg[wv * kHvwParts + part] - cb, c1 = seg[wv * kHvwParts + part + 1] - cb;
+            const int r = k * (kNW * kHvwParts + 1) + r0;
+            const GOCP_AS4 int32_t *seg = cptr(hsegp) + r;
+            // the wave's run of classes [c0, c1) in the stage, and the string
+            // base sb of the stage's magnitudes (string s at S.coef[s - sb])
+            int c0, c1, sb;
+            if (loc) {
+                int a = ra, e = rb, sa = sa0;
+                if (k > 0) {
+                    const GOCP_AS4 int32_t *sp = cptr(hsegps) + r;
+                    a = seg[0];
+                    e = seg[1];
+                    sa = sp[0];
+                    load_run(a, e - a, sa, sp[1] - sa);
+                    store_run(e - a, sp[1] - sa);
+                }
+                c0 = wv * kHvwWaveCls;
+                c1 = c0 + (e - a);
+                sb = sa - wv * kHvwWaveStr;
+            } else {
+                const int4 bd = load_rec(cptr(I.hchunk), k);
+                const int cb = bd.x, ce = bd.y;
+                sb = bd.z;
+                __syncthreads();
+                stage_copy(S.cls, I.hcls + cb, ce - cb);
+                stage_coef(S, I.hcoef, sb, bd.w);
+                __syncthreads();
+                c0 = seg[0] - cb;
+                c1 = seg[1] - cb;
+            }
+            const GOCP_AS4 uint32_t *zs = cptr(hzs) + sb;
             for (int t = slot; t * kWave < n_act; t += kHvwSlots) {
                 // this lane's amplitude: list entry g, found in the block prefix
                 const int g = t * kWave + lane;
@@ -1317,10 +1530,12 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw_act(const InstDev *__re
                         const int mid = (lo + hi) >> 1;
                         if (pre[mid] <= g) lo = mid; else hi = mid;
                     }
-                    d = I.act[(size_t)lo * 2 * kPairBlock + (g - pre[lo])] & (dim - 1u);
+                    d = act[(size_t)lo * 2 * kPairBlock + (g - pre[lo])] & (dim - 1u);
                 }
                 double acc[4] = {0.0, 0.0, 0.0, 0.0};
-                walk_classes_r1<T, 2>(S, zs, c0, c1, sb, d, I.v, I.w,
+                // runs of a few classes: the class walk, whose pipeline fills
+                // faster than the grouped walk's
+                walk_classes_r1<T, 2>(S, zs, c0, c1, sb, d, vv, vw,
                                       [&](int, double f, const typename Amp<T>::Raw (&p)[2]) {
 #pragma unroll
                                           for (int v = 0; v < 2; ++v) {
@@ -1330,7 +1545,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw_act(const InstDev *__re
                                           }
                                       });
                 if (on) {
-                    const double2 ov = Amp<T>::load(I.v, d), ow = Amp<T>::load(I.w, d);
+                    const double2 ov = Amp<T>::load(vv, d), ow = Amp<T>::load(vw, d);
                     p3 += ov.x * acc[0] + ov.y * acc[1];
                     p5 += ow.x * acc[2] + ow.y * acc[3];
                     p6 += ov.x * acc[2] + ov.y * acc[3];
@@ -1362,26 +1577,58 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw_act(const InstDev *__re
 // the five dot products, each summed in a fixed order, give the landscape, and
 // wave 0 searches it.  Returns theta and the substep count in every thread;
 // the workgroup of pair block 0 also writes the iteration record.
-__device__ void choose_angle(const InstDev &I, AdaptState *st, int j, bool writer, double &theta, int &ns) {
+// Inputs of the landscape: the state's scalars and the selected operator's
+// gradient and norm (scalar loads), and this thread's shares of the five
+// line-search dot products (vector loads).  Issued in one batch; the values
+// are first used by choose_angle.
+struct AngleIn {
+    double nrm, e_num, gj, onorm;
+    double r[5];                // the thread's first share (masked by use3, use2)
+    double q[5];                // the sum of its further shares
+    bool use3, use2;
+};
+__device__ __forceinline__ void angle_loads(const AdaptState *st, const double *g, const double *op_norm1,
+                                            const double *part_l, int n_pblk, int n_lpart, int j, AngleIn &in) {
+    in.nrm = cptr(&st->nrm)[0];
+    in.e_num = cptr(&st->e_num)[0];
+    in.gj = cptr(g)[j];
+    in.onorm = cptr(op_norm1)[j];
+    // a thread's first share is loaded (at a clamped index) and left
+    // unused until the angle is chosen, so nothing waits on it here; further
+    // shares, for states with more partials than threads, are summed in
+    // their loops
+    const GOCP_AS1 double *pp = gptr(part_l), *pl = pp + 2 * n_pblk;
+    const int i0 = threadIdx.x;
+    const int l3 = min(i0, n_lpart - 1), l2 = min(i0, n_pblk - 1);
+    in.use3 = i0 < n_lpart;
+    in.use2 = i0 < n_pblk;
+    in.r[0] = pl[3 * l3];
+    in.r[1] = pl[3 * l3 + 1];
+    in.r[2] = pl[3 * l3 + 2];
+    in.r[3] = pp[2 * l2];
+    in.r[4] = pp[2 * l2 + 1];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) in.q[k] = 0.0;
+    for (int i = i0 + kPairBlock; i < n_lpart; i += kPairBlock) {
+        in.q[0] += pl[3 * i];
+        in.q[1] += pl[3 * i + 1];
+        in.q[2] += pl[3 * i + 2];
+    }
+    for (int i = i0 + kPairBlock; i < n_pblk; i += kPairBlock) {
+        in.q[3] += pp[2 * i];
+        in.q[4] += pp[2 * i + 1];
+    }
+}
+
+__device__ void choose_angle(const AngleIn &in, AdaptState *st, int j, bool writer, double &theta, int &ns) {
     __shared__ double red[5][kPairBlock / kWave];
     __shared__ double s_th;
     __shared__ int s_ns;
     const int lane = threadIdx.x & (kWave - 1), wv = wave_id();
-    // scalar inputs of the landscape, loaded before the partial sums so that
-    // their latency overlaps
-    const double nrm = cptr(&st->nrm)[0], e_num = cptr(&st->e_num)[0];
-    const double gj = cptr(st->g)[j], onorm = cptr(I.op_norm1)[j];
-    double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const GOCP_AS1 double *pp = gptr(I.part_l), *pl = pp + 2 * I.n_pblk;
-    for (int i = threadIdx.x; i < I.n_lpart; i += kPairBlock) {
-        q[0] += pl[3 * i];
-        q[1] += pl[3 * i + 1];
-        q[2] += pl[3 * i + 2];
-    }
-    for (int i = threadIdx.x; i < I.n_pblk; i += kPairBlock) {
-        q[3] += pp[2 * i];
-        q[4] += pp[2 * i + 1];
-    }
+    const double nrm = in.nrm, e_num = in.e_num, gj = in.gj, onorm = in.onorm;
+    double q[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) q[k] = ((k < 3 ? in.use3 : in.use2) ? in.r[k] : 0.0) + in.q[k];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         const double v = wave_sum(q[k]);
@@ -1425,17 +1672,23 @@ __device__ void choose_angle(const InstDev &I, AdaptState *st, int j, bool write
                         be = nb;
                     }
                 }
-                st->upd_alpha = al;
-                st->upd_beta = be;
-                st->upd_scale = 1.0 / sqrt(nrm);
-                st->theta = th;
-                st->nsub = n;
-                st->pred = L.value(th);
-                const int it = st->iter;
-                if (st->hist_op) st->hist_op[it] = j;
-                if (st->hist_theta) st->hist_theta[it] = th;
-                if (st->hist_nsub) st->hist_nsub[it] = n;
-                if (st->hist_pred) st->hist_pred[it] = st->pred;
+                // global (not flat) stores; the history pointers are never
+                // written by a kernel
+                GOCP_AS1 AdaptState *gs = gmut(st);
+                const double pred = L.value(th);
+                gs->upd_alpha = al;
+                gs->upd_beta = be;
+                gs->upd_scale = 1.0 / sqrt(nrm);
+                gs->theta = th;
+                gs->nsub = n;
+                gs->pred = pred;
+                const int it = cptr(&st->iter)[0];
+                int32_t *h_op = cptr(&st->hist_op)[0], *h_ns = cptr(&st->hist_nsub)[0];
+                double *h_th = cptr(&st->hist_theta)[0], *h_pr = cptr(&st->hist_pred)[0];
+                if (h_op) gmut(h_op)[it] = j;
+                if (h_th) gmut(h_th)[it] = th;
+                if (h_ns) gmut(h_ns)[it] = n;
+                if (h_pr) gmut(h_pr)[it] = pred;
             }
         }
     }
@@ -1450,35 +1703,55 @@ __device__ void choose_angle(const InstDev &I, AdaptState *st, int j, bool write
 // (the renormalisation of the previous update, applied here); one-shot calls
 // pass them as arguments.  Writes the per-workgroup |psi|^2 of the result to
 // part_t.
-template <typename T>
+template <typename T, bool Adapt>
 __global__ __launch_bounds__(kPairBlock) void k_taylor5(const InstDev *__restrict__ insts,
-                                                       const int2 *__restrict__ blk, int adapt,
-                                                       int j_arg, double theta_arg, int s_arg) {
+                                                       const int2 *__restrict__ blk, int j_arg, double theta_arg,
+                                                       int s_arg) {
     const int2 b = blk[blockIdx.x];
     const InstDev &I = insts[b.x];
+    // Loads in batches ahead of their uses (a chain of one load per field
+    // otherwise): the descriptor fields; the state record's head; then the
+    // generator's record, gradient and norm together with the line-search
+    // partials; then its strings and the pair's amplitudes.  None of the pair
+    // work depends on the angle, so all of it is read before the angle is
+    // chosen.
     AdaptState *st = I.st;
-    if (adapt && state_done(st)) return;
-    const int j = adapt ? cptr(&st->jsel)[0] : j_arg;
-    // the pair, its generator coefficients and amplitudes do not depend on
-    // the angle: they are read before the angle is chosen
-    const HClass C = load_rec(cptr(I.pop), j);
+    const HClass *pop = I.pop;
+    const HTerm *pterm = I.pterm;
+    const double *op_norm1 = I.op_norm1, *part_l = I.part_l;
+    void *psi = I.psi;
+    const int nq = I.n_qubits, npb = I.n_pblk, nlp = I.n_lpart;
+    asm volatile("" ::"s"(st), "s"(pop), "s"(pterm), "s"(op_norm1), "s"(part_l), "s"(psi), "s"(nq), "s"(npb),
+                 "s"(nlp));
+    int j = j_arg;
+    const double *gv = nullptr;
+    if constexpr (Adapt) {
+        const StHead h = load_head(st);
+        gv = cptr(&st->g)[0];
+        asm volatile("" ::"s"(h.done), "s"(h.jsel), "s"(gv));
+        if (h.done) return;
+        j = h.jsel;
+    }
+    const HClass C = load_rec(cptr(pop), j);
+    AngleIn in;
+    if constexpr (Adapt) angle_loads(st, gv, op_norm1, part_l, npb, nlp, j, in);
     const uint32_t m = C.x;
     const int hb = 31 - __clz(m);
-    const uint32_t half = 1u << (I.n_qubits - 1);
+    const uint32_t half = 1u << (nq - 1);
     const uint32_t p = (uint32_t)b.y * kPairBlock + threadIdx.x;
     const bool own = p < half;
     const uint32_t d = own ? insert_zero_bit(p, hb) : 0u, e = d ^ m;
     double hd = 0.0, he = 0.0;
     double2 a = make_double2(0.0, 0.0), c = a;
     if (own) {
-        a = Amp<T>::load(I.psi, d);
-        c = Amp<T>::load(I.psi, e);
-        string_sum2(cptr(I.pterm), C.s0, C.s1, d, e, hd, he);
+        a = Amp<T>::load(psi, d);
+        c = Amp<T>::load(psi, e);
+        string_sum2(cptr(pterm), C.s0, C.s1, d, e, hd, he);
     }
     double theta = theta_arg;
     int ns = s_arg;
-    if (adapt) choose_angle(I, st, j, b.y == 0, theta, ns);
-    const double scale = adapt ? 1.0 / sqrt(cptr(&st->nrm)[0]) : 1.0;
+    if constexpr (Adapt) choose_angle(in, st, j, b.y == 0, theta, ns);
+    const double scale = Adapt ? 1.0 / sqrt(in.nrm) : 1.0;
     double nn = 0.0;
     if (own) {
         a.x *= scale; a.y *= scale;
@@ -1594,7 +1867,10 @@ static void launch_all(int which, int R, const InstDev *insts, const int2 *blk, 
     case 1: hipLaunchKernelGGL(k_screen_reduce, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode); break;
     case 7: hipLaunchKernelGGL(k_screen_sum1, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode); break;
     case 2: hipLaunchKernelGGL(k_line_vw<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk); break;
-    case 4: hipLaunchKernelGGL(k_taylor5<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode, j, th, ns); break;
+    case 4:
+        if (mode) hipLaunchKernelGGL((k_taylor5<T, true>), dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, j, th, ns);
+        else hipLaunchKernelGGL((k_taylor5<T, false>), dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, j, th, ns);
+        break;
     case 5: hipLaunchKernelGGL(k_normalize<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode); break;
     case 6: hipLaunchKernelGGL(k_state_unit_norm, dim3(nblk), dim3(64), 0, s, insts, blk); break;
     default: break;
