@@ -307,3 +307,29 @@ def test_complex64_compacted_line_search_dense_state(g, ctx):
     assert r32["ops"] == r64["ops"]
     assert np.abs(r32["energies"] - r64["energies"]).max() <= 1e-6
     assert np.abs(np.array(r32["thetas"]) - np.array(r64["thetas"])).max() <= 1e-5
+
+
+def test_complex64_compacted_line_search_large_class(g, ctx):
+    """A Hamiltonian with one X-mask class longer than a wave's share of the
+    compacted H v / H w launch's stage (the diagonal class, 400 extra Z
+    strings at 12 qubits): that launch stages whole chunks instead of each
+    wave's own run.  The complex64 trajectory must follow the FP64 path."""
+    _say("[c64] 12q large diagonal class, compacted line search with full staging")
+    s = system(g, 12, "jw")
+    x, z, c = s["gH"].terms()
+    rng = np.random.default_rng(5)
+    present = {int(zz) for xx, zz in zip(x, z) if int(xx) == 0}
+    extra = [m for m in rng.permutation(np.arange(1, 1 << 12)) if int(m) not in present][:400]
+    xs = np.concatenate([x, np.zeros(len(extra), dtype=x.dtype)])
+    zs = np.concatenate([z, np.array(extra, dtype=z.dtype)])
+    cs = np.concatenate([c, rng.uniform(-0.01, 0.01, len(extra))])
+    H = g.pauli_hamiltonian_load_terms(12, xs, zs, cs)
+    assert int(np.sum(H.terms()[0] == 0)) > 256
+    runs = {}
+    for dtype in ("c128", "c64"):
+        psi = torch.zeros(1 << 12, dtype=torch.complex128 if dtype == "c128" else torch.complex64, device="cuda")
+        g.state_basis(ctx, 12, s["hf"], psi)
+        runs[dtype] = g.adapt_solve(ctx, H, s["gP"], psi, 12, grad_tol=0.0, schedule=1)
+    r64, r32 = runs["c128"], runs["c64"]
+    assert r32["ops"] == r64["ops"]
+    assert np.abs(r32["energies"] - r64["energies"]).max() <= 1e-6
