@@ -185,6 +185,9 @@ struct Group {
             hip_check(hipMemcpyAsync(bact, ba.data(), ba.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
         if (!bh.empty())
             hip_check(hipMemcpyAsync(bhvw, bh.data(), bh.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
+        // a group of one instance launches with null row tables: its rows
+        // are (0, workgroup index), which the kernels then form without a load
+        if (inst.size() == 1) btile = bpair = binst = bgrp = bact = bhvw = nullptr;
     }
 
     // One ADAPT iteration of every member: the selection from the pending

@@ -166,6 +166,14 @@ __device__ __forceinline__ void string_sum2(const GOCP_AS4 HTerm *t, int s0, int
 
 __device__ __forceinline__ int state_done(const AdaptState *st) { return cptr(&st->done)[0]; }
 
+// The workgroup's work row (instance, index).  A null table stands for a
+// group of one instance, whose rows are (0, workgroup index): no load.
+__device__ __forceinline__ int2 work_row(const int2 *blk) {
+    if (!blk) return make_int2(0, (int)blockIdx.x);
+    const GOCP_AS4 int32_t *r = cptr(reinterpret_cast<const int32_t *>(blk)) + 2 * blockIdx.x;
+    return make_int2(r[0], r[1]);
+}
+
 // The leading fields of an instance's state record, read in one scalar load.
 struct StHead {
     int32_t iter, max_iter, done, converged, jsel, nsub, status, pad0, pend_it, pend_mode, sel_it, sel_mode;
@@ -689,7 +697,7 @@ __device__ __forceinline__ uint32_t insert_zero_bit(uint32_t p, int hb) {
 template <typename T, int R>
 __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__restrict__ insts,
                                                              const int2 *__restrict__ blk, int mode) {
-    const int2 b = blk[blockIdx.x];
+    const int2 b = work_row(blk);
     const InstDev &I = insts[b.x];
     AdaptState *st = I.st;
     // the descriptor fields and the state record's head are each loaded in
@@ -883,7 +891,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
 // operator's partial (thread = operator, all kGroup loads in flight).
 __global__ __launch_bounds__(kPairBlock) void k_screen_sum1(const InstDev *__restrict__ insts,
                                                            const int2 *__restrict__ blk, int mode) {
-    const int2 b = blk[blockIdx.x];
+    const int2 b = work_row(blk);
     const InstDev &I = insts[b.x];
     // The descriptor fields are loaded in one batch; then the state record's
     // head and the group's partials are loaded together: the sums are formed
@@ -1061,7 +1069,7 @@ __device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it,
 // partials again writes the same record).
 __global__ __launch_bounds__(kPairBlock) void k_screen_reduce(const InstDev *__restrict__ insts,
                                                              const int2 *__restrict__ blk, int mode) {
-    const InstDev &I = insts[blk[blockIdx.x].x];
+    const InstDev &I = insts[work_row(blk).x];
     AdaptState *st = I.st;
     int it = 0;
     if (mode == kModePending) {
@@ -1090,7 +1098,7 @@ __global__ __launch_bounds__(kPairBlock) void k_screen_reduce(const InstDev *__r
 template <typename T>
 __global__ __launch_bounds__(kPairBlock) void k_line_vw(const InstDev *__restrict__ insts,
                                                        const int2 *__restrict__ blk) {
-    const int2 b = blk[blockIdx.x];
+    const int2 b = work_row(blk);
     const InstDev &I = insts[b.x];
     // the descriptor fields used by the selection and the pair work, then the
     // state record's head, are each loaded in one batch ahead of their uses
@@ -1313,7 +1321,7 @@ __device__ double line_search_wave(const Landscape &L, double g) {
 template <typename T, int R>
 __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restrict__ insts,
                                                         const int2 *__restrict__ blk, int mode) {
-    const int2 b = blk[blockIdx.x];
+    const int2 b = work_row(blk);
     const InstDev &I = insts[b.x];
     AdaptState *st = I.st;
     if (mode != 0 && state_done(st)) return;
@@ -1409,7 +1417,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
 template <typename T>
 __global__ __launch_bounds__(kNW *kWave) void k_line_hvw_act(const InstDev *__restrict__ insts,
                                                             const int2 *__restrict__ blk, int mode) {
-    const int2 b = blk[blockIdx.x];
+    const int2 b = work_row(blk);
     const InstDev &I = insts[b.x];
     const int slot = b.y / kHvwParts, part = b.y % kHvwParts;
     const int lane = threadIdx.x & (kWave - 1);
@@ -1707,7 +1715,7 @@ template <typename T, bool Adapt>
 __global__ __launch_bounds__(kPairBlock) void k_taylor5(const InstDev *__restrict__ insts,
                                                        const int2 *__restrict__ blk, int j_arg, double theta_arg,
                                                        int s_arg) {
-    const int2 b = blk[blockIdx.x];
+    const int2 b = work_row(blk);
     const InstDev &I = insts[b.x];
     // Loads in batches ahead of their uses (a chain of one load per field
     // otherwise): the descriptor fields; the state record's head; then the
@@ -1799,7 +1807,7 @@ template <typename T>
 __global__ __launch_bounds__(kPairBlock) void k_normalize(const InstDev *__restrict__ insts,
                                                          const int2 *__restrict__ blk,
                                                          int from_state) {
-    const int2 b = blk[blockIdx.x];
+    const int2 b = work_row(blk);
     const InstDev &I = insts[b.x];
     __shared__ double lds[kPairBlock];
     double nrm;
@@ -1821,7 +1829,7 @@ __global__ __launch_bounds__(kPairBlock) void k_normalize(const InstDev *__restr
 
 // After psi has been scaled to unit norm from the state's own norm: record it.
 __global__ void k_state_unit_norm(const InstDev *__restrict__ insts, const int2 *__restrict__ blk) {
-    const int2 b = blk[blockIdx.x];
+    const int2 b = work_row(blk);
     AdaptState *st = insts[b.x].st;
     if (threadIdx.x == 0) {
         st->e_num = st->energy;
