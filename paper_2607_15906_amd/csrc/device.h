@@ -43,10 +43,6 @@ constexpr int kGroup = 16;
 // workgroups loop over further tiles), and states whose pair blocks number
 // more than kActMaxBlocks use the whole-state launch.
 constexpr int kHvwParts = 8;
-// A wave's slice of the stage when the compacted launch copies only its own
-// run of classes (records, strings).
-constexpr int kHvwWaveCls = kStageCls / kNW;
-constexpr int kHvwWaveStr = kStageTerms / kNW;
 constexpr int kHvwSlots = 32;
 constexpr int kActMaxBlocks = 1024;
 // Launch mode of k_screen_reduce that selects the pending partials of an
@@ -127,7 +123,6 @@ struct InstDev {
     const int4 *hchunk;         // per LDS stage: class range [x, y), string range [z, w)
     const int32_t *hseg;        // n_hchunks x (kNW + 1) class boundaries of the waves
     const int32_t *hsegp;       // n_hchunks x (kNW kHvwParts + 1): each wave's run cut into kHvwParts
-    const int32_t *hsegps;      // string positions of the hsegp boundaries
     const uint32_t *hgx;        // X mask of each group of kStrGroup strings (the group's class)
     const int32_t *hgseg;       // n_hchunks x (kNW + 1) group boundaries of the waves (equal runs)
     // pool, in pool order (pair kernels)
@@ -167,7 +162,6 @@ struct InstDev {
     int32_t n_pchunks;
     int32_t n_groups;
     int32_t n_lpart;            // workgroups of the H v, H w launch (partial triples)
-    int32_t hvw_local;          // every hsegp run fits a wave's slice of the stage
 };
 
 struct DeviceHam {
@@ -179,8 +173,6 @@ struct DeviceHam {
     int4 *hchunk = nullptr;
     int32_t *hseg = nullptr;     // per chunk, kNW + 1 wave boundaries of its classes
     int32_t *hsegp = nullptr;    // per chunk, kNW kHvwParts + 1 boundaries of the waves' runs
-    int32_t *hsegps = nullptr;   // string positions of the hsegp boundaries
-    int hvw_local = 0;           // every hsegp run fits a wave's slice of the stage
     uint32_t *hgx = nullptr;     // per group of strings, its class's X mask
     int32_t *hgseg = nullptr;    // per chunk, kNW + 1 group boundaries of the waves (equal runs)
     int n_chunks = 0;

@@ -612,14 +612,16 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
         const int4 bd = load_rec(hch, k);
         const int cb = bd.x, ce = bd.y, sb = bd.z, se = bd.w;
         __syncthreads();
-        if (R > 1) {
-            stage_copy(S.cls, I.hcls + cb, ce - cb);
-            stage_copy(S.sub, I.hsub + cb, ce - cb);
-        }
+        // one vector at one amplitude per lane: the grouped walk (no class
+        // records); two vectors (H v, H w of complex128 states) keep the class
+        // walk, which measured faster there (20.7 against 28.2 us at 14 qubits)
+        constexpr bool grouped = R == 1 && NV == 1;
+        if (!grouped) stage_copy(S.cls, I.hcls + cb, ce - cb);
+        if (R > 1) stage_copy(S.sub, I.hsub + cb, ce - cb);
         stage_coef(S, I.hcoef, sb, se);
         const GOCP_AS4 uint32_t *zs = cptr(I.hzs) + sb;
         __syncthreads();
-        if constexpr (R == 1) {
+        if constexpr (grouped) {
             // the wave's run of string groups
             const int gb = sb / kStrGroup;
             const GOCP_AS4 int32_t *t = cptr(I.hgseg) + k * (kNW + 1) + wv;
@@ -629,6 +631,18 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
         }
         int c0, c1;
         wave_range(I.hseg, k, cb, c0, c1);
+        if constexpr (R == 1) {
+            walk_classes_r1<T, NV>(S, zs, c0, c1, sb, d0 < dim ? d0 : 0u, v0, v1,
+                                   [&](int, double f, const typename Amp<T>::Raw (&p)[NV]) {
+#pragma unroll
+                                       for (int v = 0; v < NV; ++v) {
+                                           const double2 a = Amp<T>::cvt(p[v]);
+                                           acc[2 * v] = fma(f, a.x, acc[2 * v]);
+                                           acc[2 * v + 1] = fma(f, a.y, acc[2 * v + 1]);
+                                       }
+                                   });
+            continue;
+        }
         int c = c0;
         uint32_t off[R];
         lane_offsets<R, Amp<T>::kShift>(d0, dim, off);
@@ -1319,8 +1333,7 @@ __device__ double line_search_wave(const Landscape &L, double g) {
 // that follows).  mode 1: ADAPT iteration (instances already done are
 // skipped); mode 0: timing.
 template <typename T, int R>
-__global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restrict__ insts,
-                                                        const int2 *__restrict__ blk, int mode) {
+__device__ __forceinline__ void line_hvw(const InstDev *__restrict__ insts, const int2 *__restrict__ blk, int mode) {
     const int2 b = work_row(blk);
     const InstDev &I = insts[b.x];
     AdaptState *st = I.st;
@@ -1404,6 +1417,18 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
     }
 }
 
+template <typename T, int R>
+__global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restrict__ insts,
+                                                        const int2 *__restrict__ blk, int mode) {
+    line_hvw<T, R>(insts, blk, mode);
+}
+// one amplitude per lane: at most 64 VGPRs, two workgroups per CU
+template <typename T>
+__global__ __launch_bounds__(kNW *kWave) __attribute__((amdgpu_waves_per_eu(8))) void k_line_hvw1(
+    const InstDev *__restrict__ insts, const int2 *__restrict__ blk, int mode) {
+    line_hvw<T, 1>(insts, blk, mode);
+}
+
 // H v, H w dots over the compacted active amplitudes (complex64 states, whose
 // line search keeps no H v, H w).  The three dots have v* or w* as left
 // factor, so only amplitudes where v or w is nonzero contribute; k_line_vw
@@ -1415,7 +1440,8 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw(const InstDev *__restri
 // v* (H_part v) etc. at once.  Writes its partial triple to row y of the
 // line-search partials.  mode 1: ADAPT iteration; mode 0: timing.
 template <typename T>
-__global__ __launch_bounds__(kNW *kWave) void k_line_hvw_act(const InstDev *__restrict__ insts,
+// (at most 64 VGPRs: two workgroups per CU, which the many rows of a batch need)
+__global__ __launch_bounds__(kNW *kWave) __attribute__((amdgpu_waves_per_eu(8))) void k_line_hvw_act(const InstDev *__restrict__ insts,
                                                             const int2 *__restrict__ blk, int mode) {
     const int2 b = work_row(blk);
     const InstDev &I = insts[b.x];
@@ -1426,53 +1452,28 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw_act(const InstDev *__re
     // chunk-0 run bounds, are each loaded in one batch ahead of their uses
     // (a chain of one load per field otherwise)
     const AdaptState *st = I.st;
-    const int nq = I.n_qubits, nb = I.n_pblk, loc = I.hvw_local;
-    const int32_t *hsegp = I.hsegp, *hsegps = I.hsegps, *act_n = I.act_n;
+    const int nq = I.n_qubits, nb = I.n_pblk;
+    const int32_t *hsegp = I.hsegp, *act_n = I.act_n;
     const void *vv = I.v, *vw = I.w;
     const uint32_t *act = I.act, *hzs = I.hzs;
     const HClass *hcls = I.hcls;
     const double *hcoef = I.hcoef;
-    asm volatile("" ::"s"(st), "s"(nq), "s"(nb), "s"(loc), "s"(hsegp), "s"(hsegps), "s"(act_n), "s"(vv), "s"(vw),
-                 "s"(act), "s"(hzs), "s"(hcls), "s"(hcoef));
+    const int4 *hchunk = I.hchunk;
+    asm volatile("" ::"s"(st), "s"(nq), "s"(nb), "s"(hsegp), "s"(act_n), "s"(vv), "s"(vw), "s"(act), "s"(hzs),
+                 "s"(hcls), "s"(hcoef), "s"(hchunk));
     const int r0 = wv * kHvwParts + part;
     const int done = cptr(&st->done)[0];
-    const int ra = cptr(hsegp)[r0], rb = cptr(hsegp)[r0 + 1], sa0 = cptr(hsegps)[r0], sb0 = cptr(hsegps)[r0 + 1];
-    asm volatile("" ::"s"(done), "s"(ra), "s"(rb), "s"(sa0), "s"(sb0));
+    const int ra = cptr(hsegp)[r0], rb = cptr(hsegp)[r0 + 1];
+    const int4 bd0 = load_rec(cptr(hchunk), 0);
+    asm volatile("" ::"s"(done), "s"(ra), "s"(rb), "s"(bd0.x), "s"(bd0.y), "s"(bd0.z), "s"(bd0.w));
     if (mode != 0 && done) return;
     const uint32_t dim = 1u << nq;
     __shared__ int pre[kActMaxBlocks + 1];
     __shared__ Stage S;
     __shared__ double rsum[3][kNW];
-    // When every run fits a wave's slice of the stage, each wave copies only
-    // its own run of chunk k (records, magnitudes) into its slice: no
-    // workgroup barrier, as the slice is the wave's alone and a wave's LDS
-    // accesses complete in order.  Chunk 0's copy is issued first, so that its
-    // loads overlap those of the counts below.
-    static_assert(kHvwWaveCls <= kWave && kActMaxBlocks <= kNW * kWave, "one record and one count per thread");
-    constexpr int kPer = kHvwWaveStr / kWave;
-    HClass rec{};
-    double cv[kPer];
-    auto load_run = [&](int a, int n, int sa, int sz) {
-        if (lane < n) rec = load_rec(cptr(hcls), a + lane);
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            const int i = lane + j * kWave;
-            cv[j] = i < sz ? gptr(hcoef)[sa + i] : 0.0;
-        }
-    };
-    auto store_run = [&](int n, int sz) {
-        if (lane < n) S.cls[wv * kHvwWaveCls + lane] = rec;
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            const int i = lane + j * kWave;
-            if (i < sz) S.coef[wv * kHvwWaveStr + i] = cv[j];
-        }
-    };
-    // chunk 0's run and the blocks' counts: every load is issued before the
-    // first LDS write
-    if (loc) load_run(ra, rb - ra, sa0, sb0 - sa0);
+    // the blocks' counts, loaded by all threads at once
+    static_assert(kActMaxBlocks <= kNW * kWave, "one count per thread");
     const int cnt = threadIdx.x < nb ? min(max(gptr(act_n)[threadIdx.x], 0), 2 * kPairBlock) : 0;
-    if (loc) store_run(rb - ra, sb0 - sa0);
     // exclusive prefix of the blocks' counts (each at most 2 kPairBlock),
     // scanned by wave 0, 64 at a time
     if (threadIdx.x < nb) pre[threadIdx.x + 1] = cnt;
@@ -1499,33 +1500,15 @@ __global__ __launch_bounds__(kNW *kWave) void k_line_hvw_act(const InstDev *__re
         for (int k = 0; k < I.n_hchunks; ++k) {
             const int r = k * (kNW * kHvwParts + 1) + r0;
             const GOCP_AS4 int32_t *seg = cptr(hsegp) + r;
-            // the wave's run of classes [c0, c1) in the stage, and the string
-            // base sb of the stage's magnitudes (string s at S.coef[s - sb])
-            int c0, c1, sb;
-            if (loc) {
-                int a = ra, e = rb, sa = sa0;
-                if (k > 0) {
-                    const GOCP_AS4 int32_t *sp = cptr(hsegps) + r;
-                    a = seg[0];
-                    e = seg[1];
-                    sa = sp[0];
-                    load_run(a, e - a, sa, sp[1] - sa);
-                    store_run(e - a, sp[1] - sa);
-                }
-                c0 = wv * kHvwWaveCls;
-                c1 = c0 + (e - a);
-                sb = sa - wv * kHvwWaveStr;
-            } else {
-                const int4 bd = load_rec(cptr(I.hchunk), k);
-                const int cb = bd.x, ce = bd.y;
-                sb = bd.z;
-                __syncthreads();
-                stage_copy(S.cls, I.hcls + cb, ce - cb);
-                stage_coef(S, I.hcoef, sb, bd.w);
-                __syncthreads();
-                c0 = seg[0] - cb;
-                c1 = seg[1] - cb;
-            }
+            // the wave's run of classes [c0, c1) of the staged chunk (the first
+            // chunk's bounds were loaded with the state's flag)
+            const int4 bd = k == 0 ? bd0 : load_rec(cptr(hchunk), k);
+            const int cb = bd.x, ce = bd.y, sb = bd.z;
+            __syncthreads();
+            stage_copy(S.cls, hcls + cb, ce - cb);
+            stage_coef(S, hcoef, sb, bd.w);
+            __syncthreads();
+            const int c0 = (k == 0 ? ra : seg[0]) - cb, c1 = (k == 0 ? rb : seg[1]) - cb;
             const GOCP_AS4 uint32_t *zs = cptr(hzs) + sb;
             for (int t = slot; t * kWave < n_act; t += kHvwSlots) {
                 // this lane's amplitude: list entry g, found in the block prefix
@@ -1854,10 +1837,13 @@ __global__ void k_basis(void *psi, uint32_t dim, uint32_t index) {
 
 template <typename T, int R>
 static void launch_tile(int which, const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s) {
-    if (which == 0)
+    if (which == 0) {
         hipLaunchKernelGGL((k_energy_screen<T, R>), dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode);
-    else
+    } else if constexpr (R == 1) {
+        hipLaunchKernelGGL((k_line_hvw1<T>), dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode);
+    } else {
         hipLaunchKernelGGL((k_line_hvw<T, R>), dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode);
+    }
 }
 
 template <typename T>

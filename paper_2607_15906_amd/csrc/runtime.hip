@@ -184,7 +184,6 @@ void release_device_ham(DeviceHam *d) {
     (void)hipFree(d->hchunk);
     (void)hipFree(d->hseg);
     (void)hipFree(d->hsegp);
-    (void)hipFree(d->hsegps);
     (void)hipFree(d->hgx);
     (void)hipFree(d->hgseg);
     delete d;
@@ -250,18 +249,6 @@ const DeviceHam *device_ham(const Ham &h, int dev) {
     // zero groups past the end: the walk's read-ahead stays in the tables
     zs.resize(zs.size() + (size_t)kTablePadGroups * kStrGroup, 0u);
     gx.resize(gx.size() + kTablePadGroups, 0u);
-    // string positions of the runs' boundaries, and whether every run fits a
-    // wave's slice of the stage (then the compacted launch copies runs alone)
-    std::vector<int32_t> segps;
-    for (int32_t i : segp) segps.push_back(i < (int32_t)cls.size() ? cls[i].s0 : (int32_t)co.size());
-    bool local = true;
-    for (size_t k = 0; k + 1 < ch.size(); ++k) {
-        const size_t o = k * (kNW * kHvwParts + 1);
-        for (int r = 0; r < kNW * kHvwParts; ++r)
-            local = local && segp[o + r + 1] - segp[o + r] <= kHvwWaveCls && segps[o + r + 1] - segps[o + r] <= kHvwWaveStr;
-    }
-    d->hsegps = dev_upload(segps);
-    d->hvw_local = local ? 1 : 0;
     d->hgx = dev_upload(gx);
     d->hgseg = dev_upload(gseg);
     d->hcls = dev_upload(cls);
@@ -404,8 +391,6 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
         I.hchunk = dh->hchunk;
         I.hseg = dh->hseg;
         I.hsegp = dh->hsegp;
-        I.hsegps = dh->hsegps;
-        I.hvw_local = dh->hvw_local;
         I.hgx = dh->hgx;
         I.hgseg = dh->hgseg;
         I.n_hchunks = dh->n_chunks;
