@@ -39,7 +39,7 @@ LANE_OPS_PER_STRING_AMP = 5
 # scaled by a 256 MiB copy), from the rocprofv3 counter runs summarised under
 # profiles/; keyed by (kernel, amplitudes per lane).  An entry is removed when
 # the kernel changes, until the counters are taken again.
-TRAFFIC_BYTES = {("k_energy_screen", 1): 2666283}
+TRAFFIC_BYTES = {("k_energy_screen", 1): 2629417}
 # the dominant kernel is bracketed by HIP events in every 8th timed iteration
 # (events around every launch would slow the loop by several per cent)
 LIVE_SAMPLE_EVERY = 8
@@ -74,7 +74,8 @@ def _amp_updates(nq, T, S, off, ops, subs):
     return tot * (1 << nq)
 
 
-def run_adapt_timed(g, ctx, H, P, nq, ne, mapping, dtype, steps, warmup, schedule=0, timed_kernel=None):
+def run_adapt_timed(g, ctx, H, P, nq, ne, mapping, dtype, steps, warmup, schedule=0, timed_kernel=None,
+                    sample_every=LIVE_SAMPLE_EVERY):
     """Warm-up iterations (graph replays), then the timed iterations.  With
     timed_kernel (an index of Batch.STEP_KERNELS) the timed iterations are
     launched directly with HIP events around every launch of that kernel, and
@@ -91,7 +92,7 @@ def run_adapt_timed(g, ctx, H, P, nq, ne, mapping, dtype, steps, warmup, schedul
         b.step(steps)
     else:
         k = timed_kernel(pre) if callable(timed_kernel) else timed_kernel
-        _, kernel_ms = b.step_timed(steps, k, LIVE_SAMPLE_EVERY)
+        _, kernel_ms = b.step_timed(steps, k, sample_every)
         kernel_ms = (k, kernel_ms)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -196,6 +197,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the c128 and batched extras")
     ap.add_argument("--serve-requests", type=int, default=96,
                     help="measured requests of the serving stream (after 16 warm-up requests)")
+    ap.add_argument("--sample-every", type=int, default=LIVE_SAMPLE_EVERY,
+                    help="HIP events around every n-th launch of the dominant kernel in the timed region")
     ap.add_argument("--schedule", type=int, default=0, choices=(0, 1, 2, 4),
                     help="amplitudes per lane of the tile kernels (0: autotune)")
     ap.add_argument("--serve-amps-per-lane", type=int, default=0, choices=(0, 1, 2, 4),
@@ -241,7 +244,8 @@ def main():
     # region then feeds the roofline
     b, r, dt, live = run_adapt_timed(g, ctx, H, P, nq, ne, mapping, torch.complex64, args.steps,
                                      args.warmup, schedule=args.schedule,
-                                     timed_kernel=lambda pre: 3 if pre[0] >= pre[1] else 1)
+                                     timed_kernel=lambda pre: 3 if pre[0] >= pre[1] else 1,
+                                     sample_every=args.sample_every)
     sched = b.schedule
     w0, w1 = args.warmup, args.warmup + args.steps
     iters = r["n_iter"]
@@ -273,7 +277,7 @@ def main():
                 "peak": round(VALU_PEAK_TOPS, 4), "unit": "Tlane-op/s",
                 "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": traffic,
                 "avg_launch_us": round(kms * 1e3, 3),
-                "launches_sampled": (args.steps + LIVE_SAMPLE_EVERY - 1) // LIVE_SAMPLE_EVERY,
+                "launches_sampled": (args.steps + args.sample_every - 1) // args.sample_every,
                 "algorithmic_string_amps_per_launch": int(string_amps[dom]),
                 "algorithmic_lane_ops_per_launch": int(lane_ops),
                 "fp64_view": {"achieved_tflops": round(achieved_fp64, 4), "peak_tflops": FP64_PEAK_TFLOPS,

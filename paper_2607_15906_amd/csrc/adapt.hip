@@ -231,9 +231,13 @@ int gocp_batch_step_timed(gocp_batch *b, int32_t n_iter, int32_t kernel, int32_t
     static const int kids[5] = {K_LINE_VW, K_LINE_HVW, K_TAYLOR, K_ENERGY_SCREEN, K_SCREEN_SUM1};
     if (kernel < 0 || kernel > 4) throw Error(GOCP_EINVAL, "kernel must be 0..4");
     hipStream_t s = b->group.ctx->user_stream;
-    std::vector<hipEvent_t> ev(2 * (size_t)n_iter + 2);
+    // events for the sampled launches and the two ends only (creating and
+    // destroying one per iteration costs host time of the same order as the
+    // iteration itself)
+    const int n_samp = (n_iter + every - 1) / every;
+    std::vector<hipEvent_t> ev(2 * (size_t)n_samp + 2);
     for (hipEvent_t &e : ev) hip_check(hipEventCreate(&e), "hipEventCreate");
-    hip_check(hipEventRecord(ev[2 * n_iter], s), "hipEventRecord");
+    hip_check(hipEventRecord(ev[2 * n_samp], s), "hipEventRecord");
     int sampled = 0;
     for (int i = 0; i < n_iter; ++i) {
         for (Instance *in : b->group.inst) in->finalized = false;
@@ -245,8 +249,8 @@ int gocp_batch_step_timed(gocp_batch *b, int32_t n_iter, int32_t kernel, int32_t
         }
     }
     b->group.select_pending(s);
-    hip_check(hipEventRecord(ev[2 * n_iter + 1], s), "hipEventRecord");
-    hip_check(hipEventSynchronize(ev[2 * n_iter + 1]), "hipEventSynchronize");
+    hip_check(hipEventRecord(ev[2 * n_samp + 1], s), "hipEventRecord");
+    hip_check(hipEventSynchronize(ev[2 * n_samp + 1]), "hipEventSynchronize");
     double k = 0.0;
     for (int i = 0; i < sampled; ++i) {
         float ms = 0.f;
@@ -254,7 +258,7 @@ int gocp_batch_step_timed(gocp_batch *b, int32_t n_iter, int32_t kernel, int32_t
         k += ms;
     }
     float tot = 0.f;
-    hip_check(hipEventElapsedTime(&tot, ev[2 * n_iter], ev[2 * n_iter + 1]), "hipEventElapsedTime");
+    hip_check(hipEventElapsedTime(&tot, ev[2 * n_samp], ev[2 * n_samp + 1]), "hipEventElapsedTime");
     for (hipEvent_t &e : ev) (void)hipEventDestroy(e);
     b->issued += n_iter;
     *total_ms = tot;
