@@ -333,3 +333,54 @@ def test_complex64_compacted_line_search_large_class(g, ctx):
     r64, r32 = runs["c128"], runs["c64"]
     assert r32["ops"] == r64["ops"]
     assert np.abs(r32["energies"] - r64["energies"]).max() <= 1e-6
+
+
+def _multichunk_12q(g, s, n_extra=3000, seed=9):
+    """The 12-qubit Hamiltonian plus n_extra random Hermitian strings (an even
+    number of Y factors, real folded coefficients): more strings and X-mask
+    classes than one LDS stage chunk holds, so the tile kernels walk several
+    chunks.  Returns the oracle Pauli sum and the library Hamiltonian."""
+    x, z, c = s["gH"].terms()
+    rng = np.random.default_rng(seed)
+    have = set(zip(x.tolist(), z.tolist()))
+    ex, ez, ec = [], [], []
+    while len(ex) < n_extra:
+        xx, zz = int(rng.integers(0, 1 << 12)), int(rng.integers(0, 1 << 12))
+        if bin(xx & zz).count("1") % 2 or (xx, zz) in have:
+            continue
+        have.add((xx, zz))
+        ex.append(xx); ez.append(zz); ec.append(float(rng.choice([-1, 1]) * rng.uniform(1e-3, 1e-2)))
+    H = dict(s["H"])
+    for xx, zz, cc in zip(ex, ez, ec):
+        H[(xx, zz)] = cc * (1j ** bin(xx & zz).count("1"))   # unfold: c = c_folded i^y
+    gH = g.pauli_hamiltonian_load_terms(12, np.concatenate([x, np.array(ex, dtype=x.dtype)]),
+                                        np.concatenate([z, np.array(ez, dtype=z.dtype)]),
+                                        np.concatenate([c, np.array(ec)]))
+    assert gH.n_terms > 4096 and gH.n_classes > 1024
+    return H, gH
+
+
+def test_multichunk_energy_gradients_and_adapt(g, ctx):
+    """H split over several LDS stage chunks (by strings and by classes):
+    energy, sigma and pool gradients against the oracle, and a complex64
+    ADAPT run against the FP64 path (grouped walk, compacted line search)."""
+    _say("[multichunk] 12q + 3000 random strings")
+    s = system(g, 12, "jw")
+    H, gH = _multichunk_12q(g, s)
+    psi = rand_state(12, 31)
+    sig_ref = apply_h(H, psi)
+    e_ref = o_energy(H, psi, sig_ref)
+    sig = torch.zeros(1 << 12, dtype=torch.complex128, device="cuda")
+    e = g.apply_hamiltonian(ctx, gH, to_dev(psi), sig)
+    assert abs(e - e_ref) <= 1e-12 * max(1.0, abs(e_ref))
+    assert np.abs(sig.cpu().numpy() - sig_ref).max() <= 1e-12 * max(1.0, np.abs(sig_ref).max())
+    g_ref = o_gradients(s["ops"], psi, sig_ref)
+    gg = g.pool_gradients(ctx, gH, s["gP"], to_dev(psi))
+    assert np.abs(gg - g_ref).max() <= 1e-12 * max(1.0, np.abs(g_ref).max())
+    runs = {}
+    for dtype in ("c128", "c64"):
+        d = torch.zeros(1 << 12, dtype=torch.complex128 if dtype == "c128" else torch.complex64, device="cuda")
+        g.state_basis(ctx, 12, s["hf"], d)
+        runs[dtype] = g.adapt_solve(ctx, gH, s["gP"], d, 8, grad_tol=0.0, schedule=1)
+    assert runs["c64"]["ops"] == runs["c128"]["ops"]
+    assert np.abs(runs["c64"]["energies"] - runs["c128"]["energies"]).max() <= 1e-6
