@@ -35,6 +35,13 @@ constexpr int kOpCost = 36;
 // Strings a pair kernel reads at once; each pool operator's strings are padded
 // to a multiple of it (zero strings) in pool order.
 constexpr int kPairGroup = 8;
+// A screened operator whose strings share their Z bits outside a mask b of at
+// most kFactBits bits has f(d) = (-1)^popcount(d & z_b) F(d & b); when F is
+// nonzero at no more than two patterns t1, t2 (values v1, v2), the operator is
+// stored as one group of parameters {v1, v2, 0, 0 | z_b, b, t1, t2} and its
+// X mask carries this flag.
+constexpr uint32_t kFactBit = 0x80000000u;
+constexpr int kFactBits = 4;
 // Tiles per group in the first stage of the screen reduction.
 constexpr int kGroup = 16;
 // Compacted H v, H w launch (complex64 states): each tile of 64 active
@@ -136,6 +143,13 @@ struct InstDev {
     const HSub *psub;
     const int4 *pchunk;         // per LDS stage: operator range [x, y), string range [z, w)
     const int32_t *pseg;        // n_pchunks x (kNW + 1) operator boundaries of the waves
+    // the same schedule for one amplitude per lane, with factored operators
+    // (x | kFactBit, one group of parameters instead of strings)
+    const HClass *sop1;
+    const double *scoef1;
+    const uint32_t *szs1;
+    const int4 *pchunk1;
+    const int32_t *pseg1;
     // buffers (psi, v, w in the state precision; sigma FP64)
     void *psi;
     double2 *sigma;
@@ -160,6 +174,7 @@ struct InstDev {
     int32_t n_pblk;
     int32_t n_hchunks;
     int32_t n_pchunks;
+    int32_t n_pchunks1;
     int32_t n_groups;
     int32_t n_lpart;            // workgroups of the H v, H w launch (partial triples)
 };
@@ -190,6 +205,13 @@ struct DevicePool {
     int4 *pchunk = nullptr;
     int32_t *pseg = nullptr;     // per chunk, kNW + 1 wave boundaries of its operators
     int n_chunks = 0;
+    // one amplitude per lane, factored operators (see InstDev)
+    HClass *sop1 = nullptr;
+    double *scoef1 = nullptr;
+    uint32_t *szs1 = nullptr;
+    int4 *pchunk1 = nullptr;
+    int32_t *pseg1 = nullptr;
+    int n_chunks1 = 0;
 };
 
 void hip_check(hipError_t e, const char *what);

@@ -410,7 +410,10 @@ __device__ __forceinline__ void lane_offsets(uint32_t d0, uint32_t dim, uint32_t
 // from v0 (and v1) are in flight, and the record after that is being read.
 // d must lie in the state (its bits feed the gather index directly).
 // fin(c, f_c(d), raw amplitudes at d ^ x_c) is called for every record in order.
-template <typename T, int NV, typename Fin>
+// With FACT, records flagged kFactBit hold one group of parameters instead
+// of strings (a factored pool operator): f(d) = (-1)^popcount(d & z_b) times
+// v1 or v2 where d & b equals t1 or t2, and 0 elsewhere.
+template <typename T, int NV, bool FACT, typename Fin>
 __device__ __forceinline__ void walk_classes_r1(const Stage &S, const GOCP_AS4 uint32_t *zs, int c0, int c1, int sb,
                                                 uint32_t d, const void *v0, const void *v1, Fin &&fin) {
     using Raw = typename Amp<T>::Raw;
@@ -441,6 +444,15 @@ __device__ __forceinline__ void walk_classes_r1(const Stage &S, const GOCP_AS4 u
     // f(d) of a record whose first group is in registers; further groups are
     // read here (the string range is uniform: scalar loop bounds)
     auto coef = [&](const Rec &k, const Grp &g) {
+        if constexpr (FACT) {
+            if (k.x & kFactBit) {
+                const uint32_t u = d & g.z[1];
+                double v = u == g.z[2] ? g.c[0] : 0.0;
+                v = u == g.z[3] ? g.c[1] : v;
+                const uint32_t bit = (uint32_t)__popc(d & g.z[0]) << 31;
+                return __hiloint2double((int)((uint32_t)__double2hiint(v) ^ bit), __double2loint(v));
+            }
+        }
         double f0 = signed_cz(g.c[0], g.z[0], dz) + signed_cz(g.c[2], g.z[2], dz);
         double f1 = signed_cz(g.c[1], g.z[1], dz) + signed_cz(g.c[3], g.z[3], dz);
         const int s1 = uni(k.s1);
@@ -632,7 +644,7 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
         int c0, c1;
         wave_range(I.hseg, k, cb, c0, c1);
         if constexpr (R == 1) {
-            walk_classes_r1<T, NV>(S, zs, c0, c1, sb, d0 < dim ? d0 : 0u, v0, v1,
+            walk_classes_r1<T, NV, false>(S, zs, c0, c1, sb, d0 < dim ? d0 : 0u, v0, v1,
                                    [&](int, double f, const typename Amp<T>::Raw (&p)[NV]) {
 #pragma unroll
                                        for (int v = 0; v < NV; ++v) {
@@ -815,19 +827,25 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
         double2 sg[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) sg[r] = s_sig[r][lane];
-        const GOCP_AS4 int4 *pch = cptr(I.pchunk);
-        for (int k = 0; k < I.n_pchunks; ++k) {
+        // one amplitude per lane: the schedule with factored operators
+        const HClass *sop = R == 1 ? I.sop1 : I.sop;
+        const double *scoef = R == 1 ? I.scoef1 : I.scoef;
+        const uint32_t *szs = R == 1 ? I.szs1 : I.szs;
+        const int32_t *pseg = R == 1 ? I.pseg1 : I.pseg;
+        const int npc = R == 1 ? I.n_pchunks1 : I.n_pchunks;
+        const GOCP_AS4 int4 *pch = cptr(R == 1 ? I.pchunk1 : I.pchunk);
+        for (int k = 0; k < npc; ++k) {
             const int4 bd = load_rec(pch, k);
             const int ob = bd.x, oe = bd.y, sb = bd.z, se = bd.w;
             __syncthreads();
-            stage_copy(S.cls, I.sop + ob, oe - ob);
+            stage_copy(S.cls, sop + ob, oe - ob);
             if (R > 1) stage_copy(S.sub, I.psub + ob, oe - ob);
-            stage_coef(S, I.scoef, sb, se);
-            const GOCP_AS4 uint32_t *zs = cptr(I.szs) + sb;
+            stage_coef(S, scoef, sb, se);
+            const GOCP_AS4 uint32_t *zs = cptr(szs) + sb;
             __syncthreads();
             const int no = oe - ob;
             int o0, o1;
-            wave_range(I.pseg, k, ob, o0, o1);
+            wave_range(pseg, k, ob, o0, o1);
             // Per-operator sums over the wave's 64 amplitudes, four operators
             // at a time: every lane stores its contribution to the wave's
             // buffer; after every fourth operator of the wave's run (and after
@@ -850,7 +868,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                 if (++nbuf == 4) flush();
             };
             if constexpr (R == 1) {
-                walk_classes_r1<T, 1>(S, zs, o0, o1, sb, d0 < dim ? d0 : 0u, I.psi, nullptr,
+                walk_classes_r1<T, 1, true>(S, zs, o0, o1, sb, d0 < dim ? d0 : 0u, I.psi, nullptr,
                                       [&](int o, double h, const typename Amp<T>::Raw (&p)[1]) {
                                           const double2 a = Amp<T>::cvt(p[0]);
                                           push(o, h * (sg[0].x * a.x + sg[0].y * a.y));
@@ -1526,7 +1544,7 @@ __global__ __launch_bounds__(kNW *kWave) __attribute__((amdgpu_waves_per_eu(8)))
                 double acc[4] = {0.0, 0.0, 0.0, 0.0};
                 // runs of a few classes: the class walk, whose pipeline fills
                 // faster than the grouped walk's
-                walk_classes_r1<T, 2>(S, zs, c0, c1, sb, d, vv, vw,
+                walk_classes_r1<T, 2, false>(S, zs, c0, c1, sb, d, vv, vw,
                                       [&](int, double f, const typename Amp<T>::Raw (&p)[2]) {
 #pragma unroll
                                           for (int v = 0; v < 2; ++v) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -162,6 +163,40 @@ std::vector<int4> stage_bounds(const std::vector<int32_t> &b, const std::vector<
     return out;
 }
 
+// Operator j as f(d) = (-1)^popcount(d & zb) F(d & bm): its strings' Z masks
+// agree outside bm (at most kFactBits bits), F(u) = sum_s c_s
+// (-1)^popcount(u & z_s) over the submasks u of bm, and F is nonzero at one
+// or two patterns.  Fills the parameter group {v1, v2, 0, 0 | zb, bm, t1, t2}
+// (t2 = all ones, never matched, when there is one pattern).
+bool factor_op(const Pool &p, int j, double (&co)[kStrGroup], uint32_t (&zs)[kStrGroup]) {
+    const int a = p.op_off[j], b = p.op_off[j + 1];
+    if (b - a < 2) return false;
+    const uint32_t z0 = p.str_z[a];
+    uint32_t bm = 0;
+    double scale = 0.0;
+    for (int s = a; s < b; ++s) {
+        bm |= p.str_z[s] ^ z0;
+        scale += std::fabs(p.str_c[s]);
+    }
+    if (__builtin_popcount(bm) > kFactBits || (bm & kFactBit)) return false;
+    std::vector<std::pair<uint32_t, double>> nz;
+    for (uint32_t u = bm;; u = (u - 1) & bm) {
+        double f = 0.0;
+        for (int s = a; s < b; ++s) f += (__builtin_popcount(u & p.str_z[s]) & 1) ? -p.str_c[s] : p.str_c[s];
+        if (std::fabs(f) > 1e-12 * scale) nz.emplace_back(u, f);
+        if (u == 0) break;
+    }
+    if (nz.empty() || nz.size() > 2) return false;
+    co[0] = nz[0].second;
+    co[1] = nz.size() > 1 ? nz[1].second : 0.0;
+    co[2] = co[3] = 0.0;
+    zs[0] = z0 & ~bm;
+    zs[1] = bm;
+    zs[2] = nz[0].first;
+    zs[3] = nz.size() > 1 ? nz[1].first : 0xffffffffu;
+    return true;
+}
+
 // Padded string offsets of records taken in the order `rec` with `count(r)` strings.
 template <typename F>
 std::vector<int32_t> padded_offsets(int n, F count) {
@@ -200,6 +235,11 @@ void release_device_pool(DevicePool *d) {
     (void)hipFree(d->psub);
     (void)hipFree(d->pchunk);
     (void)hipFree(d->pseg);
+    (void)hipFree(d->sop1);
+    (void)hipFree(d->scoef1);
+    (void)hipFree(d->szs1);
+    (void)hipFree(d->pchunk1);
+    (void)hipFree(d->pseg1);
     delete d;
 }
 
@@ -312,6 +352,52 @@ const DevicePool *device_pool(const Pool &p, int dev) {
     d->pchunk = dev_upload(stage_bounds(pch, sop));
     d->pseg = dev_upload(seg);
     d->n_chunks = (int)pch.size() - 1;
+    // the same schedule for one amplitude per lane, where factored operators
+    // take one group of parameters (and cost a fixed share of a group)
+    {
+        std::vector<char> fac(m);
+        std::vector<std::array<double, kStrGroup>> fco(m);
+        std::vector<std::array<uint32_t, kStrGroup>> fzs(m);
+        for (int r = 0; r < m; ++r) {
+            double c4[kStrGroup];
+            uint32_t z4[kStrGroup];
+            fac[r] = factor_op(p, p.fam_members[r], c4, z4);
+            for (int q = 0; q < kStrGroup; ++q) {
+                fco[r][q] = c4[q];
+                fzs[r][q] = z4[q];
+            }
+        }
+        auto count1 = [&](int r) { return fac[r] ? kStrGroup : count(r); };
+        const std::vector<int32_t> pch1 = stage_chunks(padded_offsets(m, count1));
+        std::vector<int> cost1(m);
+        for (int r = 0; r < m; ++r) cost1[r] = fac[r] ? kOpCost + 3 * kStrGroup : record_cost(count(r), kOpCost);
+        std::vector<int32_t> order1, seg1;
+        for (size_t k = 0; k + 1 < pch1.size(); ++k) wave_split(cost1, pch1[k], pch1[k + 1], order1, seg1);
+        std::vector<HClass> sop1;
+        std::vector<double> co1;
+        std::vector<uint32_t> zs1;
+        for (int32_t r : order1) {
+            const int32_t j = p.fam_members[r];
+            HClass rec{p.op_x[j], (int32_t)co1.size(), 0, j};
+            if (fac[r]) {
+                rec.x |= kFactBit;
+                for (int q = 0; q < kStrGroup; ++q) {
+                    co1.push_back(fco[r][q]);
+                    zs1.push_back(fzs[r][q]);
+                }
+            } else {
+                bucket_strings(p.str_c, p.str_z, p.op_off[j], p.op_off[j + 1], co1, zs1);
+            }
+            rec.s1 = (int32_t)co1.size();
+            sop1.push_back(rec);
+        }
+        d->sop1 = dev_upload(sop1);
+        d->scoef1 = dev_upload(co1);
+        d->szs1 = dev_upload(zs1);
+        d->pchunk1 = dev_upload(stage_bounds(pch1, sop1));
+        d->pseg1 = dev_upload(seg1);
+        d->n_chunks1 = (int)pch1.size() - 1;
+    }
     p.dev[dev] = d.release();
     return p.dev[dev];
 }
@@ -407,6 +493,12 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
         I.pchunk = dp->pchunk;
         I.pseg = dp->pseg;
         I.n_pchunks = dp->n_chunks;
+        I.sop1 = dp->sop1;
+        I.scoef1 = dp->scoef1;
+        I.szs1 = dp->szs1;
+        I.pchunk1 = dp->pchunk1;
+        I.pseg1 = dp->pseg1;
+        I.n_pchunks1 = dp->n_chunks1;
     }
     I.psi = psi;
     I.sigma = sigma_override ? sigma_override : reinterpret_cast<double2 *>(b + ip.o_sigma);
