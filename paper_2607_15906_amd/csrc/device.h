@@ -136,20 +136,14 @@ struct InstDev {
     const HClass *pop;          // one record per operator
     const HTerm *pterm;
     const double *op_norm1;
-    // pool in GOCP family order (gradient screen); HClass.pad = pool index
+    // pool in GOCP family order (gradient screen); HClass.pad = pool index;
+    // factored operators have x | kFactBit and one group of parameters
     const HClass *sop;
     const double *scoef;        // |c| and z | sign << 31 of the screen's strings
     const uint32_t *szs;
     const HSub *psub;
     const int4 *pchunk;         // per LDS stage: operator range [x, y), string range [z, w)
     const int32_t *pseg;        // n_pchunks x (kNW + 1) operator boundaries of the waves
-    // the same schedule for one amplitude per lane, with factored operators
-    // (x | kFactBit, one group of parameters instead of strings)
-    const HClass *sop1;
-    const double *scoef1;
-    const uint32_t *szs1;
-    const int4 *pchunk1;
-    const int32_t *pseg1;
     // buffers (psi, v, w in the state precision; sigma FP64)
     void *psi;
     double2 *sigma;
@@ -174,7 +168,6 @@ struct InstDev {
     int32_t n_pblk;
     int32_t n_hchunks;
     int32_t n_pchunks;
-    int32_t n_pchunks1;
     int32_t n_groups;
     int32_t n_lpart;            // workgroups of the H v, H w launch (partial triples)
 };
@@ -205,13 +198,6 @@ struct DevicePool {
     int4 *pchunk = nullptr;
     int32_t *pseg = nullptr;     // per chunk, kNW + 1 wave boundaries of its operators
     int n_chunks = 0;
-    // one amplitude per lane, factored operators (see InstDev)
-    HClass *sop1 = nullptr;
-    double *scoef1 = nullptr;
-    uint32_t *szs1 = nullptr;
-    int4 *pchunk1 = nullptr;
-    int32_t *pseg1 = nullptr;
-    int n_chunks1 = 0;
 };
 
 void hip_check(hipError_t e, const char *what);

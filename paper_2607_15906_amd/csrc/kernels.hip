@@ -363,10 +363,26 @@ __device__ __forceinline__ void wht(double *g) {
 
 // Class (or operator) c of the staged chunk: f_r for the lane's R amplitudes
 // (zs = the chunk's Z masks).
-template <int R>
+template <int R, bool FACT = false>
 __device__ __forceinline__ void class_coeffs(const Stage &S, const GOCP_AS4 uint32_t *zs, int c, int sb, uint32_t d0,
                                              double *f) {
     const int s0 = uni(S.cls[c].s0) - sb, s1 = uni(S.cls[c].s1) - sb;
+    if constexpr (FACT) {
+        // a factored operator, evaluated at each of the lane's amplitudes
+        if ((uint32_t)uni((int)S.cls[c].x) & kFactBit) {
+            const double v1 = S.coef[s0], v2 = S.coef[s0 + 1];
+            const uint32_t zb = zs[s0], bm = zs[s0 + 1], t1 = zs[s0 + 2], t2 = zs[s0 + 3];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t d = d0 | ((uint32_t)r << 6), u = d & bm;
+                double v = u == t1 ? v1 : 0.0;
+                v = u == t2 ? v2 : v;
+                const uint32_t bit = (uint32_t)__popc(d & zb) << 31;
+                f[r] = __hiloint2double((int)((uint32_t)__double2hiint(v) ^ bit), __double2loint(v));
+            }
+            return;
+        }
+    }
     const uint32_t dz = with_sign_bit(d0);
     if (R == 1) {
         f[0] = lds_string_sum(S.coef, zs, s0, s1, dz);
@@ -827,13 +843,12 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
         double2 sg[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) sg[r] = s_sig[r][lane];
-        // one amplitude per lane: the schedule with factored operators
-        const HClass *sop = R == 1 ? I.sop1 : I.sop;
-        const double *scoef = R == 1 ? I.scoef1 : I.scoef;
-        const uint32_t *szs = R == 1 ? I.szs1 : I.szs;
-        const int32_t *pseg = R == 1 ? I.pseg1 : I.pseg;
-        const int npc = R == 1 ? I.n_pchunks1 : I.n_pchunks;
-        const GOCP_AS4 int4 *pch = cptr(R == 1 ? I.pchunk1 : I.pchunk);
+        const HClass *sop = I.sop;
+        const double *scoef = I.scoef;
+        const uint32_t *szs = I.szs;
+        const int32_t *pseg = I.pseg;
+        const int npc = I.n_pchunks;
+        const GOCP_AS4 int4 *pch = cptr(I.pchunk);
         for (int k = 0; k < npc; ++k) {
             const int4 bd = load_rec(pch, k);
             const int ob = bd.x, oe = bd.y, sb = bd.z, se = bd.w;
@@ -894,7 +909,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                     for (int r = 0; r < R; ++r) rn[r] = Amp<T>::raw_at(I.psi, off[r] ^ xn);
                 }
                 double h[R];
-                class_coeffs<R>(S, zs, o, sb, d0, h);
+                class_coeffs<R, true>(S, zs, o, sb, d0, h);
                 double val = 0.0;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {

@@ -235,11 +235,6 @@ void release_device_pool(DevicePool *d) {
     (void)hipFree(d->psub);
     (void)hipFree(d->pchunk);
     (void)hipFree(d->pseg);
-    (void)hipFree(d->sop1);
-    (void)hipFree(d->scoef1);
-    (void)hipFree(d->szs1);
-    (void)hipFree(d->pchunk1);
-    (void)hipFree(d->pseg1);
     delete d;
 }
 
@@ -329,9 +324,24 @@ const DevicePool *device_pool(const Pool &p, int dev) {
     // wave keeping family order)
     const int m = p.n_ops();
     auto count = [&](int r) { const int j = p.fam_members[r]; return p.op_off[j + 1] - p.op_off[j]; };
-    const std::vector<int32_t> pch = stage_chunks(padded_offsets(m, count));
+    // factored operators (factor_op) take one group of parameters instead of
+    // their strings, flagged by kFactBit in the X mask
+    std::vector<char> fac(m);
+    std::vector<std::array<double, kStrGroup>> fco(m);
+    std::vector<std::array<uint32_t, kStrGroup>> fzs(m);
+    for (int r = 0; r < m; ++r) {
+        double c4[kStrGroup];
+        uint32_t z4[kStrGroup];
+        fac[r] = factor_op(p, p.fam_members[r], c4, z4);
+        for (int q = 0; q < kStrGroup; ++q) {
+            fco[r][q] = c4[q];
+            fzs[r][q] = z4[q];
+        }
+    }
+    auto count_st = [&](int r) { return fac[r] ? kStrGroup : count(r); };
+    const std::vector<int32_t> pch = stage_chunks(padded_offsets(m, count_st));
     std::vector<int> cost(m);
-    for (int r = 0; r < m; ++r) cost[r] = record_cost(count(r), kOpCost);
+    for (int r = 0; r < m; ++r) cost[r] = fac[r] ? kOpCost + 3 * kStrGroup : record_cost(count(r), kOpCost);
     std::vector<int32_t> order, seg;
     for (size_t k = 0; k + 1 < pch.size(); ++k) wave_split(cost, pch[k], pch[k + 1], order, seg);
     std::vector<HClass> sop;
@@ -341,7 +351,16 @@ const DevicePool *device_pool(const Pool &p, int dev) {
     for (int32_t r : order) {
         const int32_t j = p.fam_members[r];
         HClass rec{p.op_x[j], (int32_t)co.size(), 0, j};
-        psub.push_back(bucket_strings(p.str_c, p.str_z, p.op_off[j], p.op_off[j + 1], co, zs));
+        if (fac[r]) {
+            rec.x |= kFactBit;
+            for (int q = 0; q < kStrGroup; ++q) {
+                co.push_back(fco[r][q]);
+                zs.push_back(fzs[r][q]);
+            }
+            psub.push_back(HSub{});
+        } else {
+            psub.push_back(bucket_strings(p.str_c, p.str_z, p.op_off[j], p.op_off[j + 1], co, zs));
+        }
         rec.s1 = (int32_t)co.size();
         sop.push_back(rec);
     }
@@ -352,52 +371,6 @@ const DevicePool *device_pool(const Pool &p, int dev) {
     d->pchunk = dev_upload(stage_bounds(pch, sop));
     d->pseg = dev_upload(seg);
     d->n_chunks = (int)pch.size() - 1;
-    // the same schedule for one amplitude per lane, where factored operators
-    // take one group of parameters (and cost a fixed share of a group)
-    {
-        std::vector<char> fac(m);
-        std::vector<std::array<double, kStrGroup>> fco(m);
-        std::vector<std::array<uint32_t, kStrGroup>> fzs(m);
-        for (int r = 0; r < m; ++r) {
-            double c4[kStrGroup];
-            uint32_t z4[kStrGroup];
-            fac[r] = factor_op(p, p.fam_members[r], c4, z4);
-            for (int q = 0; q < kStrGroup; ++q) {
-                fco[r][q] = c4[q];
-                fzs[r][q] = z4[q];
-            }
-        }
-        auto count1 = [&](int r) { return fac[r] ? kStrGroup : count(r); };
-        const std::vector<int32_t> pch1 = stage_chunks(padded_offsets(m, count1));
-        std::vector<int> cost1(m);
-        for (int r = 0; r < m; ++r) cost1[r] = fac[r] ? kOpCost + 3 * kStrGroup : record_cost(count(r), kOpCost);
-        std::vector<int32_t> order1, seg1;
-        for (size_t k = 0; k + 1 < pch1.size(); ++k) wave_split(cost1, pch1[k], pch1[k + 1], order1, seg1);
-        std::vector<HClass> sop1;
-        std::vector<double> co1;
-        std::vector<uint32_t> zs1;
-        for (int32_t r : order1) {
-            const int32_t j = p.fam_members[r];
-            HClass rec{p.op_x[j], (int32_t)co1.size(), 0, j};
-            if (fac[r]) {
-                rec.x |= kFactBit;
-                for (int q = 0; q < kStrGroup; ++q) {
-                    co1.push_back(fco[r][q]);
-                    zs1.push_back(fzs[r][q]);
-                }
-            } else {
-                bucket_strings(p.str_c, p.str_z, p.op_off[j], p.op_off[j + 1], co1, zs1);
-            }
-            rec.s1 = (int32_t)co1.size();
-            sop1.push_back(rec);
-        }
-        d->sop1 = dev_upload(sop1);
-        d->scoef1 = dev_upload(co1);
-        d->szs1 = dev_upload(zs1);
-        d->pchunk1 = dev_upload(stage_bounds(pch1, sop1));
-        d->pseg1 = dev_upload(seg1);
-        d->n_chunks1 = (int)pch1.size() - 1;
-    }
     p.dev[dev] = d.release();
     return p.dev[dev];
 }
@@ -493,12 +466,6 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
         I.pchunk = dp->pchunk;
         I.pseg = dp->pseg;
         I.n_pchunks = dp->n_chunks;
-        I.sop1 = dp->sop1;
-        I.scoef1 = dp->scoef1;
-        I.szs1 = dp->szs1;
-        I.pchunk1 = dp->pchunk1;
-        I.pseg1 = dp->pseg1;
-        I.n_pchunks1 = dp->n_chunks1;
     }
     I.psi = psi;
     I.sigma = sigma_override ? sigma_override : reinterpret_cast<double2 *>(b + ip.o_sigma);
