@@ -179,11 +179,17 @@ bool factor_op(const Pool &p, int j, double (&co)[kStrGroup], uint32_t (&zs)[kSt
         scale += std::fabs(p.str_c[s]);
     }
     if (__builtin_popcount(bm) > kFactBits || (bm & kFactBit)) return false;
+    // F is taken as zero only where the sum is exactly zero (the coefficients
+    // of the fermionic pools are dyadic, so their cancellations are exact); a
+    // pattern whose sum merely nearly cancels keeps the operator's strings
     std::vector<std::pair<uint32_t, double>> nz;
     for (uint32_t u = bm;; u = (u - 1) & bm) {
         double f = 0.0;
         for (int s = a; s < b; ++s) f += (__builtin_popcount(u & p.str_z[s]) & 1) ? -p.str_c[s] : p.str_c[s];
-        if (std::fabs(f) > 1e-12 * scale) nz.emplace_back(u, f);
+        if (f != 0.0) {
+            if (std::fabs(f) < 1e-12 * scale) return false;
+            nz.emplace_back(u, f);
+        }
         if (u == 0) break;
     }
     if (nz.empty() || nz.size() > 2) return false;
