@@ -130,8 +130,13 @@ struct InstDev {
     const int4 *hchunk;         // per LDS stage: class range [x, y), string range [z, w)
     const int32_t *hseg;        // n_hchunks x (kNW + 1) class boundaries of the waves
     const int32_t *hsegp;       // n_hchunks x (kNW kHvwParts + 1): each wave's run cut into kHvwParts
-    const uint32_t *hgx;        // X mask of each group of kStrGroup strings (the group's class)
-    const int32_t *hgseg;       // n_hchunks x (kNW + 1) group boundaries of the waves (equal runs)
+    // the grouped walk's table (one amplitude per lane): per chunk, factored
+    // classes' parameter groups, then the other classes' groups of strings
+    const double *hcoefG;
+    const uint32_t *hzsG;
+    const int4 *hchunkG;        // per chunk: start, end of the factored groups, end (in strings)
+    const uint32_t *hgx;        // X mask of each group of hcoefG / hzsG
+    const int32_t *hgseg;       // n_hchunks x 2 (kNW + 1): the waves' runs of each kind (group indices)
     // pool, in pool order (pair kernels)
     const HClass *pop;          // one record per operator
     const HTerm *pterm;
@@ -181,8 +186,11 @@ struct DeviceHam {
     int4 *hchunk = nullptr;
     int32_t *hseg = nullptr;     // per chunk, kNW + 1 wave boundaries of its classes
     int32_t *hsegp = nullptr;    // per chunk, kNW kHvwParts + 1 boundaries of the waves' runs
-    uint32_t *hgx = nullptr;     // per group of strings, its class's X mask
-    int32_t *hgseg = nullptr;    // per chunk, kNW + 1 group boundaries of the waves (equal runs)
+    double *hcoefG = nullptr;    // the grouped walk's table (see InstDev)
+    uint32_t *hzsG = nullptr;
+    int4 *hchunkG = nullptr;
+    uint32_t *hgx = nullptr;
+    int32_t *hgseg = nullptr;
     int n_chunks = 0;
 };
 

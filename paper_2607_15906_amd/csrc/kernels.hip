@@ -515,7 +515,11 @@ __device__ __forceinline__ void walk_classes_r1(const Stage &S, const GOCP_AS4 u
 // read from the tables' zero padding or from the following groups (a run reads
 // up to 4 K - 1 groups past its end).
 // d must lie in the state.
-template <typename T, int NV, int K>
+// With FG the groups are factored classes, one group of parameters each
+// {|v|, 0, 0, 0 | m0, m1, m2, 0}: f(d) = |v| (-1)^popcount(dz & m0) when
+// popcount(dz & m1) and popcount(dz & m2) are both even (dz = d | 1 << 31),
+// else 0; only the first magnitude of a group is read from LDS.
+template <typename T, int NV, int K, bool FG>
 __device__ __forceinline__ void walk_groups_r1(const Stage &S, const GOCP_AS4 uint32_t *zs,
                                                const GOCP_AS4 uint32_t *gx, int g0, int g1, uint32_t d,
                                                const void *v0, const void *v1, double *acc) {
@@ -549,7 +553,7 @@ __device__ __forceinline__ void walk_groups_r1(const Stage &S, const GOCP_AS4 ui
             int ci = g + k < g1 ? kStrGroup * (g + k) : kStageTerms;
             asm volatile("" : "+s"(ci));
 #pragma unroll
-            for (int q = 0; q < kStrGroup; ++q) b.c[k][q] = S.coef[ci + q];
+            for (int q = 0; q < (FG ? 1 : kStrGroup); ++q) b.c[k][q] = S.coef[ci + q];
         }
     };
     auto gather = [&](Bat &b, const uint32_t (&x)[K]) {
@@ -573,9 +577,18 @@ __device__ __forceinline__ void walk_groups_r1(const Stage &S, const GOCP_AS4 ui
     auto compute = [&](const Bat &b) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const double f0 = signed_cz(b.c[k][0], b.z[k][0], dz) + signed_cz(b.c[k][2], b.z[k][2], dz);
-            const double f1 = signed_cz(b.c[k][1], b.z[k][1], dz) + signed_cz(b.c[k][3], b.z[k][3], dz);
-            const double f = f0 + f1;
+            double f;
+            if constexpr (FG) {
+                const uint32_t off = ((uint32_t)__popc(dz & b.z[k][1]) | (uint32_t)__popc(dz & b.z[k][2])) & 1u;
+                const uint32_t keep = off - 1u;                  // all ones when both are even
+                const double cv = b.c[k][0];
+                const uint32_t hi = ((uint32_t)__popc(dz & b.z[k][0]) << 31) | (uint32_t)__double2hiint(cv);
+                f = __hiloint2double((int)(hi & keep), (int)((uint32_t)__double2loint(cv) & keep));
+            } else {
+                const double f0 = signed_cz(b.c[k][0], b.z[k][0], dz) + signed_cz(b.c[k][2], b.z[k][2], dz);
+                const double f1 = signed_cz(b.c[k][1], b.z[k][1], dz) + signed_cz(b.c[k][3], b.z[k][3], dz);
+                f = f0 + f1;
+            }
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 const double2 a = Amp<T>::cvt(b.p[k][v]);
@@ -644,17 +657,22 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
         // records); two vectors (H v, H w of complex128 states) keep the class
         // walk, which measured faster there (20.7 against 28.2 us at 14 qubits)
         constexpr bool grouped = R == 1 && NV == 1;
+        // the grouped walk stages its own table (factored classes first)
+        const int4 gbd = grouped ? load_rec(cptr(I.hchunkG), k) : make_int4(0, 0, 0, 0);
         if (!grouped) stage_copy(S.cls, I.hcls + cb, ce - cb);
         if (R > 1) stage_copy(S.sub, I.hsub + cb, ce - cb);
-        stage_coef(S, I.hcoef, sb, se);
+        if (grouped) stage_coef(S, I.hcoefG, gbd.x, gbd.z);
+        else stage_coef(S, I.hcoef, sb, se);
         const GOCP_AS4 uint32_t *zs = cptr(I.hzs) + sb;
         __syncthreads();
         if constexpr (grouped) {
-            // the wave's run of string groups
-            const int gb = sb / kStrGroup;
-            const GOCP_AS4 int32_t *t = cptr(I.hgseg) + k * (kNW + 1) + wv;
-            walk_groups_r1<T, NV, kWalkBatch>(S, zs, cptr(I.hgx) + gb, t[0] - gb, t[1] - gb,
-                                              d0 < dim ? d0 : 0u, v0, v1, acc);
+            // the wave's run of factored classes, then its run of string groups
+            const int gb = gbd.x / kStrGroup;
+            const GOCP_AS4 uint32_t *zg = cptr(I.hzsG) + gbd.x, *gx = cptr(I.hgx) + gb;
+            const GOCP_AS4 int32_t *t = cptr(I.hgseg) + k * 2 * (kNW + 1) + wv;
+            const uint32_t dd = d0 < dim ? d0 : 0u;
+            walk_groups_r1<T, NV, kWalkBatch, true>(S, zg, gx, t[0] - gb, t[1] - gb, dd, v0, v1, acc);
+            walk_groups_r1<T, NV, kWalkBatch, false>(S, zg, gx, t[kNW + 1] - gb, t[kNW + 2] - gb, dd, v0, v1, acc);
             continue;
         }
         int c0, c1;

@@ -163,6 +163,33 @@ std::vector<int4> stage_bounds(const std::vector<int32_t> &b, const std::vector<
     return out;
 }
 
+// H's class of exactly four strings whose Z masks form an affine set z0 +
+// {0, u, v, u + v} (three nonzero offsets, each the XOR of the other two)
+// with coefficients c, c (-1)^alpha, c (-1)^beta, c (-1)^(alpha + beta):
+// f(d) = 4 c (-1)^popcount(d & z0) [popcount(d & u) = alpha mod 2]
+// [popcount(d & v) = beta mod 2], since each of the two sums over a factor of
+// the set is 2 or 0.  Fills the group {|4c|, 0, 0, 0 | z0 | sign(c) << 31,
+// u | alpha << 31, v | beta << 31, 0}: with d | 1 << 31, the three popcounts
+// give the sign and the two conditions (both even).
+bool factor_class(const std::vector<double> &c, const std::vector<uint32_t> &z, int a, int b,
+                  double (&co)[kStrGroup], uint32_t (&zs)[kStrGroup]) {
+    if (b - a != 4) return false;
+    const uint32_t z0 = z[a], u = z[a + 1] ^ z0, v = z[a + 2] ^ z0;
+    const double c0 = c[a], cu = c[a + 1], cv = c[a + 2], cuv = c[a + 3];
+    if (c0 == 0.0 || u == 0 || v == 0 || u == v || (z[a + 3] ^ z0) != (u ^ v) || ((u | v | z0) >> 31)) return false;
+    if (std::fabs(cu) != std::fabs(c0) || std::fabs(cv) != std::fabs(c0) || std::fabs(cuv) != std::fabs(c0))
+        return false;
+    const uint32_t alpha = (cu < 0) != (c0 < 0), beta = (cv < 0) != (c0 < 0);
+    if (((cuv < 0) != (c0 < 0)) != ((alpha ^ beta) != 0)) return false;
+    co[0] = std::fabs(4.0 * c0);
+    co[1] = co[2] = co[3] = 0.0;
+    zs[0] = z0 | (c0 < 0 ? 1u << 31 : 0u);
+    zs[1] = u | (alpha << 31);
+    zs[2] = v | (beta << 31);
+    zs[3] = 0u;
+    return true;
+}
+
 // Operator j as f(d) = (-1)^popcount(d & zb) F(d & bm): its strings' Z masks
 // agree outside bm (at most kFactBits bits), F(u) = sum_s c_s
 // (-1)^popcount(u & z_s) over the submasks u of bm, and F is nonzero at one
@@ -225,6 +252,9 @@ void release_device_ham(DeviceHam *d) {
     (void)hipFree(d->hchunk);
     (void)hipFree(d->hseg);
     (void)hipFree(d->hsegp);
+    (void)hipFree(d->hcoefG);
+    (void)hipFree(d->hzsG);
+    (void)hipFree(d->hchunkG);
     (void)hipFree(d->hgx);
     (void)hipFree(d->hgseg);
     delete d;
@@ -276,20 +306,52 @@ const DeviceHam *device_ham(const Ham &h, int dev) {
         sub.push_back(bucket_strings(h.str_c, h.str_z, h.cls_off[c], h.cls_off[c + 1], co, zs));
         cls.push_back(HClass{h.cls_x[c], s0, (int32_t)co.size(), 0});
     }
-    // per group of strings its class's X mask; per chunk, the group walk's
-    // wave runs: the chunk's groups cut into kNW contiguous runs of equal
-    // length (the walk is linear in the groups, so a class may span two waves)
-    std::vector<uint32_t> gx;
-    for (const HClass &r : cls)
-        for (int s = r.s0; s < r.s1; s += kStrGroup) gx.push_back(r.x);
+    // The grouped walk's table (one amplitude per lane): per chunk, the
+    // groups of the factored classes (factor_class: one group of parameters
+    // each), then every other class's groups of strings, each kind cut into
+    // kNW contiguous runs of equal length, one per wave (the walk is linear
+    // in the groups, so their order and a class spanning two waves do not
+    // matter); per group its class's X mask.
+    std::vector<double> gco;
+    std::vector<uint32_t> gzs, gx;
     std::vector<int32_t> gseg;
+    std::vector<int4> gchunk;
     for (size_t k = 0; k + 1 < ch.size(); ++k) {
-        const int32_t a = cls[ch[k]].s0 / kStrGroup, b = cls[ch[k + 1] - 1].s1 / kStrGroup;
-        for (int w = 0; w <= kNW; ++w) gseg.push_back(a + (int32_t)((int64_t)(b - a) * w / kNW));
+        const int32_t sb = (int32_t)gco.size();
+        std::vector<char> fac(ch[k + 1] - ch[k], 0);
+        for (int32_t i = ch[k]; i < ch[k + 1]; ++i) {
+            const int32_t c = order[i];
+            double c4[kStrGroup];
+            uint32_t z4[kStrGroup];
+            if (!factor_class(h.str_c, h.str_z, h.cls_off[c], h.cls_off[c + 1], c4, z4)) continue;
+            fac[i - ch[k]] = 1;
+            for (int q = 0; q < kStrGroup; ++q) {
+                gco.push_back(c4[q]);
+                gzs.push_back(z4[q]);
+            }
+            gx.push_back(cls[i].x);
+        }
+        const int32_t fe = (int32_t)gco.size();
+        for (int32_t i = ch[k]; i < ch[k + 1]; ++i) {
+            if (fac[i - ch[k]]) continue;
+            for (int32_t s = cls[i].s0; s < cls[i].s1; ++s) {
+                gco.push_back(co[s]);
+                gzs.push_back(zs[s]);
+                if ((s - cls[i].s0) % kStrGroup == 0) gx.push_back(cls[i].x);
+            }
+        }
+        const int32_t se = (int32_t)gco.size();
+        const int32_t g0 = sb / kStrGroup, g1 = fe / kStrGroup, g2 = se / kStrGroup;
+        for (int w = 0; w <= kNW; ++w) gseg.push_back(g0 + (int32_t)((int64_t)(g1 - g0) * w / kNW));
+        for (int w = 0; w <= kNW; ++w) gseg.push_back(g1 + (int32_t)((int64_t)(g2 - g1) * w / kNW));
+        gchunk.push_back(make_int4(sb, fe, se, 0));
     }
     // zero groups past the end: the walk's read-ahead stays in the tables
-    zs.resize(zs.size() + (size_t)kTablePadGroups * kStrGroup, 0u);
+    gzs.resize(gzs.size() + (size_t)kTablePadGroups * kStrGroup, 0u);
     gx.resize(gx.size() + kTablePadGroups, 0u);
+    d->hcoefG = dev_upload(gco);
+    d->hzsG = dev_upload(gzs);
+    d->hchunkG = dev_upload(gchunk);
     d->hgx = dev_upload(gx);
     d->hgseg = dev_upload(gseg);
     d->hcls = dev_upload(cls);
@@ -456,6 +518,9 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
         I.hchunk = dh->hchunk;
         I.hseg = dh->hseg;
         I.hsegp = dh->hsegp;
+        I.hcoefG = dh->hcoefG;
+        I.hzsG = dh->hzsG;
+        I.hchunkG = dh->hchunkG;
         I.hgx = dh->hgx;
         I.hgseg = dh->hgseg;
         I.n_hchunks = dh->n_chunks;
