@@ -363,11 +363,32 @@ __device__ __forceinline__ void wht(double *g) {
 
 // Class (or operator) c of the staged chunk: f_r for the lane's R amplitudes
 // (zs = the chunk's Z masks).
-template <int R, bool FACT = false>
+// Flagged records (kFactBit in the X mask) hold one group of parameters:
+// factored H classes (FK = kFactH: f = |v| (-1)^popcount(dz & m0) when
+// popcount(dz & m1) and popcount(dz & m2) are even, dz = d | 1 << 31) or
+// factored pool operators (FK = kFactPool).
+constexpr int kFactNone = 0, kFactPool = 1, kFactH = 2;
+__device__ __forceinline__ double fact_h(double v, uint32_t m0, uint32_t m1, uint32_t m2, uint32_t dz) {
+    const uint32_t off = ((uint32_t)__popc(dz & m1) | (uint32_t)__popc(dz & m2)) & 1u;
+    const uint32_t keep = off - 1u;                  // all ones when both are even
+    const uint32_t hi = ((uint32_t)__popc(dz & m0) << 31) | (uint32_t)__double2hiint(v);
+    return __hiloint2double((int)(hi & keep), (int)((uint32_t)__double2loint(v) & keep));
+}
+
+template <int R, int FK = kFactNone>
 __device__ __forceinline__ void class_coeffs(const Stage &S, const GOCP_AS4 uint32_t *zs, int c, int sb, uint32_t d0,
                                              double *f) {
     const int s0 = uni(S.cls[c].s0) - sb, s1 = uni(S.cls[c].s1) - sb;
-    if constexpr (FACT) {
+    if constexpr (FK == kFactH) {
+        if ((uint32_t)uni((int)S.cls[c].x) & kFactBit) {
+            const double v = S.coef[s0];
+            const uint32_t m0 = zs[s0], m1 = zs[s0 + 1], m2 = zs[s0 + 2];
+#pragma unroll
+            for (int r = 0; r < R; ++r) f[r] = fact_h(v, m0, m1, m2, with_sign_bit(d0 | ((uint32_t)r << 6)));
+            return;
+        }
+    }
+    if constexpr (FK == kFactPool) {
         // a factored operator, evaluated at each of the lane's amplitudes
         if ((uint32_t)uni((int)S.cls[c].x) & kFactBit) {
             const double v1 = S.coef[s0], v2 = S.coef[s0 + 1];
@@ -426,10 +447,11 @@ __device__ __forceinline__ void lane_offsets(uint32_t d0, uint32_t dim, uint32_t
 // from v0 (and v1) are in flight, and the record after that is being read.
 // d must lie in the state (its bits feed the gather index directly).
 // fin(c, f_c(d), raw amplitudes at d ^ x_c) is called for every record in order.
-// With FACT, records flagged kFactBit hold one group of parameters instead
-// of strings (a factored pool operator): f(d) = (-1)^popcount(d & z_b) times
-// v1 or v2 where d & b equals t1 or t2, and 0 elsewhere.
-template <typename T, int NV, bool FACT, typename Fin>
+// Records flagged kFactBit hold one group of parameters instead of strings:
+// factored H classes (FK = kFactH, see fact_h) or factored pool operators
+// (FK = kFactPool: f(d) = (-1)^popcount(d & z_b) times v1 or v2 where d & b
+// equals t1 or t2, and 0 elsewhere).
+template <typename T, int NV, int FK, typename Fin>
 __device__ __forceinline__ void walk_classes_r1(const Stage &S, const GOCP_AS4 uint32_t *zs, int c0, int c1, int sb,
                                                 uint32_t d, const void *v0, const void *v1, Fin &&fin) {
     using Raw = typename Amp<T>::Raw;
@@ -460,7 +482,10 @@ __device__ __forceinline__ void walk_classes_r1(const Stage &S, const GOCP_AS4 u
     // f(d) of a record whose first group is in registers; further groups are
     // read here (the string range is uniform: scalar loop bounds)
     auto coef = [&](const Rec &k, const Grp &g) {
-        if constexpr (FACT) {
+        if constexpr (FK == kFactH) {
+            if (k.x & kFactBit) return fact_h(g.c[0], g.z[0], g.z[1], g.z[2], dz);
+        }
+        if constexpr (FK == kFactPool) {
             if (k.x & kFactBit) {
                 const uint32_t u = d & g.z[1];
                 double v = u == g.z[2] ? g.c[0] : 0.0;
@@ -579,11 +604,7 @@ __device__ __forceinline__ void walk_groups_r1(const Stage &S, const GOCP_AS4 ui
         for (int k = 0; k < K; ++k) {
             double f;
             if constexpr (FG) {
-                const uint32_t off = ((uint32_t)__popc(dz & b.z[k][1]) | (uint32_t)__popc(dz & b.z[k][2])) & 1u;
-                const uint32_t keep = off - 1u;                  // all ones when both are even
-                const double cv = b.c[k][0];
-                const uint32_t hi = ((uint32_t)__popc(dz & b.z[k][0]) << 31) | (uint32_t)__double2hiint(cv);
-                f = __hiloint2double((int)(hi & keep), (int)((uint32_t)__double2loint(cv) & keep));
+                f = fact_h(b.c[k][0], b.z[k][0], b.z[k][1], b.z[k][2], dz);
             } else {
                 const double f0 = signed_cz(b.c[k][0], b.z[k][0], dz) + signed_cz(b.c[k][2], b.z[k][2], dz);
                 const double f1 = signed_cz(b.c[k][1], b.z[k][1], dz) + signed_cz(b.c[k][3], b.z[k][3], dz);
@@ -678,7 +699,7 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
         int c0, c1;
         wave_range(I.hseg, k, cb, c0, c1);
         if constexpr (R == 1) {
-            walk_classes_r1<T, NV, false>(S, zs, c0, c1, sb, d0 < dim ? d0 : 0u, v0, v1,
+            walk_classes_r1<T, NV, kFactH>(S, zs, c0, c1, sb, d0 < dim ? d0 : 0u, v0, v1,
                                    [&](int, double f, const typename Amp<T>::Raw (&p)[NV]) {
 #pragma unroll
                                        for (int v = 0; v < NV; ++v) {
@@ -717,7 +738,7 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
                 }
             }
             double f[R];
-            class_coeffs<R>(S, zs, c, sb, d0, f);
+            class_coeffs<R, kFactH>(S, zs, c, sb, d0, f);
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -901,7 +922,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                 if (++nbuf == 4) flush();
             };
             if constexpr (R == 1) {
-                walk_classes_r1<T, 1, true>(S, zs, o0, o1, sb, d0 < dim ? d0 : 0u, I.psi, nullptr,
+                walk_classes_r1<T, 1, kFactPool>(S, zs, o0, o1, sb, d0 < dim ? d0 : 0u, I.psi, nullptr,
                                       [&](int o, double h, const typename Amp<T>::Raw (&p)[1]) {
                                           const double2 a = Amp<T>::cvt(p[0]);
                                           push(o, h * (sg[0].x * a.x + sg[0].y * a.y));
@@ -927,7 +948,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                     for (int r = 0; r < R; ++r) rn[r] = Amp<T>::raw_at(I.psi, off[r] ^ xn);
                 }
                 double h[R];
-                class_coeffs<R, true>(S, zs, o, sb, d0, h);
+                class_coeffs<R, kFactPool>(S, zs, o, sb, d0, h);
                 double val = 0.0;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -1577,7 +1598,7 @@ __global__ __launch_bounds__(kNW *kWave) __attribute__((amdgpu_waves_per_eu(8)))
                 double acc[4] = {0.0, 0.0, 0.0, 0.0};
                 // runs of a few classes: the class walk, whose pipeline fills
                 // faster than the grouped walk's
-                walk_classes_r1<T, 2, false>(S, zs, c0, c1, sb, d, vv, vw,
+                walk_classes_r1<T, 2, kFactH>(S, zs, c0, c1, sb, d, vv, vw,
                                       [&](int, double f, const typename Amp<T>::Raw (&p)[2]) {
 #pragma unroll
                                           for (int v = 0; v < 2; ++v) {

@@ -312,33 +312,40 @@ const DeviceHam *device_ham(const Ham &h, int dev) {
     // kNW contiguous runs of equal length, one per wave (the walk is linear
     // in the groups, so their order and a class spanning two waves do not
     // matter); per group its class's X mask.
+    // Factored classes (factor_class) keep their single group in the class
+    // tables too, holding the parameters instead of the strings, and are
+    // flagged kFactBit in their record (every kernel that walks classes
+    // evaluates them so; the gathers shift the flag out of the X mask).
+    std::vector<char> fac(cls.size(), 0);
+    for (size_t i = 0; i < cls.size(); ++i) {
+        const int32_t c = order[i];
+        double c4[kStrGroup];
+        uint32_t z4[kStrGroup];
+        if (!factor_class(h.str_c, h.str_z, h.cls_off[c], h.cls_off[c + 1], c4, z4)) continue;
+        fac[i] = 1;
+        cls[i].x |= kFactBit;
+        for (int q = 0; q < kStrGroup; ++q) {
+            co[cls[i].s0 + q] = c4[q];
+            zs[cls[i].s0 + q] = z4[q];
+        }
+    }
     std::vector<double> gco;
     std::vector<uint32_t> gzs, gx;
     std::vector<int32_t> gseg;
     std::vector<int4> gchunk;
     for (size_t k = 0; k + 1 < ch.size(); ++k) {
         const int32_t sb = (int32_t)gco.size();
-        std::vector<char> fac(ch[k + 1] - ch[k], 0);
-        for (int32_t i = ch[k]; i < ch[k + 1]; ++i) {
-            const int32_t c = order[i];
-            double c4[kStrGroup];
-            uint32_t z4[kStrGroup];
-            if (!factor_class(h.str_c, h.str_z, h.cls_off[c], h.cls_off[c + 1], c4, z4)) continue;
-            fac[i - ch[k]] = 1;
-            for (int q = 0; q < kStrGroup; ++q) {
-                gco.push_back(c4[q]);
-                gzs.push_back(z4[q]);
+        int32_t fe = sb;
+        for (int kind = 0; kind < 2; ++kind) {          // factored classes, then the others
+            for (int32_t i = ch[k]; i < ch[k + 1]; ++i) {
+                if (fac[i] != (kind == 0)) continue;
+                for (int32_t s = cls[i].s0; s < cls[i].s1; ++s) {
+                    gco.push_back(co[s]);
+                    gzs.push_back(zs[s]);
+                    if ((s - cls[i].s0) % kStrGroup == 0) gx.push_back(cls[i].x & ~kFactBit);
+                }
             }
-            gx.push_back(cls[i].x);
-        }
-        const int32_t fe = (int32_t)gco.size();
-        for (int32_t i = ch[k]; i < ch[k + 1]; ++i) {
-            if (fac[i - ch[k]]) continue;
-            for (int32_t s = cls[i].s0; s < cls[i].s1; ++s) {
-                gco.push_back(co[s]);
-                gzs.push_back(zs[s]);
-                if ((s - cls[i].s0) % kStrGroup == 0) gx.push_back(cls[i].x);
-            }
+            if (kind == 0) fe = (int32_t)gco.size();
         }
         const int32_t se = (int32_t)gco.size();
         const int32_t g0 = sb / kStrGroup, g1 = fe / kStrGroup, g2 = se / kStrGroup;
