@@ -263,10 +263,12 @@ int gocp_batch_create(gocp_ctx *ctx, int32_t n, const gocp_ham *const *hams,
 int gocp_batch_step(gocp_batch *b, int32_t n_iter);
 /*
  * Measurement form of gocp_batch_step: n_iter iterations launched directly
- * (no graph) on the context stream, with HIP events recorded around the
- * launch of one kernel of the iteration (kernel: 0 selection and line-search
- * vectors, 1 H v / H w, 2 angle and Taylor update, 3 energy and screen
- * partials, 4 their group sums) in iterations 0, every, 2 every, ...  Waits for the work;
+ * (no graph) on the context stream, with HIP events that take the dispatch
+ * timestamps (start and end, hipExtLaunchKernel) of one kernel of the
+ * iteration (kernel: 0 selection and line-search vectors, 1 H v / H w (the
+ * first launch's start to the second one's end), 2 angle and Taylor update,
+ * 3 energy and screen partials, 4 their group sums) in iterations 0, every,
+ * 2 every, ...  Waits for the work;
  * returns the elapsed time of all n_iter iterations and the mean duration of
  * the sampled launches (ms).  The iterations are the same as
  * gocp_batch_step's.  Errors: EINVAL.

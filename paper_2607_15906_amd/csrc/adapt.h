@@ -196,8 +196,9 @@ struct Group {
     // then the new state's energy and screen partials and their group sums.
     // The new state's selection is pending until the next iteration or
     // select_pending().
-    // With `timed` set, HIP events ev[0] and ev[1] are recorded on s right
-    // before and after the launch of kernel id `timed_kid`.
+    // With `ev` set, the launch of kernel id `timed_kid` records its start in
+    // ev[0] and its end in ev[1] (for the H v, H w pair: the first one's start,
+    // the second one's end).
     void enqueue_iteration(hipStream_t s, int timed_kid = -1, const hipEvent_t *ev = nullptr) const {
         if (inst.empty()) return;
         const int n = (int)inst.size();
@@ -212,18 +213,18 @@ struct Group {
                           {K_SCREEN_SUM1, 2, bgrp, ng}};
         for (const L &l : seq) {
             const bool t = ev && l.kid == timed_kid;
-            if (t) hip_check(hipEventRecord(ev[0], s), "hipEventRecord");
-            if (l.kid == K_LINE_HVW) launch_hvw(l.mode, s);
-            else launch_kernel(l.kid, dtype, R, desc, l.rows, l.nrows, l.mode, s);
-            if (t) hip_check(hipEventRecord(ev[1], s), "hipEventRecord");
+            const hipEvent_t t0 = t ? ev[0] : nullptr, t1 = t ? ev[1] : nullptr;
+            if (l.kid == K_LINE_HVW) launch_hvw(l.mode, s, t0, t1);
+            else launch_kernel(l.kid, dtype, R, desc, l.rows, l.nrows, l.mode, s, 0, 0.0, 0, t0, t1);
         }
     }
 
     // The H v, H w launches over the whole group (mode as k_line_hvw):
-    // compacted for members with lists, whole-state for the others.
-    void launch_hvw(int mode, hipStream_t s) const {
-        launch_hvw_act(desc, bact, na, mode, s);
-        launch_kernel(K_LINE_HVW, dtype, R, desc, bhvw, nh, mode, s);
+    // compacted for members with lists, whole-state for the others; t0 takes
+    // the first launch's start, t1 the second one's end.
+    void launch_hvw(int mode, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) const {
+        launch_hvw_act(desc, bact, na, mode, s, t0, nullptr);
+        launch_kernel(K_LINE_HVW, dtype, R, desc, bhvw, nh, mode, s, 0, 0.0, 0, nullptr, t1);
     }
 
     // Selection (energy, gradients, operator, record) of every member's

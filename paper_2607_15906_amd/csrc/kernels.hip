@@ -25,6 +25,7 @@
 // floating-point atomics are used.
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 
@@ -1907,57 +1908,75 @@ __global__ void k_basis(void *psi, uint32_t dim, uint32_t index) {
 
 // ------------------------------------------------------------------ launchers
 
+// Launch K over nb workgroups of nt lanes on s; with a timestamp event set, the
+// dispatch itself records it (start and / or end of the kernel).
+#define GOCP_LAUNCH(K, nb, nt, ...)                                                              \
+    do {                                                                                         \
+        if (t0 || t1) hipExtLaunchKernelGGL(K, dim3(nb), dim3(nt), 0, s, t0, t1, 0, __VA_ARGS__); \
+        else hipLaunchKernelGGL(K, dim3(nb), dim3(nt), 0, s, __VA_ARGS__);                       \
+    } while (0)
+
 template <typename T, int R>
-static void launch_tile(int which, const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s) {
+static void launch_tile(int which, const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s,
+                        hipEvent_t t0, hipEvent_t t1) {
     if (which == 0) {
-        hipLaunchKernelGGL((k_energy_screen<T, R>), dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode);
+        GOCP_LAUNCH((k_energy_screen<T, R>), nblk, kNW * kWave, insts, blk, mode);
     } else if constexpr (R == 1) {
-        hipLaunchKernelGGL((k_line_hvw1<T>), dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode);
+        GOCP_LAUNCH((k_line_hvw1<T>), nblk, kNW * kWave, insts, blk, mode);
     } else {
-        hipLaunchKernelGGL((k_line_hvw<T, R>), dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode);
+        GOCP_LAUNCH((k_line_hvw<T, R>), nblk, kNW * kWave, insts, blk, mode);
     }
 }
 
 template <typename T>
 static void launch_all(int which, int R, const InstDev *insts, const int2 *blk, int nblk, int mode,
-                       hipStream_t s, int j, double th, int ns) {
+                       hipStream_t s, int j, double th, int ns, hipEvent_t t0, hipEvent_t t1) {
     switch (which) {
     case 0:
     case 3: {
         const int w = which == 0 ? 0 : 1;
-        if (R == 4) launch_tile<T, 4>(w, insts, blk, nblk, mode, s);
-        else if (R == 2) launch_tile<T, 2>(w, insts, blk, nblk, mode, s);
-        else launch_tile<T, 1>(w, insts, blk, nblk, mode, s);
+        if (R == 4) launch_tile<T, 4>(w, insts, blk, nblk, mode, s, t0, t1);
+        else if (R == 2) launch_tile<T, 2>(w, insts, blk, nblk, mode, s, t0, t1);
+        else launch_tile<T, 1>(w, insts, blk, nblk, mode, s, t0, t1);
         break;
     }
-    case 1: hipLaunchKernelGGL(k_screen_reduce, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode); break;
-    case 7: hipLaunchKernelGGL(k_screen_sum1, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode); break;
-    case 2: hipLaunchKernelGGL(k_line_vw<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk); break;
+    case 1: GOCP_LAUNCH(k_screen_reduce, nblk, kPairBlock, insts, blk, mode); break;
+    case 7: GOCP_LAUNCH(k_screen_sum1, nblk, kPairBlock, insts, blk, mode); break;
+    case 2: GOCP_LAUNCH(k_line_vw<T>, nblk, kPairBlock, insts, blk); break;
     case 4:
-        if (mode) hipLaunchKernelGGL((k_taylor5<T, true>), dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, j, th, ns);
-        else hipLaunchKernelGGL((k_taylor5<T, false>), dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, j, th, ns);
+        if (mode) GOCP_LAUNCH((k_taylor5<T, true>), nblk, kPairBlock, insts, blk, j, th, ns);
+        else GOCP_LAUNCH((k_taylor5<T, false>), nblk, kPairBlock, insts, blk, j, th, ns);
         break;
-    case 5: hipLaunchKernelGGL(k_normalize<T>, dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, mode); break;
-    case 6: hipLaunchKernelGGL(k_state_unit_norm, dim3(nblk), dim3(64), 0, s, insts, blk); break;
+    case 5: GOCP_LAUNCH(k_normalize<T>, nblk, kPairBlock, insts, blk, mode); break;
+    case 6: GOCP_LAUNCH(k_state_unit_norm, nblk, 64, insts, blk); break;
     default: break;
     }
 }
 
+// No rows: the timestamp events, if any, mark the empty launch's place in s.
+static void record_empty(hipEvent_t t0, hipEvent_t t1, hipStream_t s) {
+    if (t0) hip_check(hipEventRecord(t0, s), "hipEventRecord");
+    if (t1) hip_check(hipEventRecord(t1, s), "hipEventRecord");
+}
+
 void launch_kernel(int which, int dtype, int R, const InstDev *insts, const int2 *blk, int nblk, int mode,
-                   hipStream_t s, int j, double th, int ns) {
-    if (nblk <= 0) return;
+                   hipStream_t s, int j, double th, int ns, hipEvent_t t0, hipEvent_t t1) {
+    if (nblk <= 0) return record_empty(t0, t1, s);
     if (dtype == GOCP_C64)
-        launch_all<float2>(which, R, insts, blk, nblk, mode, s, j, th, ns);
+        launch_all<float2>(which, R, insts, blk, nblk, mode, s, j, th, ns, t0, t1);
     else
-        launch_all<double2>(which, R, insts, blk, nblk, mode, s, j, th, ns);
+        launch_all<double2>(which, R, insts, blk, nblk, mode, s, j, th, ns, t0, t1);
     hip_check(hipGetLastError(), "kernel launch");
 }
 
-void launch_hvw_act(const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s) {
-    if (nblk <= 0) return;
-    hipLaunchKernelGGL(k_line_hvw_act<float2>, dim3(nblk), dim3(kNW * kWave), 0, s, insts, blk, mode);
+void launch_hvw_act(const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s, hipEvent_t t0,
+                    hipEvent_t t1) {
+    if (nblk <= 0) return record_empty(t0, t1, s);
+    GOCP_LAUNCH(k_line_hvw_act<float2>, nblk, kNW * kWave, insts, blk, mode);
     hip_check(hipGetLastError(), "kernel launch");
 }
+
+#undef GOCP_LAUNCH
 
 void launch_gather_done(const InstDev *insts, int n, int32_t *out, hipStream_t s) {
     if (n <= 0) return;

@@ -26,11 +26,16 @@ enum {
 };
 
 // R = amplitudes per lane of the tile kernels (1, 2 or 4); the pair kernels ignore it.
+// t0 / t1, when set, take the dispatch's own start / end timestamps
+// (hipExtLaunchKernel), so the span between them holds the kernel alone and not
+// the queue's launch latency; with no rows to launch they are recorded at once.
 void launch_kernel(int which, int dtype, int R, const InstDev *insts, const int2 *blk, int nblk, int mode,
-                   hipStream_t s, int j = 0, double th = 0.0, int ns = 0);
+                   hipStream_t s, int j = 0, double th = 0.0, int ns = 0, hipEvent_t t0 = nullptr,
+                   hipEvent_t t1 = nullptr);
 // Compacted H v, H w launch (complex64 states with a compaction list): rows
-// (instance, slot kHvwParts + part).
-void launch_hvw_act(const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s);
+// (instance, slot kHvwParts + part); t0 / t1 as for launch_kernel.
+void launch_hvw_act(const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s,
+                    hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_basis(int dtype, void *psi, uint32_t dim, uint32_t index, hipStream_t s);
 void launch_gather_done(const InstDev *insts, int n, int32_t *out, hipStream_t s);
 
