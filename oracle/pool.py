@@ -22,7 +22,7 @@ from __future__ import annotations
 from .pauli import psum_mul, psum_add, psum_dagger, psum_clean
 from .mapping import ladder_ops
 
-__all__ = ["pool_excitations", "pool_operators"]
+__all__ = ["pool_excitations", "pool_operators", "pauli_pool_operators"]
 
 
 def pool_excitations(N: int, n_electrons: int):
@@ -61,3 +61,22 @@ def pool_operators(N: int, n_electrons: int, mapping: str):
         A = psum_clean(psum_add(tau, psum_dagger(tau), -1.0))
         ops.append((kind, idx, A))
     return ops
+
+
+def pauli_pool_operators(N: int, n_electrons: int, mapping: str):
+    """Pauli (qubit) pool: every string of every generator as its own operator.
+
+    Not in the paper (its pool is the fermionic one of Table II); the reading
+    here: the string ``c P(x, z)`` of ``A_k`` becomes ``B = (c / |c|) P(x, z)``.
+    ``c`` is purely imaginary for an anti-Hermitian ``A_k`` and ``P`` is
+    Hermitian, so ``B`` is anti-Hermitian and ``B^2 = -1``.  Order: generators
+    in pool order, each one's strings by ascending ``(x, z)`` (one ``x`` per
+    generator).  Entries ``(kind + 2, indices, B)``.
+    """
+    out = []
+    for kind, idx, A in pool_operators(N, n_electrons, mapping):
+        for (x, z) in sorted(A):
+            c = A[(x, z)]
+            out.append((kind + 2, idx, {(x, z): c / abs(c)}))
+    return out
+
