@@ -113,11 +113,24 @@ int gocp_ham_free(gocp_ham *h);
  */
 int pool_build(int n_qubits, int n_electrons, int mapping, gocp_pool **out);
 
+/*
+ * pool_build_pauli -- the Pauli (qubit) pool of the same excitations: every
+ * string of every pool_build generator (Sec. II.B, mapped as in Eq. 3) becomes
+ * an operator of its own, B = sign(c) Z^z X^x with unit coefficient (anti-
+ * Hermitian, B^2 = -1, so the line search and the Taylor chain of Sec. III.B
+ * apply unchanged).  Order: generators in pool_build order, each one's strings
+ * by ascending Z mask; M = S = 2 singles + 8 doubles.  gocp_pool_op reports
+ * kind 3 (string of a single) or 4 (string of a double) with the parent's
+ * indices.  Caller owns the handle (gocp_pool_free).  Errors as pool_build.
+ */
+int pool_build_pauli(int n_qubits, int n_electrons, int mapping, gocp_pool **out);
+
 /* Sizes: qubits, operators M, total strings S.  Any output may be NULL. */
 int gocp_pool_info(const gocp_pool *p, int32_t *n_qubits, int32_t *n_ops, int32_t *n_strings);
 
-/* Operator k: kind (1 single, 2 double), spin-orbital indices (i, a, -1, -1)
- * or (i, j, a, b), and its X mask.  Errors: EINVAL if k is out of range. */
+/* Operator k: kind (1 single, 2 double; 3, 4 one string of either, from
+ * pool_build_pauli), spin-orbital indices (i, a, -1, -1) or (i, j, a, b), and
+ * its X mask.  Errors: EINVAL if k is out of range. */
 int gocp_pool_op(const gocp_pool *p, int32_t k, int32_t *kind, int32_t idx[4], uint32_t *xmask);
 
 /* All strings: op_offsets[M+1] (CSR), z[S], c[S] folded coefficients; x per op

@@ -54,6 +54,7 @@ SIGNATURES = {
     "gocp_ham_terms": [_P, C.c_int64, _U32P, _U32P, _F64P],
     "gocp_ham_free": [_P],
     "pool_build": [C.c_int, C.c_int, C.c_int, _PP],
+    "pool_build_pauli": [C.c_int, C.c_int, C.c_int, _PP],
     "gocp_pool_info": [_P, _I32P, _I32P, _I32P],
     "gocp_pool_op": [_P, C.c_int32, _I32P, _I32P, _U32P],
     "gocp_pool_strings": [_P, _I32P, _U32P, _F64P],

@@ -15,7 +15,7 @@ import numpy as np
 from ._lib import load, check, AdaptParams, AdaptResult, RequestInfo, GOCP_EBUSY
 
 __all__ = ["MAPPINGS", "Hamiltonian", "Pool", "Context", "pauli_hamiltonian_load",
-           "pauli_hamiltonian_load_terms", "pool_build", "gocp_partition", "hf_index",
+           "pauli_hamiltonian_load_terms", "pool_build", "pool_build_pauli", "gocp_partition", "hf_index",
            "state_basis", "energy", "apply_hamiltonian", "pool_gradients", "taylor5_apply",
            "adapt_solve", "Batch", "Server", "request_footprint", "version"]
 
@@ -143,6 +143,13 @@ def pauli_hamiltonian_load_terms(n_qubits: int, x, z, c) -> Hamiltonian:
 def pool_build(n_qubits: int, n_electrons: int, mapping) -> Pool:
     out = C.c_void_p()
     check(load().pool_build(n_qubits, n_electrons, _mapping(mapping), C.byref(out)))
+    return Pool(out)
+
+
+def pool_build_pauli(n_qubits: int, n_electrons: int, mapping) -> Pool:
+    """One operator per string of the pool_build generators, unit coefficients."""
+    out = C.c_void_p()
+    check(load().pool_build_pauli(n_qubits, n_electrons, _mapping(mapping), C.byref(out)))
     return Pool(out)
 
 

@@ -105,6 +105,14 @@ int pool_build(int n_qubits, int n_electrons, int mapping, gocp_pool **out) {
     GOCP_GUARD_END
 }
 
+int pool_build_pauli(int n_qubits, int n_electrons, int mapping, gocp_pool **out) {
+    GOCP_GUARD_BEGIN
+    if (!out) throw Error(GOCP_EINVAL, "null output handle");
+    *out = reinterpret_cast<gocp_pool *>(build_pool(n_qubits, n_electrons, mapping, true));
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
 int gocp_pool_info(const gocp_pool *pp, int32_t *n_qubits, int32_t *n_ops, int32_t *n_strings) {
     GOCP_GUARD_BEGIN
     if (!pp) throw Error(GOCP_EINVAL, "null pool");

@@ -213,7 +213,7 @@ uint64_t hf_index(int nq, int ne, int mapping) {
     return bk.apply(bk.beta_rows, occ);
 }
 
-Pool *build_pool(int nq, int ne, int mapping) {
+Pool *build_pool(int nq, int ne, int mapping, bool pauli) {
     check_qubits(nq);
     if (ne <= 0 || ne >= nq || (ne & 1)) throw Error(GOCP_EINVAL, "electron count must be even and in (0, n_qubits)");
     if (mapping != GOCP_JW && mapping != GOCP_BK) throw Error(GOCP_EINVAL, "unknown mapping");
@@ -240,9 +240,25 @@ Pool *build_pool(int nq, int ne, int mapping) {
         std::sort(ts.begin(), ts.end(), [](const Term &u, const Term &v) { return u.z < v.z; });
         const size_t want = kind == 1 ? 2 : 8;
         if (ts.size() != want) throw Error(GOCP_EINVAL, "internal: unexpected generator string count");
+        for (const Term &t : ts)
+            if (t.x != ts[0].x) throw Error(GOCP_EINVAL, "internal: generator with several X masks");
+        if (pauli) {
+            // one operator per string, its coefficient scaled to unit
+            // magnitude: each string of an anti-Hermitian generator is
+            // anti-Hermitian by itself and squares to -1
+            for (const Term &t : ts) {
+                p->str_z.push_back(t.z);
+                p->str_c.push_back(t.c > 0.0 ? 1.0 : -1.0);
+                p->op_x.push_back(t.x);
+                p->op_off.push_back((int32_t)p->str_z.size());
+                p->op_norm1.push_back(1.0);
+                p->kind.push_back(kind + 2);
+                p->idx.insert(p->idx.end(), {i, j, a, b});
+            }
+            return;
+        }
         double n1 = 0.0;
         for (const Term &t : ts) {
-            if (t.x != ts[0].x) throw Error(GOCP_EINVAL, "internal: generator with several X masks");
             p->str_z.push_back(t.z);
             p->str_c.push_back(t.c);
             n1 += std::fabs(t.c);

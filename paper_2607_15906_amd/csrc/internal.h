@@ -48,7 +48,7 @@ struct Ham {
 
 struct Pool {
     int n_qubits = 0, n_electrons = 0, mapping = 0;
-    std::vector<int32_t> kind;            // 1 single, 2 double
+    std::vector<int32_t> kind;            // 1 single, 2 double; 3, 4 one string of either
     std::vector<int32_t> idx;             // 4 per op (-1 padded)
     std::vector<uint32_t> op_x;           // X mask per op
     std::vector<int32_t> op_off;          // CSR into str_z / str_c
@@ -71,7 +71,8 @@ struct Pool {
 Ham *build_hamiltonian(int n_spatial, const double *h1, const double *eri, double e_core,
                        int mapping);
 Ham *hamiltonian_from_terms(int n_qubits, const std::vector<Term> &terms);
-Pool *build_pool(int n_qubits, int n_electrons, int mapping);
+// pauli: one operator per string of the generators (unit coefficients)
+Pool *build_pool(int n_qubits, int n_electrons, int mapping, bool pauli = false);
 uint64_t hf_index(int n_qubits, int n_electrons, int mapping);
 void partition_pool(Pool &p);   // fills family_of, order, fam_off, fam_members, degree
 

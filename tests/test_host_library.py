@@ -15,7 +15,7 @@ import paper_2607_15906_amd as g
 from paper_2607_15906_amd._lib import load, GocpError, LIB_PATH
 from oracle.mapping import hamiltonian, hf_index
 from oracle.pauli import to_folded
-from oracle.pool import pool_operators, pool_excitations
+from oracle.pool import pool_operators, pool_excitations, pauli_pool_operators
 from oracle.gocp import gocp_partition
 from workloads import molecular_integrals, electron_count
 
@@ -95,6 +95,32 @@ def test_partition_bit_exact_with_oracle(nq, ne, mapping):
     ne_, deg = P.degrees()
     assert ne_ == int(oadj.sum()) // 2
     assert deg.tolist() == oadj.sum(axis=1).tolist()
+
+
+@pytest.mark.parametrize("nq,ne", [(4, 2), (8, 4), (12, 6), (14, 6)])
+@pytest.mark.parametrize("mapping", ["jw", "bk"])
+def test_pauli_pool_tables_match_oracle(nq, ne, mapping):
+    P = g.pool_build_pauli(nq, ne, mapping)
+    ops = pauli_pool_operators(nq, ne, mapping)
+    assert P.n_ops == P.n_strings == len(ops)
+    off, xm, z, c = P.strings()
+    assert np.array_equal(off, np.arange(len(ops) + 1))
+    for k, (kind, idx, B) in enumerate(ops):
+        pk, pidx, px = P.op(k)
+        assert pk == kind and pidx == tuple(idx)
+        ox, oz, oc = to_folded(B)
+        assert px == ox[0] and z[k] == oz[0] and c[k] == oc[0].real     # unit, exact
+
+
+@pytest.mark.parametrize("nq,ne", [(4, 2), (8, 4), (10, 4), (12, 6)])
+@pytest.mark.parametrize("mapping", ["jw", "bk"])
+def test_pauli_pool_partition_bit_exact_with_oracle(nq, ne, mapping):
+    P = g.pool_build_pauli(nq, ne, mapping)
+    fam, K, order = g.gocp_partition(P)
+    ofam, ofams, oorder, oadj = gocp_partition([B for _, _, B in pauli_pool_operators(nq, ne, mapping)], nq)
+    assert fam.tolist() == ofam
+    assert order.tolist() == oorder
+    assert K == len(ofams)
 
 
 @pytest.mark.parametrize("nq,ne", [(4, 2), (12, 6), (14, 6), (16, 8)])
