@@ -322,6 +322,17 @@ def main():
                                    "final_state_fidelity_c64": fid,
                                    "max_abs_dg_final_c64": float(np.abs(g64 - g128).max())}
 
+        _say("[bench] Pauli pool: 14q c64")
+        PP = g.pool_build_pauli(nq, ne, mapping)
+        offp = PP.strings()[0]
+        b3, r3, dt3, _ = run_adapt_timed(g, ctx, H, PP, nq, ne, mapping, torch.complex64, args.steps,
+                                         args.warmup, schedule=0)
+        out["pauli_pool"] = {"pool_ops": PP.n_ops, "pool_strings": PP.n_strings, "state": "complex64",
+                             "amps_per_lane": b3.schedule, "iters_per_s": round(args.steps / dt3, 3),
+                             "amp_updates_per_s": float(f"{_amp_updates(nq, T, PP.n_strings, offp, r3['ops'][w0:w1], r3['substeps'][w0:w1]) / dt3:.6g}"),
+                             "final_energy": float(r3["energies"][-1])}
+        b3.close()
+
         _say("[bench] batched form: 64 instances x 30 iterations")
         insts = batched_instances()
         hams, pools, psis, meta = [], [], [], []

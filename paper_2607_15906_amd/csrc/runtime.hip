@@ -193,11 +193,11 @@ bool factor_class(const std::vector<double> &c, const std::vector<uint32_t> &z, 
 // Operator j as f(d) = (-1)^popcount(d & zb) F(d & bm): its strings' Z masks
 // agree outside bm (at most kFactBits bits), F(u) = sum_s c_s
 // (-1)^popcount(u & z_s) over the submasks u of bm, and F is nonzero at one
-// or two patterns.  Fills the parameter group {v1, v2, 0, 0 | zb, bm, t1, t2}
+// or two patterns (a single string: bm = 0, one pattern).  Fills the parameter group {v1, v2, 0, 0 | zb, bm, t1, t2}
 // (t2 = all ones, never matched, when there is one pattern).
 bool factor_op(const Pool &p, int j, double (&co)[kStrGroup], uint32_t (&zs)[kStrGroup]) {
     const int a = p.op_off[j], b = p.op_off[j + 1];
-    if (b - a < 2) return false;
+    if (b <= a) return false;
     const uint32_t z0 = p.str_z[a];
     uint32_t bm = 0;
     double scale = 0.0;
