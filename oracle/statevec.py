@@ -39,7 +39,7 @@ from .pauli import apply_psum
 
 __all__ = ["apply_h", "energy", "gradients", "gradients_commutator", "select",
            "substeps", "taylor5", "line_coefficients", "landscape",
-           "landscape_derivative", "line_search", "hf_state", "TIE_RTOL"]
+           "landscape_derivative", "line_search", "hf_state", "TIE_RTOL", "taylor5_family"]
 
 TIE_RTOL = 1e-12
 
@@ -111,6 +111,17 @@ def taylor5(A: dict, theta: float, psi: np.ndarray, renormalize: bool = True):
     if renormalize:
         psi = psi / math.sqrt(np.vdot(psi, psi).real)
     return psi, s
+
+
+def taylor5_family(As, thetas, psi: np.ndarray):
+    """GOCP multi-operator step: members of one commuting family (Sec. III.A)
+    each advanced by its own substepped chain (Eq. 5-6) in the given order,
+    then one renormalisation.  Returns (new psi, substeps per operator)."""
+    subs = []
+    for A, th in zip(As, thetas):
+        psi, s = taylor5(A, th, psi, renormalize=False)
+        subs.append(s)
+    return psi / math.sqrt(np.vdot(psi, psi).real), subs
 
 
 def line_coefficients(H: dict, A: dict, psi: np.ndarray, sigma: np.ndarray):
