@@ -216,6 +216,24 @@ int pool_gradients(gocp_ctx *ctx, const gocp_ham *h, const gocp_pool *p, const v
 int taylor5_apply(gocp_ctx *ctx, const gocp_pool *p, int32_t k, double theta, void *psi_dev,
                   int dtype, int32_t *n_substeps_out);
 
+/*
+ * taylor5_apply_family -- GOCP multi-operator step: psi <- prod_i T5(theta_i
+ * A_{ops[i]}) psi, then psi <- psi / ||psi|| once (FP64).  The operators are
+ * members of one GOCP family (Sec. III.A, Algorithm 1: they commute, so the
+ * product is order-free), each with its own substepped O(5) chain (Eq. 5-6,
+ * s_i = max(1, ceil(|theta_i| ||A||_1 / 0.5)); theta_i = 0 skips it), all
+ * applied in one pass over the state.
+ *   n           : 1..4 operators; ops[n] pool indices, distinct, one family,
+ *                 X masks linearly independent over GF(2); thetas[n] finite.
+ *   psi_dev     : device state of the pool's qubit count, dtype GOCP_C128 or
+ *                 GOCP_C64 (FP64 arithmetic either way), updated in place.
+ *   n_substeps_out: optional n outputs (s_i, 0 for a zero angle).
+ * Asynchronous on the context stream.  Errors: EINVAL (counts, indices,
+ * repeats, families, angles, null pointers), ENOTSUP (dependent X masks).
+ */
+int taylor5_apply_family(gocp_ctx *ctx, const gocp_pool *p, int32_t n, const int32_t *ops,
+                         const double *thetas, void *psi_dev, int dtype, int32_t *n_substeps_out);
+
 /* ---------------------------------------------------------------------
  * ADAPT loop (Sec. II.B with the Sec. III.B update), device-resident.
  * One iteration: gradient screen, selection (largest |g_j|; gradients within

@@ -15,7 +15,7 @@ import numpy as np
 from ._lib import load, check, AdaptParams, AdaptResult, RequestInfo, GOCP_EBUSY
 
 __all__ = ["MAPPINGS", "Hamiltonian", "Pool", "Context", "pauli_hamiltonian_load",
-           "pauli_hamiltonian_load_terms", "pool_build", "pool_build_pauli", "gocp_partition", "hf_index",
+           "pauli_hamiltonian_load_terms", "pool_build", "pool_build_pauli", "taylor5_apply_family", "gocp_partition", "hf_index",
            "state_basis", "energy", "apply_hamiltonian", "pool_gradients", "taylor5_apply",
            "adapt_solve", "Batch", "Server", "request_footprint", "version"]
 
@@ -258,6 +258,19 @@ def taylor5_apply(ctx: Context, pool: Pool, k: int, theta: float, psi) -> int:
     s = C.c_int32()
     check(load().taylor5_apply(ctx.handle, pool.handle, k, float(theta), p, dt, C.byref(s)))
     return s.value
+
+
+def taylor5_apply_family(ctx: Context, pool: Pool, ops, thetas, psi):
+    """GOCP multi-operator step over 1-4 operators of one family; substeps per operator."""
+    o = np.ascontiguousarray(ops, dtype=np.int32)
+    th = _f64(thetas)
+    if len(o) != len(th):
+        raise ValueError("one angle per operator")
+    p, dt = _state(psi)
+    ns = np.zeros(len(o), dtype=np.int32)
+    check(load().taylor5_apply_family(ctx.handle, pool.handle, len(o), _ptr(o, C.c_int32),
+                                      _ptr(th, C.c_double), p, dt, _ptr(ns, C.c_int32)))
+    return ns
 
 
 class _Record:

@@ -51,6 +51,15 @@ constexpr int kGroup = 16;
 // more than kActMaxBlocks use the whole-state launch.
 constexpr int kHvwParts = 8;
 constexpr int kHvwSlots = 32;
+
+// GOCP multi-operator step: at most kFuseMax operators of one family per pass.
+constexpr int kFuseMax = 4;
+struct FuseArgs {
+    int32_t op[kFuseMax];     // pool indices
+    int32_t ns[kFuseMax];     // substeps (0: the operator is skipped)
+    int32_t piv[kFuseMax];    // echelon pivot bits of the X masks' span, ascending
+    double x[kFuseMax];       // substep angle theta / ns
+};
 constexpr int kActMaxBlocks = 1024;
 // Launch mode of k_screen_reduce that selects the pending partials of an
 // ADAPT run (the iteration and mode k_energy_screen recorded with them).

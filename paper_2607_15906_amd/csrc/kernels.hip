@@ -1858,6 +1858,98 @@ __global__ __launch_bounds__(kPairBlock) void k_taylor5(const InstDev *__restric
     }
 }
 
+// GOCP multi-operator step (Sec. III.A families, Eq. 5-6 chains): N pool
+// operators of one commuting family, X masks independent over GF(2), applied
+// in one pass.  The masks span a group of 2^N bit flips; each operator maps
+// every coset (orbit) of it into itself, so a lane loads its orbit's 2^N
+// amplitudes once, runs every operator's substepped O(5) chain on them in
+// registers, and stores them once.  Orbit o's representative has zero bits at
+// the span's echelon pivots; local index m (bit j for operator j) is that
+// representative XOR the masks of m's bits, so operator j pairs m with
+// m ^ 2^j.  The operators' polynomials commute, so their order is free.  The
+// workgroup's norm partial of the new state goes to part_t (workgroups past
+// the last orbit write zero).
+template <typename T, int N>
+__global__ __launch_bounds__(kPairBlock) void k_taylor5_fused(const InstDev *__restrict__ insts,
+                                                             const int2 *__restrict__ blk, FuseArgs fa) {
+    constexpr int NR = 1 << N;
+    const int2 b = work_row(blk);
+    const InstDev &I = insts[b.x];
+    const int nq = I.n_qubits;
+    const uint32_t o = (uint32_t)b.y * kPairBlock + threadIdx.x;
+    double nn = 0.0;
+    if (o < (1u << (nq - N))) {
+        HClass C[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) C[j] = load_rec(cptr(I.pop), fa.op[j]);
+        uint32_t rep = o;
+#pragma unroll
+        for (int j = 0; j < N; ++j) rep = insert_zero_bit(rep, fa.piv[j]);
+        uint32_t d[NR];
+        double2 a[NR];
+#pragma unroll
+        for (int m = 0; m < NR; ++m) {
+            uint32_t v = rep;
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                if ((m >> j) & 1) v ^= C[j].x;
+            d[m] = v;
+            a[m] = Amp<T>::load(I.psi, v);
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            // (A_j v)[d_m] = f(d_m) v[d_m ^ x_j] = f(d_m) v[m ^ 2^j]
+            double f[NR];
+#pragma unroll
+            for (int m = 0; m < NR; ++m) {
+                double h = 0.0;
+                for (int t = C[j].s0; t < C[j].s1; ++t) h += signed_coef(load_rec(cptr(I.pterm), t), d[m]);
+                f[m] = h;
+            }
+            const double x = fa.x[j];
+            for (int sub = 0; sub < fa.ns[j]; ++sub) {
+                double2 v[NR];
+#pragma unroll
+                for (int m = 0; m < NR; ++m) v[m] = a[m];
+                double coef = 1.0;
+#pragma unroll
+                for (int n = 1; n <= 5; ++n) {
+#pragma unroll
+                    for (int m = 0; m < NR; ++m) {
+                        if ((m >> j) & 1) continue;
+                        const int e = m | (1 << j);
+                        const double2 vm = v[m], ve = v[e];
+                        v[m] = make_double2(f[m] * ve.x, f[m] * ve.y);
+                        v[e] = make_double2(f[e] * vm.x, f[e] * vm.y);
+                    }
+                    coef = coef * x / n;
+#pragma unroll
+                    for (int m = 0; m < NR; ++m) {
+                        a[m].x = fma(coef, v[m].x, a[m].x);
+                        a[m].y = fma(coef, v[m].y, a[m].y);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NR; ++m) {
+            Amp<T>::store(I.psi, d[m], a[m]);
+            const double2 r = Amp<T>::rounded(a[m]);
+            nn += r.x * r.x + r.y * r.y;
+        }
+    }
+    __shared__ double rn[kPairBlock / kWave];
+    nn = wave_sum(nn);
+    const int wv = wave_id(), lane = threadIdx.x & (kWave - 1);
+    if (lane == 0) rn[wv] = nn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kPairBlock / kWave; ++k) t += rn[k];
+        I.part_t[b.y] = t;
+    }
+}
+
 // psi *= 1 / sqrt(sum of part_t)   (from_state: 1 / sqrt(st->nrm) instead)
 template <typename T>
 __global__ __launch_bounds__(kPairBlock) void k_normalize(const InstDev *__restrict__ insts,
@@ -1977,6 +2069,26 @@ void launch_hvw_act(const InstDev *insts, const int2 *blk, int nblk, int mode, h
 }
 
 #undef GOCP_LAUNCH
+
+template <typename T>
+static void launch_fused_t(int n, const InstDev *insts, const int2 *blk, int nblk, const FuseArgs &fa,
+                           hipStream_t s) {
+    switch (n) {
+    case 1: hipLaunchKernelGGL((k_taylor5_fused<T, 1>), dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, fa); break;
+    case 2: hipLaunchKernelGGL((k_taylor5_fused<T, 2>), dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, fa); break;
+    case 3: hipLaunchKernelGGL((k_taylor5_fused<T, 3>), dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, fa); break;
+    case 4: hipLaunchKernelGGL((k_taylor5_fused<T, 4>), dim3(nblk), dim3(kPairBlock), 0, s, insts, blk, fa); break;
+    default: break;       // the host entry accepts 1 to kFuseMax operators only
+    }
+}
+
+void launch_fused(int dtype, int n, const InstDev *insts, const int2 *blk, int nblk, const FuseArgs &fa,
+                  hipStream_t s) {
+    if (nblk <= 0) return;
+    if (dtype == GOCP_C64) launch_fused_t<float2>(n, insts, blk, nblk, fa, s);
+    else launch_fused_t<double2>(n, insts, blk, nblk, fa, s);
+    hip_check(hipGetLastError(), "kernel launch");
+}
 
 void launch_gather_done(const InstDev *insts, int n, int32_t *out, hipStream_t s) {
     if (n <= 0) return;

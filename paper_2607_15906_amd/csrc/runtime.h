@@ -37,6 +37,9 @@ void launch_kernel(int which, int dtype, int R, const InstDev *insts, const int2
 void launch_hvw_act(const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s,
                     hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_basis(int dtype, void *psi, uint32_t dim, uint32_t index, hipStream_t s);
+// GOCP multi-operator step over the pair-block rows (norm partials in part_t).
+void launch_fused(int dtype, int n, const InstDev *insts, const int2 *blk, int nblk, const FuseArgs &fa,
+                  hipStream_t s);
 void launch_gather_done(const InstDev *insts, int n, int32_t *out, hipStream_t s);
 
 // Byte offsets of one instance's buffers inside its workspace.

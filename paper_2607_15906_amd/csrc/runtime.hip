@@ -824,4 +824,46 @@ int taylor5_apply(gocp_ctx *ctx, const gocp_pool *pp, int32_t k, double theta, v
     GOCP_GUARD_END
 }
 
+int taylor5_apply_family(gocp_ctx *ctx, const gocp_pool *pp, int32_t n, const int32_t *ops,
+                         const double *thetas, void *psi_dev, int dtype, int32_t *n_substeps_out) {
+    GOCP_GUARD_BEGIN
+    check_ctx(ctx);
+    const Pool *p = as_pool(pp);
+    if (!ops || !thetas) throw Error(GOCP_EINVAL, "null operator or angle array");
+    if (n < 1 || n > kFuseMax) throw Error(GOCP_EINVAL, "a fused step takes 1 to 4 operators");
+    if (!psi_dev) throw Error(GOCP_EINVAL, "null state pointer");
+    FuseArgs fa{};
+    uint32_t basis[32] = {};          // echelon basis of the X masks, by leading bit
+    bool any = false;
+    for (int i = 0; i < n; ++i) {
+        const int k = ops[i];
+        if (k < 0 || k >= p->n_ops()) throw Error(GOCP_EINVAL, "operator index out of range");
+        if (!std::isfinite(thetas[i])) throw Error(GOCP_EINVAL, "non-finite angle");
+        for (int i2 = 0; i2 < i; ++i2)
+            if (ops[i2] == k) throw Error(GOCP_EINVAL, "an operator appears twice");
+        if (p->family_of[k] != p->family_of[ops[0]]) throw Error(GOCP_EINVAL, "operators of different GOCP families");
+        uint32_t v = p->op_x[k];
+        for (int bit = 31; bit >= 0; --bit)
+            if (((v >> bit) & 1u) && basis[bit]) v ^= basis[bit];
+        if (!v) throw Error(GOCP_ENOTSUP, "X masks linearly dependent over GF(2)");
+        basis[31 - __builtin_clz(v)] = v;
+        const double th = thetas[i];
+        const int ns = th == 0.0 ? 0 : std::max(1, (int)std::ceil(std::fabs(th) * p->op_norm1[k] / 0.5));
+        fa.op[i] = k;
+        fa.ns[i] = ns;
+        fa.x[i] = ns ? th / ns : 0.0;
+        any = any || ns > 0;
+    }
+    for (int bit = 0, q = 0; bit < 32; ++bit)
+        if (basis[bit]) fa.piv[q++] = bit;
+    if (n_substeps_out)
+        for (int i = 0; i < n; ++i) n_substeps_out[i] = fa.ns[i];
+    if (!any) return GOCP_OK;
+    OneShot o = one_shot(ctx, nullptr, p, psi_dev, dtype);
+    launch_fused(dtype, n, o.desc, o.bpair, o.np, fa, ctx->user_stream);
+    launch_kernel(K_NORMALIZE, dtype, 1, o.desc, o.bpair, o.np, 0, ctx->user_stream);
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
 }  // extern "C"
