@@ -74,6 +74,59 @@ def _amp_updates(nq, T, S, off, ops, subs):
     return tot * (1 << nq)
 
 
+def _fused_step_timing(g, ctx, P, nq, reps=200):
+    """One GOCP multi-operator step (four members of one family, X masks
+    independent) against the same four operators applied one call each,
+    on complex64 and complex128 states; mean microseconds per step over
+    `reps` back-to-back steps on the context's stream (torch's current one)."""
+    import numpy as np
+    import torch
+    fam, _, _ = g.gocp_partition(P)
+    mem = None
+    for f in range(int(fam.max()) + 1):
+        basis, pick = {}, []
+        for k in np.flatnonzero(fam == f):
+            v = P.op(int(k))[2]
+            for bit in sorted(basis, reverse=True):
+                if (v >> bit) & 1:
+                    v ^= basis[bit]
+            if v:
+                basis[v.bit_length() - 1] = v
+                pick.append(int(k))
+            if len(pick) == 4:
+                mem = pick
+                break
+        if mem:
+            break
+    thetas = [0.3, -0.2, 0.45, -0.1]
+    res = {"ops": mem, "thetas": thetas, "reps": reps}
+    for name, dt in (("c64", torch.complex64), ("c128", torch.complex128)):
+        psi = torch.zeros(1 << nq, dtype=dt, device="cuda")
+        psi[0] = 1.0
+        psi += 1e-3
+        times = {}
+        for mode in ("fused", "sequential"):
+            def step():
+                if mode == "fused":
+                    g.taylor5_apply_family(ctx, P, mem, thetas, psi)
+                else:
+                    for j, t in zip(mem, thetas):
+                        g.taylor5_apply(ctx, P, j, t, psi)
+            for _ in range(10):
+                step()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            times[mode] = e0.elapsed_time(e1) * 1e3 / reps
+        res[name] = {"fused_us": round(times["fused"], 3), "sequential_us": round(times["sequential"], 3),
+                     "speedup": round(times["sequential"] / times["fused"], 3)}
+    return res
+
+
 def run_adapt_timed(g, ctx, H, P, nq, ne, mapping, dtype, steps, warmup, schedule=0, timed_kernel=None,
                     sample_every=LIVE_SAMPLE_EVERY):
     """Warm-up iterations (graph replays), then the timed iterations.  With
@@ -204,6 +257,8 @@ def main():
     ap.add_argument("--serve-amps-per-lane", type=int, default=0, choices=(0, 1, 2, 4),
                     help="server schedule (0: chosen from the active set)")
     ap.add_argument("--serve-state", default="complex128", choices=("complex64", "complex128"))
+    ap.add_argument("--fused-step-only", action="store_true",
+                    help="time only the GOCP multi-operator step against single chains (kernel profiling)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (a known-size "
                          "kernel that calibrates memory-traffic counters)")
@@ -235,6 +290,9 @@ def main():
     mapping = "jw"
     ctx = g.Context(0)
     H, P = _system(g, nq, ne, mapping, seed)
+    if args.fused_step_only:
+        print(json.dumps({"gocp_fused_step": _fused_step_timing(g, ctx, P, nq, reps=50)}))
+        return
     off = P.strings()[0]
     T, C, S, M = H.n_terms, H.n_classes, P.n_strings, P.n_ops
 
@@ -332,6 +390,9 @@ def main():
                              "amp_updates_per_s": float(f"{_amp_updates(nq, T, PP.n_strings, offp, r3['ops'][w0:w1], r3['substeps'][w0:w1]) / dt3:.6g}"),
                              "final_energy": float(r3["energies"][-1])}
         b3.close()
+
+        _say("[bench] GOCP multi-operator step: 14q, 4 members of one family")
+        out["gocp_fused_step"] = _fused_step_timing(g, ctx, P, nq)
 
         _say("[bench] batched form: 64 instances x 30 iterations")
         insts = batched_instances()

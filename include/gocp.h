@@ -229,7 +229,8 @@ int taylor5_apply(gocp_ctx *ctx, const gocp_pool *p, int32_t k, double theta, vo
  *                 GOCP_C64 (FP64 arithmetic either way), updated in place.
  *   n_substeps_out: optional n outputs (s_i, 0 for a zero angle).
  * Asynchronous on the context stream.  Errors: EINVAL (counts, indices,
- * repeats, families, angles, null pointers), ENOTSUP (dependent X masks).
+ * repeats, families, angles, null pointers), ENOTSUP (dependent X masks, or
+ * n equal to the qubit count).
  */
 int taylor5_apply_family(gocp_ctx *ctx, const gocp_pool *p, int32_t n, const int32_t *ops,
                          const double *thetas, void *psi_dev, int dtype, int32_t *n_substeps_out);

@@ -1861,81 +1861,71 @@ __global__ __launch_bounds__(kPairBlock) void k_taylor5(const InstDev *__restric
 // GOCP multi-operator step (Sec. III.A families, Eq. 5-6 chains): N pool
 // operators of one commuting family, X masks independent over GF(2), applied
 // in one pass.  The masks span a group of 2^N bit flips; each operator maps
-// every coset (orbit) of it into itself, so a lane loads its orbit's 2^N
-// amplitudes once, runs every operator's substepped O(5) chain on them in
-// registers, and stores them once.  Orbit o's representative has zero bits at
-// the span's echelon pivots; local index m (bit j for operator j) is that
-// representative XOR the masks of m's bits, so operator j pairs m with
-// m ^ 2^j.  The operators' polynomials commute, so their order is free.  The
-// workgroup's norm partial of the new state goes to part_t (workgroups past
-// the last orbit write zero).
+// every coset (orbit) of it into itself.  An orbit's 2^N amplitudes sit in
+// 2^N adjacent lanes: local index m (the lane's low N bits; bit j for
+// operator j) holds the representative XOR the masks of m's bits, the
+// representative having zero bits at the span's echelon pivots.  Operator j
+// pairs m with m ^ 2^j, a lane shuffle, so every operator's substepped O(5)
+// chain runs in registers and the state is read and written once.  Each lane
+// takes its local index in two orbits (the first and the second half of the
+// orbit numbers), so the launch has the pair kernels' workgroups and norm
+// partials (part_t).  The operators' polynomials commute: their order is free.
 template <typename T, int N>
 __global__ __launch_bounds__(kPairBlock) void k_taylor5_fused(const InstDev *__restrict__ insts,
                                                              const int2 *__restrict__ blk, FuseArgs fa) {
-    constexpr int NR = 1 << N;
     const int2 b = work_row(blk);
     const InstDev &I = insts[b.x];
     const int nq = I.n_qubits;
-    const uint32_t o = (uint32_t)b.y * kPairBlock + threadIdx.x;
+    const uint32_t gid = (uint32_t)b.y * kPairBlock + threadIdx.x;
+    const bool own = gid < (1u << (nq - 1));
+    const uint32_t m = gid & ((1u << N) - 1u), o = own ? gid >> N : 0u;
+    const uint32_t half_orbits = 1u << (nq - N - 1);      // N < n_qubits
+    HClass C[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) C[j] = load_rec(cptr(I.pop), fa.op[j]);
+    uint32_t d[2];
+    double2 a[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        uint32_t v = o + (uint32_t)r * half_orbits;
+#pragma unroll
+        for (int j = 0; j < N; ++j) v = insert_zero_bit(v, fa.piv[j]);
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            if ((m >> j) & 1u) v ^= C[j].x;
+        d[r] = v;
+        a[r] = Amp<T>::load(I.psi, v);
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        // (A_j v)[d] = f(d) v[d ^ x_j], and d ^ x_j sits in lane ^ 2^j
+        double f0, f1;
+        string_sum2(cptr(I.pterm), C[j].s0, C[j].s1, d[0], d[1], f0, f1);
+        const double x = fa.x[j];
+        for (int sub = 0; sub < fa.ns[j]; ++sub) {
+            double2 v0 = a[0], v1 = a[1];
+            double coef = 1.0;
+#pragma unroll
+            for (int n = 1; n <= 5; ++n) {
+                const double p0x = __shfl_xor(v0.x, 1 << j), p0y = __shfl_xor(v0.y, 1 << j);
+                const double p1x = __shfl_xor(v1.x, 1 << j), p1y = __shfl_xor(v1.y, 1 << j);
+                v0 = make_double2(f0 * p0x, f0 * p0y);
+                v1 = make_double2(f1 * p1x, f1 * p1y);
+                coef = coef * x / n;
+                a[0].x = fma(coef, v0.x, a[0].x);
+                a[0].y = fma(coef, v0.y, a[0].y);
+                a[1].x = fma(coef, v1.x, a[1].x);
+                a[1].y = fma(coef, v1.y, a[1].y);
+            }
+        }
+    }
     double nn = 0.0;
-    if (o < (1u << (nq - N))) {
-        HClass C[N];
+    if (own) {
 #pragma unroll
-        for (int j = 0; j < N; ++j) C[j] = load_rec(cptr(I.pop), fa.op[j]);
-        uint32_t rep = o;
-#pragma unroll
-        for (int j = 0; j < N; ++j) rep = insert_zero_bit(rep, fa.piv[j]);
-        uint32_t d[NR];
-        double2 a[NR];
-#pragma unroll
-        for (int m = 0; m < NR; ++m) {
-            uint32_t v = rep;
-#pragma unroll
-            for (int j = 0; j < N; ++j)
-                if ((m >> j) & 1) v ^= C[j].x;
-            d[m] = v;
-            a[m] = Amp<T>::load(I.psi, v);
-        }
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            // (A_j v)[d_m] = f(d_m) v[d_m ^ x_j] = f(d_m) v[m ^ 2^j]
-            double f[NR];
-#pragma unroll
-            for (int m = 0; m < NR; ++m) {
-                double h = 0.0;
-                for (int t = C[j].s0; t < C[j].s1; ++t) h += signed_coef(load_rec(cptr(I.pterm), t), d[m]);
-                f[m] = h;
-            }
-            const double x = fa.x[j];
-            for (int sub = 0; sub < fa.ns[j]; ++sub) {
-                double2 v[NR];
-#pragma unroll
-                for (int m = 0; m < NR; ++m) v[m] = a[m];
-                double coef = 1.0;
-#pragma unroll
-                for (int n = 1; n <= 5; ++n) {
-#pragma unroll
-                    for (int m = 0; m < NR; ++m) {
-                        if ((m >> j) & 1) continue;
-                        const int e = m | (1 << j);
-                        const double2 vm = v[m], ve = v[e];
-                        v[m] = make_double2(f[m] * ve.x, f[m] * ve.y);
-                        v[e] = make_double2(f[e] * vm.x, f[e] * vm.y);
-                    }
-                    coef = coef * x / n;
-#pragma unroll
-                    for (int m = 0; m < NR; ++m) {
-                        a[m].x = fma(coef, v[m].x, a[m].x);
-                        a[m].y = fma(coef, v[m].y, a[m].y);
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < NR; ++m) {
-            Amp<T>::store(I.psi, d[m], a[m]);
-            const double2 r = Amp<T>::rounded(a[m]);
-            nn += r.x * r.x + r.y * r.y;
+        for (int r = 0; r < 2; ++r) {
+            Amp<T>::store(I.psi, d[r], a[r]);
+            const double2 q = Amp<T>::rounded(a[r]);
+            nn += q.x * q.x + q.y * q.y;
         }
     }
     __shared__ double rn[kPairBlock / kWave];

@@ -854,6 +854,7 @@ int taylor5_apply_family(gocp_ctx *ctx, const gocp_pool *pp, int32_t n, const in
         fa.x[i] = ns ? th / ns : 0.0;
         any = any || ns > 0;
     }
+    if (n >= p->n_qubits) throw Error(GOCP_ENOTSUP, "the operators' X masks span every qubit");
     for (int bit = 0, q = 0; bit < 32; ++bit)
         if (basis[bit]) fa.piv[q++] = bit;
     if (n_substeps_out)
