@@ -78,7 +78,8 @@ def _fused_step_timing(g, ctx, P, nq, reps=200):
     """One GOCP multi-operator step (four members of one family, X masks
     independent) against the same four operators applied one call each,
     on complex64 and complex128 states; mean microseconds per step over
-    `reps` back-to-back steps on the context's stream (torch's current one)."""
+    back-to-back steps on the context's stream (torch's current one): the
+    median over five batches of reps / 5 steps, after 20 untimed steps."""
     import numpy as np
     import torch
     fam, _, _ = g.gocp_partition(P)
@@ -112,16 +113,20 @@ def _fused_step_timing(g, ctx, P, nq, reps=200):
                 else:
                     for j, t in zip(mem, thetas):
                         g.taylor5_apply(ctx, P, j, t, psi)
-            for _ in range(10):
+            for _ in range(20):
                 step()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            e0.record()
-            for _ in range(reps):
-                step()
-            e1.record()
-            torch.cuda.synchronize()
-            times[mode] = e0.elapsed_time(e1) * 1e3 / reps
+            # median of five batches of reps / 5 steps
+            per = []
+            for _ in range(5):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(max(1, reps // 5)):
+                    step()
+                e1.record()
+                torch.cuda.synchronize()
+                per.append(e0.elapsed_time(e1) * 1e3 / max(1, reps // 5))
+            times[mode] = float(np.median(per))
         res[name] = {"fused_us": round(times["fused"], 3), "sequential_us": round(times["sequential"], 3),
                      "speedup": round(times["sequential"] / times["fused"], 3)}
     return res

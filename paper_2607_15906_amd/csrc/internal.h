@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <atomic>
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -33,7 +34,15 @@ struct DevicePool;   // device copy of a pool
 
 // Hamiltonian grouped by X mask.  Classes are sorted by x; strings within a
 // class by z.  cls_off is CSR into str_z / str_c.
+// Identity of a Hamiltonian or pool for caches keyed across calls (addresses
+// can be reused after a free; these numbers are not).
+inline uint64_t next_uid() {
+    static std::atomic<uint64_t> n{0};
+    return ++n;
+}
+
 struct Ham {
+    uint64_t uid = next_uid();
     int n_qubits = 0;
     std::vector<uint32_t> cls_x;
     std::vector<int32_t> cls_off;
@@ -47,6 +56,7 @@ struct Ham {
 };
 
 struct Pool {
+    uint64_t uid = next_uid();
     int n_qubits = 0, n_electrons = 0, mapping = 0;
     std::vector<int32_t> kind;            // 1 single, 2 double; 3, 4 one string of either
     std::vector<int32_t> idx;             // 4 per op (-1 padded)

@@ -14,6 +14,12 @@ struct gocp_ctx {
     hipStream_t own_stream = nullptr;    // private stream used for graph capture
     char *arena = nullptr;               // workspace of the one-shot calls
     size_t arena_cap = 0;
+    // what the arena's descriptor and row tables were last written for
+    // (Hamiltonian and pool uids, state, sigma, dtype); cleared when the
+    // arena or the stream changes
+    uint64_t shot_h = 0, shot_p = 0;
+    const void *shot_psi = nullptr, *shot_sig = nullptr;
+    int shot_dtype = -1;
     std::string arch;
     int n_cu = 0;
 };

@@ -648,6 +648,7 @@ OneShot one_shot(gocp_ctx *ctx, const Ham *h, const Pool *p, const void *psi, in
         const size_t cap = std::max(a.used, (size_t)1 << 20);
         hip_check(hipMalloc(&ctx->arena, cap), "hipMalloc workspace");
         ctx->arena_cap = cap;
+        ctx->shot_dtype = -1;
     }
     char *b = ctx->arena;
     o.base = b;
@@ -655,9 +656,20 @@ OneShot one_shot(gocp_ctx *ctx, const Ham *h, const Pool *p, const void *psi, in
     InstDev I = make_desc(ctx->device, o.ip, b, h, p, const_cast<void *>(psi), sigma_override);
     AdaptState st = make_state(o.ip, b, 0, 0.0, false);
     hip_check(hipMemcpyAsync(b + o.ip.o_st, &st, sizeof(st), hipMemcpyHostToDevice, s), "H2D");
-    hip_check(hipMemcpyAsync(b + o.o_desc, &I, sizeof(I), hipMemcpyHostToDevice, s), "H2D");
-    hip_check(hipMemcpyAsync(b + o.o_btile, bt.data(), bt.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
-    hip_check(hipMemcpyAsync(b + o.o_bpair, bp.data(), bp.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
+    // the descriptor and row tables are a function of the key alone and no
+    // kernel writes them: a call with the last call's key finds them in place
+    const uint64_t kh = h ? h->uid : 0, kp = p ? p->uid : 0;
+    if (ctx->shot_dtype != dtype || ctx->shot_h != kh || ctx->shot_p != kp || ctx->shot_psi != psi ||
+        ctx->shot_sig != sigma_override) {
+        hip_check(hipMemcpyAsync(b + o.o_desc, &I, sizeof(I), hipMemcpyHostToDevice, s), "H2D");
+        hip_check(hipMemcpyAsync(b + o.o_btile, bt.data(), bt.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
+        hip_check(hipMemcpyAsync(b + o.o_bpair, bp.data(), bp.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
+        ctx->shot_dtype = dtype;
+        ctx->shot_h = kh;
+        ctx->shot_p = kp;
+        ctx->shot_psi = psi;
+        ctx->shot_sig = sigma_override;
+    }
     o.desc = reinterpret_cast<InstDev *>(b + o.o_desc);
     o.btile = reinterpret_cast<int2 *>(b + o.o_btile);
     o.bpair = reinterpret_cast<int2 *>(b + o.o_bpair);
