@@ -217,8 +217,9 @@ int taylor5_apply(gocp_ctx *ctx, const gocp_pool *p, int32_t k, double theta, vo
                   int dtype, int32_t *n_substeps_out);
 
 /*
- * taylor5_apply_family -- GOCP multi-operator step: psi <- prod_i T5(theta_i
- * A_{ops[i]}) psi, then psi <- psi / ||psi|| once (FP64).  The operators are
+ * taylor5_apply_family -- GOCP multi-operator step:
+ *   psi <- prod_i T5(theta_i / s_i A_{ops[i]})^{s_i} psi,  then psi <- psi / ||psi||
+ * once (FP64), with T5 and s_i as in taylor5_apply.  The operators are
  * members of one GOCP family (Sec. III.A, Algorithm 1: they commute, so the
  * product is order-free), each with its own substepped O(5) chain (Eq. 5-6,
  * s_i = max(1, ceil(|theta_i| ||A||_1 / 0.5)); theta_i = 0 skips it), all

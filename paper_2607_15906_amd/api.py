@@ -171,17 +171,34 @@ def hf_index(n_qubits: int, n_electrons: int, mapping) -> int:
 
 # ---------------------------------------------------------------- device side
 
-def _state(psi):
+def _state(psi, n_qubits: int):
+    """Pointer and dtype code of a state tensor of 2^n_qubits amplitudes.
+
+    The C ABI receives a bare device pointer and cannot see the buffer's
+    length, so the length is checked here, before any launch."""
     import torch
-    if not psi.is_cuda:
+    if not isinstance(psi, torch.Tensor) or not psi.is_cuda:
         raise ValueError("state must be a device tensor")
     if not psi.is_contiguous():
         raise ValueError("state must be contiguous")
     if psi.dtype == torch.complex128:
-        return C.c_void_p(psi.data_ptr()), C128
-    if psi.dtype == torch.complex64:
-        return C.c_void_p(psi.data_ptr()), C64
-    raise ValueError("state must be complex128 or complex64")
+        code = C128
+    elif psi.dtype == torch.complex64:
+        code = C64
+    else:
+        raise ValueError("state must be complex128 or complex64")
+    if not 1 <= int(n_qubits) <= 30 or psi.numel() != (1 << int(n_qubits)):
+        raise ValueError(f"state has {psi.numel()} amplitudes, expected 2^{n_qubits}")
+    return C.c_void_p(psi.data_ptr()), code
+
+
+def _device_f64(out, n_min: int, what: str):
+    """Pointer of a contiguous float64 device tensor holding at least n_min values."""
+    import torch
+    if (not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.float64
+            or not out.is_contiguous() or out.numel() < n_min):
+        raise ValueError(f"{what} must be a contiguous float64 device tensor of >= {n_min} values")
+    return C.cast(C.c_void_p(out.data_ptr()), C.POINTER(C.c_double))
 
 
 class Context:
@@ -218,12 +235,12 @@ class Context:
 
 
 def state_basis(ctx: Context, n_qubits: int, index: int, psi):
-    p, dt = _state(psi)
+    p, dt = _state(psi, n_qubits)
     check(load().gocp_state_basis(ctx.handle, n_qubits, index, p, dt))
 
 
 def energy(ctx: Context, ham: Hamiltonian, psi) -> float:
-    p, dt = _state(psi)
+    p, dt = _state(psi, ham.n_qubits)
     e = C.c_double()
     check(load().energy(ctx.handle, ham.handle, p, dt, C.byref(e)))
     return e.value
@@ -231,9 +248,10 @@ def energy(ctx: Context, ham: Hamiltonian, psi) -> float:
 
 def apply_hamiltonian(ctx: Context, ham: Hamiltonian, psi, sigma, want_energy: bool = True):
     import torch
-    if sigma.dtype != torch.complex128 or not sigma.is_cuda or not sigma.is_contiguous():
-        raise ValueError("sigma must be a contiguous complex128 device tensor")
-    p, dt = _state(psi)
+    if (not isinstance(sigma, torch.Tensor) or sigma.dtype != torch.complex128 or not sigma.is_cuda
+            or not sigma.is_contiguous() or sigma.numel() != (1 << ham.n_qubits)):
+        raise ValueError(f"sigma must be a contiguous complex128 device tensor of 2^{ham.n_qubits} values")
+    p, dt = _state(psi, ham.n_qubits)
     e = C.c_double()
     check(load().gocp_apply_hamiltonian(ctx.handle, ham.handle, p, dt, C.c_void_p(sigma.data_ptr()),
                                         C.byref(e) if want_energy else None))
@@ -242,19 +260,21 @@ def apply_hamiltonian(ctx: Context, ham: Hamiltonian, psi, sigma, want_energy: b
 
 def pool_gradients(ctx: Context, ham: Hamiltonian, pool: Pool, psi, out=None):
     """Gradients of every pool operator; host numpy array, or into a device tensor `out`."""
-    p, dt = _state(psi)
+    if ham.n_qubits != pool.n_qubits:
+        raise ValueError(f"Hamiltonian has {ham.n_qubits} qubits, pool {pool.n_qubits}")
+    p, dt = _state(psi, ham.n_qubits)
     if out is None:
         g = np.zeros(pool.n_ops, dtype=np.float64)
         check(load().pool_gradients(ctx.handle, ham.handle, pool.handle, p, dt,
                                     _ptr(g, C.c_double), 0))
         return g
     check(load().pool_gradients(ctx.handle, ham.handle, pool.handle, p, dt,
-                                C.cast(C.c_void_p(out.data_ptr()), C.POINTER(C.c_double)), 1))
+                                _device_f64(out, pool.n_ops, "out"), 1))
     return out
 
 
 def taylor5_apply(ctx: Context, pool: Pool, k: int, theta: float, psi) -> int:
-    p, dt = _state(psi)
+    p, dt = _state(psi, pool.n_qubits)
     s = C.c_int32()
     check(load().taylor5_apply(ctx.handle, pool.handle, k, float(theta), p, dt, C.byref(s)))
     return s.value
@@ -266,7 +286,7 @@ def taylor5_apply_family(ctx: Context, pool: Pool, ops, thetas, psi):
     th = _f64(thetas)
     if len(o) != len(th):
         raise ValueError("one angle per operator")
-    p, dt = _state(psi)
+    p, dt = _state(psi, pool.n_qubits)
     ns = np.zeros(len(o), dtype=np.int32)
     check(load().taylor5_apply_family(ctx.handle, pool.handle, len(o), _ptr(o, C.c_int32),
                                       _ptr(th, C.c_double), p, dt, _ptr(ns, C.c_int32)))
@@ -302,7 +322,9 @@ def adapt_solve(ctx: Context, ham: Hamiltonian, pool: Pool, psi, max_iter: int,
 
     schedule: amplitudes per lane of the tile kernels (1, 2, 4) or 0 to autotune.
     """
-    p, dt = _state(psi)
+    if ham.n_qubits != pool.n_qubits:
+        raise ValueError(f"Hamiltonian has {ham.n_qubits} qubits, pool {pool.n_qubits}")
+    p, dt = _state(psi, ham.n_qubits)
     rec = _Record(max_iter)
     prm = AdaptParams(float(grad_tol), int(max_iter), 1 if use_graph else 0, int(schedule), 0)
     check(load().adapt_solve(ctx.handle, ham.handle, pool.handle, p, dt, C.byref(prm),
@@ -320,8 +342,10 @@ class Batch:
             raise ValueError("hams, pools and psis must have the same non-zero length")
         dts = set()
         ptrs = []
-        for t in psis:
-            p_, dt = _state(t)
+        for t, h, q in zip(psis, hams, pools):
+            if h.n_qubits != q.n_qubits:
+                raise ValueError(f"Hamiltonian has {h.n_qubits} qubits, pool {q.n_qubits}")
+            p_, dt = _state(t, h.n_qubits)
             ptrs.append(p_.value)
             dts.add(dt)
         if len(dts) != 1:

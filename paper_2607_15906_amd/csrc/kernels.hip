@@ -19,10 +19,10 @@
 //   write of the state per update instead of five matrix-vector passes.
 //
 // Reductions are deterministic: wave butterflies, then fixed-order sums over
-// waves and over workgroups.  The cross-workgroup step is done by the last
-// workgroup to arrive (release/acquire fences at device scope around an
-// arrival counter), so a kernel and its reduction are one launch and no
-// floating-point atomics are used.
+// waves inside a workgroup.  Every cross-workgroup sum is formed by a later
+// launch that reads the plain-stored per-workgroup partials in a fixed order
+// (no atomics, no arrival counters, no floating-point atomics), so results are
+// bit-reproducible and do not depend on which instances share a launch.
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>

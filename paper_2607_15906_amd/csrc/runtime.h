@@ -16,7 +16,7 @@ struct gocp_ctx {
     size_t arena_cap = 0;
     // what the arena's descriptor and row tables were last written for
     // (Hamiltonian and pool uids, state, sigma, dtype); cleared when the
-    // arena or the stream changes
+    // arena is reallocated (a stream change keeps them: the tables stay valid)
     uint64_t shot_h = 0, shot_p = 0;
     const void *shot_psi = nullptr, *shot_sig = nullptr;
     int shot_dtype = -1;

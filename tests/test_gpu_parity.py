@@ -2,7 +2,8 @@
 
 Sizes: 4 qubits (one partial tile and a partial pair block: the ragged case),
 8 qubits (several tiles), 12 and 14 qubits (the paper's register sizes,
-hundreds of tiles), 16 qubits for sampled checks.  Tolerances: FP64 path
+hundreds of tiles); 16 qubits and the benchmarked 14-qubit runs are in
+test_gpu_oracle_workloads.py.  Tolerances: FP64 path
 1e-12 relative on energies and gradients (rounding of sums of a few thousand
 terms), 1e-10 Ha on ADAPT energies; complex64 states: 1e-6 Ha and fidelity
 1 - 1e-6.
@@ -153,11 +154,53 @@ def test_shape_errors(g, ctx):
     s12 = system(g, 12, "jw")
     s14 = system(g, 14, "jw")
     d = to_dev(rand_state(12, 1))
-    with pytest.raises(g.GocpError) as e:
+    with pytest.raises(ValueError):
         g.pool_gradients(ctx, s12["gH"], s14["gP"], d)
-    assert e.value.code == -4
+    # the C ABI itself reports ESHAPE for handles of different qubit counts
+    import ctypes as C
+    from paper_2607_15906_amd._lib import load
+    gout = np.zeros(s14["gP"].n_ops)
+    rc = load().pool_gradients(ctx.handle, s12["gH"].handle, s14["gP"].handle, C.c_void_p(d.data_ptr()),
+                               0, gout.ctypes.data_as(C.POINTER(C.c_double)), 0)
+    assert rc == -4
     with pytest.raises(g.GocpError):
         g.taylor5_apply(ctx, s12["gP"], s12["gP"].n_ops, 0.1, d)
+
+
+def test_binding_rejects_buffers_of_the_wrong_size_before_any_launch(g, ctx):
+    """The C ABI takes bare device pointers; the binding checks every buffer's
+    length, dtype and device against the handles, and raises before calling."""
+    s12 = system(g, 12, "jw")
+    s14 = system(g, 14, "jw")
+    d12 = to_dev(rand_state(12, 2))
+    before = d12.clone()
+    n14 = s14["gP"].n_ops
+    bad = [
+        lambda: g.energy(ctx, s14["gH"], d12),
+        lambda: g.apply_hamiltonian(ctx, s14["gH"], d12, torch.zeros(1 << 14, dtype=torch.complex128, device="cuda")),
+        lambda: g.apply_hamiltonian(ctx, s12["gH"], d12, torch.zeros(1 << 11, dtype=torch.complex128, device="cuda")),
+        lambda: g.apply_hamiltonian(ctx, s12["gH"], d12, torch.zeros(1 << 12, dtype=torch.complex64, device="cuda")),
+        lambda: g.pool_gradients(ctx, s14["gH"], s14["gP"], d12),
+        lambda: g.pool_gradients(ctx, s12["gH"], s12["gP"], d12,
+                                 out=torch.zeros(s12["gP"].n_ops - 1, dtype=torch.float64, device="cuda")),
+        lambda: g.pool_gradients(ctx, s12["gH"], s12["gP"], d12,
+                                 out=torch.zeros(s12["gP"].n_ops, dtype=torch.float32, device="cuda")),
+        lambda: g.pool_gradients(ctx, s12["gH"], s12["gP"], d12, out=torch.zeros(s12["gP"].n_ops, dtype=torch.float64)),
+        lambda: g.taylor5_apply(ctx, s14["gP"], 3, 0.2, d12),
+        lambda: g.taylor5_apply_family(ctx, s14["gP"], [0], [0.1], d12),
+        lambda: g.adapt_solve(ctx, s14["gH"], s14["gP"], d12, 2),
+        lambda: g.adapt_solve(ctx, s12["gH"], s14["gP"], d12, 2),
+        lambda: g.state_basis(ctx, 14, 0, d12),
+        lambda: g.Batch(ctx, [s14["gH"]], [s14["gP"]], [d12], max_iter=2),
+        lambda: g.energy(ctx, s12["gH"], d12.cpu()),
+        lambda: g.energy(ctx, s12["gH"], torch.zeros(1 << 12, dtype=torch.float64, device="cuda")),
+    ]
+    for k, f in enumerate(bad):
+        with pytest.raises(ValueError):
+            f()
+    torch.cuda.synchronize()
+    assert torch.equal(d12, before)
+    assert n14 > 0
 
 
 def _adapt_gpu(g, ctx, s, nq, iters, dtype="c128", tol=0.0, use_graph=True, schedule=1):

@@ -255,6 +255,90 @@ def test_landscape_matches_dense_exponential_scan():
         assert abs(landscape_derivative(coef, 0.0) - g) < 1e-12
 
 
+def _dense_line(H, A, psi, nq):
+    """E(theta) = <e^{theta A} psi|H|e^{theta A} psi> from dense matrices (no
+    oracle line-search arithmetic involved)."""
+    Hd = psum_matrix(H, nq)
+    Ad = psum_matrix(A, nq)
+    # A is anti-Hermitian: A = -i K with K Hermitian, so exp(theta A) =
+    # V diag(exp(-i theta lam)) V^+ from the eigenpairs of K (checked against
+    # expm at one angle)
+    lam, V = np.linalg.eigh(1j * Ad)
+    c = V.conj().T @ psi
+    assert np.abs(V @ (np.exp(-0.7j * lam) * c) - expm(0.7 * Ad) @ psi).max() < 1e-12
+    def e(th):
+        p = V @ (np.exp(-1j * th * lam) * c)
+        return float((p.conj() @ Hd @ p).real)
+    return e
+
+
+def _derivative_pin_error(deriv, coef, e_dense, thetas, h=1e-5):
+    """Largest gap between deriv(coef, theta) and the central difference of the
+    dense energy at the given angles."""
+    return max(abs(deriv(coef, th) - (e_dense(th + h) - e_dense(th - h)) / (2 * h)) for th in thetas)
+
+
+def test_landscape_derivative_matches_dense_central_differences_away_from_zero():
+    """E'(theta) at angles away from 0, where every term of the derivative
+    contributes (at theta = 0 the sin-theta terms vanish and the pin against g
+    cannot see them): central differences of the dense exponential's energy.
+    A sign error in any single term of the derivative is caught."""
+    h1, eri, ec, H, ops, hf, ne = _system(8)
+    psi = _sector_state(8, ne, np.random.default_rng(11))
+    sigma = apply_h(H, psi)
+    thetas = [-2.7, -1.3, -0.4, 0.25, 0.9, 1.7, 2.9]
+    for j in (1, 13, 25):
+        coef = line_coefficients(H, ops[j], psi, sigma)
+        e_dense = _dense_line(H, ops[j], psi, 8)
+        assert _derivative_pin_error(landscape_derivative, coef, e_dense, thetas) < 1e-8
+        # each term of E'(theta) flipped in sign in turn must fail the pin
+        auu, auv, auw, avv, avw, aww = coef
+        def term(k):
+            def f(c, th):
+                cs, sn = math.cos(th), math.sin(th)
+                parts = [-2.0 * auv * sn, 2.0 * auw * cs, -2.0 * avv * sn * cs,
+                         2.0 * avw * (cs * cs - sn * sn), 2.0 * aww * sn * cs]
+                parts[k] = -parts[k]
+                return sum(parts)
+            return f
+        for k in range(5):
+            assert _derivative_pin_error(term(k), coef, e_dense, thetas) > 1e-4, k
+
+
+def test_line_search_angle_is_first_minimum_of_dense_energy_scan():
+    """theta* against the dense exponential alone: walking from 0 downhill on a
+    0.05-degree grid of dense energies, the first grid minimum lies next to
+    theta*, and a bounded minimisation of the dense energy around it lands on
+    theta* to the precision a minimum allows (~sqrt(machine epsilon))."""
+    from scipy.optimize import minimize_scalar
+    h1, eri, ec, H, ops, hf, ne = _system(8)
+    psi = _sector_state(8, ne, np.random.default_rng(12))
+    sigma = apply_h(H, psi)
+    g = gradients(ops, psi, sigma)
+    step = math.pi / 3600
+    for j in (0, 7, 13, 25):
+        coef = line_coefficients(H, ops[j], psi, sigma)
+        th = line_search(coef, g[j])
+        d = -np.sign(g[j])
+        e_dense = _dense_line(H, ops[j], psi, 8)
+        prev = e_dense(0.0)
+        k = 1
+        while True:
+            cur = e_dense(d * k * step)
+            if cur > prev:
+                break
+            prev = cur
+            k += 1
+            assert k < 7200
+        t_grid = d * (k - 1) * step
+        assert abs(t_grid - th) <= step
+        lo, hi = sorted((t_grid - 2 * step, t_grid + 2 * step))
+        t_min = minimize_scalar(e_dense, bounds=(lo, hi), method="bounded",
+                                options={"xatol": 1e-10}).x
+        assert abs(t_min - th) < 1e-6
+        assert e_dense(th) <= e_dense(t_min) + 1e-13
+
+
 def test_line_search_matches_brentq():
     h1, eri, ec, H, ops, hf, ne = _system(8)
     psi = _sector_state(8, ne, np.random.default_rng(8))
