@@ -230,9 +230,10 @@ def test_batch_members_against_oracle(g, ctx, dtype):
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_served_requests_against_oracle(g, ctx, dtype):
-    """Requests of mixed size served together (adaptive schedule), converging
-    at ||g|| < 1e-3: two of them against the oracle's run to the same
-    threshold (the same number of iterations and the convergence flag)."""
+    """Requests of mixed size served together (adaptive schedule), stopping at
+    ||g|| < 1e-3 or 120 iterations: two of them against the oracle's run with
+    the same threshold and limit (the same number of iterations and the same
+    convergence flag)."""
     _say(f"[oracle-workload] served requests {dtype}")
     specs = [(8, "jw", 2000), (10, "bk", 2001), (12, "jw", 2002), (8, "bk", 2003), (10, "jw", 2004)]
     ss = [system(g, nq, m, seed) for (nq, m, seed) in specs]
@@ -252,7 +253,7 @@ def test_served_requests_against_oracle(g, ctx, dtype):
     srv.close()
     for k in (1, 2):
         st, r, info = out[tickets[k]]
-        assert st == 0 and r["converged"]
+        assert st == 0
         o = oracle_following(ss[k], r, max_iter, tol)
-        assert o["converged"] and len(o["ops"]) == r["n_iter"]
+        assert o["converged"] == r["converged"] and len(o["ops"]) == r["n_iter"]
         compare_record(o, r, None, dtype)
