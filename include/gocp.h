@@ -206,6 +206,29 @@ int pool_gradients(gocp_ctx *ctx, const gocp_ham *h, const gocp_pool *p, const v
                    int dtype, double *g_out, int g_on_device);
 
 /*
+ * pool_gradients_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same gradients as pool_gradients with g_on_device = 1,
+ * computed by the same kernels into g_dev (M FP64 values, caller-owned device
+ * memory), with the call's workspace in a fixed 8 MiB device array that the
+ * library holds on each device until the process ends.  The call allocates
+ * nothing: no hipMalloc, hipFree or allocating library routine.
+ *   - The Hamiltonian's and the pool's tables must already be on the device
+ *     (any earlier device call taking them, e.g. energy or pool_gradients,
+ *     uploads them); otherwise EINVAL.
+ *   - Problems whose workspace exceeds the array (about 2^n (48 + M / 8)
+ *     bytes for complex128 states: every pool at 14 qubits, the full
+ *     singles+doubles pool at 16) are rejected with ENOTSUP; use pool_gradients.
+ *   - Every call on one device shares that device's array: calls that overlap
+ *     on one device (on different streams or host threads) race and must be
+ *     serialised by the caller.  Nothing in the array needs to start at zero.
+ * Asynchronous on the context stream (no status check of the result).
+ * Errors: EINVAL, ESHAPE, ENOTSUP as above.
+ */
+int pool_gradients_noalloc(gocp_ctx *ctx, const gocp_ham *h, const gocp_pool *p, const void *psi_dev,
+                           int dtype, double *g_dev);
+
+/*
  * taylor5_apply -- Eq. 5-6: psi <- T5(theta/s)^s psi / ||.||, in place, with
  * T5(x) = sum_{n=0..5} x^n/n! A_k^n evaluated as the chain v_n = A_k v_{n-1},
  * s = max(1, ceil(|theta| * ||A_k||_1 / 0.5)) substeps, and one FP64

@@ -70,6 +70,7 @@ SIGNATURES = {
     "energy": [_P, _P, _P, C.c_int, _F64P],
     "gocp_apply_hamiltonian": [_P, _P, _P, C.c_int, _P, _F64P],
     "pool_gradients": [_P, _P, _P, _P, C.c_int, _F64P, C.c_int],
+    "pool_gradients_noalloc": [_P, _P, _P, _P, C.c_int, _F64P],
     "taylor5_apply": [_P, _P, C.c_int32, C.c_double, _P, C.c_int, _I32P],
     "taylor5_apply_family": [_P, _P, C.c_int32, _I32P, C.POINTER(C.c_double), _P, C.c_int, _I32P],
     "adapt_solve": [_P, _P, _P, _P, C.c_int, C.POINTER(AdaptParams), C.POINTER(AdaptResult)],

@@ -16,7 +16,8 @@ from ._lib import load, check, AdaptParams, AdaptResult, RequestInfo, GOCP_EBUSY
 
 __all__ = ["MAPPINGS", "Hamiltonian", "Pool", "Context", "pauli_hamiltonian_load",
            "pauli_hamiltonian_load_terms", "pool_build", "pool_build_pauli", "taylor5_apply_family", "gocp_partition", "hf_index",
-           "state_basis", "energy", "apply_hamiltonian", "pool_gradients", "taylor5_apply",
+           "state_basis", "energy", "apply_hamiltonian", "pool_gradients", "pool_gradients_noalloc",
+           "taylor5_apply",
            "adapt_solve", "Batch", "Server", "request_footprint", "version"]
 
 MAPPINGS = {"jw": 0, "bk": 1, 0: 0, 1: 1}
@@ -270,6 +271,17 @@ def pool_gradients(ctx: Context, ham: Hamiltonian, pool: Pool, psi, out=None):
         return g
     check(load().pool_gradients(ctx.handle, ham.handle, pool.handle, p, dt,
                                 _device_f64(out, pool.n_ops, "out"), 1))
+    return out
+
+
+def pool_gradients_noalloc(ctx: Context, ham: Hamiltonian, pool: Pool, psi, out):
+    """pool_gradients into the device tensor `out` without any device
+    allocation (fixed library workspace; the tables must already be resident)."""
+    if ham.n_qubits != pool.n_qubits:
+        raise ValueError(f"Hamiltonian has {ham.n_qubits} qubits, pool {pool.n_qubits}")
+    p, dt = _state(psi, ham.n_qubits)
+    check(load().pool_gradients_noalloc(ctx.handle, ham.handle, pool.handle, p, dt,
+                                        _device_f64(out, pool.n_ops, "out")))
     return out
 
 

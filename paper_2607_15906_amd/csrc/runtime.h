@@ -63,11 +63,18 @@ struct InstPlan {
 // too, adapt (FP64 states only) the H v and H w an ADAPT iteration keeps.
 InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi, bool adapt = true);
 
+// Device copies of a Hamiltonian's / pool's tables on device `dev`, uploaded
+// on first use (allocates).  The *_resident forms never upload: they return
+// nullptr when the tables are not on the device yet.
 const DeviceHam *device_ham(const Ham &h, int dev);
 const DevicePool *device_pool(const Pool &p, int dev);
+const DeviceHam *device_ham_resident(const Ham &h, int dev);
+const DevicePool *device_pool_resident(const Pool &p, int dev);
 
+// Descriptor of an instance whose workspace starts at `base`; with upload
+// false the tables must already be resident (else GOCP_EINVAL).
 InstDev make_desc(int device, const InstPlan &ip, char *base, const Ham *h, const Pool *p, void *psi,
-                  double2 *sigma_override);
+                  double2 *sigma_override, bool upload = true);
 AdaptState make_state(const InstPlan &ip, char *base, int max_iter, double grad_tol, bool hist);
 
 const Ham *as_ham(const gocp_ham *h);

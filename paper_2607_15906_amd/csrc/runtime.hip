@@ -8,9 +8,19 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "runtime.h"
+
+// Workspace of the allocation-free gradient screen (pool_gradients_noalloc):
+// one fixed array per device, held until the process ends.  Host code never
+// passes `scratch` itself to a kernel or a copy: it is a host-side stand-in.
+// The device address is looked up once per device (hipGetSymbolAddress, at
+// context creation) and only that address is used.
+static constexpr size_t kNoAllocScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
 
 namespace gocp {
 
@@ -274,6 +284,16 @@ void release_device_pool(DevicePool *d) {
     delete d;
 }
 
+const DeviceHam *device_ham_resident(const Ham &h, int dev) {
+    std::lock_guard<std::mutex> lk(h.mu);
+    return (int)h.dev.size() > dev ? h.dev[dev] : nullptr;
+}
+
+const DevicePool *device_pool_resident(const Pool &p, int dev) {
+    std::lock_guard<std::mutex> lk(p.mu);
+    return (int)p.dev.size() > dev ? p.dev[dev] : nullptr;
+}
+
 const DeviceHam *device_ham(const Ham &h, int dev) {
     std::lock_guard<std::mutex> lk(h.mu);
     if ((int)h.dev.size() <= dev) h.dev.resize(dev + 1, nullptr);
@@ -513,11 +533,14 @@ InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi, boo
 }
 
 InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const Pool *p, void *psi,
-                  double2 *sigma_override) {
+                  double2 *sigma_override, bool upload) {
     InstDev I;
     std::memset(&I, 0, sizeof(I));
     if (h) {
-        const DeviceHam *dh = device_ham(*h, device);
+        const DeviceHam *dh = upload ? device_ham(*h, device) : device_ham_resident(*h, device);
+        if (!dh)
+            throw Error(GOCP_EINVAL, "the Hamiltonian's tables are not on this device yet (a device call "
+                                     "that takes the Hamiltonian, e.g. energy, uploads them)");
         I.hcls = dh->hcls;
         I.hcoef = dh->hcoef;
         I.hzs = dh->hzs;
@@ -533,7 +556,10 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
         I.n_hchunks = dh->n_chunks;
     }
     if (p) {
-        const DevicePool *dp = device_pool(*p, device);
+        const DevicePool *dp = upload ? device_pool(*p, device) : device_pool_resident(*p, device);
+        if (!dp)
+            throw Error(GOCP_EINVAL, "the pool's tables are not on this device yet (a device call that "
+                                     "takes the pool, e.g. pool_gradients, uploads them)");
         I.pop = dp->pop;
         I.pterm = dp->pterm;
         I.op_norm1 = dp->op_norm1;
@@ -609,6 +635,28 @@ void check_dtype(int dtype) {
 }
 
 namespace {
+
+// Device address of `scratch` on each device, resolved once per device with
+// that device current; read under the mutex.
+std::mutex scratch_mu;
+std::vector<char *> scratch_addr;
+
+void resolve_scratch(int device) {
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if ((int)scratch_addr.size() <= device) scratch_addr.resize(device + 1, nullptr);
+    if (scratch_addr[device]) return;
+    void *ptr = nullptr;
+    hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) throw Error(GOCP_EDEVICE, "hipGetSymbolAddress(scratch) returned a null address");
+    scratch_addr[device] = static_cast<char *>(ptr);
+}
+
+char *scratch_base(int device) {
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    char *b = (int)scratch_addr.size() > device ? scratch_addr[device] : nullptr;
+    if (!b) throw Error(GOCP_EDEVICE, "the allocation-free workspace of this device was not resolved");
+    return b;
+}
 
 // Workspace of a one-shot call: one instance plus its descriptor and block
 // tables, carved from the context's arena (grown on demand).
@@ -709,6 +757,7 @@ int gocp_ctx_create(int device, void *stream, gocp_ctx **out) {
     c->device = device;
     c->arch = arch;
     c->n_cu = prop.multiProcessorCount;
+    resolve_scratch(device);
     hip_check(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking), "hipStreamCreate");
     c->user_stream = static_cast<hipStream_t>(stream);   // NULL: the default stream
     *out = c.release();
@@ -811,6 +860,39 @@ int pool_gradients(gocp_ctx *ctx, const gocp_ham *hh, const gocp_pool *pp, const
         const AdaptState st = read_state(ctx, o);
         if (st.status) throw Error(st.status, "non-finite gradient");
     }
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
+int pool_gradients_noalloc(gocp_ctx *ctx, const gocp_ham *hh, const gocp_pool *pp, const void *psi_dev,
+                           int dtype, double *g_dev) {
+    GOCP_GUARD_BEGIN
+    check_ctx(ctx);
+    if (!psi_dev || !g_dev) throw Error(GOCP_EINVAL, "null state or output pointer");
+    check_dtype(dtype);
+    const Ham *h = as_ham(hh);
+    const Pool *p = as_pool(pp);
+    if (h->n_qubits != p->n_qubits) throw Error(GOCP_ESHAPE, "Hamiltonian and pool act on different qubit counts");
+    // layout inside the scratch: the descriptor, then the one-shot workspace
+    const InstPlan ip = plan_instance(h->n_qubits, p->n_ops(), 0, dtype, false, false);
+    const size_t o_work = (sizeof(InstDev) + 255) & ~(size_t)255;
+    if (o_work + ip.bytes > kNoAllocScratchBytes)
+        throw Error(GOCP_ENOTSUP, "pool_gradients_noalloc: the workspace of " + std::to_string(o_work + ip.bytes) +
+                                      " bytes exceeds its fixed " + std::to_string(kNoAllocScratchBytes) +
+                                      "-byte device scratch (use pool_gradients)");
+    char *base = scratch_base(ctx->device);
+    char *b = base + o_work;
+    const InstDev I = make_desc(ctx->device, ip, b, h, p, const_cast<void *>(psi_dev), nullptr, false);
+    AdaptState st = make_state(ip, b, 0, 0.0, false);
+    st.g = g_dev;                     // the selection pass writes the gradients straight to the caller
+    hipStream_t s = ctx->user_stream;
+    hip_check(hipMemcpyAsync(base, &I, sizeof(I), hipMemcpyHostToDevice, s), "H2D");
+    hip_check(hipMemcpyAsync(b + ip.o_st, &st, sizeof(st), hipMemcpyHostToDevice, s), "H2D");
+    // one instance: null row tables, the kernels take rows (0, workgroup)
+    const InstDev *desc = reinterpret_cast<const InstDev *>(base);
+    launch_kernel(K_ENERGY_SCREEN, dtype, 1, desc, nullptr, ip.n_tiles, 0, s);
+    launch_kernel(K_SCREEN_SUM1, dtype, 1, desc, nullptr, ip.n_groups, 0, s);
+    launch_kernel(K_SCREEN_REDUCE, dtype, 1, desc, nullptr, 1, 0, s);
     return GOCP_OK;
     GOCP_GUARD_END
 }
