@@ -117,11 +117,11 @@ struct Group {
             di.n_groups = (di.n_tiles + kGroup - 1) / kGroup;
             // members that keep a list of the amplitudes where v or w is
             // nonzero (complex64 states) take the compacted H v, H w launch:
-            // kHvwSlots tile slots (fewer for small states) of kHvwParts
+            // one slot per pair block (at most kHvwSlots) of kHvwParts
             // workgroups, a function of the member alone, so its results do
             // not depend on the group it runs in
             if (di.act) {
-                di.n_lpart = std::min(kHvwSlots, tiles_for(di.n_qubits, 1)) * kHvwParts;
+                di.n_lpart = std::min(kHvwSlots, inst[i]->ip.n_pblk) * kHvwParts;
                 for (int y = 0; y < di.n_lpart; ++y) ba.push_back(make_int2((int)i, y));
             } else {
                 di.n_lpart = di.n_tiles;

@@ -51,6 +51,11 @@ constexpr int kGroup = 16;
 // more than kActMaxBlocks use the whole-state launch.
 constexpr int kHvwParts = 8;
 constexpr int kHvwSlots = 32;
+// Class records per batch of the compacted launch's walk (table values read
+// through the scalar cache): two measured faster than three or four at 14
+// qubits (6.1 against 6.2 and 6.7 us per launch), whose larger batches spill
+// scalar registers.
+constexpr int kHvwBatch = 2;
 
 // GOCP multi-operator step: at most kFuseMax operators of one family per pass.
 constexpr int kFuseMax = 4;

@@ -1502,118 +1502,135 @@ __global__ __launch_bounds__(kNW *kWave) __attribute__((amdgpu_waves_per_eu(8)))
     line_hvw<T, 1>(insts, blk, mode);
 }
 
-// H v, H w dots over the compacted active amplitudes (complex64 states, whose
+// H applied to two vectors at the lane's amplitude d over the records
+// [c0, c1) of H's class table (global indices), every table value read
+// through the scalar cache (no LDS staging):
+//   acc[2 v + {0,1}] += f_c(d) vec_v(d ^ x_c),  v = 0, 1.
+// NB records per batch: the batch's records are read in one go, then every
+// record's first string group and its two gathers are issued together, then
+// the strings are summed (a record's further groups are read where they are
+// used).  Records past c1 re-read the run's last record and are not summed.
+// Factored classes (kFactBit) hold one group of parameters (see fact_h).
+template <typename T, int NB>
+__device__ __forceinline__ void walk_run_scalar(const HClass *hcls, const double *hcoef, const uint32_t *hzs,
+                                                int c0, int c1, uint32_t d, const void *v0, const void *v1,
+                                                double (&acc)[4]) {
+    using Raw = typename Amp<T>::Raw;
+    if (c0 >= c1) return;
+    uint32_t doff = d << Amp<T>::kShift;
+    asm volatile("" : "+v"(doff));      // keep the shifted offset: one XOR per gather
+    const uint32_t dz = with_sign_bit(d);
+    const GOCP_AS4 HClass *rec = cptr(hcls);
+    const GOCP_AS4 double *co = cptr(hcoef);
+    const GOCP_AS4 uint32_t *zs = cptr(hzs);
+    for (int c = c0; c < c1; c += NB) {
+        HClass r[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) r[k] = load_rec(rec, min(c + k, c1 - 1));
+        double cm[NB][kStrGroup];
+        uint32_t zm[NB][kStrGroup];
+        Raw p[NB][2];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const uint32_t o = doff ^ (r[k].x << Amp<T>::kShift);
+            p[k][0] = Amp<T>::raw_at(v0, o);
+            p[k][1] = Amp<T>::raw_at(v1, o);
+#pragma unroll
+            for (int q = 0; q < kStrGroup; ++q) {
+                cm[k][q] = co[r[k].s0 + q];
+                zm[k][q] = zs[r[k].s0 + q];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            if (c + k >= c1) break;
+            double f;
+            if (r[k].x & kFactBit) {
+                f = fact_h(cm[k][0], zm[k][0], zm[k][1], zm[k][2], dz);
+            } else {
+                double f0 = signed_cz(cm[k][0], zm[k][0], dz) + signed_cz(cm[k][2], zm[k][2], dz);
+                double f1 = signed_cz(cm[k][1], zm[k][1], dz) + signed_cz(cm[k][3], zm[k][3], dz);
+                for (int q = r[k].s0 + kStrGroup; q < r[k].s1; q += kStrGroup) {
+                    f0 += signed_cz(co[q], zs[q], dz) + signed_cz(co[q + 2], zs[q + 2], dz);
+                    f1 += signed_cz(co[q + 1], zs[q + 1], dz) + signed_cz(co[q + 3], zs[q + 3], dz);
+                }
+                f = f0 + f1;
+            }
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const double2 a = Amp<T>::cvt(p[k][v]);
+                acc[2 * v] = fma(f, a.x, acc[2 * v]);
+                acc[2 * v + 1] = fma(f, a.y, acc[2 * v + 1]);
+            }
+        }
+    }
+}
+
+// H v, H w dots over the listed active amplitudes (complex64 states, whose
 // line search keeps no H v, H w).  The three dots have v* or w* as left
 // factor, so only amplitudes where v or w is nonzero contribute; k_line_vw
-// lists them per pair block.  Row (instance, slot kHvwParts + part): the
-// workgroup takes tiles slot, slot + kHvwSlots, ... of 64 listed amplitudes
-// (lane l of tile t has list entry 64 t + l, in pair-block order) and applies
-// the classes of run `part` of each wave segment (a 1 / kHvwParts share of H);
-// since the dots are linear in H v and H w, each (chunk, tile) adds
-// v* (H_part v) etc. at once.  Writes its partial triple to row y of the
-// line-search partials.  mode 1: ADAPT iteration; mode 0: timing.
+// lists them per pair block (entries [0, count) of the block's list).
+// Row (instance, slot kHvwParts + part), slot < min(kHvwSlots, pair blocks):
+// the workgroup takes the lists of pair blocks slot, slot + slots, ..., 64
+// entries at a time (one per lane), and wave w applies run `part` of its
+// segment of H's classes (a 1 / (kNW kHvwParts) share of H) with the table
+// read through the scalar cache.  Since the dots are linear in H v and H w,
+// each (block, tile, run) adds v* (H_run v) etc. at once; the workgroup writes
+// its partial triple to row y of the line-search partials.  The row count is
+// a function of the instance alone.  Every table and list value is loaded in
+// as few dependent steps as the data allow: the descriptor, then the state's
+// flag with the wave's run bounds and the first block's count and entries,
+// then the class records, then the strings with the gathers.
+// mode 1: ADAPT iteration; mode 0: timing.
 template <typename T>
 // (at most 64 VGPRs: two workgroups per CU, which the many rows of a batch need)
-__global__ __launch_bounds__(kNW *kWave) __attribute__((amdgpu_waves_per_eu(8))) void k_line_hvw_act(const InstDev *__restrict__ insts,
-                                                            const int2 *__restrict__ blk, int mode) {
+__global__ __launch_bounds__(kNW *kWave) __attribute__((amdgpu_waves_per_eu(8))) void k_line_hvw_act(
+    const InstDev *__restrict__ insts, const int2 *__restrict__ blk, int mode) {
     const int2 b = work_row(blk);
     const InstDev &I = insts[b.x];
     const int slot = b.y / kHvwParts, part = b.y % kHvwParts;
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = wave_id();
-    // the descriptor fields, then the state record's flag and the wave's
-    // chunk-0 run bounds, are each loaded in one batch ahead of their uses
-    // (a chain of one load per field otherwise)
     const AdaptState *st = I.st;
-    const int nq = I.n_qubits, nb = I.n_pblk;
+    const int nq = I.n_qubits, nb = I.n_pblk, nhc = I.n_hchunks;
     const int32_t *hsegp = I.hsegp, *act_n = I.act_n;
     const void *vv = I.v, *vw = I.w;
     const uint32_t *act = I.act, *hzs = I.hzs;
     const HClass *hcls = I.hcls;
     const double *hcoef = I.hcoef;
-    const int4 *hchunk = I.hchunk;
-    asm volatile("" ::"s"(st), "s"(nq), "s"(nb), "s"(hsegp), "s"(act_n), "s"(vv), "s"(vw), "s"(act), "s"(hzs),
-                 "s"(hcls), "s"(hcoef), "s"(hchunk));
+    double *part_l = I.part_l;
+    asm volatile("" ::"s"(st), "s"(nq), "s"(nb), "s"(nhc), "s"(hsegp), "s"(act_n), "s"(vv), "s"(vw), "s"(act),
+                 "s"(hzs), "s"(hcls), "s"(hcoef), "s"(part_l));
+    const int nslot = min(kHvwSlots, nb);
     const int r0 = wv * kHvwParts + part;
+    constexpr int kList = 2 * kPairBlock;          // list capacity of a pair block
     const int done = cptr(&st->done)[0];
     const int ra = cptr(hsegp)[r0], rb = cptr(hsegp)[r0 + 1];
-    const int4 bd0 = load_rec(cptr(hchunk), 0);
-    asm volatile("" ::"s"(done), "s"(ra), "s"(rb), "s"(bd0.x), "s"(bd0.y), "s"(bd0.z), "s"(bd0.w));
+    const int cnt0 = cptr(act_n)[slot];
+    const uint32_t e0 = gptr(act)[(size_t)slot * kList + lane];
+    asm volatile("" ::"s"(done), "s"(ra), "s"(rb), "s"(cnt0));
     if (mode != 0 && done) return;
     const uint32_t dim = 1u << nq;
-    __shared__ int pre[kActMaxBlocks + 1];
-    __shared__ Stage S;
     __shared__ double rsum[3][kNW];
-    // the blocks' counts, loaded by all threads at once
-    static_assert(kActMaxBlocks <= kNW * kWave, "one count per thread");
-    const int cnt = threadIdx.x < nb ? min(max(gptr(act_n)[threadIdx.x], 0), 2 * kPairBlock) : 0;
-    // exclusive prefix of the blocks' counts (each at most 2 kPairBlock),
-    // scanned by wave 0, 64 at a time
-    if (threadIdx.x < nb) pre[threadIdx.x + 1] = cnt;
-    __syncthreads();
-    if (wv == 0) {
-        int carry = 0;
-        for (int base = 0; base < nb; base += kWave) {
-            const int i = base + lane;
-            int v = i < nb ? pre[i + 1] : 0;
-#pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-                const int u = __shfl_up(v, off, kWave);
-                if (lane >= off) v += u;
-            }
-            if (i < nb) pre[i + 1] = carry + v;
-            carry += __shfl(v, kWave - 1, kWave);
-        }
-        if (lane == 0) pre[0] = 0;
-    }
-    __syncthreads();
-    const int n_act = pre[nb];
     double p3 = 0.0, p5 = 0.0, p6 = 0.0;
-    if (slot * kWave < n_act) {
-        for (int k = 0; k < I.n_hchunks; ++k) {
-            const int r = k * (kNW * kHvwParts + 1) + r0;
-            const GOCP_AS4 int32_t *seg = cptr(hsegp) + r;
-            // the wave's run of classes [c0, c1) of the staged chunk (the first
-            // chunk's bounds were loaded with the state's flag)
-            const int4 bd = k == 0 ? bd0 : load_rec(cptr(hchunk), k);
-            const int cb = bd.x, ce = bd.y, sb = bd.z;
-            __syncthreads();
-            stage_copy(S.cls, hcls + cb, ce - cb);
-            stage_coef(S, hcoef, sb, bd.w);
-            __syncthreads();
-            const int c0 = (k == 0 ? ra : seg[0]) - cb, c1 = (k == 0 ? rb : seg[1]) - cb;
-            const GOCP_AS4 uint32_t *zs = cptr(hzs) + sb;
-            for (int t = slot; t * kWave < n_act; t += kHvwSlots) {
-                // this lane's amplitude: list entry g, found in the block prefix
-                const int g = t * kWave + lane;
-                const bool on = g < n_act;
-                uint32_t d = 0;
-                if (on) {
-                    int lo = 0, hi = nb;                  // pre[lo] <= g < pre[hi]
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (pre[mid] <= g) lo = mid; else hi = mid;
-                    }
-                    d = act[(size_t)lo * 2 * kPairBlock + (g - pre[lo])] & (dim - 1u);
-                }
-                double acc[4] = {0.0, 0.0, 0.0, 0.0};
-                // runs of a few classes: the class walk, whose pipeline fills
-                // faster than the grouped walk's
-                walk_classes_r1<T, 2, kFactH>(S, zs, c0, c1, sb, d, vv, vw,
-                                      [&](int, double f, const typename Amp<T>::Raw (&p)[2]) {
-#pragma unroll
-                                          for (int v = 0; v < 2; ++v) {
-                                              const double2 a = Amp<T>::cvt(p[v]);
-                                              acc[2 * v] = fma(f, a.x, acc[2 * v]);
-                                              acc[2 * v + 1] = fma(f, a.y, acc[2 * v + 1]);
-                                          }
-                                      });
-                if (on) {
-                    const double2 ov = Amp<T>::load(vv, d), ow = Amp<T>::load(vw, d);
-                    p3 += ov.x * acc[0] + ov.y * acc[1];
-                    p5 += ow.x * acc[2] + ow.y * acc[3];
-                    p6 += ov.x * acc[2] + ov.y * acc[3];
-                }
+    for (int bk = slot; bk < nb; bk += nslot) {
+        const int cnt = min(max(bk == slot ? cnt0 : cptr(act_n)[bk], 0), kList);
+        for (int t = 0; t * kWave < cnt; ++t) {
+            const int g = t * kWave + lane;
+            const bool on = g < cnt;
+            uint32_t d = bk == slot && t == 0 ? e0 : gptr(act)[(size_t)bk * kList + min(g, kList - 1)];
+            d = on ? d & (dim - 1u) : 0u;
+            const double2 ov = Amp<T>::load(vv, d), ow = Amp<T>::load(vw, d);
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int k = 0; k < nhc; ++k) {
+                const int r = k * (kNW * kHvwParts + 1) + r0;
+                const int c0 = k == 0 ? ra : cptr(hsegp)[r], c1 = k == 0 ? rb : cptr(hsegp)[r + 1];
+                walk_run_scalar<T, kHvwBatch>(hcls, hcoef, hzs, c0, c1, d, vv, vw, acc);
+            }
+            if (on) {
+                p3 += ov.x * acc[0] + ov.y * acc[1];
+                p5 += ow.x * acc[2] + ow.y * acc[3];
+                p6 += ov.x * acc[2] + ov.y * acc[3];
             }
         }
     }
@@ -1630,7 +1647,7 @@ __global__ __launch_bounds__(kNW *kWave) __attribute__((amdgpu_waves_per_eu(8)))
     if (threadIdx.x < 3) {
         double a = 0.0;
         for (int k = 0; k < kNW; ++k) a += rsum[threadIdx.x][k];
-        I.part_l[2 * I.n_pblk + 3 * b.y + threadIdx.x] = a;
+        part_l[2 * nb + 3 * b.y + threadIdx.x] = a;
     }
 }
 
