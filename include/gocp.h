@@ -357,14 +357,24 @@ int gocp_batch_destroy(gocp_batch *b);
 
 /* ---------------------------------------------------------------------
  * Serving form: continuous batching of ADAPT solves on one device.
- * Requests are queued from any thread.  A worker thread admits them in
- * arrival order while a slot is free and the request's device footprint fits
- * the HBM budget, starts each from its Hartree-Fock state, and advances all
- * admitted requests together (iters_per_step iterations per step, one launch
- * per kernel for all of them).  After every step it retires finished requests
- * (converged or at max_iter), frees their memory and admits waiting ones, so
- * requests arriving while others run join the running set.  Each request
- * computes exactly what adapt_solve computes for it alone.
+ * Requests are queued from any thread.  The server allocates its device
+ * memory once, at creation: an arena of the HBM budget, from which each
+ * admitted request gets one block holding its workspace and its own copy of
+ * its Hamiltonian's and pool's device tables (gocp_request_bytes), plus fixed
+ * table and flag buffers; its worker thread never allocates or frees device
+ * memory.  The worker admits requests in arrival order while a slot is free
+ * and the request's block fits the arena, starts each from its Hartree-Fock
+ * state, and advances all admitted requests together (iters_per_step
+ * iterations per step, one launch per kernel for all of them).  Two steps stay
+ * queued on the device: while one runs, the worker reads the previous step's
+ * done flags (event polling), retires finished requests (converged or at
+ * max_iter), admits waiting ones into free blocks and prepares the next
+ * step's tables, so requests arriving while others run join the running set
+ * and admission overlaps device work.  Each request computes exactly what
+ * adapt_solve computes for it alone.
+ * Test hook: with the environment variable GOCP_TEST_FAIL_ADMISSION=k at
+ * gocp_server_create, the server's k-th admission fails as a device error
+ * would (that request ends with GOCP_EDEVICE; the others are unaffected).
  * ------------------------------------------------------------------- */
 typedef struct {
     int32_t status;         /* GOCP_OK, GOCP_ENOMEM (never fits the budget),
@@ -375,9 +385,15 @@ typedef struct {
     int64_t t_done_ns;
 } gocp_request_info;
 
-/* Device bytes one request occupies while admitted (workspace + term tables). */
+/* An estimate, from the sizes alone, of the device bytes one request occupies
+ * while admitted (workspace + term tables). */
 int gocp_request_footprint(int n_qubits, int n_ops, int n_strings, int64_t n_terms, int n_classes,
                            int max_iter, int dtype, int64_t *bytes);
+/* The exact bytes of the arena block a server gives the request (ham, pool,
+ * max_iter, dtype): its workspace and its own copy of both handles' device
+ * tables.  Lays the handles' tables out in pinned host memory if that was not
+ * done yet (a host-side allocation; no device memory).  Errors: EINVAL, ESHAPE. */
+int gocp_request_bytes(const gocp_ham *h, const gocp_pool *p, int32_t max_iter, int dtype, int64_t *bytes);
 /* Start a server on ctx's device with its own stream and worker thread; the
  * tile kernels run with amps_per_lane (1, 2 or 4) amplitudes per lane, or with
  * 0 a schedule chosen whenever the active set changes: 1 while the set has
@@ -395,9 +411,12 @@ int gocp_server_submit(gocp_server *s, const gocp_ham *h, const gocp_pool *p, in
 /* GOCP_EBUSY while the request is queued or running; otherwise the request's
  * status, with its record in *res (arrays sized as for adapt_solve; may be
  * NULL) and its times in *info (may be NULL).  A finished ticket is released
- * by the poll that returns it. */
+ * by the poll that returns it.  GOCP_EDEVICE for an unfinished request once
+ * the worker has failed (every unfinished request then ends with it). */
 int gocp_server_poll(gocp_server *s, uint64_t ticket, gocp_adapt_result *res, gocp_request_info *info);
-/* Running and queued requests, requests finished so far, admitted bytes, steps. */
+/* Running and queued requests, requests finished so far, bytes of the arena
+ * in use (the blocks of admitted requests and of retired ones whose record is
+ * still being copied), steps. */
 int gocp_server_stats(gocp_server *s, int32_t *active, int32_t *queued, int64_t *completed,
                       int64_t *bytes_in_use, int64_t *steps);
 /* Stop the worker; unfinished requests end with GOCP_ECANCELED. */

@@ -85,6 +85,7 @@ SIGNATURES = {
     "gocp_batch_schedule": [_P, _I32P],
     "gocp_batch_destroy": [_P],
     "gocp_request_footprint": [C.c_int, C.c_int, C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int, _I64P],
+    "gocp_request_bytes": [_P, _P, C.c_int32, C.c_int, _I64P],
     "gocp_server_create": [_P, C.c_int64, C.c_int32, C.c_int, C.c_int32, C.c_int32, _PP],
     "gocp_server_submit": [_P, _P, _P, C.c_int32, C.c_double, _U64P],
     "gocp_server_poll": [_P, C.c_uint64, C.POINTER(AdaptResult), C.POINTER(RequestInfo)],

@@ -425,10 +425,9 @@ class Batch:
 
 
 def request_footprint(ham: Hamiltonian, pool: Pool, max_iter: int, dtype: int = C64) -> int:
-    """Device bytes one serving request occupies while admitted."""
+    """Device bytes one serving request occupies while admitted (its arena block)."""
     out = C.c_int64()
-    check(load().gocp_request_footprint(ham.n_qubits, pool.n_ops, pool.n_strings, ham.n_terms,
-                                        ham.n_classes, int(max_iter), int(dtype), C.byref(out)))
+    check(load().gocp_request_bytes(ham.handle, pool.handle, int(max_iter), int(dtype), C.byref(out)))
     return out.value
 
 

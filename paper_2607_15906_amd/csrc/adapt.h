@@ -24,16 +24,21 @@ struct Instance {
     char *mem = nullptr;
     InstDev desc;
     bool finalized = false;
+    bool owns_mem = true;
     ~Instance() {
-        if (mem) (void)hipFree(mem);
+        if (mem && owns_mem) (void)hipFree(mem);
     }
 };
 
 // Validate, allocate and initialise one instance (state upload and counter
 // reset are stream-ordered on s).  With psi == nullptr the instance holds its
-// own state buffer, initialised to the Hartree-Fock basis state `hf`.
+// own state buffer, initialised to the Hartree-Fock basis state `hf`.  With
+// `at` the workspace is placed there (ip.bytes, allocated by the caller) and
+// the tables `dh`, `dp` are used instead of the handles' device caches: no
+// device memory is allocated.
 inline Instance *instance_create(gocp_ctx *ctx, const Ham *h, const Pool *p, void *psi, int dtype,
-                          int max_iter, double tol, uint64_t hf, hipStream_t s) {
+                          int max_iter, double tol, uint64_t hf, hipStream_t s, char *at = nullptr,
+                          const DeviceHam *dh = nullptr, const DevicePool *dp = nullptr) {
     if (!h || !p) throw Error(GOCP_EINVAL, "null Hamiltonian or pool");
     if (h->n_qubits != p->n_qubits)
         throw Error(GOCP_ESHAPE, "Hamiltonian and pool act on different qubit counts");
@@ -47,9 +52,15 @@ inline Instance *instance_create(gocp_ctx *ctx, const Ham *h, const Pool *p, voi
     in->tol = tol;
     const bool own = psi == nullptr;
     in->ip = plan_instance(h->n_qubits, p->n_ops(), max_iter, dtype, own);
-    hip_check(hipMalloc(&in->mem, in->ip.bytes), "hipMalloc instance workspace");
+    if (at) {
+        in->mem = at;
+        in->owns_mem = false;
+    } else {
+        hip_check(hipMalloc(&in->mem, in->ip.bytes), "hipMalloc instance workspace");
+    }
     in->psi = own ? in->mem + in->ip.o_psi : psi;
-    in->desc = make_desc(ctx->device, in->ip, in->mem, h, p, in->psi, nullptr);
+    in->desc = at ? make_desc_at(in->ip, in->mem, dh, dp, in->psi, nullptr)
+                  : make_desc(ctx->device, in->ip, in->mem, h, p, in->psi, nullptr);
     const AdaptState st = make_state(in->ip, in->mem, max_iter, tol, true);
     hip_check(hipMemsetAsync(in->mem + in->ip.o_v, 0, in->ip.o_pe - in->ip.o_v, s), "hipMemsetAsync");
     if (in->ip.o_hv)
@@ -87,10 +98,16 @@ struct Group {
     static constexpr int kChunk = 8;
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
+    // Caller-provided table buffers (the server's): each rebuild writes the
+    // one the previous rebuild did not, so launches still queued with the
+    // previous tables read them intact; rebuild() then never allocates.
+    char *ext[2] = {nullptr, nullptr};
+    size_t ext_cap = 0;
+    int ext_cur = 0;
 
     ~Group() {
         drop_graphs();
-        if (meta) (void)hipFree(meta);
+        if (meta && !ext[0]) (void)hipFree(meta);
     }
 
     void drop_graphs() {
@@ -153,7 +170,12 @@ struct Group {
         const size_t o_bh = o_ba + al(std::max<size_t>(ba.size(), 1) * sizeof(int2));
         const size_t o_dn = o_bh + al(std::max<size_t>(bh.size(), 1) * sizeof(int2));
         const size_t need = o_dn + al(std::max<size_t>(inst.size(), 1) * sizeof(int32_t));
-        if (need > meta_cap) {
+        if (ext[0]) {
+            if (need > ext_cap) throw Error(GOCP_ENOMEM, "group tables exceed the server's table buffers");
+            ext_cur ^= 1;
+            meta = ext[ext_cur];
+            meta_cap = ext_cap;
+        } else if (need > meta_cap) {
             if (meta) {
                 hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
                 hip_check(hipFree(meta), "hipFree");

@@ -191,8 +191,12 @@ struct InstDev {
     int32_t n_lpart;            // workgroups of the H v, H w launch (partial triples)
 };
 
+// Device tables of a Hamiltonian or pool: every array lies in one block of
+// device memory (`base`, laid out as the handle's TableImage), either owned
+// by the handle's per-device cache or placed inside a serving request's block.
 struct DeviceHam {
     int device = -1;
+    char *base = nullptr;
     HClass *hcls = nullptr;
     double *hcoef = nullptr;
     uint32_t *hzs = nullptr;
@@ -210,6 +214,7 @@ struct DeviceHam {
 
 struct DevicePool {
     int device = -1;
+    char *base = nullptr;
     HClass *pop = nullptr;
     HTerm *pterm = nullptr;
     double *op_norm1 = nullptr;

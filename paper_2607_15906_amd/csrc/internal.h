@@ -3,6 +3,7 @@
 
 #include <cstdint>
 #include <atomic>
+#include <memory>
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -31,6 +32,7 @@ struct Term {
 
 struct DeviceHam;    // device copy of a Hamiltonian, defined in the HIP sources
 struct DevicePool;   // device copy of a pool
+struct TableImage;   // a handle's device tables laid out in one pinned host buffer
 
 // Hamiltonian grouped by X mask.  Classes are sorted by x; strings within a
 // class by z.  cls_off is CSR into str_z / str_c.
@@ -51,6 +53,7 @@ struct Ham {
     // device copies, one per device ordinal (lazy, guarded by mu)
     mutable std::mutex mu;
     mutable std::vector<DeviceHam *> dev;
+    mutable std::shared_ptr<TableImage> img;   // built on first device use (guarded by mu)
     int64_t n_terms() const { return (int64_t)str_z.size(); }
     int n_classes() const { return (int)cls_x.size(); }
 };
@@ -74,6 +77,7 @@ struct Pool {
     int64_t n_edges = 0;
     mutable std::mutex mu;
     mutable std::vector<DevicePool *> dev;
+    mutable std::shared_ptr<TableImage> img;   // built on first device use (guarded by mu)
     int n_ops() const { return (int)op_x.size(); }
 };
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -75,6 +76,24 @@ const DevicePool *device_pool_resident(const Pool &p, int dev);
 // false the tables must already be resident (else GOCP_EINVAL).
 InstDev make_desc(int device, const InstPlan &ip, char *base, const Ham *h, const Pool *p, void *psi,
                   double2 *sigma_override, bool upload = true);
+// The same with the tables given (either may be null).
+InstDev make_desc_at(const InstPlan &ip, char *base, const DeviceHam *dh, const DevicePool *dp, void *psi,
+                     double2 *sigma_override);
+
+// A handle's device tables laid out in one pinned host buffer: `ham` / `pool`
+// hold the arrays' byte offsets in the pointer fields, and place_* turns them
+// into a DeviceHam / DevicePool for a copy of the image at a device address.
+struct TableImage {
+    char *host = nullptr;     // pinned (hipHostMalloc)
+    size_t bytes = 0;         // a multiple of 256
+    DeviceHam ham;
+    DevicePool pool;
+    ~TableImage();
+};
+std::shared_ptr<const TableImage> ham_image(const Ham &h);
+std::shared_ptr<const TableImage> pool_image(const Pool &p);
+DeviceHam place_ham(const TableImage &im, char *base, int device);
+DevicePool place_pool(const TableImage &im, char *base, int device);
 AdaptState make_state(const InstPlan &ip, char *base, int max_iter, double grad_tol, bool hist);
 
 const Ham *as_ham(const gocp_ham *h);

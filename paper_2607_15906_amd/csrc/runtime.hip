@@ -33,13 +33,32 @@ void hip_check(hipError_t e, const char *what) {
 
 namespace {
 
+// Lays the arrays of one handle's device tables out in one buffer, each at a
+// 256-byte aligned offset; add() returns the offset in the pointer's type
+// (rebased onto a device address by place_*).
+struct ImagePacker {
+    std::vector<std::pair<size_t, std::vector<char>>> parts;
+    size_t used = 0;
+    template <typename T>
+    T *add(const std::vector<T> &v) {
+        const size_t off = (used + 255) & ~(size_t)255;
+        std::vector<char> b(std::max<size_t>(1, v.size()) * sizeof(T), 0);
+        if (!v.empty()) std::memcpy(b.data(), v.data(), v.size() * sizeof(T));
+        used = off + b.size();
+        parts.emplace_back(off, std::move(b));
+        return reinterpret_cast<T *>(off);
+    }
+    void finish(TableImage &im) {
+        im.bytes = (used + 255) & ~(size_t)255;
+        hip_check(hipHostMalloc(reinterpret_cast<void **>(&im.host), im.bytes, 0), "hipHostMalloc table image");
+        std::memset(im.host, 0, im.bytes);
+        for (const auto &pr : parts) std::memcpy(im.host + pr.first, pr.second.data(), pr.second.size());
+    }
+};
+
 template <typename T>
-T *dev_upload(const std::vector<T> &v) {
-    T *p = nullptr;
-    const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
-    hip_check(hipMalloc(&p, bytes), "hipMalloc");
-    if (!v.empty()) hip_check(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
-    return p;
+void rebase(T *&p, char *base) {
+    p = reinterpret_cast<T *>(base + reinterpret_cast<uintptr_t>(p));
 }
 
 HTerm make_term(double c, uint32_t z) { return HTerm{std::fabs(c), z, std::signbit(c) ? 1u : 0u}; }
@@ -253,35 +272,55 @@ std::vector<int32_t> padded_offsets(int n, F count) {
 
 }  // namespace
 
+TableImage::~TableImage() {
+    if (host) (void)hipHostFree(host);
+}
+
 void release_device_ham(DeviceHam *d) {
     if (!d) return;
-    (void)hipFree(d->hcls);
-    (void)hipFree(d->hcoef);
-    (void)hipFree(d->hzs);
-    (void)hipFree(d->hsub);
-    (void)hipFree(d->hchunk);
-    (void)hipFree(d->hseg);
-    (void)hipFree(d->hsegp);
-    (void)hipFree(d->hcoefG);
-    (void)hipFree(d->hzsG);
-    (void)hipFree(d->hchunkG);
-    (void)hipFree(d->hgx);
-    (void)hipFree(d->hgseg);
+    (void)hipFree(d->base);
     delete d;
 }
 
 void release_device_pool(DevicePool *d) {
     if (!d) return;
-    (void)hipFree(d->pop);
-    (void)hipFree(d->pterm);
-    (void)hipFree(d->op_norm1);
-    (void)hipFree(d->sop);
-    (void)hipFree(d->scoef);
-    (void)hipFree(d->szs);
-    (void)hipFree(d->psub);
-    (void)hipFree(d->pchunk);
-    (void)hipFree(d->pseg);
+    (void)hipFree(d->base);
     delete d;
+}
+
+DeviceHam place_ham(const TableImage &im, char *base, int device) {
+    DeviceHam d = im.ham;
+    d.device = device;
+    d.base = base;
+    rebase(d.hcls, base);
+    rebase(d.hcoef, base);
+    rebase(d.hzs, base);
+    rebase(d.hsub, base);
+    rebase(d.hchunk, base);
+    rebase(d.hseg, base);
+    rebase(d.hsegp, base);
+    rebase(d.hcoefG, base);
+    rebase(d.hzsG, base);
+    rebase(d.hchunkG, base);
+    rebase(d.hgx, base);
+    rebase(d.hgseg, base);
+    return d;
+}
+
+DevicePool place_pool(const TableImage &im, char *base, int device) {
+    DevicePool d = im.pool;
+    d.device = device;
+    d.base = base;
+    rebase(d.pop, base);
+    rebase(d.pterm, base);
+    rebase(d.op_norm1, base);
+    rebase(d.sop, base);
+    rebase(d.scoef, base);
+    rebase(d.szs, base);
+    rebase(d.psub, base);
+    rebase(d.pchunk, base);
+    rebase(d.pseg, base);
+    return d;
 }
 
 const DeviceHam *device_ham_resident(const Ham &h, int dev) {
@@ -294,12 +333,14 @@ const DevicePool *device_pool_resident(const Pool &p, int dev) {
     return (int)p.dev.size() > dev ? p.dev[dev] : nullptr;
 }
 
-const DeviceHam *device_ham(const Ham &h, int dev) {
-    std::lock_guard<std::mutex> lk(h.mu);
-    if ((int)h.dev.size() <= dev) h.dev.resize(dev + 1, nullptr);
-    if (h.dev[dev]) return h.dev[dev];
-    std::unique_ptr<DeviceHam> d(new DeviceHam());
-    d->device = dev;
+namespace {
+
+// The device tables of H in one pinned host image (caller holds h.mu).
+const TableImage &ham_image_locked(const Ham &h) {
+    if (h.img) return *h.img;
+    std::shared_ptr<TableImage> im = std::make_shared<TableImage>();
+    ImagePacker pk;
+    DeviceHam *d = &im->ham;
     // LDS stage chunks over the classes, then within each chunk the classes
     // re-laid out wave by wave (a chunk keeps the same classes, so its string
     // total and boundaries are unchanged)
@@ -376,29 +417,30 @@ const DeviceHam *device_ham(const Ham &h, int dev) {
     // zero groups past the end: the walk's read-ahead stays in the tables
     gzs.resize(gzs.size() + (size_t)kTablePadGroups * kStrGroup, 0u);
     gx.resize(gx.size() + kTablePadGroups, 0u);
-    d->hcoefG = dev_upload(gco);
-    d->hzsG = dev_upload(gzs);
-    d->hchunkG = dev_upload(gchunk);
-    d->hgx = dev_upload(gx);
-    d->hgseg = dev_upload(gseg);
-    d->hcls = dev_upload(cls);
-    d->hcoef = dev_upload(co);
-    d->hzs = dev_upload(zs);
-    d->hsub = dev_upload(sub);
-    d->hchunk = dev_upload(stage_bounds(ch, cls));
-    d->hseg = dev_upload(seg);
-    d->hsegp = dev_upload(segp);
+    d->hcoefG = pk.add(gco);
+    d->hzsG = pk.add(gzs);
+    d->hchunkG = pk.add(gchunk);
+    d->hgx = pk.add(gx);
+    d->hgseg = pk.add(gseg);
+    d->hcls = pk.add(cls);
+    d->hcoef = pk.add(co);
+    d->hzs = pk.add(zs);
+    d->hsub = pk.add(sub);
+    d->hchunk = pk.add(stage_bounds(ch, cls));
+    d->hseg = pk.add(seg);
+    d->hsegp = pk.add(segp);
     d->n_chunks = (int)ch.size() - 1;
-    h.dev[dev] = d.release();
-    return h.dev[dev];
+    pk.finish(*im);
+    h.img = im;
+    return *h.img;
 }
 
-const DevicePool *device_pool(const Pool &p, int dev) {
-    std::lock_guard<std::mutex> lk(p.mu);
-    if ((int)p.dev.size() <= dev) p.dev.resize(dev + 1, nullptr);
-    if (p.dev[dev]) return p.dev[dev];
-    std::unique_ptr<DevicePool> d(new DevicePool());
-    d->device = dev;
+// The device tables of a pool in one pinned host image (caller holds p.mu).
+const TableImage &pool_image_locked(const Pool &p) {
+    if (p.img) return *p.img;
+    std::shared_ptr<TableImage> im = std::make_shared<TableImage>();
+    ImagePacker pk;
+    DevicePool *d = &im->pool;
     // pool order (pair kernels): each operator's strings padded with zero
     // strings to a multiple of kPairGroup, read kPairGroup at a time
     std::vector<HClass> ops(p.n_ops());
@@ -409,9 +451,9 @@ const DevicePool *device_pool(const Pool &p, int dev) {
         while ((terms.size() - s0) % kPairGroup) terms.push_back(HTerm{0.0, 0u, 0u});
         ops[k] = HClass{p.op_x[k], s0, (int32_t)terms.size(), p.kind[k]};
     }
-    d->pop = dev_upload(ops);
-    d->pterm = dev_upload(terms);
-    d->op_norm1 = dev_upload(p.op_norm1);
+    d->pop = pk.add(ops);
+    d->pterm = pk.add(terms);
+    d->op_norm1 = pk.add(p.op_norm1);
     // gradient screen schedule: operators and their strings re-laid out in
     // GOCP family order (families in creation order, members in assignment
     // order); each record keeps its pool index
@@ -459,14 +501,57 @@ const DevicePool *device_pool(const Pool &p, int dev) {
         rec.s1 = (int32_t)co.size();
         sop.push_back(rec);
     }
-    d->sop = dev_upload(sop);
-    d->scoef = dev_upload(co);
-    d->szs = dev_upload(zs);
-    d->psub = dev_upload(psub);
-    d->pchunk = dev_upload(stage_bounds(pch, sop));
-    d->pseg = dev_upload(seg);
+    d->sop = pk.add(sop);
+    d->scoef = pk.add(co);
+    d->szs = pk.add(zs);
+    d->psub = pk.add(psub);
+    d->pchunk = pk.add(stage_bounds(pch, sop));
+    d->pseg = pk.add(seg);
     d->n_chunks = (int)pch.size() - 1;
-    p.dev[dev] = d.release();
+    pk.finish(*im);
+    p.img = im;
+    return *p.img;
+}
+
+}  // namespace
+
+std::shared_ptr<const TableImage> ham_image(const Ham &h) {
+    std::lock_guard<std::mutex> lk(h.mu);
+    ham_image_locked(h);
+    return h.img;
+}
+
+std::shared_ptr<const TableImage> pool_image(const Pool &p) {
+    std::lock_guard<std::mutex> lk(p.mu);
+    pool_image_locked(p);
+    return p.img;
+}
+
+const DeviceHam *device_ham(const Ham &h, int dev) {
+    std::lock_guard<std::mutex> lk(h.mu);
+    if ((int)h.dev.size() <= dev) h.dev.resize(dev + 1, nullptr);
+    if (h.dev[dev]) return h.dev[dev];
+    const TableImage &im = ham_image_locked(h);
+    char *base = nullptr;
+    hip_check(hipMalloc(&base, im.bytes), "hipMalloc Hamiltonian tables");
+    const hipError_t e = hipMemcpy(base, im.host, im.bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) (void)hipFree(base);
+    hip_check(e, "hipMemcpy Hamiltonian tables");
+    h.dev[dev] = new DeviceHam(place_ham(im, base, dev));
+    return h.dev[dev];
+}
+
+const DevicePool *device_pool(const Pool &p, int dev) {
+    std::lock_guard<std::mutex> lk(p.mu);
+    if ((int)p.dev.size() <= dev) p.dev.resize(dev + 1, nullptr);
+    if (p.dev[dev]) return p.dev[dev];
+    const TableImage &im = pool_image_locked(p);
+    char *base = nullptr;
+    hip_check(hipMalloc(&base, im.bytes), "hipMalloc pool tables");
+    const hipError_t e = hipMemcpy(base, im.host, im.bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) (void)hipFree(base);
+    hip_check(e, "hipMemcpy pool tables");
+    p.dev[dev] = new DevicePool(place_pool(im, base, dev));
     return p.dev[dev];
 }
 
@@ -534,13 +619,28 @@ InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi, boo
 
 InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const Pool *p, void *psi,
                   double2 *sigma_override, bool upload) {
-    InstDev I;
-    std::memset(&I, 0, sizeof(I));
+    const DeviceHam *dh = nullptr;
+    const DevicePool *dp = nullptr;
     if (h) {
-        const DeviceHam *dh = upload ? device_ham(*h, device) : device_ham_resident(*h, device);
+        dh = upload ? device_ham(*h, device) : device_ham_resident(*h, device);
         if (!dh)
             throw Error(GOCP_EINVAL, "the Hamiltonian's tables are not on this device yet (a device call "
                                      "that takes the Hamiltonian, e.g. energy, uploads them)");
+    }
+    if (p) {
+        dp = upload ? device_pool(*p, device) : device_pool_resident(*p, device);
+        if (!dp)
+            throw Error(GOCP_EINVAL, "the pool's tables are not on this device yet (a device call that "
+                                     "takes the pool, e.g. pool_gradients, uploads them)");
+    }
+    return make_desc_at(ip, b, dh, dp, psi, sigma_override);
+}
+
+InstDev make_desc_at(const InstPlan &ip, char *b, const DeviceHam *dh, const DevicePool *dp, void *psi,
+                     double2 *sigma_override) {
+    InstDev I;
+    std::memset(&I, 0, sizeof(I));
+    if (dh) {
         I.hcls = dh->hcls;
         I.hcoef = dh->hcoef;
         I.hzs = dh->hzs;
@@ -555,11 +655,7 @@ InstDev make_desc(int device, const InstPlan &ip, char *b, const Ham *h, const P
         I.hgseg = dh->hgseg;
         I.n_hchunks = dh->n_chunks;
     }
-    if (p) {
-        const DevicePool *dp = upload ? device_pool(*p, device) : device_pool_resident(*p, device);
-        if (!dp)
-            throw Error(GOCP_EINVAL, "the pool's tables are not on this device yet (a device call that "
-                                     "takes the pool, e.g. pool_gradients, uploads them)");
+    if (dp) {
         I.pop = dp->pop;
         I.pterm = dp->pterm;
         I.op_norm1 = dp->op_norm1;

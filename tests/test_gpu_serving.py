@@ -178,3 +178,45 @@ def test_shutdown_with_requests_in_flight(g, ctx):
     time.sleep(0.01)
     srv.close()                                   # cancels; must not hang or fault
     assert True
+
+
+def test_admission_failure_ends_that_request_only(g, ctx, monkeypatch):
+    """The server's second admission is made to fail from the host (the test
+    hook GOCP_TEST_FAIL_ADMISSION): that request ends with GOCP_EDEVICE, every
+    other request completes normally, and no poll waits forever."""
+    _say("[serve] admission failure")
+    reqs = [_req(g, 8, "jw" if i % 2 else "bk", 110 + i) for i in range(4)]
+    monkeypatch.setenv("GOCP_TEST_FAIL_ADMISSION", "2")
+    srv = g.Server(ctx, hbm_budget_bytes=1 << 28, max_slots=8, dtype=1, iters_per_step=2)
+    monkeypatch.delenv("GOCP_TEST_FAIL_ADMISSION")
+    tickets = [srv.submit(r["H"], r["P"], 30, 1e-3) for r in reqs]
+    res = _drain(srv, tickets)
+    st = srv.stats()
+    srv.close()
+    codes = [res[t][0] for t in tickets]
+    assert codes.count(-3) == 1 and codes.count(0) == 3, codes
+    assert st["bytes_in_use"] == 0
+    for r, t in zip(reqs, tickets):
+        if res[t][0] == 0:
+            _same(res[t][1], _solo(g, ctx, r, 30, 1e-3, torch.complex64))
+
+
+def test_bytes_in_use_is_the_admitted_blocks(g, ctx):
+    """bytes_in_use counts each admitted request's arena block (its workspace
+    and its own copy of the Hamiltonian's and pool's device tables) and drops
+    to zero once the requests have finished."""
+    _say("[serve] bytes in use")
+    r = _req(g, 12, "jw", 120)
+    block = g.request_footprint(r["H"], r["P"], 400, 1)
+    srv = g.Server(ctx, hbm_budget_bytes=1 << 28, max_slots=4, dtype=1, iters_per_step=1)
+    t = srv.submit(r["H"], r["P"], 400, 0.0)
+    seen = set()
+    t0 = time.time()
+    while srv.poll(t) is None:
+        seen.add(srv.stats()["bytes_in_use"])
+        assert time.time() - t0 < 60
+    st = srv.stats()
+    srv.close()
+    assert block in seen
+    assert max(seen) == block
+    assert st["bytes_in_use"] == 0 and st["completed"] == 1
