@@ -4,19 +4,25 @@
 A step is one ADAPT iteration of the 14-qubit, 6-electron (BeH2-sized,
 Tables I-II) synthetic system under Jordan-Wigner: gradient screen of the
 whole pool, selection, line search, fifth-order Taylor update and the new
-energy, with a complex64 statevector and FP64 accumulation.  The iteration
-runs device-resident as captured hipGraphs; W untimed steps precede exactly K
-timed steps.  Prints one JSON line.
+energy, with a complex64 statevector and FP64 accumulation.  W untimed
+iterations (captured-graph replays) precede exactly K timed iterations,
+launched directly so that the dominant kernel can be bracketed by its own
+dispatch timestamps (HIP events) in every n-th iteration.  Prints one JSON
+line.
 
-Also reported: the complex128 path on the same workload, the 64-instance
-batched form, the roofline of the dominant kernel (HIP-event timed), and the
-FP64 CPU oracle on a bounded sample of the same iterations.
+Also reported: the precision form against the FP64 oracle, the complex128
+path, the Bravyi-Kitaev mapping and a later window of the same run, the Pauli
+pool, the GOCP multi-operator step, the 64-instance batched form (with its
+roofline and an oracle baseline over worker processes) and the serving stream
+(512 requests after 32 warm-up ones, at 0.7x and 1.2x of capacity).  The CPU
+legs (the oracle) run first, before the GPU is touched.
 """
 
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -40,21 +46,86 @@ LANE_OPS_PER_STRING_AMP = 5
 # profiles/; keyed by (kernel, amplitudes per lane).  An entry is removed when
 # the kernel changes, until the counters are taken again.
 TRAFFIC_BYTES = {("k_energy_screen", 1): 2553596}
-# the dominant kernel is bracketed by HIP events in every 8th timed iteration
-# (events around every launch would slow the loop by several per cent)
-LIVE_SAMPLE_EVERY = 8
 
 
 def _say(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _pct(x, q):
+    import numpy as np
+    return round(float(np.percentile(np.asarray(x), q)), 3) if len(x) else None
+
+
+# ---------------------------------------------------------------- CPU legs (oracle)
+
+def _oracle_system(nq, ne, mapping, seed):
+    from oracle.mapping import hamiltonian, hf_index
+    from oracle.pool import pool_operators
+    from workloads import molecular_integrals
+    h1, eri, ec = molecular_integrals(nq // 2, seed)
+    return hamiltonian(h1, eri, ec, mapping), [A for _, _, A in pool_operators(nq, ne, mapping)], \
+        hf_index(nq, ne, mapping)
+
+
+def oracle_headline(nq, ne, mapping, seed, iters):
+    """The oracle on the first `iters` iterations of the headline system, one
+    host thread: the CPU baseline, and the reference of the precision form."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle.adapt import adapt_run
+    from oracle.statevec import apply_h, gradients
+    H, ops, hf = _oracle_system(nq, ne, mapping, seed)
+    psi0 = np.zeros(1 << nq, dtype=np.complex128)
+    psi0[hf] = 1.0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        o = adapt_run(H, ops, psi0, iters, keep_gradients=True)
+        dt = time.perf_counter() - t0
+        g_final = gradients(ops, o["psi"], apply_h(H, o["psi"]))
+    return dict(run=o, seconds=dt, g_final=g_final, H=H, ops=ops, psi0=psi0)
+
+
+def _oracle_task(spec):
+    """One worker's share of the batched baseline: one instance, `iters`
+    oracle iterations, one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle.adapt import adapt_run
+    nq, ne, mapping, seed, iters = spec
+    with threadpool_limits(limits=1):
+        H, ops, hf = _oracle_system(nq, ne, mapping, seed)
+        psi0 = np.zeros(1 << nq, dtype=np.complex128)
+        psi0[hf] = 1.0
+        t0 = time.perf_counter()
+        adapt_run(H, ops, psi0, iters)
+        return time.perf_counter() - t0
+
+
+def oracle_batch_baseline(iters, workers):
+    """The oracle over the 64 batched instances, `iters` iterations each, on
+    `workers` processes (forked before the GPU is touched)."""
+    import multiprocessing as mp
+    from workloads import batched_instances
+    specs = [(d["n_qubits"], d["n_electrons"], d["mapping"], d["seed"], iters) for d in batched_instances()]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        per = pool.map(_oracle_task, specs, chunksize=1)
+    wall = time.perf_counter() - t0
+    return {"value": round(len(specs) * iters / wall, 4), "unit": "instance-iters/s", "cores": workers,
+            "kind": "oracle", "sample": f"{iters} ADAPT iterations of each of the 64 batched instances, FP64 "
+                                        f"NumPy oracle on {workers} worker processes (one thread each); "
+                                        f"{wall:.1f} s wall, {sum(per):.1f} s of iterations (Hamiltonian and "
+                                        f"pool construction inside the wall time)"}
+
+
+# ---------------------------------------------------------------- GPU legs
+
 def _system(g, nq, ne, mapping, seed):
     from workloads import molecular_integrals
     h1, eri, ec = molecular_integrals(nq // 2, seed)
-    H = g.pauli_hamiltonian_load(h1, eri, ec, mapping)
-    P = g.pool_build(nq, ne, mapping)
-    return H, P
+    return g.pauli_hamiltonian_load(h1, eri, ec, mapping), g.pool_build(nq, ne, mapping)
 
 
 def _hf_state(g, ctx, nq, ne, mapping, dtype):
@@ -64,14 +135,37 @@ def _hf_state(g, ctx, nq, ne, mapping, dtype):
     return t
 
 
-def _amp_updates(nq, T, S, off, ops, subs):
+def _string_amps(nq, T, S, off, ops, subs):
     """Algorithmic Pauli-term amplitude updates of the given iterations:
-    2^n (3T + S + 2k + 5 k s) per iteration, k = strings of the chosen operator."""
+    2^n (3T + S + 2k + 5 k s) per iteration, k = strings of the chosen
+    operator (every string applied to every amplitude counts once, whatever
+    the kernels skip, fuse or factor)."""
     tot = 0
     for j, s in zip(ops, subs):
         k = int(off[j + 1] - off[j])
         tot += 3 * T + S + 2 * k + 5 * k * s
     return tot * (1 << nq)
+
+
+def run_adapt_timed(g, ctx, H, P, nq, ne, mapping, dtype, steps, warmup, schedule=0, timed_kernel=3,
+                    sample_every=2):
+    """Warm-up iterations (graph replays), then `steps` timed iterations
+    launched directly, with dispatch-timestamp events around the launch of
+    Batch.STEP_KERNELS[timed_kernel] in every sample_every-th of them.
+    Returns (batch, record, seconds, mean kernel ms, launches sampled)."""
+    import torch
+    psi = _hf_state(g, ctx, nq, ne, mapping, dtype)
+    b = g.Batch(ctx, [H], [P], [psi], max_iter=warmup + steps, use_graph=True, schedule=schedule)
+    if warmup:
+        b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, kms = b.step_timed(steps, timed_kernel, sample_every)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r = b.result(0)
+    r["psi"] = psi
+    return b, r, dt, kms, (steps + sample_every - 1) // sample_every
 
 
 def _fused_step_timing(g, ctx, P, nq, reps=200):
@@ -115,7 +209,6 @@ def _fused_step_timing(g, ctx, P, nq, reps=200):
                         g.taylor5_apply(ctx, P, j, t, psi)
             for _ in range(20):
                 step()
-            # median of five batches of reps / 5 steps
             per = []
             for _ in range(5):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -132,39 +225,99 @@ def _fused_step_timing(g, ctx, P, nq, reps=200):
     return res
 
 
-def run_adapt_timed(g, ctx, H, P, nq, ne, mapping, dtype, steps, warmup, schedule=0, timed_kernel=None,
-                    sample_every=LIVE_SAMPLE_EVERY):
-    """Warm-up iterations (graph replays), then the timed iterations.  With
-    timed_kernel (an index of Batch.STEP_KERNELS) the timed iterations are
-    launched directly with HIP events around every launch of that kernel, and
-    its mean duration over the timed region is returned as well."""
+def precision_block(g, ctx, H, P, nq, ne, mapping, oracle):
+    """The precision form against the FP64 oracle on the oracle's iterations:
+    the complex64 run free-running (its own selections) and operator-forced
+    (the oracle re-run with the complex64 run's selections when they differ);
+    energy error per iteration, infidelity of the final state, gradient error
+    of every pool operator at the final state, and the same for the complex128
+    GPU path."""
+    import numpy as np
     import torch
-    psi = _hf_state(g, ctx, nq, ne, mapping, dtype)
-    b = g.Batch(ctx, [H], [P], [psi], max_iter=warmup + steps, use_graph=True, schedule=schedule)
-    pre = {w: b.time_kernel(w, 20) for w in (0, 1)}   # dry launches: which tile kernel dominates
-    b.step(warmup)
+    from oracle.adapt import adapt_run
+    o = oracle["run"]
+    iters = len(o["ops"])
+    out = {"reference": f"FP64 NumPy oracle, first {iters} iterations from Hartree-Fock"}
+    for name, dt in (("complex64", torch.complex64), ("complex128", torch.complex128)):
+        psi = _hf_state(g, ctx, nq, ne, mapping, dt)
+        r = g.adapt_solve(ctx, H, P, psi, iters, schedule=1)
+        gg = g.pool_gradients(ctx, H, P, psi)
+        p = psi.to(torch.complex128).cpu().numpy()
+        p = p / np.linalg.norm(p)
+        same = r["ops"] == o["ops"]
+        blk = {"same_operator_sequence": same,
+               "max_abs_dE_ha": float(np.abs(np.asarray(o["energies"]) - r["energies"]).max()),
+               "infidelity_final": float(1.0 - abs(np.vdot(o["psi"], p)) ** 2),
+               "max_abs_dg_final": float(np.abs(oracle["g_final"] - gg).max()),
+               "max_abs_dgnorm": float(np.abs(np.asarray(o["gnorms"]) - r["gnorms"]).max())}
+        if same:
+            blk["operator_forced"] = "identical to free-running (same selections)"
+        else:
+            of = adapt_run(oracle["H"], oracle["ops"], oracle["psi0"], iters, forced_ops=list(r["ops"]) + [0])
+            blk["operator_forced"] = {"max_abs_dE_ha": float(np.abs(np.asarray(of["energies"]) - r["energies"]).max()),
+                                      "infidelity_final": float(1.0 - abs(np.vdot(of["psi"], p)) ** 2)}
+        out[name] = blk
+    out["targets"] = {"complex64_dE_ha": 1e-6, "complex64_fidelity": 1 - 1e-6, "complex128_dE_ha": 1e-10}
+    return out
+
+
+def batched_block(g, ctx, schedule, oracle_baseline):
+    """The 64-instance batch (24 x 10q, 24 x 12q, 16 x 14q, JW/BK alternating),
+    30 iterations each, launched directly with the energy+screen launch timed
+    by its dispatch timestamps in every other iteration; its algorithmic lane
+    operations over that mean give the batch's roofline fraction."""
+    import torch
+    from workloads import batched_instances
+    insts = batched_instances()
+    hams, pools, psis, meta = [], [], [], []
+    for d in insts:
+        Hi, Pi = _system(g, d["n_qubits"], d["n_electrons"], d["mapping"], d["seed"])
+        hams.append(Hi)
+        pools.append(Pi)
+        psis.append(_hf_state(g, ctx, d["n_qubits"], d["n_electrons"], d["mapping"], torch.complex64))
+        meta.append((d["n_qubits"], Hi.n_terms, Pi.n_strings, Pi.strings()[0]))
+    iters_b = 30
+    bb = g.Batch(ctx, hams, pools, psis, max_iter=iters_b, use_graph=True, schedule=schedule)
     torch.cuda.synchronize()
-    kernel_ms = None
     t0 = time.perf_counter()
-    if timed_kernel is None:
-        b.step(steps)
-    else:
-        k = timed_kernel(pre) if callable(timed_kernel) else timed_kernel
-        _, kernel_ms = b.step_timed(steps, k, sample_every)
-        kernel_ms = (k, kernel_ms)
+    _, kms = bb.step_timed(iters_b, 3, 2)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    r = b.result(0)
-    r["psi"] = psi
-    return b, r, dt, kernel_ms
+    dtb = time.perf_counter() - t0
+    sched_b = bb.schedule
+    ub = 0
+    for i in range(len(insts)):
+        ri = bb.result(i)
+        nqi, Ti, Si, offi = meta[i]
+        ub += _string_amps(nqi, Ti, Si, offi, ri["ops"], ri["substeps"])
+    bb.close()
+    sa = sum((1 << nqi) * (Ti + Si) for (nqi, Ti, Si, _) in meta)
+    lane_ops = LANE_OPS_PER_STRING_AMP * sa
+    achieved = lane_ops / (kms * 1e-3) / 1e12
+    ips = len(insts) * iters_b / dtb
+    out = {"instances": len(insts), "mix": "24x10q + 24x12q + 16x14q, JW/BK alternating",
+           "iterations_each": iters_b, "amps_per_lane": sched_b, "state": "complex64",
+           "seconds": round(dtb, 6), "instance_iters_per_s": round(ips, 2),
+           "algorithmic_amp_updates_per_s": float(f"{ub / dtb:.6g}"),
+           "roofline": {"bound": "alu", "kernel": "k_energy_screen (all 64 instances per launch)",
+                        "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TOPS, 4), "unit": "Tlane-op/s",
+                        "frac": round(achieved / VALU_PEAK_TOPS, 5), "avg_launch_us": round(kms * 1e3, 3),
+                        "launches_sampled": (iters_b + 1) // 2,
+                        "algorithmic_lane_ops_per_launch": int(lane_ops)}}
+    if oracle_baseline:
+        out["cpu_baseline"] = oracle_baseline
+        out["vs_cpu_oracle"] = round(ips / oracle_baseline["value"], 1)
+    return out
 
 
-def serving_bench(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, load=0.7, amps_per_lane=0,
-                  state="complex128"):
-    """Poisson stream of ADAPT solves (8-16 qubits, ||g|| < 1e-3, at most 300
-    iterations), states of the given precision.  Capacity is measured first with all
-    requests submitted at once; the timed stream then arrives at `load` times
-    that capacity.  Latency is submission to completion (library clock)."""
+def serving_block(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, loads=(0.7, 1.2), amps_per_lane=0,
+                  state="complex128", deadline_s=600.0):
+    """The serving workload: a Poisson stream of ADAPT solves (8-16 qubits,
+    ||g|| < 1e-3, at most 300 iterations).  Capacity is measured first with
+    every request submitted at once; the stream then arrives at each `load`
+    times that capacity, `warm` warm-up requests first (excluded from the
+    figures), then `n_req` measured ones.  Latency is submission to
+    completion on the library's clock; the baseline is sequential plain FP64
+    adapt_solve on the same device."""
     import numpy as np
     import torch
     from workloads import serving_requests
@@ -172,77 +325,96 @@ def serving_bench(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, load=0.7,
     reqs = []
     for d in specs:
         H, P = _system(g, d["n_qubits"], d["n_electrons"], d["mapping"], d["seed"])
-        reqs.append((d, H, P))
+        reqs.append((d, H, P, P.strings()[0]))
     tol, max_iter = 1e-3, 300
     budget = 8 << 30
+    code = 1 if state == "complex64" else 0
 
-    def drain(srv, tickets, done):
+    def drain(srv, tickets, done, t_end=None):
         for t in list(tickets):
             r = srv.poll(t)
             if r is not None:
                 done[t] = r
                 tickets.remove(t)
+        if t_end is not None and time.perf_counter() > t_end:
+            raise TimeoutError(f"serving: {len(tickets)} requests unfinished at the deadline")
+
+    def new_server():
+        return g.Server(ctx, budget, max_slots, dtype=code, iters_per_step=iters_per_step,
+                        amps_per_lane=amps_per_lane)
 
     # capacity: everything at once
-    code = 1 if state == "complex64" else 0
-    srv = g.Server(ctx, budget, max_slots, dtype=code, iters_per_step=iters_per_step,
-                   amps_per_lane=amps_per_lane)
+    srv = new_server()
     t0 = time.perf_counter()
-    pend = [srv.submit(H, P, max_iter, tol) for (_, H, P) in reqs[warm:]]
+    pend = [srv.submit(H, P, max_iter, tol) for (_, H, P, _) in reqs[warm:]]
     done = {}
     while pend:
-        drain(srv, pend, done)
+        drain(srv, pend, done, t0 + deadline_s)
         time.sleep(0.0005)
     cap = n_req / (time.perf_counter() - t0)
     srv.close()
+    work = 0
+    for (d, H, P, off), t in zip(reqs[warm:], [k for k in sorted(done)]):
+        rec = done[t][1]
+        if rec is not None:
+            work += _string_amps(d["n_qubits"], H.n_terms, P.n_strings, off, rec["ops"], rec["substeps"])
 
-    # timed Poisson stream at `load` x capacity (warm-up requests first)
-    rate = load * cap
-    srv = g.Server(ctx, budget, max_slots, dtype=code, iters_per_step=iters_per_step,
-                   amps_per_lane=amps_per_lane)
-    arrivals = [d["arrival_s"] / rate for (d, _, _) in reqs]
-    pend, done, meas = [], {}, []
-    t0 = time.perf_counter()
-    for k, (d, H, P) in enumerate(reqs):
-        while time.perf_counter() - t0 < arrivals[k]:
-            drain(srv, pend, done)
-            time.sleep(0.0002)
-        t = srv.submit(H, P, max_iter, tol)
-        pend.append(t)
-        if k >= warm:
-            meas.append(t)
-    t_first = None
-    while pend:
-        drain(srv, pend, done)
-        time.sleep(0.0005)
-    st = srv.stats()
-    srv.close()
-    lat = np.array([(done[t][2]["t_done_ns"] - done[t][2]["t_submit_ns"]) * 1e-6 for t in meas])
-    t_sub = min(done[t][2]["t_submit_ns"] for t in meas)
-    t_end = max(done[t][2]["t_done_ns"] for t in meas)
-    ok = sum(1 for t in meas if done[t][0] == 0)
-    conv = sum(1 for t in meas if done[t][1] is not None and done[t][1]["converged"])
+    runs = {}
+    for load in loads:
+        rate = load * cap
+        srv = new_server()
+        arrivals = [d["arrival_s"] / rate for (d, _, _, _) in reqs]
+        pend, done, meas = [], {}, []
+        t0 = time.perf_counter()
+        t_end = t0 + deadline_s
+        for k, (d, H, P, _) in enumerate(reqs):
+            while time.perf_counter() - t0 < arrivals[k]:
+                drain(srv, pend, done, t_end)
+                time.sleep(0.0002)
+            t = srv.submit(H, P, max_iter, tol)
+            pend.append(t)
+            if k >= warm:
+                meas.append((t, d["n_qubits"]))
+        while pend:
+            drain(srv, pend, done, t_end)
+            time.sleep(0.0005)
+        st = srv.stats()
+        srv.close()
+        lat = {t: (done[t][2]["t_done_ns"] - done[t][2]["t_submit_ns"]) * 1e-6 for t, _ in meas}
+        t_sub = min(done[t][2]["t_submit_ns"] for t, _ in meas)
+        t_fin = max(done[t][2]["t_done_ns"] for t, _ in meas)
+        per_q = {}
+        for nq in sorted({q for _, q in meas}):
+            ls = [lat[t] for t, q in meas if q == nq]
+            per_q[str(nq)] = {"requests": len(ls), "p50_ms": _pct(ls, 50), "p99_ms": _pct(ls, 99)}
+        runs[f"{load:g}x"] = {
+            "offered_rate_hz": round(rate, 2),
+            "solves_per_s": round(n_req / ((t_fin - t_sub) * 1e-9), 2),
+            "p50_ms": _pct(list(lat.values()), 50), "p99_ms": _pct(list(lat.values()), 99),
+            "per_qubit_count": per_q,
+            "completed_ok": sum(1 for t, _ in meas if done[t][0] == 0),
+            "converged": sum(1 for t, _ in meas if done[t][1] is not None and done[t][1]["converged"]),
+            "server_steps": st["steps"]}
 
     # sequential plain FP64: one adapt_solve at a time, complex128
     t0 = time.perf_counter()
-    nseq = 0
-    for (d, H, P) in reqs[warm:]:
+    for (d, H, P, _) in reqs[warm:]:
         psi = _hf_state(g, ctx, d["n_qubits"], d["n_electrons"], d["mapping"], torch.complex128)
         g.adapt_solve(ctx, H, P, psi, max_iter, grad_tol=tol)
-        nseq += 1
     torch.cuda.synchronize()
-    seq = nseq / (time.perf_counter() - t0)
+    seq = n_req / (time.perf_counter() - t0)
+    cap_dt = n_req / cap
+    achieved = LANE_OPS_PER_STRING_AMP * work / cap_dt / 1e12
     return {"requests": n_req, "warmup_requests": warm, "qubits": "uniform over {8,10,12,14,16}",
             "grad_tol": tol, "max_iter": max_iter, "state": state, "max_slots": max_slots,
-            "iters_per_step": iters_per_step,
-            "amps_per_lane": amps_per_lane if amps_per_lane else "adaptive",
-            "hbm_budget_bytes": budget,
-            "capacity_solves_per_s": round(cap, 2), "offered_rate_hz": round(rate, 2),
-            "solves_per_s": round(n_req / ((t_end - t_sub) * 1e-9), 2),
-            "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "completed_ok": ok, "converged": conv, "server_steps": st["steps"],
-            "sequential_fp64_solves_per_s": round(seq, 2)}
+            "iters_per_step": iters_per_step, "amps_per_lane": amps_per_lane if amps_per_lane else "adaptive",
+            "hbm_budget_bytes": budget, "capacity_solves_per_s": round(cap, 2),
+            "loads": runs, "sequential_fp64_solves_per_s": round(seq, 2),
+            "capacity_vs_sequential_fp64": round(cap / seq, 3),
+            "capacity_roofline": {"bound": "alu", "what": "algorithmic lane operations of every served "
+                                  "iteration over the capacity run's wall time (all kernels, idle gaps included)",
+                                  "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TOPS, 4),
+                                  "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 5)}}
 
 
 def main():
@@ -250,18 +422,24 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-sample-iters", type=int, default=8,
-                    help="oracle iterations timed for the CPU baseline (0 disables it)")
-    ap.add_argument("--no-forms", action="store_true", help="skip the c128 and batched extras")
-    ap.add_argument("--serve-requests", type=int, default=96,
-                    help="measured requests of the serving stream (after 16 warm-up requests)")
-    ap.add_argument("--sample-every", type=int, default=LIVE_SAMPLE_EVERY,
-                    help="HIP events around every n-th launch of the dominant kernel in the timed region")
+    ap.add_argument("--cpu-sample-iters", type=int, default=12,
+                    help="oracle iterations of the headline system: the CPU baseline and the precision "
+                         "form's reference (0 disables both)")
+    ap.add_argument("--no-forms", action="store_true", help="only the headline (and the CPU legs)")
+    ap.add_argument("--serve-requests", type=int, default=512, help="measured requests of the serving stream")
+    ap.add_argument("--serve-warmup", type=int, default=32, help="warm-up requests before the measured ones")
+    ap.add_argument("--sample-every", type=int, default=0,
+                    help="dispatch-timestamp events around every n-th launch of the dominant kernel in the "
+                         "timed region (0: every 4th up to 100 steps, else every 8th; each sample costs the "
+                         "loop a few microseconds)")
     ap.add_argument("--schedule", type=int, default=0, choices=(0, 1, 2, 4),
                     help="amplitudes per lane of the tile kernels (0: autotune)")
     ap.add_argument("--serve-amps-per-lane", type=int, default=0, choices=(0, 1, 2, 4),
                     help="server schedule (0: chosen from the active set)")
     ap.add_argument("--serve-state", default="complex128", choices=("complex64", "complex128"))
+    ap.add_argument("--oracle-workers", type=int, default=0,
+                    help="worker processes of the batched oracle baseline (0: min(16, CPUs))")
+    ap.add_argument("--batch-oracle-iters", type=int, default=4)
     ap.add_argument("--fused-step-only", action="store_true",
                     help="time only the GOCP multi-operator step against single chains (kernel profiling)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -276,11 +454,29 @@ def main():
     if args.steps <= 0 or args.warmup < 0:
         print("need --steps > 0 and --warmup >= 0", file=sys.stderr)
         sys.exit(2)
+    # every 4th launch up to 100 steps (5 samples at 20), every 8th beyond
+    every = args.sample_every or (4 if args.steps <= 100 else 8)
+
+    from workloads import CONFIGS
+    cfg = CONFIGS["c3_14q"]
+    nq, ne, seed = cfg["n_qubits"], cfg["n_electrons"], cfg["seed"]
+    mapping = "jw"
+
+    # CPU legs first: nothing has touched the GPU yet, so the oracle worker
+    # processes can be forked safely
+    oracle = None
+    if args.cpu_sample_iters > 0 and not args.fused_step_only:
+        _say(f"[bench] CPU oracle: {args.cpu_sample_iters} iterations at 14q (one thread)")
+        oracle = oracle_headline(nq, ne, mapping, seed, args.cpu_sample_iters)
+    batch_oracle = None
+    if not args.no_forms and not args.fused_step_only and args.batch_oracle_iters > 0:
+        workers = args.oracle_workers or min(16, os.cpu_count() or 1)
+        _say(f"[bench] CPU oracle: batched instances on {workers} workers")
+        batch_oracle = oracle_batch_baseline(args.batch_oracle_iters, workers)
 
     import numpy as np
     import torch
     import paper_2607_15906_amd as g
-    from workloads import CONFIGS, batched_instances
 
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
@@ -290,9 +486,6 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    cfg = CONFIGS["c3_14q"]
-    nq, ne, seed = cfg["n_qubits"], cfg["n_electrons"], cfg["seed"]
-    mapping = "jw"
     ctx = g.Context(0)
     H, P = _system(g, nq, ne, mapping, seed)
     if args.fused_step_only:
@@ -302,33 +495,31 @@ def main():
     T, C, S, M = H.n_terms, H.n_classes, P.n_strings, P.n_ops
 
     _say(f"[bench] 14q c64: {args.warmup} warmup + {args.steps} timed ADAPT iterations")
-    # the dominant tile kernel (k_energy_screen: STEP_KERNELS[3], or k_line_hvw:
-    # [1]) from dry timing-hook launches; its live duration over the timed
-    # region then feeds the roofline
-    b, r, dt, live = run_adapt_timed(g, ctx, H, P, nq, ne, mapping, torch.complex64, args.steps,
-                                     args.warmup, schedule=args.schedule,
-                                     timed_kernel=lambda pre: 3 if pre[0] >= pre[1] else 1,
-                                     sample_every=args.sample_every)
-    sched = b.schedule
+    # which tile kernel dominates, from dry timing-hook launches on a scratch batch
+    psi_d = _hf_state(g, ctx, nq, ne, mapping, torch.complex64)
+    bd = g.Batch(ctx, [H], [P], [psi_d], max_iter=1, schedule=args.schedule)
+    pre = {w: bd.time_kernel(w, 20) for w in (0, 1)}
+    sched = bd.schedule
+    bd.close()
+    dom = 3 if pre[0] >= pre[1] else 1
+    b, r, dt, kms, nsamp = run_adapt_timed(g, ctx, H, P, nq, ne, mapping, torch.complex64, args.steps,
+                                           args.warmup, schedule=sched, timed_kernel=dom, sample_every=every)
     w0, w1 = args.warmup, args.warmup + args.steps
-    iters = r["n_iter"]
-    if iters != w1:
-        raise RuntimeError(f"expected {w1} iterations, ran {iters}")
+    if r["n_iter"] != w1:
+        raise RuntimeError(f"expected {w1} iterations, ran {r['n_iter']}")
     ips = args.steps / dt
-    upd = _amp_updates(nq, T, S, off, r["ops"][w0:w1], r["substeps"][w0:w1])
+    upd = _string_amps(nq, T, S, off, r["ops"][w0:w1], r["substeps"][w0:w1])
 
     # roofline of the dominant kernel, which is bound by VALU issue: the
     # algorithmic lane operations per launch (LANE_OPS_PER_STRING_AMP per
     # string-amplitude: H psi and the screen for k_energy_screen, two H
     # applications for k_line_hvw) over its mean launch duration, measured
-    # live with HIP events over the timed region; beside it the FP64 view (one
-    # signed add per string-amplitude, a real-by-complex multiply-add (4
-    # flops) per (class or operator, amplitude), and the dot products)
+    # live over the timed region; beside it the FP64 view (one signed add per
+    # string-amplitude, a real-by-complex multiply-add (4 flops) per (class or
+    # operator, amplitude), and the dot products)
     dim = 1 << nq
     string_amps = {3: dim * (T + S), 1: 2 * dim * T}
-    flops = {3: dim * (T + 4 * C + 4) + dim * (S + 4 * M),   # H psi + energy + screen partials
-             1: dim * (T + 8 * C + 12)}                      # H v and H w + three dots
-    dom, kms = live
+    flops = {3: dim * (T + 4 * C + 4) + dim * (S + 4 * M), 1: dim * (T + 8 * C + 12)}
     name = g.Batch.STEP_KERNELS[dom]
     lane_ops = LANE_OPS_PER_STRING_AMP * string_amps[dom]
     achieved = lane_ops / (kms * 1e-3) / 1e12
@@ -339,8 +530,7 @@ def main():
     roofline = {"bound": "alu", "kernel": name, "achieved": round(achieved, 4),
                 "peak": round(VALU_PEAK_TOPS, 4), "unit": "Tlane-op/s",
                 "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": traffic,
-                "avg_launch_us": round(kms * 1e3, 3),
-                "launches_sampled": (args.steps + args.sample_every - 1) // args.sample_every,
+                "avg_launch_us": round(kms * 1e3, 3), "launches_sampled": nsamp,
                 "algorithmic_string_amps_per_launch": int(string_amps[dom]),
                 "algorithmic_lane_ops_per_launch": int(lane_ops),
                 "fp64_view": {"achieved_tflops": round(achieved_fp64, 4), "peak_tflops": FP64_PEAK_TFLOPS,
@@ -355,44 +545,59 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "ADAPT iteration, 14 qubits / 6 electrons, Jordan-Wigner, "
-                               "complex64 state with FP64 accumulation",
+                               "complex64 state storage with FP64 arithmetic and reductions",
                    "n_qubits": nq, "n_electrons": ne, "mapping": mapping, "integral_seed": seed,
                    "pauli_terms": T, "xmask_classes": C, "pool_ops": M, "pool_strings": S,
-                   "state": "complex64", "graph_replay": True, "amps_per_lane": sched},
-        "amp_updates_per_s": float(f"{upd / dt:.6g}"),
+                   "state": "complex64", "timed_iterations": f"{w0}..{w1 - 1} from Hartree-Fock",
+                   "launch": "warm-up as captured hipGraph replays, timed iterations as direct launches",
+                   "amps_per_lane": sched},
+        "algorithmic_amp_updates_per_s": float(f"{upd / dt:.6g}"),
+        "algorithmic_amp_updates_note": "2^n (3T + S + 2k + 5ks) string-amplitudes per iteration, whether or "
+                                        "not the kernels skip, fuse or factor them",
         "final_energy": float(r["energies"][-1]),
         "roofline": roofline,
     }
 
+    if oracle is not None:
+        _say("[bench] precision form against the oracle")
+        out["precision"] = precision_block(g, ctx, H, P, nq, ne, mapping, oracle)
+
     if not args.no_forms:
         _say("[bench] 14q c128 path")
-        b2, r2, dt2, _ = run_adapt_timed(g, ctx, H, P, nq, ne, mapping, torch.complex128,
-                                         args.steps, args.warmup, schedule=sched)
+        b2, r2, dt2, _, _ = run_adapt_timed(g, ctx, H, P, nq, ne, mapping, torch.complex128,
+                                            args.steps, args.warmup, schedule=sched, sample_every=every)
         b2.close()
-        u2 = _amp_updates(nq, T, S, off, r2["ops"][w0:w1], r2["substeps"][w0:w1])
-        same_ops = r2["ops"] == r["ops"]
-        p64 = r["psi"].to(torch.complex128)
-        fid = float(torch.abs(torch.vdot(r2["psi"], p64)) ** 2 /
-                    (torch.vdot(p64, p64).real * torch.vdot(r2["psi"], r2["psi"]).real))
-        # precision form: gradients of the final complex64 state against those of
-        # the complex128 state, both on the device with FP64 accumulation
-        g64 = g.pool_gradients(ctx, H, P, r["psi"])
-        g128 = g.pool_gradients(ctx, H, P, r2["psi"])
+        u2 = _string_amps(nq, T, S, off, r2["ops"][w0:w1], r2["substeps"][w0:w1])
         out["complex128_state"] = {"iters_per_s": round(args.steps / dt2, 3),
-                                   "amp_updates_per_s": float(f"{u2 / dt2:.6g}"),
-                                   "same_operator_sequence": same_ops,
-                                   "max_abs_dE_vs_c64": float(np.abs(r2["energies"] - r["energies"]).max()),
-                                   "final_state_fidelity_c64": fid,
-                                   "max_abs_dg_final_c64": float(np.abs(g64 - g128).max())}
+                                   "algorithmic_amp_updates_per_s": float(f"{u2 / dt2:.6g}"),
+                                   "same_operator_sequence_as_c64": r2["ops"] == r["ops"],
+                                   "max_abs_dE_vs_c64": float(np.abs(r2["energies"] - r["energies"]).max())}
+
+        _say("[bench] 14q c64 under Bravyi-Kitaev")
+        Hb, Pb = _system(g, nq, ne, "bk", seed)
+        b4, r4, dt4, _, _ = run_adapt_timed(g, ctx, Hb, Pb, nq, ne, "bk", torch.complex64, args.steps,
+                                            args.warmup, schedule=sched, sample_every=every)
+        b4.close()
+        out["bravyi_kitaev_14q"] = {"iters_per_s": round(args.steps / dt4, 3), "state": "complex64",
+                                    "same_operator_sequence_as_jw": r4["ops"] == r["ops"],
+                                    "max_abs_dE_vs_jw": float(np.abs(r4["energies"] - r["energies"]).max())}
+
+        _say("[bench] later window: iterations 30-59")
+        b5, r5, dt5, _, _ = run_adapt_timed(g, ctx, H, P, nq, ne, mapping, torch.complex64, 30, 30,
+                                            schedule=sched, sample_every=every)
+        b5.close()
+        out["later_window_14q"] = {"iterations": "30..59 from Hartree-Fock", "state": "complex64",
+                                   "iters_per_s": round(30 / dt5, 3)}
 
         _say("[bench] Pauli pool: 14q c64")
         PP = g.pool_build_pauli(nq, ne, mapping)
         offp = PP.strings()[0]
-        b3, r3, dt3, _ = run_adapt_timed(g, ctx, H, PP, nq, ne, mapping, torch.complex64, args.steps,
-                                         args.warmup, schedule=0)
+        b3, r3, dt3, _, _ = run_adapt_timed(g, ctx, H, PP, nq, ne, mapping, torch.complex64, args.steps,
+                                            args.warmup, schedule=0, sample_every=every)
         out["pauli_pool"] = {"pool_ops": PP.n_ops, "pool_strings": PP.n_strings, "state": "complex64",
                              "amps_per_lane": b3.schedule, "iters_per_s": round(args.steps / dt3, 3),
-                             "amp_updates_per_s": float(f"{_amp_updates(nq, T, PP.n_strings, offp, r3['ops'][w0:w1], r3['substeps'][w0:w1]) / dt3:.6g}"),
+                             "algorithmic_amp_updates_per_s": float(
+                                 f"{_string_amps(nq, T, PP.n_strings, offp, r3['ops'][w0:w1], r3['substeps'][w0:w1]) / dt3:.6g}"),
                              "final_energy": float(r3["energies"][-1])}
         b3.close()
 
@@ -400,58 +605,20 @@ def main():
         out["gocp_fused_step"] = _fused_step_timing(g, ctx, P, nq)
 
         _say("[bench] batched form: 64 instances x 30 iterations")
-        insts = batched_instances()
-        hams, pools, psis, meta = [], [], [], []
-        for d in insts:
-            Hi, Pi = _system(g, d["n_qubits"], d["n_electrons"], d["mapping"], d["seed"])
-            hams.append(Hi); pools.append(Pi)
-            psis.append(_hf_state(g, ctx, d["n_qubits"], d["n_electrons"], d["mapping"], torch.complex64))
-            meta.append((d["n_qubits"], Hi.n_terms, Pi.n_strings, Pi.strings()[0]))
-        iters_b = 30
-        bb = g.Batch(ctx, hams, pools, psis, max_iter=iters_b, use_graph=True, schedule=args.schedule)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        bb.step(iters_b)
-        torch.cuda.synchronize()
-        dtb = time.perf_counter() - t0
-        sched_b = bb.schedule
-        ub = 0
-        for i in range(len(insts)):
-            ri = bb.result(i)
-            nqi, Ti, Si, offi = meta[i]
-            ub += _amp_updates(nqi, Ti, Si, offi, ri["ops"], ri["substeps"])
-        bb.close()
-        out["batched"] = {"instances": len(insts), "mix": "24x10q + 24x12q + 16x14q, JW/BK alternating",
-                          "iterations_each": iters_b, "amps_per_lane": sched_b,
-                          "seconds": round(dtb, 6),
-                          "instance_iters_per_s": round(len(insts) * iters_b / dtb, 2),
-                          "amp_updates_per_s": float(f"{ub / dtb:.6g}")}
+        out["batched"] = batched_block(g, ctx, args.schedule, batch_oracle)
 
-        _say("[bench] serving form: Poisson stream of ADAPT solves")
-        out["serving"] = serving_bench(g, ctx, n_req=args.serve_requests, warm=16,
+        _say(f"[bench] serving form: {args.serve_warmup} + {args.serve_requests} requests")
+        out["serving"] = serving_block(g, ctx, n_req=args.serve_requests, warm=args.serve_warmup,
                                        amps_per_lane=args.serve_amps_per_lane, state=args.serve_state)
 
-    if args.cpu_sample_iters > 0:
-        _say(f"[bench] CPU oracle baseline: {args.cpu_sample_iters} iterations at 14q")
-        from threadpoolctl import threadpool_limits
-        from oracle.mapping import hamiltonian, hf_index
-        from oracle.pool import pool_operators
-        from oracle.adapt import adapt_run
-        from workloads import molecular_integrals
-        h1, eri, ec = molecular_integrals(nq // 2, seed)
-        Ho = hamiltonian(h1, eri, ec, mapping)
-        ops = [A for _, _, A in pool_operators(nq, ne, mapping)]
-        psi0 = np.zeros(1 << nq, dtype=np.complex128)
-        psi0[hf_index(nq, ne, mapping)] = 1.0
-        with threadpool_limits(limits=1):
-            t0 = time.perf_counter()
-            adapt_run(Ho, ops, psi0, args.cpu_sample_iters)
-            dto = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(args.cpu_sample_iters / dto, 5), "unit": "iters/s",
-                               "cores": 1, "kind": "oracle",
-                               "sample": f"first {args.cpu_sample_iters} ADAPT iterations of the same "
-                                         f"14q JW system from Hartree-Fock, FP64 NumPy oracle, "
-                                         f"{dto:.1f} s on {os.cpu_count()} host CPUs (1 thread used)"}
+    if oracle is not None:
+        n_it = args.cpu_sample_iters
+        out["cpu_baseline"] = {"value": round(n_it / oracle["seconds"], 5), "unit": "iters/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"first {n_it} ADAPT iterations of the same 14q JW system from "
+                                         f"Hartree-Fock, FP64 NumPy oracle, {oracle['seconds']:.1f} s on one of "
+                                         f"{os.cpu_count()} host CPUs"}
+        out["vs_cpu_oracle"] = round(ips / out["cpu_baseline"]["value"], 1)
     print(json.dumps(out), flush=True)
 
 

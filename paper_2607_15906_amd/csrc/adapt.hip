@@ -155,6 +155,13 @@ struct gocp_batch {
     int max_iter = 0;
     bool use_graph = true;
     int issued = 0;
+    // events of gocp_batch_step_timed, created with the batch (2 per sampled
+    // launch and the two ends) so that a timed call creates and destroys none
+    std::vector<hipEvent_t> tev;
+    ~gocp_batch() {
+        for (hipEvent_t e : tev)
+            if (e) (void)hipEventDestroy(e);
+    }
 };
 
 using namespace gocp;
@@ -196,6 +203,8 @@ int gocp_batch_create(gocp_ctx *ctx, int32_t n, const gocp_ham *const *hams,
     b->group.dtype = dtype;
     b->max_iter = params->max_iter;
     b->use_graph = params->use_graph != 0;
+    b->tev.assign(2 * (size_t)std::min(std::max(params->max_iter, 0), 512) + 2, nullptr);
+    for (hipEvent_t &e : b->tev) hip_check(hipEventCreate(&e), "hipEventCreate");
     for (int i = 0; i < n; ++i) {
         if (!psi_dev[i]) throw Error(GOCP_EINVAL, "null state pointer");
         b->owned.emplace_back(instance_create(ctx, as_ham(hams[i]), as_pool(pools[i]), psi_dev[i],
@@ -231,12 +240,15 @@ int gocp_batch_step_timed(gocp_batch *b, int32_t n_iter, int32_t kernel, int32_t
     static const int kids[5] = {K_LINE_VW, K_LINE_HVW, K_TAYLOR, K_ENERGY_SCREEN, K_SCREEN_SUM1};
     if (kernel < 0 || kernel > 4) throw Error(GOCP_EINVAL, "kernel must be 0..4");
     hipStream_t s = b->group.ctx->user_stream;
-    // events for the sampled launches and the two ends only (creating and
-    // destroying one per iteration costs host time of the same order as the
-    // iteration itself)
+    // events for the sampled launches and the two ends, from the batch's set
+    // (grown here only for more iterations than the batch was created for)
     const int n_samp = (n_iter + every - 1) / every;
-    std::vector<hipEvent_t> ev(2 * (size_t)n_samp + 2);
-    for (hipEvent_t &e : ev) hip_check(hipEventCreate(&e), "hipEventCreate");
+    while (b->tev.size() < 2 * (size_t)n_samp + 2) {
+        hipEvent_t e = nullptr;
+        hip_check(hipEventCreate(&e), "hipEventCreate");
+        b->tev.push_back(e);
+    }
+    const std::vector<hipEvent_t> &ev = b->tev;
     hip_check(hipEventRecord(ev[2 * n_samp], s), "hipEventRecord");
     int sampled = 0;
     for (int i = 0; i < n_iter; ++i) {
@@ -259,7 +271,6 @@ int gocp_batch_step_timed(gocp_batch *b, int32_t n_iter, int32_t kernel, int32_t
     }
     float tot = 0.f;
     hip_check(hipEventElapsedTime(&tot, ev[2 * n_samp], ev[2 * n_samp + 1]), "hipEventElapsedTime");
-    for (hipEvent_t &e : ev) (void)hipEventDestroy(e);
     b->issued += n_iter;
     *total_ms = tot;
     *kernel_ms = k / sampled;
