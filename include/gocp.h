@@ -296,6 +296,53 @@ int adapt_solve(gocp_ctx *ctx, const gocp_ham *h, const gocp_pool *p, void *psi_
                 const gocp_adapt_params *params, gocp_adapt_result *res);
 
 /* ---------------------------------------------------------------------
+ * ADAPT with full re-optimisation (textbook ADAPT, Sec. II.B): after each
+ * appended operator every angle of the ansatz is optimised again, instead of
+ * freezing the earlier ones.  The ansatz state is the chain of layers of
+ * Eq. 5, psi(theta) = L_k(theta_k) ... L_1(theta_1) psi_0, each layer the
+ * substepped O(5) Taylor propagator of Eq. 6 of its generator,
+ * L = T5(theta/s)^s with s = max(1, ceil(max(|theta|, pi) ||A||_1 / 0.5))
+ * (constant for |theta| <= pi, so the energy is smooth in the angles).  The
+ * energy (Eq. 1) and its exact gradient come from one forward pass over the
+ * layers (intermediate states kept on the device), H psi, and one adjoint
+ * backward pass; BFGS (host) optimises the angles from the previous ones and
+ * 0 for the new angle: direction -Hinv g, backtracking from step 1 by halving
+ * until E decreases by 1e-4 t g.p (up to 1e-14 (1 + |E|) of rounding), the
+ * update skipped when s.y <= 1e-12 |s| |y|; it stops when max |dE/dtheta| <
+ * bfgs_gtol, after bfgs_max_iter steps or when the line search fails.  The
+ * screen (Eq. 4) and the selection (as in adapt_solve) run on the optimised
+ * state; convergence when ||g||_2 < grad_tol.
+ * ------------------------------------------------------------------- */
+typedef struct {
+    double grad_tol;        /* stop when ||g||_2 < grad_tol (0: never)               */
+    int32_t max_iter;       /* operators appended at most                            */
+    int32_t bfgs_max_iter;  /* BFGS steps per re-optimisation (<= 0: 200)            */
+    double bfgs_gtol;       /* BFGS stops at max |dE/dtheta| < bfgs_gtol (<= 0: 1e-8) */
+} gocp_reopt_params;
+
+typedef struct {
+    int32_t n_iter;         /* operators appended                                    */
+    int32_t converged;      /* 1 if stopped by grad_tol                              */
+    double *energies;       /* caller array, max_iter+1: E at the optimised angles   */
+    int32_t *ops;           /* caller array, max_iter: chosen pool indices           */
+    double *thetas;         /* caller array, max_iter: the final angles, one a layer */
+    double *gnorms;         /* caller array, max_iter+1: ||g||_2 of each screen      */
+    int32_t *bfgs_steps;    /* caller array, max_iter: BFGS steps (may be NULL)      */
+    int32_t *bfgs_evals;    /* caller array, max_iter: energy+gradient evaluations
+                               (may be NULL)                                         */
+} gocp_reopt_result;
+
+/*
+ * adapt_reopt_solve -- from the state in psi_dev (normally the HF state);
+ * psi_dev receives the final normalised state.  Allocates its workspace
+ * ((max_iter + 1) states of the dtype, two complex128 vectors) for the call.
+ * Synchronises; fills *res.  Errors: ESHAPE, EINVAL (null arrays, max_iter
+ * < 0), ENUMERIC.
+ */
+int adapt_reopt_solve(gocp_ctx *ctx, const gocp_ham *h, const gocp_pool *p, void *psi_dev, int dtype,
+                      const gocp_reopt_params *params, gocp_reopt_result *res);
+
+/* ---------------------------------------------------------------------
  * Batched form: many independent ADAPT problems advanced in lock-step.
  * Every kernel of an iteration is launched once for the whole batch over a
  * table of (instance, tile) work items, so instances of different qubit

@@ -25,6 +25,18 @@ class AdaptParams(C.Structure):
                 ("schedule", C.c_int32), ("reserved", C.c_int32)]
 
 
+class ReoptParams(C.Structure):
+    _fields_ = [("grad_tol", C.c_double), ("max_iter", C.c_int32), ("bfgs_max_iter", C.c_int32),
+                ("bfgs_gtol", C.c_double)]
+
+
+class ReoptResult(C.Structure):
+    _fields_ = [("n_iter", C.c_int32), ("converged", C.c_int32),
+                ("energies", C.POINTER(C.c_double)), ("ops", C.POINTER(C.c_int32)),
+                ("thetas", C.POINTER(C.c_double)), ("gnorms", C.POINTER(C.c_double)),
+                ("bfgs_steps", C.POINTER(C.c_int32)), ("bfgs_evals", C.POINTER(C.c_int32))]
+
+
 class RequestInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("n_qubits", C.c_int32), ("t_submit_ns", C.c_int64),
                 ("t_admit_ns", C.c_int64), ("t_done_ns", C.c_int64)]
@@ -74,6 +86,7 @@ SIGNATURES = {
     "taylor5_apply": [_P, _P, C.c_int32, C.c_double, _P, C.c_int, _I32P],
     "taylor5_apply_family": [_P, _P, C.c_int32, _I32P, C.POINTER(C.c_double), _P, C.c_int, _I32P],
     "adapt_solve": [_P, _P, _P, _P, C.c_int, C.POINTER(AdaptParams), C.POINTER(AdaptResult)],
+    "adapt_reopt_solve": [_P, _P, _P, _P, C.c_int, C.POINTER(ReoptParams), C.POINTER(ReoptResult)],
     "gocp_batch_create": [_P, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                           C.POINTER(C.c_void_p), C.c_int, C.POINTER(AdaptParams), _PP],
     "gocp_batch_step": [_P, C.c_int32],

@@ -12,13 +12,13 @@ import ctypes as C
 
 import numpy as np
 
-from ._lib import load, check, AdaptParams, AdaptResult, RequestInfo, GOCP_EBUSY
+from ._lib import load, check, AdaptParams, AdaptResult, ReoptParams, ReoptResult, RequestInfo, GOCP_EBUSY
 
 __all__ = ["MAPPINGS", "Hamiltonian", "Pool", "Context", "pauli_hamiltonian_load",
            "pauli_hamiltonian_load_terms", "pool_build", "pool_build_pauli", "taylor5_apply_family", "gocp_partition", "hf_index",
            "state_basis", "energy", "apply_hamiltonian", "pool_gradients", "pool_gradients_noalloc",
            "taylor5_apply",
-           "adapt_solve", "Batch", "Server", "request_footprint", "version"]
+           "adapt_solve", "adapt_reopt_solve", "Batch", "Server", "request_footprint", "version"]
 
 MAPPINGS = {"jw": 0, "bk": 1, 0: 0, 1: 1}
 C128, C64 = 0, 1
@@ -342,6 +342,33 @@ def adapt_solve(ctx: Context, ham: Hamiltonian, pool: Pool, psi, max_iter: int,
     check(load().adapt_solve(ctx.handle, ham.handle, pool.handle, p, dt, C.byref(prm),
                              C.byref(rec.res)))
     return rec.as_dict()
+
+
+def adapt_reopt_solve(ctx: Context, ham: Hamiltonian, pool: Pool, psi, max_iter: int, grad_tol: float = 0.0,
+                      bfgs_gtol: float = 1e-8, bfgs_max_iter: int = 200):
+    """ADAPT with every angle re-optimised by BFGS after each appended
+    operator; psi (the starting state) receives the final normalised state.
+    Returns energies, ops, thetas (final angles), gnorms, BFGS steps and
+    evaluations per iteration."""
+    if ham.n_qubits != pool.n_qubits:
+        raise ValueError(f"Hamiltonian has {ham.n_qubits} qubits, pool {pool.n_qubits}")
+    p, dt = _state(psi, ham.n_qubits)
+    n = int(max_iter)
+    e = np.zeros(n + 1)
+    ops = np.zeros(max(n, 1), dtype=np.int32)
+    th = np.zeros(max(n, 1))
+    gn = np.zeros(n + 1)
+    bs = np.zeros(max(n, 1), dtype=np.int32)
+    be = np.zeros(max(n, 1), dtype=np.int32)
+    res = ReoptResult(0, 0, _ptr(e, C.c_double), _ptr(ops, C.c_int32), _ptr(th, C.c_double),
+                      _ptr(gn, C.c_double), _ptr(bs, C.c_int32), _ptr(be, C.c_int32))
+    prm = ReoptParams(float(grad_tol), n, int(bfgs_max_iter), float(bfgs_gtol))
+    check(load().adapt_reopt_solve(ctx.handle, ham.handle, pool.handle, p, dt, C.byref(prm), C.byref(res)))
+    k = res.n_iter
+    nscr = k + (1 if res.converged else 0)
+    return dict(n_iter=k, converged=bool(res.converged), energies=e[:k + 1].copy(), ops=ops[:k].tolist(),
+                thetas=th[:k].copy(), gnorms=gn[:nscr].copy(), bfgs_steps=bs[:k].tolist(),
+                bfgs_evals=be[:k].tolist())
 
 
 class Batch:

@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgocp.so")
 
 HOST_SOURCES = ["host_mapping.cpp", "host_gocp.cpp", "capi_host.cpp"]
-HIP_SOURCES = ["kernels.hip", "runtime.hip", "adapt.hip", "serve.hip"]
+HIP_SOURCES = ["kernels.hip", "runtime.hip", "adapt.hip", "serve.hip", "reopt.hip"]
 
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")

@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "device.h"
@@ -1875,6 +1876,120 @@ __global__ __launch_bounds__(kPairBlock) void k_taylor5(const InstDev *__restric
     }
 }
 
+// ------------------------------------------------------------------ re-optimisation layers
+
+// ADAPT with every angle re-optimised: the ansatz is a chain of layers
+// L(theta) = T5(x)^s (Eq. 5-6, x = theta / s), each a pool generator with one
+// X mask, so one lane owns one amplitude pair (d, e = d ^ x_A) of the layer's
+// generator and applies its polynomials in registers.  On a pair,
+// (A v)[d] = h(d) v[e] and (A v)[e] = h(e) v[d].
+
+// sum_{n <= N} x^n A^n / n! on the pair (a at d, c at e), as the power sum of Eq. 6.
+template <int N>
+__device__ __forceinline__ void pair_series(double hd, double he, double x, double2 &a, double2 &c) {
+    double2 va = a, vc = c, acca = a, accc = c;
+    double coef = 1.0;
+#pragma unroll
+    for (int n = 1; n <= N; ++n) {
+        const double2 na = make_double2(hd * vc.x, hd * vc.y);
+        const double2 nc = make_double2(he * va.x, he * va.y);
+        va = na;
+        vc = nc;
+        coef = coef * x / n;
+        acca.x = fma(coef, va.x, acca.x);
+        acca.y = fma(coef, va.y, acca.y);
+        accc.x = fma(coef, vc.x, accc.x);
+        accc.y = fma(coef, vc.y, accc.y);
+    }
+    a = acca;
+    c = accc;
+}
+
+// The pair of lane p for generator record C on 2^nq amplitudes: d (bit hb of
+// the mask cleared), e = d ^ mask, and whether the lane owns a pair.
+__device__ __forceinline__ bool layer_pair(const HClass &C, int nq, uint32_t &d, uint32_t &e) {
+    const uint32_t m = C.x;
+    const int hb = 31 - __clz(m);
+    const uint32_t p = blockIdx.x * kPairBlock + threadIdx.x;
+    const bool own = p < (1u << (nq - 1));
+    d = own ? insert_zero_bit(p, hb) : 0u;
+    e = d ^ m;
+    return own;
+}
+
+// Forward layer, out of place: out = T5(x)^ns in on every pair of generator j.
+template <typename T>
+__global__ __launch_bounds__(kPairBlock) void k_layer_fwd(const void *__restrict__ in, void *__restrict__ out,
+                                                         const HClass *__restrict__ pop,
+                                                         const HTerm *__restrict__ pterm, int j, int ns, double x,
+                                                         int nq) {
+    const HClass C = load_rec(cptr(pop), j);
+    uint32_t d, e;
+    if (!layer_pair(C, nq, d, e)) return;
+    double2 a = Amp<T>::load(in, d), c = Amp<T>::load(in, e);
+    double hd, he;
+    string_sum2(cptr(pterm), C.s0, C.s1, d, e, hd, he);
+    for (int sub = 0; sub < ns; ++sub) pair_series<5>(hd, he, x, a, c);
+    Amp<T>::store(out, d, a);
+    Amp<T>::store(out, e, c);
+}
+
+// Backward layer: with phi the state before the layer and lam the adjoint
+// vector after it (complex128, updated in place),
+//   partial[block] = sum over the block's pairs of Re <lam | T5(x)^(ns-1) A T4(x) phi>
+//   lam <- T5(-x)^ns lam
+// (the layer's derivative and its adjoint: the series in -A, since A^+ = -A).
+// When sigma is given this is the last layer: lam is first formed as
+// sigma - E psi with psi = the ansatz state (state type T) and E = e_num / nrm
+// of the state record st.
+template <typename T>
+__global__ __launch_bounds__(kPairBlock) void k_layer_adj(const void *__restrict__ phi, double2 *__restrict__ lam,
+                                                         double *__restrict__ partial,
+                                                         const HClass *__restrict__ pop,
+                                                         const HTerm *__restrict__ pterm, int j, int ns, double x,
+                                                         int nq, const double2 *__restrict__ sigma,
+                                                         const void *__restrict__ psi,
+                                                         const AdaptState *__restrict__ st) {
+    const HClass C = load_rec(cptr(pop), j);
+    uint32_t d, e;
+    const bool own = layer_pair(C, nq, d, e);
+    double dot = 0.0;
+    if (own) {
+        double hd, he;
+        string_sum2(cptr(pterm), C.s0, C.s1, d, e, hd, he);
+        double2 la, lc;
+        if (sigma) {
+            const double en = cptr(&st->e_num)[0] / cptr(&st->nrm)[0];
+            const double2 sa = sigma[d], sc = sigma[e], pa = Amp<T>::load(psi, d), pc = Amp<T>::load(psi, e);
+            la = make_double2(sa.x - en * pa.x, sa.y - en * pa.y);
+            lc = make_double2(sc.x - en * pc.x, sc.y - en * pc.y);
+        } else {
+            la = lam[d];
+            lc = lam[e];
+        }
+        double2 a = Amp<T>::load(phi, d), c = Amp<T>::load(phi, e);
+        pair_series<4>(hd, he, x, a, c);
+        const double2 na = make_double2(hd * c.x, hd * c.y), nc = make_double2(he * a.x, he * a.y);
+        a = na;
+        c = nc;
+        for (int sub = 1; sub < ns; ++sub) pair_series<5>(hd, he, x, a, c);
+        dot = (la.x * a.x + la.y * a.y) + (lc.x * c.x + lc.y * c.y);
+        for (int sub = 0; sub < ns; ++sub) pair_series<5>(hd, he, -x, la, lc);
+        lam[d] = la;
+        lam[e] = lc;
+    }
+    __shared__ double rd[kPairBlock / kWave];
+    dot = wave_sum(dot);
+    const int wv = wave_id(), lane = threadIdx.x & (kWave - 1);
+    if (lane == 0) rd[wv] = dot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0;
+        for (int k = 0; k < kPairBlock / kWave; ++k) a += rd[k];
+        partial[blockIdx.x] = a;
+    }
+}
+
 // GOCP multi-operator step (Sec. III.A families, Eq. 5-6 chains): N pool
 // operators of one commuting family, X masks independent over GF(2), applied
 // in one pass.  The masks span a group of 2^N bit flips; each operator maps
@@ -2097,9 +2212,51 @@ void launch_fused(int dtype, int n, const InstDev *insts, const int2 *blk, int n
     hip_check(hipGetLastError(), "kernel launch");
 }
 
+void launch_layer_fwd(int dtype, const void *in, void *out, const HClass *pop, const HTerm *pterm, int j, int ns,
+                      double x, int nq, hipStream_t s) {
+    const int nb = std::max(1, ((1 << (nq - 1)) + kPairBlock - 1) / kPairBlock);
+    if (dtype == GOCP_C64)
+        hipLaunchKernelGGL(k_layer_fwd<float2>, dim3(nb), dim3(kPairBlock), 0, s, in, out, pop, pterm, j, ns, x, nq);
+    else
+        hipLaunchKernelGGL(k_layer_fwd<double2>, dim3(nb), dim3(kPairBlock), 0, s, in, out, pop, pterm, j, ns, x, nq);
+    hip_check(hipGetLastError(), "kernel launch");
+}
+
+void launch_layer_adj(int dtype, const void *phi, double2 *lam, double *partial, const HClass *pop,
+                      const HTerm *pterm, int j, int ns, double x, int nq, const double2 *sigma, const void *psi,
+                      const AdaptState *st, hipStream_t s) {
+    const int nb = std::max(1, ((1 << (nq - 1)) + kPairBlock - 1) / kPairBlock);
+    if (dtype == GOCP_C64)
+        hipLaunchKernelGGL(k_layer_adj<float2>, dim3(nb), dim3(kPairBlock), 0, s, phi, lam, partial, pop, pterm, j,
+                           ns, x, nq, sigma, psi, st);
+    else
+        hipLaunchKernelGGL(k_layer_adj<double2>, dim3(nb), dim3(kPairBlock), 0, s, phi, lam, partial, pop, pterm,
+                           j, ns, x, nq, sigma, psi, st);
+    hip_check(hipGetLastError(), "kernel launch");
+}
+
 void launch_gather_done(const InstDev *insts, int n, int32_t *out, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_gather_done, dim3((n + 255) / 256), dim3(256), 0, s, insts, n, out);
+    hip_check(hipGetLastError(), "kernel launch");
+}
+
+// dst[i] = scale * src[i] for a state of dim amplitudes (FP64 product, rounded
+// to the state's precision once).
+template <typename T>
+__global__ void k_scale_copy(const void *src, void *dst, uint32_t dim, double scale) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= dim) return;
+    const double2 v = Amp<T>::load(src, i);
+    Amp<T>::store(dst, i, make_double2(scale * v.x, scale * v.y));
+}
+
+void launch_scale_copy(int dtype, const void *src, void *dst, uint32_t dim, double scale, hipStream_t s) {
+    const int nb = (int)((dim + 255) / 256);
+    if (dtype == GOCP_C64)
+        hipLaunchKernelGGL(k_scale_copy<float2>, dim3(nb), dim3(256), 0, s, src, dst, dim, scale);
+    else
+        hipLaunchKernelGGL(k_scale_copy<double2>, dim3(nb), dim3(256), 0, s, src, dst, dim, scale);
     hip_check(hipGetLastError(), "kernel launch");
 }
 

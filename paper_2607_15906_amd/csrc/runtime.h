@@ -32,6 +32,16 @@ enum {
     K_NORMALIZE = 5, K_UNIT_NORM = 6, K_SCREEN_SUM1 = 7
 };
 
+// Re-optimisation layers (one block of kPairBlock pairs per 2 kPairBlock
+// amplitudes): out = T5(x)^ns in for pool generator j; and the backward step
+// (partial[block] of Re <lam | dL phi>, lam <- L^+ lam; lam formed from sigma,
+// psi and the state record's energy when sigma is not null).
+void launch_layer_fwd(int dtype, const void *in, void *out, const HClass *pop, const HTerm *pterm, int j, int ns,
+                      double x, int nq, hipStream_t s);
+void launch_layer_adj(int dtype, const void *phi, double2 *lam, double *partial, const HClass *pop,
+                      const HTerm *pterm, int j, int ns, double x, int nq, const double2 *sigma, const void *psi,
+                      const AdaptState *st, hipStream_t s);
+
 // R = amplitudes per lane of the tile kernels (1, 2 or 4); the pair kernels ignore it.
 // t0 / t1, when set, take the dispatch's own start / end timestamps
 // (hipExtLaunchKernel), so the span between them holds the kernel alone and not
@@ -44,6 +54,10 @@ void launch_kernel(int which, int dtype, int R, const InstDev *insts, const int2
 void launch_hvw_act(const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s,
                     hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_basis(int dtype, void *psi, uint32_t dim, uint32_t index, hipStream_t s);
+void launch_scale_copy(int dtype, const void *src, void *dst, uint32_t dim, double scale, hipStream_t s);
+// Queue sigma = H psi and the energy of psi (one-shot workspace of ctx) on the
+// context stream; returns the device state record holding e_num, nrm, energy.
+const AdaptState *enqueue_energy_sigma(gocp_ctx *ctx, const Ham *h, const void *psi, int dtype, double2 *sigma);
 // GOCP multi-operator step over the pair-block rows (norm partials in part_t).
 void launch_fused(int dtype, int n, const InstDev *insts, const int2 *blk, int nblk, const FuseArgs &fa,
                   hipStream_t s);

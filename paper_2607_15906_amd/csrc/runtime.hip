@@ -831,6 +831,14 @@ AdaptState read_state(gocp_ctx *ctx, const OneShot &o) {
 
 }  // namespace
 
+const AdaptState *enqueue_energy_sigma(gocp_ctx *ctx, const Ham *h, const void *psi, int dtype, double2 *sigma) {
+    OneShot o = one_shot(ctx, h, nullptr, psi, dtype, sigma);
+    launch_kernel(K_ENERGY_SCREEN, dtype, 1, o.desc, o.btile, o.nt, 0, ctx->user_stream);
+    launch_kernel(K_SCREEN_SUM1, dtype, 1, o.desc, o.btile, o.ip.n_groups, 0, ctx->user_stream);
+    launch_kernel(K_SCREEN_REDUCE, dtype, 1, o.desc, o.btile, 1, 0, ctx->user_stream);
+    return reinterpret_cast<const AdaptState *>(o.base + o.ip.o_st);
+}
+
 }  // namespace gocp
 
 using namespace gocp;
