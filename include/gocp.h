@@ -160,6 +160,16 @@ int gocp_conflict_degrees(const gocp_pool *p, int64_t *n_edges, int32_t *deg);
  */
 int gocp_hf_index(int n_qubits, int n_electrons, int mapping, uint64_t *index);
 
+/*
+ * Parity-aware decoding (Sec. IV.B: tree encodings spread the occupation
+ * parity over several qubits): the spin-orbital occupations of basis index
+ * `index` under `mapping`, bit j = occupation of spin-orbital j (JW: the index
+ * itself; BK: beta^{-1} index over GF(2), each occupation the parity of a set
+ * of qubits).  gocp_basis_occupation(n, m, gocp_hf_index(n, ne, m)) is the
+ * HF occupation 2^ne - 1 under both mappings.  Errors: EINVAL (index >= 2^n).
+ */
+int gocp_basis_occupation(int n_qubits, int mapping, uint64_t index, uint64_t *occupation);
+
 /* ======================================================================
  * Device calls
  * ==================================================================== */
@@ -180,6 +190,25 @@ int gocp_ctx_synchronize(gocp_ctx *ctx);
 
 /* Write the basis state |index> into psi_dev (2^n_qubits amplitudes). */
 int gocp_state_basis(gocp_ctx *ctx, int n_qubits, uint64_t index, void *psi_dev, int dtype);
+
+/*
+ * The encoded Hartree-Fock reference: |gocp_hf_index(...)> into psi_dev.
+ */
+int gocp_state_hf(gocp_ctx *ctx, int n_qubits, int n_electrons, int mapping, void *psi_dev, int dtype);
+
+/*
+ * Weight of a state inside the pool's symmetry sector under an encoding
+ * (Sec. IV.B): sum |psi_d|^2 over the basis states d whose decoded occupation
+ * (gocp_basis_occupation) holds n_electrons electrons, as many spin-up (even
+ * spin-orbitals) as spin-down (odd), divided by <psi|psi> (FP64 sums in a
+ * fixed order).  The pool's operators conserve both numbers, so a state with
+ * weight 0 (for example an occupation bitstring used as a BK index without
+ * encoding it) stays outside the sector: every ADAPT iteration from it is
+ * decoupled from the sector's ground state.  Synchronises.
+ * Errors: EINVAL, ENUMERIC (zero norm).
+ */
+int gocp_sector_weight(gocp_ctx *ctx, int n_qubits, int n_electrons, int mapping, const void *psi_dev, int dtype,
+                       double *weight);
 
 /*
  * energy -- Eq. 1: E = Re<psi|H|psi> / <psi|psi>, FP64, written to *e_out

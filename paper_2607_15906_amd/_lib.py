@@ -74,6 +74,9 @@ SIGNATURES = {
     "gocp_partition": [_P, _I32P, _I32P, _I32P],
     "gocp_conflict_degrees": [_P, _I64P, _I32P],
     "gocp_hf_index": [C.c_int, C.c_int, C.c_int, _U64P],
+    "gocp_basis_occupation": [C.c_int, C.c_int, C.c_uint64, _U64P],
+    "gocp_state_hf": [_P, C.c_int, C.c_int, C.c_int, _P, C.c_int],
+    "gocp_sector_weight": [_P, C.c_int, C.c_int, C.c_int, _P, C.c_int, _F64P],
     "gocp_ctx_create": [C.c_int, _P, _PP],
     "gocp_ctx_destroy": [_P],
     "gocp_ctx_set_stream": [_P, _P],

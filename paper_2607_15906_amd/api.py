@@ -16,6 +16,7 @@ from ._lib import load, check, AdaptParams, AdaptResult, ReoptParams, ReoptResul
 
 __all__ = ["MAPPINGS", "Hamiltonian", "Pool", "Context", "pauli_hamiltonian_load",
            "pauli_hamiltonian_load_terms", "pool_build", "pool_build_pauli", "taylor5_apply_family", "gocp_partition", "hf_index",
+           "basis_occupation", "state_hf", "sector_weight",
            "state_basis", "energy", "apply_hamiltonian", "pool_gradients", "pool_gradients_noalloc",
            "taylor5_apply",
            "adapt_solve", "adapt_reopt_solve", "Batch", "Server", "request_footprint", "version"]
@@ -170,6 +171,13 @@ def hf_index(n_qubits: int, n_electrons: int, mapping) -> int:
     return out.value
 
 
+def basis_occupation(n_qubits: int, mapping, index: int) -> int:
+    """Spin-orbital occupations (bit j) of a basis index under the encoding."""
+    out = C.c_uint64()
+    check(load().gocp_basis_occupation(n_qubits, _mapping(mapping), int(index), C.byref(out)))
+    return out.value
+
+
 # ---------------------------------------------------------------- device side
 
 def _state(psi, n_qubits: int):
@@ -238,6 +246,20 @@ class Context:
 def state_basis(ctx: Context, n_qubits: int, index: int, psi):
     p, dt = _state(psi, n_qubits)
     check(load().gocp_state_basis(ctx.handle, n_qubits, index, p, dt))
+
+
+def state_hf(ctx: Context, n_qubits: int, n_electrons: int, mapping, psi):
+    """The encoded Hartree-Fock reference into psi."""
+    p, dt = _state(psi, n_qubits)
+    check(load().gocp_state_hf(ctx.handle, n_qubits, n_electrons, _mapping(mapping), p, dt))
+
+
+def sector_weight(ctx: Context, n_qubits: int, n_electrons: int, mapping, psi) -> float:
+    """Weight of psi inside the (n_electrons, S_z = 0) sector, decoded through the encoding."""
+    p, dt = _state(psi, n_qubits)
+    w = C.c_double()
+    check(load().gocp_sector_weight(ctx.handle, n_qubits, n_electrons, _mapping(mapping), p, dt, C.byref(w)))
+    return w.value
 
 
 def energy(ctx: Context, ham: Hamiltonian, psi) -> float:

@@ -155,11 +155,16 @@ struct gocp_batch {
     int max_iter = 0;
     bool use_graph = true;
     int issued = 0;
-    // events of gocp_batch_step_timed, created with the batch (2 per sampled
-    // launch and the two ends) so that a timed call creates and destroys none
+    // events of gocp_batch_step_timed, created with the batch so that a timed
+    // call creates and destroys none: two per sampled launch, without the
+    // system-scope fence (timing only: no cache writeback and invalidation
+    // around the sampled kernel), and the two ends of the timed region
     std::vector<hipEvent_t> tev;
+    hipEvent_t tend[2] = {nullptr, nullptr};
     ~gocp_batch() {
         for (hipEvent_t e : tev)
+            if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : tend)
             if (e) (void)hipEventDestroy(e);
     }
 };
@@ -203,8 +208,9 @@ int gocp_batch_create(gocp_ctx *ctx, int32_t n, const gocp_ham *const *hams,
     b->group.dtype = dtype;
     b->max_iter = params->max_iter;
     b->use_graph = params->use_graph != 0;
-    b->tev.assign(2 * (size_t)std::min(std::max(params->max_iter, 0), 512) + 2, nullptr);
-    for (hipEvent_t &e : b->tev) hip_check(hipEventCreate(&e), "hipEventCreate");
+    b->tev.assign(2 * (size_t)std::min(std::max(params->max_iter, 0), 512), nullptr);
+    for (hipEvent_t &e : b->tev) hip_check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
+    for (hipEvent_t &e : b->tend) hip_check(hipEventCreate(&e), "hipEventCreate");
     for (int i = 0; i < n; ++i) {
         if (!psi_dev[i]) throw Error(GOCP_EINVAL, "null state pointer");
         b->owned.emplace_back(instance_create(ctx, as_ham(hams[i]), as_pool(pools[i]), psi_dev[i],
@@ -243,13 +249,13 @@ int gocp_batch_step_timed(gocp_batch *b, int32_t n_iter, int32_t kernel, int32_t
     // events for the sampled launches and the two ends, from the batch's set
     // (grown here only for more iterations than the batch was created for)
     const int n_samp = (n_iter + every - 1) / every;
-    while (b->tev.size() < 2 * (size_t)n_samp + 2) {
+    while (b->tev.size() < 2 * (size_t)n_samp) {
         hipEvent_t e = nullptr;
-        hip_check(hipEventCreate(&e), "hipEventCreate");
+        hip_check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
         b->tev.push_back(e);
     }
     const std::vector<hipEvent_t> &ev = b->tev;
-    hip_check(hipEventRecord(ev[2 * n_samp], s), "hipEventRecord");
+    hip_check(hipEventRecord(b->tend[0], s), "hipEventRecord");
     int sampled = 0;
     for (int i = 0; i < n_iter; ++i) {
         for (Instance *in : b->group.inst) in->finalized = false;
@@ -261,8 +267,8 @@ int gocp_batch_step_timed(gocp_batch *b, int32_t n_iter, int32_t kernel, int32_t
         }
     }
     b->group.select_pending(s);
-    hip_check(hipEventRecord(ev[2 * n_samp + 1], s), "hipEventRecord");
-    hip_check(hipEventSynchronize(ev[2 * n_samp + 1]), "hipEventSynchronize");
+    hip_check(hipEventRecord(b->tend[1], s), "hipEventRecord");
+    hip_check(hipEventSynchronize(b->tend[1]), "hipEventSynchronize");
     double k = 0.0;
     for (int i = 0; i < sampled; ++i) {
         float ms = 0.f;
@@ -270,7 +276,7 @@ int gocp_batch_step_timed(gocp_batch *b, int32_t n_iter, int32_t kernel, int32_t
         k += ms;
     }
     float tot = 0.f;
-    hip_check(hipEventElapsedTime(&tot, ev[2 * n_samp], ev[2 * n_samp + 1]), "hipEventElapsedTime");
+    hip_check(hipEventElapsedTime(&tot, b->tend[0], b->tend[1]), "hipEventElapsedTime");
     b->issued += n_iter;
     *total_ms = tot;
     *kernel_ms = k / sampled;

@@ -180,6 +180,14 @@ int gocp_conflict_degrees(const gocp_pool *pp, int64_t *n_edges, int32_t *deg) {
     GOCP_GUARD_END
 }
 
+int gocp_basis_occupation(int n_qubits, int mapping, uint64_t index, uint64_t *occupation) {
+    GOCP_GUARD_BEGIN
+    if (!occupation) throw Error(GOCP_EINVAL, "null output");
+    *occupation = basis_occupation(n_qubits, mapping, index);
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
 int gocp_hf_index(int n_qubits, int n_electrons, int mapping, uint64_t *index) {
     GOCP_GUARD_BEGIN
     if (!index) throw Error(GOCP_EINVAL, "null output");

@@ -57,6 +57,13 @@ constexpr int kHvwSlots = 32;
 // scalar registers.
 constexpr int kHvwBatch = 2;
 
+// Occupation decoding of a basis index (bit j = parity(r[j] & index)) and the
+// electron count of the sector, passed by value to the sector-weight kernel.
+struct SectorRows {
+    uint32_t r[32];
+    int32_t n, ne;
+};
+
 // GOCP multi-operator step: at most kFuseMax operators of one family per pass.
 constexpr int kFuseMax = 4;
 struct FuseArgs {

@@ -56,8 +56,9 @@ struct BkBasis {
     int n = 0;
     std::vector<uint32_t> beta_rows;     // (beta x)_j = parity(beta_rows[j] & x)
     std::vector<uint32_t> inv_t_rows;    // (beta^{-T} z)_j = parity(inv_t_rows[j] & z)
+    std::vector<uint32_t> inv_rows;      // (beta^{-1} b)_j = parity(inv_rows[j] & b)
 
-    explicit BkBasis(int nq) : n(nq), beta_rows(nq), inv_t_rows(nq) {
+    explicit BkBasis(int nq) : n(nq), beta_rows(nq), inv_t_rows(nq), inv_rows(nq) {
         for (int j = 0; j < n; ++j) {
             const int lb = (j + 1) & -(j + 1);
             uint32_t r = 0;
@@ -78,6 +79,7 @@ struct BkBasis {
             for (int r = 0; r < n; ++r)
                 if (r != col && ((a[r] >> col) & 1u)) { a[r] ^= a[col]; inv[r] ^= inv[col]; }
         }
+        inv_rows = inv;
         // row j of beta^{-T} = column j of beta^{-1}
         for (int j = 0; j < n; ++j) {
             uint32_t r = 0;
@@ -211,6 +213,25 @@ uint64_t hf_index(int nq, int ne, int mapping) {
     if (mapping != GOCP_BK) throw Error(GOCP_EINVAL, "unknown mapping");
     BkBasis bk(nq);
     return bk.apply(bk.beta_rows, occ);
+}
+
+std::vector<uint32_t> occupation_rows(int nq, int mapping) {
+    check_qubits(nq);
+    std::vector<uint32_t> rows(nq);
+    if (mapping == GOCP_JW) {
+        for (int j = 0; j < nq; ++j) rows[j] = 1u << j;
+        return rows;
+    }
+    if (mapping != GOCP_BK) throw Error(GOCP_EINVAL, "unknown mapping");
+    return BkBasis(nq).inv_rows;
+}
+
+uint64_t basis_occupation(int nq, int mapping, uint64_t index) {
+    const std::vector<uint32_t> rows = occupation_rows(nq, mapping);
+    if (index >> nq) throw Error(GOCP_EINVAL, "basis index out of range");
+    uint64_t occ = 0;
+    for (int j = 0; j < nq; ++j) occ |= (uint64_t)(__builtin_popcount(rows[j] & (uint32_t)index) & 1) << j;
+    return occ;
 }
 
 Pool *build_pool(int nq, int ne, int mapping, bool pauli) {

@@ -88,6 +88,11 @@ Ham *hamiltonian_from_terms(int n_qubits, const std::vector<Term> &terms);
 // pauli: one operator per string of the generators (unit coefficients)
 Pool *build_pool(int n_qubits, int n_electrons, int mapping, bool pauli = false);
 uint64_t hf_index(int n_qubits, int n_electrons, int mapping);
+// Decoding a basis index into spin-orbital occupations under an encoding:
+// occupation bit j = parity(rows[j] & index) (JW: the index itself; BK: the
+// rows of beta^{-1}, a non-local parity of several qubits).
+std::vector<uint32_t> occupation_rows(int n_qubits, int mapping);
+uint64_t basis_occupation(int n_qubits, int mapping, uint64_t index);
 void partition_pool(Pool &p);   // fills family_of, order, fam_off, fam_members, degree
 
 // device-side release hooks (defined in the HIP sources)

@@ -2241,6 +2241,46 @@ void launch_gather_done(const InstDev *insts, int n, int32_t *out, hipStream_t s
     hip_check(hipGetLastError(), "kernel launch");
 }
 
+// Per block: the weight of the block's amplitudes inside the sector (decoded
+// occupation with ne electrons, as many in even as in odd spin-orbitals) and
+// their total weight, into part[2 block], part[2 block + 1].
+template <typename T>
+__global__ __launch_bounds__(256) void k_sector_weight(const void *psi, uint32_t dim, SectorRows rows, double *part) {
+    double in = 0.0, all = 0.0;
+    for (uint32_t d = blockIdx.x * 256 + threadIdx.x; d < dim; d += gridDim.x * 256) {
+        uint32_t occ = 0;
+        for (int j = 0; j < rows.n; ++j) occ |= (uint32_t)(__popc(rows.r[j] & d) & 1) << j;
+        const double2 a = Amp<T>::load(psi, d);
+        const double w = a.x * a.x + a.y * a.y;
+        all += w;
+        const int ne = __popc(occ), nu = __popc(occ & 0x55555555u);
+        if (ne == rows.ne && 2 * nu == ne) in += w;
+    }
+    __shared__ double r[2][256 / kWave];
+    in = wave_sum(in);
+    all = wave_sum(all);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+    if (lane == 0) {
+        r[0][wv] = in;
+        r[1][wv] = all;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double a = 0.0;
+        for (int k = 0; k < 256 / kWave; ++k) a += r[threadIdx.x][k];
+        part[2 * blockIdx.x + threadIdx.x] = a;
+    }
+}
+
+void launch_sector_weight(int dtype, const void *psi, uint32_t dim, const SectorRows &rows, double *part, int nblk,
+                          hipStream_t s) {
+    if (dtype == GOCP_C64)
+        hipLaunchKernelGGL(k_sector_weight<float2>, dim3(nblk), dim3(256), 0, s, psi, dim, rows, part);
+    else
+        hipLaunchKernelGGL(k_sector_weight<double2>, dim3(nblk), dim3(256), 0, s, psi, dim, rows, part);
+    hip_check(hipGetLastError(), "kernel launch");
+}
+
 // dst[i] = scale * src[i] for a state of dim amplitudes (FP64 product, rounded
 // to the state's precision once).
 template <typename T>

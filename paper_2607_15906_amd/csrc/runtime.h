@@ -55,6 +55,8 @@ void launch_hvw_act(const InstDev *insts, const int2 *blk, int nblk, int mode, h
                     hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_basis(int dtype, void *psi, uint32_t dim, uint32_t index, hipStream_t s);
 void launch_scale_copy(int dtype, const void *src, void *dst, uint32_t dim, double scale, hipStream_t s);
+void launch_sector_weight(int dtype, const void *psi, uint32_t dim, const SectorRows &rows, double *part, int nblk,
+                          hipStream_t s);
 // Queue sigma = H psi and the energy of psi (one-shot workspace of ctx) on the
 // context stream; returns the device state record holding e_num, nrm, energy.
 const AdaptState *enqueue_energy_sigma(gocp_ctx *ctx, const Ham *h, const void *psi, int dtype, double2 *sigma);

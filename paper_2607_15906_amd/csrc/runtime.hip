@@ -910,6 +910,58 @@ int gocp_state_basis(gocp_ctx *ctx, int n_qubits, uint64_t index, void *psi_dev,
     GOCP_GUARD_END
 }
 
+int gocp_state_hf(gocp_ctx *ctx, int n_qubits, int n_electrons, int mapping, void *psi_dev, int dtype) {
+    GOCP_GUARD_BEGIN
+    check_ctx(ctx);
+    check_dtype(dtype);
+    if (!psi_dev) throw Error(GOCP_EINVAL, "null state pointer");
+    if (n_qubits < 1 || n_qubits > kMaxQubits) throw Error(GOCP_ENOTSUP, "qubit count out of range");
+    const uint64_t idx = hf_index(n_qubits, n_electrons, mapping);
+    launch_basis(dtype, psi_dev, 1u << n_qubits, (uint32_t)idx, ctx->user_stream);
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
+int gocp_sector_weight(gocp_ctx *ctx, int n_qubits, int n_electrons, int mapping, const void *psi_dev, int dtype,
+                       double *weight) {
+    GOCP_GUARD_BEGIN
+    check_ctx(ctx);
+    check_dtype(dtype);
+    if (!psi_dev || !weight) throw Error(GOCP_EINVAL, "null state or output");
+    if (n_qubits < 1 || n_qubits > kMaxQubits) throw Error(GOCP_ENOTSUP, "qubit count out of range");
+    if (n_electrons < 0 || n_electrons > n_qubits) throw Error(GOCP_EINVAL, "electron count out of range");
+    SectorRows rows{};
+    const std::vector<uint32_t> r = occupation_rows(n_qubits, mapping);
+    for (int j = 0; j < n_qubits; ++j) rows.r[j] = r[j];
+    rows.n = n_qubits;
+    rows.ne = n_electrons;
+    const uint32_t dim = 1u << n_qubits;
+    const int nblk = (int)std::min<uint32_t>(1024, (dim + 255) / 256);
+    double *part = nullptr;
+    hip_check(hipMalloc(&part, sizeof(double) * 2 * nblk), "hipMalloc");
+    std::vector<double> h(2 * nblk);
+    hipError_t e = hipSuccess;
+    try {
+        launch_sector_weight(dtype, psi_dev, dim, rows, part, nblk, ctx->user_stream);
+        e = hipMemcpyAsync(h.data(), part, sizeof(double) * 2 * nblk, hipMemcpyDeviceToHost, ctx->user_stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->user_stream);
+    } catch (...) {
+        (void)hipFree(part);
+        throw;
+    }
+    (void)hipFree(part);
+    hip_check(e, "sector weight");
+    double in = 0.0, all = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        in += h[2 * b];
+        all += h[2 * b + 1];
+    }
+    if (!(all > 0.0)) throw Error(GOCP_ENUMERIC, "zero norm");
+    *weight = in / all;
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
 int energy(gocp_ctx *ctx, const gocp_ham *hh, const void *psi_dev, int dtype, double *e_out) {
     GOCP_GUARD_BEGIN
     check_ctx(ctx);
