@@ -45,7 +45,7 @@ LANE_OPS_PER_STRING_AMP = 5
 # scaled by a 256 MiB copy), from the rocprofv3 counter runs summarised under
 # profiles/; keyed by (kernel, amplitudes per lane).  An entry is removed when
 # the kernel changes, until the counters are taken again.
-TRAFFIC_BYTES = {("k_energy_screen", 1): 2553596}
+TRAFFIC_BYTES = {("k_energy_screen", 1): 2557723}
 
 
 def _say(msg):
@@ -344,7 +344,8 @@ def serving_block(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, loads=(0.
     times that capacity, `warm` warm-up requests first (excluded from the
     figures), then `n_req` measured ones.  Latency is submission to
     completion on the library's clock; the baseline is sequential plain FP64
-    adapt_solve on the same device."""
+    adapt_solve on the same device.  A second capacity run serves the same
+    requests with the other state precision."""
     import numpy as np
     import torch
     from workloads import serving_requests
@@ -366,20 +367,24 @@ def serving_block(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, loads=(0.
         if t_end is not None and time.perf_counter() > t_end:
             raise TimeoutError(f"serving: {len(tickets)} requests unfinished at the deadline")
 
-    def new_server():
-        return g.Server(ctx, budget, max_slots, dtype=code, iters_per_step=iters_per_step,
+    def new_server(c=code):
+        return g.Server(ctx, budget, max_slots, dtype=c, iters_per_step=iters_per_step,
                         amps_per_lane=amps_per_lane)
 
-    # capacity: everything at once
-    srv = new_server()
-    t0 = time.perf_counter()
-    pend = [srv.submit(H, P, max_iter, tol) for (_, H, P, _) in reqs[warm:]]
-    done = {}
-    while pend:
-        drain(srv, pend, done, t0 + deadline_s)
-        time.sleep(0.0005)
-    cap = n_req / (time.perf_counter() - t0)
-    srv.close()
+    def capacity(c):
+        """Every measured request submitted at once; solves/s and the results."""
+        srv = new_server(c)
+        t0 = time.perf_counter()
+        pend = [srv.submit(H, P, max_iter, tol) for (_, H, P, _) in reqs[warm:]]
+        done = {}
+        while pend:
+            drain(srv, pend, done, t0 + deadline_s)
+            time.sleep(0.0005)
+        rate = n_req / (time.perf_counter() - t0)
+        srv.close()
+        return rate, done
+
+    cap, done = capacity(code)
     # the gradient screen of every served iteration (all M operators over
     # all 2^n amplitudes, S strings): work every iteration of either
     # precision performs in full, whatever else it carries or compacts
@@ -426,6 +431,11 @@ def serving_block(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, loads=(0.
             "converged": sum(1 for t, _ in meas if done[t][1] is not None and done[t][1]["converged"]),
             "server_steps": st["steps"]}
 
+    # the same capacity run with the other state precision (complex64 storage,
+    # FP64 arithmetic, or the reverse)
+    other = 1 - code
+    cap_other, done_other = capacity(other)
+
     # sequential plain FP64: one adapt_solve at a time, complex128
     t0 = time.perf_counter()
     for (d, H, P, _) in reqs[warm:]:
@@ -441,6 +451,12 @@ def serving_block(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, loads=(0.
             "hbm_budget_bytes": budget, "capacity_solves_per_s": round(cap, 2),
             "loads": runs, "sequential_fp64_solves_per_s": round(seq, 2),
             "capacity_vs_sequential_fp64": round(cap / seq, 3),
+            "other_state": {"state": "complex64" if other == 1 else "complex128",
+                            "capacity_solves_per_s": round(cap_other, 2),
+                            "capacity_vs_sequential_fp64": round(cap_other / seq, 3),
+                            "completed_ok": sum(1 for r in done_other.values() if r[0] == 0),
+                            "converged": sum(1 for r in done_other.values()
+                                             if r[1] is not None and r[1]["converged"])},
             "capacity_screen_roofline": {"bound": "alu", "what": "algorithmic lane operations of the gradient "
                                   "screens of every served iteration (5 per string-amplitude, S strings x 2^n "
                                   "amplitudes per screen) over the capacity run's wall time; every other kernel "
