@@ -48,6 +48,12 @@ LANE_OPS_PER_STRING_AMP = 5
 TRAFFIC_BYTES = {("k_energy_screen", 1): 2557723}
 
 
+def _schedule_fields(code):
+    """A batch's schedule code as its two parts: amplitudes per lane and the
+    compacted H v, H w launch's workgroups per tile slot."""
+    return {"amps_per_lane": code & 0xFF, "hvw_parts": (code >> 8) or 8}
+
+
 def _say(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -322,7 +328,7 @@ def batched_block(g, ctx, schedule, oracle_baseline):
     achieved = lane_ops / (kms * 1e-3) / 1e12
     ips = len(insts) * iters_b / dtb
     out = {"instances": len(insts), "mix": "24x10q + 24x12q + 16x14q, JW/BK alternating",
-           "iterations_each": iters_b, "amps_per_lane": sched_b, "state": "complex64",
+           "iterations_each": iters_b, **_schedule_fields(sched_b), "state": "complex64",
            "seconds": round(dtb, 6), "instance_iters_per_s": round(ips, 2),
            "algorithmic_amp_updates_per_s": float(f"{ub / dtb:.6g}"),
            "roofline": {"bound": "alu", "kernel": "k_energy_screen (all 64 instances per launch)",
@@ -598,7 +604,7 @@ def main():
                    "pauli_terms": T, "xmask_classes": C, "pool_ops": M, "pool_strings": S,
                    "state": "complex64", "timed_iterations": f"{w0}..{w1 - 1} from Hartree-Fock",
                    "launch": "warm-up as captured hipGraph replays, timed iterations as direct launches",
-                   "amps_per_lane": sched},
+                   **_schedule_fields(sched)},
         "algorithmic_amp_updates_per_s": float(f"{upd / dt:.6g}"),
         "algorithmic_amp_updates_note": "2^n (3T + S + 2k + 5ks) string-amplitudes per iteration, whether or "
                                         "not the kernels skip, fuse or factor them",
@@ -643,7 +649,7 @@ def main():
         b3, r3, dt3, _, _ = run_adapt_timed(g, ctx, H, PP, nq, ne, mapping, torch.complex64, args.steps,
                                             args.warmup, schedule=0, sample_every=every)
         out["pauli_pool"] = {"pool_ops": PP.n_ops, "pool_strings": PP.n_strings, "state": "complex64",
-                             "amps_per_lane": b3.schedule, "iters_per_s": round(args.steps / dt3, 3),
+                             **_schedule_fields(b3.schedule), "iters_per_s": round(args.steps / dt3, 3),
                              "algorithmic_amp_updates_per_s": float(
                                  f"{_string_amps(nq, T, PP.n_strings, offp, r3['ops'][w0:w1], r3['substeps'][w0:w1]) / dt3:.6g}"),
                              "final_energy": float(r3["energies"][-1])}

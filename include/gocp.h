@@ -299,9 +299,15 @@ typedef struct {
     double grad_tol;        /* stop when ||g||_2 < grad_tol (0: never)               */
     int32_t max_iter;       /* operators appended at most                            */
     int32_t use_graph;      /* 1: replay captured hipGraphs of the iteration         */
-    int32_t schedule;       /* amplitudes per lane of the tile kernels: 1, 2 or 4;
-                               0 = autotune (time each on the instances, keep the
-                               fastest; remembered per qubit-count mix)             */
+    int32_t schedule;       /* amplitudes per lane of the tile kernels, R = 1, 2
+                               or 4, plus 256 x 4 to run the compacted H v, H w
+                               launch (complex64 states) with 4 workgroups per
+                               tile slot instead of 8; 0 = autotune (R timed on
+                               the instances, the fastest kept and remembered
+                               per qubit-count mix; 4 parts when 8 would give
+                               that launch more than four workgroups per compute
+                               unit).  Results depend on the schedule (the order
+                               of FP64 sums), bit for bit                          */
     int32_t reserved;
 } gocp_adapt_params;
 
@@ -427,7 +433,8 @@ int gocp_batch_result(gocp_batch *b, int32_t i, gocp_adapt_result *res);
  * iteration record), so a run continues exactly as without them.
  */
 int gocp_batch_time_kernel(gocp_batch *b, int32_t which, int32_t n_launch, double *avg_ms);
-/* The schedule the batch runs with (amplitudes per lane; autotuned or given). */
+/* The schedule the batch runs with, in the encoding of
+ * gocp_adapt_params.schedule (autotuned or given). */
 int gocp_batch_schedule(gocp_batch *b, int32_t *amps_per_lane);
 int gocp_batch_destroy(gocp_batch *b);
 
@@ -474,9 +481,11 @@ int gocp_request_bytes(const gocp_ham *h, const gocp_pool *p, int32_t max_iter, 
  * tile kernels run with amps_per_lane (1, 2 or 4) amplitudes per lane, or with
  * 0 a schedule chosen whenever the active set changes: 1 while the set has
  * fewer than four 64-amplitude tiles per compute unit, else 2 (GOCP_C128) or
- * 4 (GOCP_C64).  A request's result is bit-identical to adapt_solve with the
- * same schedule; under the adaptive schedule it can change between steps, so
- * results agree with adapt_solve to rounding.
+ * 4 (GOCP_C64), and the compacted H v, H w launch's parts by the rule of the
+ * autotuned schedule (gocp_adapt_params.schedule).  A request's result is
+ * bit-identical to adapt_solve with the same schedule (amps_per_lane, 8
+ * parts); under the adaptive schedule it can change between steps, so results
+ * agree with adapt_solve to rounding.
  * Errors: EINVAL (non-positive budget, slots or iters_per_step; bad schedule). */
 int gocp_server_create(gocp_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_slots, int dtype,
                        int32_t iters_per_step, int32_t amps_per_lane, gocp_server **out);

@@ -354,7 +354,10 @@ def adapt_solve(ctx: Context, ham: Hamiltonian, pool: Pool, psi, max_iter: int,
                 grad_tol: float = 0.0, use_graph: bool = True, schedule: int = 1):
     """Run ADAPT in place on psi; returns a dict of per-iteration records.
 
-    schedule: amplitudes per lane of the tile kernels (1, 2, 4) or 0 to autotune.
+    schedule: amplitudes per lane of the tile kernels (1, 2, 4), plus 256 * 4
+    for four workgroups per tile slot in the compacted H v, H w launch
+    (complex64 states; 8 otherwise), or 0 to autotune (Batch.schedule reports
+    the choice in this encoding).
     """
     if ham.n_qubits != pool.n_qubits:
         raise ValueError(f"Hamiltonian has {ham.n_qubits} qubits, pool {pool.n_qubits}")

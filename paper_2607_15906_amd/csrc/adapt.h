@@ -82,6 +82,7 @@ struct Group {
     gocp_ctx *ctx = nullptr;
     int dtype = 0;
     int R = 1;                 // amplitudes per lane of the tile kernels
+    int P = kHvwPartsHi;       // workgroups per tile slot of the compacted H v, H w launch
     std::vector<int> ntile;    // tiles of each member for R
     std::vector<int> ngroup;   // tile groups of each member (first reduction stage)
     int ng = 0;
@@ -134,11 +135,13 @@ struct Group {
             di.n_groups = (di.n_tiles + kGroup - 1) / kGroup;
             // members that keep a list of the amplitudes where v or w is
             // nonzero (complex64 states) take the compacted H v, H w launch:
-            // one slot per pair block (at most kHvwSlots) of kHvwParts
-            // workgroups, a function of the member alone, so its results do
-            // not depend on the group it runs in
+            // one slot per pair block (at most kHvwSlots) of P workgroups, a
+            // function of the member and the schedule alone, so its results
+            // do not depend on the group it runs in
+            di.hvw_parts = P;
+            if (P == kHvwPartsLo) di.hsegp = di.hsegp_lo;
             if (di.act) {
-                di.n_lpart = std::min(kHvwSlots, inst[i]->ip.n_pblk) * kHvwParts;
+                di.n_lpart = std::min(kHvwSlots, inst[i]->ip.n_pblk) * P;
                 for (int y = 0; y < di.n_lpart; ++y) ba.push_back(make_int2((int)i, y));
             } else {
                 di.n_lpart = di.n_tiles;
@@ -323,11 +326,24 @@ struct Group {
         return (double)ms / reps;
     }
 
-    // Choose the register blocking (schedule 1, 2 or 4 amplitudes per lane;
-    // 0 = autotune: time each on this group's members and keep the fastest,
-    // remembered per composition of qubit counts and precision).  Call before
-    // start(): the trial launches recompute values start() recomputes.
+    // Choose the schedule: amplitudes per lane R (1, 2 or 4) in the low byte,
+    // the compacted H v, H w launch's parts P in the next (0 for
+    // kHvwPartsHi, or kHvwPartsLo); 0 = autotune: R timed on this group's
+    // members (the fastest kept, remembered per composition of qubit counts
+    // and precision), P by parts_rule().  Call before start(): the trial
+    // launches recompute values start() recomputes.
     void choose_schedule(int schedule, hipStream_t s);
+    // The schedule in the encoding choose_schedule takes.
+    int schedule_code() const { return R | (P == kHvwPartsHi ? 0 : P << 8); }
+    // kHvwPartsLo when the compacted launch would have more than four
+    // workgroups per compute unit with kHvwPartsHi (many instances: fewer,
+    // longer runs per workgroup pay there), else kHvwPartsHi.
+    int parts_rule() const {
+        long rows = 0;
+        for (const Instance *in : inst)
+            if (in->desc.act) rows += (long)std::min(kHvwSlots, in->ip.n_pblk) * kHvwPartsHi;
+        return rows > 4L * ctx->n_cu ? kHvwPartsLo : kHvwPartsHi;
+    }
 
     // Energy, screen and selection of the starting state of the given members.
     void start(const std::vector<int> &members, hipStream_t s) {

@@ -41,12 +41,17 @@ void autotune_store(const std::vector<int> &qubits, int dtype, int R) {
 }
 
 void Group::choose_schedule(int schedule, hipStream_t s) {
-    if (schedule == 1 || schedule == 2 || schedule == 4) {
-        R = schedule;
+    const int r = schedule & 0xff, p = schedule >> 8;
+    if ((r == 1 || r == 2 || r == 4) && (p == 0 || p == kHvwPartsLo)) {
+        R = r;
+        P = p ? p : kHvwPartsHi;
         rebuild(s);
         return;
     }
-    if (schedule != 0) throw Error(GOCP_EINVAL, "schedule must be 0 (autotune), 1, 2 or 4");
+    if (schedule != 0)
+        throw Error(GOCP_EINVAL, "schedule must be 0 (autotune) or 1, 2 or 4 amplitudes per lane, plus 256 x 4 for "
+                                 "four H v, H w parts");
+    P = parts_rule();
     std::vector<int> q;
     for (Instance *in : inst) q.push_back(in->ip.n_qubits);
     int best = autotune_cached(q, dtype);
@@ -364,7 +369,7 @@ int gocp_batch_time_kernel(gocp_batch *b, int32_t which, int32_t n_launch, doubl
 int gocp_batch_schedule(gocp_batch *b, int32_t *amps_per_lane) {
     GOCP_GUARD_BEGIN
     if (!b || !amps_per_lane) throw Error(GOCP_EINVAL, "null argument");
-    *amps_per_lane = b->group.R;
+    *amps_per_lane = b->group.schedule_code();
     return GOCP_OK;
     GOCP_GUARD_END
 }

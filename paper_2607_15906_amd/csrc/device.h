@@ -45,11 +45,15 @@ constexpr int kFactBits = 4;
 // Tiles per group in the first stage of the screen reduction.
 constexpr int kGroup = 16;
 // Compacted H v, H w launch (complex64 states): each tile of 64 active
-// amplitudes is spread over kHvwParts workgroups, each applying 1 / kHvwParts
-// of H's classes; an instance gets at most kHvwSlots tile slots (its
-// workgroups loop over further tiles), and states whose pair blocks number
-// more than kActMaxBlocks use the whole-state launch.
-constexpr int kHvwParts = 8;
+// amplitudes is spread over P workgroups, each applying 1 / P of H's classes,
+// with P (the group's schedule) kHvwPartsHi or kHvwPartsLo: at 14 qubits one
+// instance runs its launch in 6.1 us with 8 and 7.2 us with 4 or 16, while
+// the 64-instance batch runs 8 % faster with 4 (2 is no faster).  An instance
+// gets at most kHvwSlots tile slots (its workgroups loop over further tiles),
+// and states whose pair blocks number more than kActMaxBlocks use the
+// whole-state launch.
+constexpr int kHvwPartsHi = 8;
+constexpr int kHvwPartsLo = 4;
 constexpr int kHvwSlots = 32;
 // Class records per batch of the compacted launch's walk (table values read
 // through the scalar cache): two measured faster than three or four at 14
@@ -150,7 +154,9 @@ struct InstDev {
     const HSub *hsub;
     const int4 *hchunk;         // per LDS stage: class range [x, y), string range [z, w)
     const int32_t *hseg;        // n_hchunks x (kNW + 1) class boundaries of the waves
-    const int32_t *hsegp;       // n_hchunks x (kNW kHvwParts + 1): each wave's run cut into kHvwParts
+    const int32_t *hsegp;       // n_hchunks x (kNW P + 1): each wave's run cut into P = hvw_parts
+    const int32_t *hsegp_lo;    // the same with P = kHvwPartsLo (hsegp holds kHvwPartsHi until a
+                                // group schedule selects this one)
     // the grouped walk's table (one amplitude per lane): per chunk, factored
     // classes' parameter groups, then the other classes' groups of strings
     const double *hcoefG;
@@ -196,6 +202,7 @@ struct InstDev {
     int32_t n_pchunks;
     int32_t n_groups;
     int32_t n_lpart;            // workgroups of the H v, H w launch (partial triples)
+    int32_t hvw_parts;          // P of the compacted H v, H w launch (kHvwPartsHi or kHvwPartsLo)
 };
 
 // Device tables of a Hamiltonian or pool: every array lies in one block of
@@ -210,7 +217,8 @@ struct DeviceHam {
     HSub *hsub = nullptr;
     int4 *hchunk = nullptr;
     int32_t *hseg = nullptr;     // per chunk, kNW + 1 wave boundaries of its classes
-    int32_t *hsegp = nullptr;    // per chunk, kNW kHvwParts + 1 boundaries of the waves' runs
+    int32_t *hsegp = nullptr;    // per chunk, kNW kHvwPartsHi + 1 boundaries of the waves' runs
+    int32_t *hsegp_lo = nullptr; // per chunk, kNW kHvwPartsLo + 1 boundaries
     double *hcoefG = nullptr;    // the grouped walk's table (see InstDev)
     uint32_t *hzsG = nullptr;
     int4 *hchunkG = nullptr;

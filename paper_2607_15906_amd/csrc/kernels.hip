@@ -1571,10 +1571,11 @@ __device__ __forceinline__ void walk_run_scalar(const HClass *hcls, const double
 // line search keeps no H v, H w).  The three dots have v* or w* as left
 // factor, so only amplitudes where v or w is nonzero contribute; k_line_vw
 // lists them per pair block (entries [0, count) of the block's list).
-// Row (instance, slot kHvwParts + part), slot < min(kHvwSlots, pair blocks):
+// Row (instance, slot P + part), P = hvw_parts (a power of two), slot <
+// min(kHvwSlots, pair blocks):
 // the workgroup takes the lists of pair blocks slot, slot + slots, ..., 64
 // entries at a time (one per lane), and wave w applies run `part` of its
-// segment of H's classes (a 1 / (kNW kHvwParts) share of H) with the table
+// segment of H's classes (a 1 / (kNW P) share of H) with the table
 // read through the scalar cache.  Since the dots are linear in H v and H w,
 // each (block, tile, run) adds v* (H_run v) etc. at once; the workgroup writes
 // its partial triple to row y of the line-search partials.  The row count is
@@ -1589,21 +1590,22 @@ __global__ __launch_bounds__(kNW *kWave) __attribute__((amdgpu_waves_per_eu(8)))
     const InstDev *__restrict__ insts, const int2 *__restrict__ blk, int mode) {
     const int2 b = work_row(blk);
     const InstDev &I = insts[b.x];
-    const int slot = b.y / kHvwParts, part = b.y % kHvwParts;
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = wave_id();
     const AdaptState *st = I.st;
-    const int nq = I.n_qubits, nb = I.n_pblk, nhc = I.n_hchunks;
+    const int nq = I.n_qubits, nb = I.n_pblk, nhc = I.n_hchunks, np = I.hvw_parts;
     const int32_t *hsegp = I.hsegp, *act_n = I.act_n;
     const void *vv = I.v, *vw = I.w;
     const uint32_t *act = I.act, *hzs = I.hzs;
     const HClass *hcls = I.hcls;
     const double *hcoef = I.hcoef;
     double *part_l = I.part_l;
-    asm volatile("" ::"s"(st), "s"(nq), "s"(nb), "s"(nhc), "s"(hsegp), "s"(act_n), "s"(vv), "s"(vw), "s"(act),
-                 "s"(hzs), "s"(hcls), "s"(hcoef), "s"(part_l));
+    asm volatile("" ::"s"(st), "s"(nq), "s"(nb), "s"(nhc), "s"(np), "s"(hsegp), "s"(act_n), "s"(vv), "s"(vw),
+                 "s"(act), "s"(hzs), "s"(hcls), "s"(hcoef), "s"(part_l));
+    const int lg = 31 - __clz(np);
+    const int slot = b.y >> lg, part = b.y & (np - 1);
     const int nslot = min(kHvwSlots, nb);
-    const int r0 = wv * kHvwParts + part;
+    const int r0 = wv * np + part;
     constexpr int kList = 2 * kPairBlock;          // list capacity of a pair block
     const int done = cptr(&st->done)[0];
     const int ra = cptr(hsegp)[r0], rb = cptr(hsegp)[r0 + 1];
@@ -1624,7 +1626,7 @@ __global__ __launch_bounds__(kNW *kWave) __attribute__((amdgpu_waves_per_eu(8)))
             const double2 ov = Amp<T>::load(vv, d), ow = Amp<T>::load(vw, d);
             double acc[4] = {0.0, 0.0, 0.0, 0.0};
             for (int k = 0; k < nhc; ++k) {
-                const int r = k * (kNW * kHvwParts + 1) + r0;
+                const int r = k * (kNW * np + 1) + r0;
                 const int c0 = k == 0 ? ra : cptr(hsegp)[r], c1 = k == 0 ? rb : cptr(hsegp)[r + 1];
                 walk_run_scalar<T, kHvwBatch>(hcls, hcoef, hzs, c0, c1, d, vv, vw, acc);
             }

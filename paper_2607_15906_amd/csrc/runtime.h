@@ -50,7 +50,7 @@ void launch_kernel(int which, int dtype, int R, const InstDev *insts, const int2
                    hipStream_t s, int j = 0, double th = 0.0, int ns = 0, hipEvent_t t0 = nullptr,
                    hipEvent_t t1 = nullptr);
 // Compacted H v, H w launch (complex64 states with a compaction list): rows
-// (instance, slot kHvwParts + part); t0 / t1 as for launch_kernel.
+// (instance, slot P + part), P = hvw_parts; t0 / t1 as for launch_kernel.
 void launch_hvw_act(const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s,
                     hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_basis(int dtype, void *psi, uint32_t dim, uint32_t index, hipStream_t s);

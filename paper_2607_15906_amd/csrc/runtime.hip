@@ -299,6 +299,7 @@ DeviceHam place_ham(const TableImage &im, char *base, int device) {
     rebase(d.hchunk, base);
     rebase(d.hseg, base);
     rebase(d.hsegp, base);
+    rebase(d.hsegp_lo, base);
     rebase(d.hcoefG, base);
     rebase(d.hzsG, base);
     rebase(d.hchunkG, base);
@@ -349,14 +350,19 @@ const TableImage &ham_image_locked(const Ham &h) {
     const std::vector<int32_t> ch = stage_chunks(padded_offsets(nc, count));
     std::vector<int> cost(nc);
     for (int c = 0; c < nc; ++c) cost[c] = record_cost(count(c), kClassCost);
-    // each wave's run is further cut into kHvwParts runs of nearly equal cost
-    // (the compacted H v, H w launch spreads a tile's classes over workgroups)
-    std::vector<int32_t> order, seg, segp;
+    // each wave's run is further cut into kHvwPartsHi (and, in a second
+    // table, kHvwPartsLo) runs of nearly equal cost (the compacted H v, H w
+    // launch spreads a tile's classes over workgroups)
+    std::vector<int32_t> order, seg, segp, segp_lo;
     for (size_t k = 0; k + 1 < ch.size(); ++k) {
         const size_t s0 = seg.size();
         wave_split(cost, ch[k], ch[k + 1], order, seg);
-        for (int w = 0; w < kNW; ++w) cut_runs(cost, order, seg[s0 + w], seg[s0 + w + 1], kHvwParts, segp);
+        for (int w = 0; w < kNW; ++w) {
+            cut_runs(cost, order, seg[s0 + w], seg[s0 + w + 1], kHvwPartsHi, segp);
+            cut_runs(cost, order, seg[s0 + w], seg[s0 + w + 1], kHvwPartsLo, segp_lo);
+        }
         segp.push_back(seg[s0 + kNW]);
+        segp_lo.push_back(seg[s0 + kNW]);
     }
     std::vector<HClass> cls;
     std::vector<HSub> sub;
@@ -429,6 +435,7 @@ const TableImage &ham_image_locked(const Ham &h) {
     d->hchunk = pk.add(stage_bounds(ch, cls));
     d->hseg = pk.add(seg);
     d->hsegp = pk.add(segp);
+    d->hsegp_lo = pk.add(segp_lo);
     d->n_chunks = (int)ch.size() - 1;
     pk.finish(*im);
     h.img = im;
@@ -591,8 +598,8 @@ InstPlan plan_instance(int nq, int M, int max_iter, int dtype, bool own_psi, boo
     ip.o_pe2 = a.take((size_t)ip.n_groups * 8);
     ip.o_pn2 = a.take((size_t)ip.n_groups * 8);
     // line-search partials: two per pair block, then three per H v, H w
-    // workgroup (one per tile, or kHvwParts per compacted tile slot)
-    const size_t n_lpart = std::max<size_t>(ip.n_tiles, (size_t)kHvwSlots * kHvwParts);
+    // workgroup (one per tile, or up to kHvwPartsHi per compacted tile slot)
+    const size_t n_lpart = std::max<size_t>(ip.n_tiles, (size_t)kHvwSlots * kHvwPartsHi);
     ip.o_pl = a.take((2 * (size_t)ip.n_pblk + 3 * n_lpart) * 8);
     ip.o_pt = a.take((size_t)ip.n_pblk * 8);
     ip.o_st = a.take(sizeof(AdaptState));
@@ -648,6 +655,7 @@ InstDev make_desc_at(const InstPlan &ip, char *b, const DeviceHam *dh, const Dev
         I.hchunk = dh->hchunk;
         I.hseg = dh->hseg;
         I.hsegp = dh->hsegp;
+        I.hsegp_lo = dh->hsegp_lo;
         I.hcoefG = dh->hcoefG;
         I.hzsG = dh->hzsG;
         I.hchunkG = dh->hchunkG;
@@ -690,6 +698,7 @@ InstDev make_desc_at(const InstPlan &ip, char *b, const DeviceHam *dh, const Dev
     I.n_tiles = ip.n_tiles;
     I.n_pblk = ip.n_pblk;
     I.n_lpart = ip.n_tiles;
+    I.hvw_parts = kHvwPartsHi;
     return I;
 }
 

@@ -217,12 +217,14 @@ void parse_record(Request *r) {
 // than four tiles of 64 amplitudes per compute unit (the launches are then
 // latency-bound and more tiles keep more units busy); otherwise wider blocking,
 // which cuts the work per amplitude (2 for complex128 states, whose widest
-// blocking runs short of registers; 4 for complex64).
+// blocking runs short of registers; 4 for complex64).  The compacted H v, H w
+// launch's parts follow the group's parts rule.
 void gocp_server::choose_schedule() {
     if (schedule != 0) return;
     long tiles = 0;
     for (gocp::Request *r : active) tiles += gocp::tiles_for(r->ip.n_qubits, 1);
     group.R = tiles < 4L * ctx->n_cu ? 1 : (dtype == GOCP_C128 ? 2 : 4);
+    group.P = group.parts_rule();
 }
 
 // Admit queued requests in arrival order while a slot is free and a block

@@ -43,7 +43,9 @@ def _psi(nq, hf, dtype):
     return t
 
 
-@pytest.mark.parametrize("schedule", [1, 2, 4])
+# schedules: amplitudes per lane, plus 256 * 4 for four workgroups per tile
+# slot in the compacted H v, H w launch
+@pytest.mark.parametrize("schedule", [1, 2, 4, 1 + 4 * 256, 4 + 4 * 256])
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 def test_batched_equals_solo(g, ctx, dtype, schedule):
     _say(f"[batch] mixed sizes {dtype} schedule={schedule}")
@@ -89,6 +91,38 @@ def test_autotuned_schedule_is_kept_and_matches_solo(g, ctx):
         assert np.array_equal(b.result(k)["energies"], rs["energies"])
         assert torch.equal(psis[k], solo)
     b.close()
+
+
+def test_autotune_takes_four_parts_for_a_large_batch(g, ctx):
+    """Eight 14-qubit complex64 instances would give the compacted H v, H w
+    launch 2048 workgroups with eight parts (more than four per compute
+    unit), so the autotuned schedule takes four; members equal their solo runs
+    with that schedule."""
+    _say("[batch] autotune parts")
+    insts = [_inst(g, 14, "jw" if k % 2 else "bk", 61 + k) for k in range(8)]
+    psis = [_psi(14, hf, torch.complex64) for (_, _, hf, _) in insts]
+    b = g.Batch(ctx, [i[0] for i in insts], [i[1] for i in insts], psis, max_iter=10, schedule=0)
+    code = b.schedule
+    assert code >> 8 == 4 and code & 0xFF in (1, 2, 4)
+    b.run()
+    assert b.poll() == 0
+    for k in (0, 3):
+        H, P, hf, nq = insts[k]
+        solo = _psi(nq, hf, torch.complex64)
+        rs = g.adapt_solve(ctx, H, P, solo, 10, schedule=code)
+        rb = b.result(k)
+        assert rb["ops"] == rs["ops"]
+        assert np.array_equal(rb["energies"], rs["energies"])
+        assert torch.equal(psis[k], solo)
+    b.close()
+
+
+def test_bad_schedule_codes_rejected(g, ctx):
+    H, P, hf, nq = _inst(g, 6, "jw", 7)
+    for code in (3, 8, 1 + 8 * 256, 1 + 2 * 256, 1 + (1 << 16), -1):
+        with pytest.raises(g.GocpError) as e:
+            g.adapt_solve(ctx, H, P, _psi(nq, hf, torch.complex64), 2, schedule=code)
+        assert e.value.code == -1
 
 
 def test_batch_run_stops_when_all_converged(g, ctx):

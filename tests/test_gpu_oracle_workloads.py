@@ -201,11 +201,13 @@ def test_16q_two_adapt_iterations_against_oracle(g, ctx, mapping):
 # --------------------------------------------------------------- batch and serving members
 
 @pytest.mark.timeout(300)
-@pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_batch_members_against_oracle(g, ctx, dtype):
+@pytest.mark.parametrize("dtype,schedule", [("c128", 0), ("c64", 0), ("c64", 4 + 4 * 256)])
+def test_batch_members_against_oracle(g, ctx, dtype, schedule):
     """A mixed batch (the batched workload's sizes, both mappings) at its
-    autotuned schedule; two members followed through 30 iterations."""
-    _say(f"[oracle-workload] batch members {dtype}")
+    autotuned schedule, and for complex64 also at four amplitudes per lane
+    with four H v / H w parts (the batched workload's choice); two members
+    followed through 30 iterations."""
+    _say(f"[oracle-workload] batch members {dtype} schedule {schedule}")
     specs = [(10, "jw", 1000), (10, "bk", 1001), (12, "jw", 1024), (12, "bk", 1025),
              (14, "jw", 1048), (14, "bk", 1049)]
     ss = [system(g, nq, m, seed) for (nq, m, seed) in specs]
@@ -216,7 +218,7 @@ def test_batch_members_against_oracle(g, ctx, dtype):
         g.state_basis(ctx, s["nq"], s["hf"], t)
         psis.append(t)
     iters = 30
-    b = g.Batch(ctx, [s["gH"] for s in ss], [s["gP"] for s in ss], psis, max_iter=iters, schedule=0)
+    b = g.Batch(ctx, [s["gH"] for s in ss], [s["gP"] for s in ss], psis, max_iter=iters, schedule=schedule)
     b.run()
     assert b.poll() == 0
     for k in (1, 2):
