@@ -350,7 +350,7 @@ def serving_block(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, loads=(0.
     times that capacity, `warm` warm-up requests first (excluded from the
     figures), then `n_req` measured ones.  Latency is submission to
     completion on the library's clock; the baseline is sequential plain FP64
-    adapt_solve on the same device.  A second capacity run serves the same
+    adapt_solve on the same device, each solve at its autotuned schedule.  A second capacity run serves the same
     requests with the other state precision."""
     import numpy as np
     import torch
@@ -442,11 +442,17 @@ def serving_block(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, loads=(0.
     other = 1 - code
     cap_other, done_other = capacity(other)
 
-    # sequential plain FP64: one adapt_solve at a time, complex128
+    # sequential plain FP64: one adapt_solve at a time, complex128, each at
+    # the schedule the autotuner picks for its size (chosen during the
+    # warm-up requests, which cover every size, and remembered)
+    for (d, H, P, _) in reqs[:warm]:
+        psi = _hf_state(g, ctx, d["n_qubits"], d["n_electrons"], d["mapping"], torch.complex128)
+        g.adapt_solve(ctx, H, P, psi, max_iter, grad_tol=tol, schedule=0)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for (d, H, P, _) in reqs[warm:]:
         psi = _hf_state(g, ctx, d["n_qubits"], d["n_electrons"], d["mapping"], torch.complex128)
-        g.adapt_solve(ctx, H, P, psi, max_iter, grad_tol=tol)
+        g.adapt_solve(ctx, H, P, psi, max_iter, grad_tol=tol, schedule=0)
     torch.cuda.synchronize()
     seq = n_req / (time.perf_counter() - t0)
     cap_dt = n_req / cap

@@ -804,9 +804,17 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
 
     __shared__ Stage S;
     __shared__ double2 s_sig[R][kWave];
-    __shared__ double gpart[kStageCls];
     __shared__ double opbuf[kNW][4][kWave];   // per wave: lane contributions of up to four operators
 
+    // Stage chunk k of the screen's tables (operator records, sub-buckets
+    // for R > 1, magnitudes) into S; the caller orders it with barriers.
+    const GOCP_AS4 int4 *pch = cptr(I.pchunk);
+    auto stage_screen = [&](int k) {
+        const int4 bd = load_rec(pch, k);
+        stage_copy(S.cls, I.sop + bd.x, bd.y - bd.x);
+        if (R > 1) stage_copy(S.sub, I.psub + bd.x, bd.y - bd.x);
+        stage_coef(S, I.scoef, bd.z, bd.w);
+    };
     // 1. sigma on the tile: H psi, or, after an update, sigma carried through
     //    it (the update is I + al A + be A^2 on scale * psi, so
     //    H psi' = scale (sigma + al H w - be H v) with the line search's H v,
@@ -824,7 +832,10 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
 #pragma unroll
         for (int i = 0; i < 2 * R; ++i) acc[i] = 0.0;
         apply_classes<T, 1, R>(I, S, d0, dim, I.psi, nullptr, acc);
-        double2 (*red)[kWave] = reinterpret_cast<double2 (*)[kWave]>(&S);
+        // the cross-wave sums go through the operator buffers, so the screen's
+        // first stage chunk is staged meanwhile
+        double2 (*red)[kWave] = reinterpret_cast<double2 (*)[kWave]>(&opbuf[0][0][0]);
+        if (screen) stage_screen(0);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             red[wv][lane] = make_double2(acc[2 * r], acc[2 * r + 1]);
@@ -849,6 +860,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
             __syncthreads();
         }
     } else {
+        if (screen) stage_screen(0);
         if (wv == 0) {
             const double al = cptr(&st->upd_alpha)[0], be = cptr(&st->upd_beta)[0];
             const double sc = cptr(&st->upd_scale)[0];
@@ -884,22 +896,20 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
         double2 sg[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) sg[r] = s_sig[r][lane];
-        const HClass *sop = I.sop;
-        const double *scoef = I.scoef;
         const uint32_t *szs = I.szs;
         const int32_t *pseg = I.pseg;
         const int npc = I.n_pchunks;
-        const GOCP_AS4 int4 *pch = cptr(I.pchunk);
         for (int k = 0; k < npc; ++k) {
             const int4 bd = load_rec(pch, k);
-            const int ob = bd.x, oe = bd.y, sb = bd.z, se = bd.w;
-            __syncthreads();
-            stage_copy(S.cls, sop + ob, oe - ob);
-            if (R > 1) stage_copy(S.sub, I.psub + ob, oe - ob);
-            stage_coef(S, scoef, sb, se);
+            const int ob = bd.x, sb = bd.z;
+            // chunk 0 was staged with the sigma sums (the barrier after them
+            // ordered it); later chunks after the previous one's walk
+            if (k > 0) {
+                __syncthreads();
+                stage_screen(k);
+                __syncthreads();
+            }
             const GOCP_AS4 uint32_t *zs = cptr(szs) + sb;
-            __syncthreads();
-            const int no = oe - ob;
             int o0, o1;
             wave_range(pseg, k, ob, o0, o1);
             // Per-operator sums over the wave's 64 amplitudes, four operators
@@ -915,7 +925,8 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                 const int r = lane >> 4, q = (lane & 15) * 4;
                 const double t4 = (opbuf[wv][r][q] + opbuf[wv][r][q + 1]) + (opbuf[wv][r][q + 2] + opbuf[wv][r][q + 3]);
                 const double t = row_sum(r < nbuf ? t4 : 0.0);
-                if ((lane & 15) == 0 && r < nbuf) gpart[obase + r] = t;
+                // the operator's partial goes straight to its pool index
+                if ((lane & 15) == 0 && r < nbuf) I.part_g[(size_t)b.y * M + S.cls[obase + r].pad] = t;
                 nbuf = 0;
             };
             auto push = [&](int o, double v) {
@@ -961,10 +972,6 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
             }
             }
             if (nbuf > 0) flush();
-            __syncthreads();
-            // wave 0 writes this stage's per-operator partials (pool-indexed)
-            if (wv == 0)
-                for (int i = lane; i < no; i += kWave) I.part_g[(size_t)b.y * M + S.cls[i].pad] = gpart[i];
         }
     }
 }
