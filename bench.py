@@ -477,6 +477,37 @@ def serving_block(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, loads=(0.
                                   "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 5)}}
 
 
+def _phase_trace(g, ctx, H, P, nq, ne, mapping, warm, iters):
+    """Phase durations of the energy+screen launch (one amplitude per lane),
+    from the measurement build's per-workgroup clock values (100 MHz): for
+    each of `iters` ADAPT iterations after `warm`, the median over workgroups
+    of each phase, then the median over iterations, in us."""
+    import numpy as np
+    import torch
+    names = ["launch ramp (first entry to workgroup entry)", "prologue (descriptor, state record)",
+             "H stage (first chunk of magnitudes into LDS)", "H walk (to the last wave's end)",
+             "sigma, energy partials, screen stage", "screen walk (to the last wave's end)"]
+    psi = _hf_state(g, ctx, nq, ne, mapping, torch.complex64)
+    b = g.Batch(ctx, [H], [P], [psi], max_iter=warm + iters, use_graph=False, schedule=1)
+    tiles = (1 << nq) // 64
+    b.step(warm)
+    per = []
+    for _ in range(iters):
+        b.step(1)
+        t = g.phase_trace(ctx, tiles).astype(np.int64)
+        t0 = t[:, 0].min()
+        edges = np.concatenate([np.full((tiles, 1), t0), t], axis=1)
+        per.append(np.median(np.diff(edges, axis=1), axis=0) * 0.01)
+        per[-1] = np.append(per[-1], (t[:, 5].max() - t0) * 0.01)
+    b.close()
+    med = np.median(np.array(per), axis=0)
+    out = {n: round(float(v), 3) for n, v in zip(names, med[:6])}
+    out["first entry to the last workgroup's end"] = round(float(med[6]), 3)
+    out["iterations"] = f"{warm}..{warm + iters - 1} from Hartree-Fock"
+    out["workgroups"] = tiles
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -500,6 +531,10 @@ def main():
     ap.add_argument("--oracle-workers", type=int, default=0,
                     help="worker processes of the batched oracle baseline (0: min(16, CPUs))")
     ap.add_argument("--batch-oracle-iters", type=int, default=4)
+    ap.add_argument("--phase-trace", type=int, default=0, metavar="ITERS",
+                    help="only the energy+screen launch's phase trace over ITERS iterations of the headline "
+                         "system (needs the measurement build: GOCP_PHASE_TRACE=1 after "
+                         "python -m paper_2607_15906_amd.build --phase-trace)")
     ap.add_argument("--fused-step-only", action="store_true",
                     help="time only the GOCP multi-operator step against single chains (kernel profiling)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -525,11 +560,11 @@ def main():
     # CPU legs first: nothing has touched the GPU yet, so the oracle worker
     # processes can be forked safely
     oracle = None
-    if args.cpu_sample_iters > 0 and not args.fused_step_only:
+    if args.cpu_sample_iters > 0 and not args.fused_step_only and not args.phase_trace:
         _say(f"[bench] CPU oracle: {args.cpu_sample_iters} iterations at 14q (one thread)")
         oracle = oracle_headline(nq, ne, mapping, seed, args.cpu_sample_iters)
     batch_oracle = None
-    if not args.no_forms and not args.fused_step_only and args.batch_oracle_iters > 0:
+    if not args.no_forms and not args.fused_step_only and not args.phase_trace and args.batch_oracle_iters > 0:
         workers = args.oracle_workers or min(16, os.cpu_count() or 1)
         _say(f"[bench] CPU oracle: batched instances on {workers} workers")
         batch_oracle = oracle_batch_baseline(args.batch_oracle_iters, workers)
@@ -550,6 +585,10 @@ def main():
     H, P = _system(g, nq, ne, mapping, seed)
     if args.fused_step_only:
         print(json.dumps({"gocp_fused_step": _fused_step_timing(g, ctx, P, nq, reps=50)}))
+        return
+    if args.phase_trace:
+        print(json.dumps({"phase_trace": _phase_trace(g, ctx, H, P, nq, ne, mapping, args.warmup,
+                                                      args.phase_trace)}))
         return
     off = P.strings()[0]
     T, C, S, M = H.n_terms, H.n_classes, P.n_strings, P.n_ops

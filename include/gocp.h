@@ -187,6 +187,17 @@ int gocp_ctx_destroy(gocp_ctx *ctx);
 int gocp_ctx_set_stream(gocp_ctx *ctx, void *stream);
 /* Block until all work queued on the context's stream has finished. */
 int gocp_ctx_synchronize(gocp_ctx *ctx);
+/* Phase trace of the energy+screen launch, for measurement (a library built
+ * with GOCP_PHASE_TRACE defined; ENOTSUP from any other build).  Such a build
+ * records, in every ADAPT-iteration launch of that kernel, the device's
+ * constant-rate clock (100 MHz) at *n_phases = 6 points of each of its first
+ * 1024 workgroups: entry, end of the prologue, H stage written, end of the H
+ * walk in the workgroup's last wave, sigma and energy partials done, end of
+ * the screen in the last wave; later launches overwrite earlier ones.
+ * Synchronises the context stream, then copies n_rows x 6 values (row =
+ * workgroup) to the caller's host array `out`.  Errors: EINVAL (null out,
+ * n_rows outside 1..1024), ENOTSUP. */
+int gocp_phase_trace(gocp_ctx *ctx, uint64_t *out, int32_t n_rows, int32_t *n_phases);
 
 /* Write the basis state |index> into psi_dev (2^n_qubits amplitudes). */
 int gocp_state_basis(gocp_ctx *ctx, int n_qubits, uint64_t index, void *psi_dev, int dtype);

@@ -6,7 +6,10 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgocp.so")
+# GOCP_PHASE_TRACE=1 selects the measurement build that records the
+# energy+screen launch's phase trace (python -m paper_2607_15906_amd.build
+# --phase-trace); the product library otherwise
+LIB_PATH = os.path.join(_HERE, "libgocp_trace.so" if os.environ.get("GOCP_PHASE_TRACE") == "1" else "libgocp.so")
 
 GOCP_OK = 0
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESHAPE",
@@ -107,6 +110,7 @@ SIGNATURES = {
     "gocp_server_poll": [_P, C.c_uint64, C.POINTER(AdaptResult), C.POINTER(RequestInfo)],
     "gocp_server_stats": [_P, _I32P, _I32P, _I64P, _I64P, _I64P],
     "gocp_server_destroy": [_P],
+    "gocp_phase_trace": [_P, C.POINTER(C.c_uint64), C.c_int32, _I32P],
 }
 
 _lib = None
@@ -118,7 +122,8 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"libgocp.so not built at {LIB_PATH}; run `python -m paper_2607_15906_amd.build`")
+        raise ImportError(f"{os.path.basename(LIB_PATH)} not built at {LIB_PATH}; run "
+                          "`python -m paper_2607_15906_amd.build` (with --phase-trace for the trace build)")
     lib = C.CDLL(LIB_PATH)
     lib.gocp_last_error.restype = C.c_char_p
     lib.gocp_last_error.argtypes = []

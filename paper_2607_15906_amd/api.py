@@ -19,7 +19,8 @@ __all__ = ["MAPPINGS", "Hamiltonian", "Pool", "Context", "pauli_hamiltonian_load
            "basis_occupation", "state_hf", "sector_weight",
            "state_basis", "energy", "apply_hamiltonian", "pool_gradients", "pool_gradients_noalloc",
            "taylor5_apply",
-           "adapt_solve", "adapt_reopt_solve", "Batch", "Server", "request_footprint", "version"]
+           "adapt_solve", "adapt_reopt_solve", "Batch", "Server", "request_footprint", "version",
+           "phase_trace"]
 
 MAPPINGS = {"jw": 0, "bk": 1, 0: 0, 1: 1}
 C128, C64 = 0, 1
@@ -41,6 +42,17 @@ def _ptr(a, ctype):
 
 def version() -> int:
     return load().gocp_version()
+
+
+def phase_trace(ctx: "Context", n_rows: int) -> np.ndarray:
+    """The energy+screen launch's phase timestamps (gocp_phase_trace): an
+    (n_rows, 6) uint64 array of 100 MHz clock values per workgroup, from the
+    measurement build only (GocpError ENOTSUP otherwise)."""
+    out = np.zeros((int(n_rows), 6), dtype=np.uint64)
+    nph = C.c_int32()
+    check(load().gocp_phase_trace(ctx.handle, out.ctypes.data_as(C.POINTER(C.c_uint64)), int(n_rows),
+                                  C.byref(nph)))
+    return out[:, :nph.value]
 
 
 class Hamiltonian:

@@ -2,7 +2,9 @@
 
 Usage: ``python -m paper_2607_15906_amd.build`` (or ``build()`` from Python).
 Objects go to ``_build/`` at the repository root; the shared library is
-written next to this file.
+written next to this file.  ``--phase-trace`` builds the measurement variant
+``libgocp_trace.so`` instead (GOCP_PHASE_TRACE defined: the energy+screen
+launch records its phase timestamps; objects in ``_build/trace``).
 """
 
 from __future__ import annotations
@@ -44,28 +46,32 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libgocp.so; returns the library path."""
+def build(verbose: bool = False, phase_trace: bool = False) -> str:
+    """Compile every source and link libgocp.so (libgocp_trace.so with
+    phase_trace); returns the library path."""
     if not os.path.exists(HIPCC):
         raise RuntimeError(f"hipcc not found at {HIPCC}")
-    os.makedirs(BUILD, exist_ok=True)
+    bdir = os.path.join(BUILD, "trace") if phase_trace else BUILD
+    lib = os.path.join(PKG, "libgocp_trace.so") if phase_trace else LIB
+    hip_flags = HIP_FLAGS + (["-DGOCP_PHASE_TRACE"] if phase_trace else [])
+    os.makedirs(bdir, exist_ok=True)
     objs = []
     for src in HOST_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
+        obj = os.path.join(bdir, src + ".o")
         _run(["g++", *COMMON, "-Wall", "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in HIP_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
-        out = _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        obj = os.path.join(bdir, src + ".o")
+        out = _run([HIPCC, *hip_flags, "-c", os.path.join(CSRC, src), "-o", obj])
         if verbose and out.strip():
             print(out)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
           f"-L{ROCM}/lib", "-lamdhip64", "-lpthread", f"-Wl,-rpath,{ROCM}/lib"])
-    shutil.move(tmp, LIB)
-    return LIB
+    shutil.move(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, phase_trace="--phase-trace" in sys.argv))

@@ -42,6 +42,10 @@ constexpr int kPairGroup = 8;
 // X mask carries this flag.
 constexpr uint32_t kFactBit = 0x80000000u;
 constexpr int kFactBits = 4;
+// Phase trace of the energy+screen launch (builds with GOCP_PHASE_TRACE):
+// workgroups recorded and points per workgroup.
+constexpr int kPhaseRows = 1024;
+constexpr int kPhases = 6;
 // Tiles per group in the first stage of the screen reduction.
 constexpr int kGroup = 16;
 // Compacted H v, H w launch (complex64 states): each tile of 64 active

@@ -34,6 +34,29 @@
 
 namespace gocp {
 
+// ------------------------------------------------------------------ phase trace
+
+// Builds with GOCP_PHASE_TRACE record, for every ADAPT-iteration launch of the
+// energy+screen kernel, the device's constant-rate clock (s_memrealtime) at
+// kPhases points of each workgroup (kPhaseRows rows; a later launch overwrites
+// them): the entry, the end of the prologue, the H stage written, the end of
+// the H walk in the last wave, sigma and the energy partials done, the end of
+// the screen in the last wave.  Other builds record nothing.
+#ifdef GOCP_PHASE_TRACE
+__device__ unsigned long long g_phase[kPhaseRows * kPhases];
+__device__ __forceinline__ void phase_mark(int slot, int mode) {
+    if (mode == 2 && threadIdx.x == 0 && blockIdx.x < kPhaseRows)
+        ((volatile unsigned long long *)g_phase)[blockIdx.x * kPhases + slot] = __builtin_amdgcn_s_memrealtime();
+}
+__device__ __forceinline__ void phase_mark_last(int slot, int mode) {
+    if (mode == 2 && (threadIdx.x & (kWave - 1)) == 0 && blockIdx.x < kPhaseRows)
+        atomicMax(&g_phase[blockIdx.x * kPhases + slot], __builtin_amdgcn_s_memrealtime());
+}
+#else
+__device__ __forceinline__ void phase_mark(int, int) {}
+__device__ __forceinline__ void phase_mark_last(int, int) {}
+#endif
+
 // ------------------------------------------------------------------ helpers
 
 // Global-memory loads go through the global address space (not flat), so
@@ -669,7 +692,7 @@ __device__ __forceinline__ void wave_range(const int32_t *seg, int k, int cb, in
 // class's strings are summed.
 template <typename T, int NV, int R>
 __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32_t d0, uint32_t dim,
-                                              const void *v0, const void *v1, double *acc) {
+                                              const void *v0, const void *v1, double *acc, int trace_mode = 0) {
     const int wv = wave_id();
     const GOCP_AS4 int4 *hch = cptr(I.hchunk);
     for (int k = 0; k < I.n_hchunks; ++k) {
@@ -688,6 +711,7 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
         else stage_coef(S, I.hcoef, sb, se);
         const GOCP_AS4 uint32_t *zs = cptr(I.hzs) + sb;
         __syncthreads();
+        if (k == 0) phase_mark(2, trace_mode);
         if constexpr (grouped) {
             // the wave's run of factored classes, then its run of string groups
             const int gb = gbd.x / kStrGroup;
@@ -780,6 +804,7 @@ __device__ __forceinline__ uint32_t insert_zero_bit(uint32_t p, int hb) {
 template <typename T, int R>
 __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__restrict__ insts,
                                                              const int2 *__restrict__ blk, int mode) {
+    phase_mark(0, mode);
     const int2 b = work_row(blk);
     const InstDev &I = insts[b.x];
     AdaptState *st = I.st;
@@ -831,7 +856,9 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
         double acc[2 * R];
 #pragma unroll
         for (int i = 0; i < 2 * R; ++i) acc[i] = 0.0;
-        apply_classes<T, 1, R>(I, S, d0, dim, I.psi, nullptr, acc);
+        phase_mark(1, mode);
+        apply_classes<T, 1, R>(I, S, d0, dim, I.psi, nullptr, acc, mode);
+        phase_mark_last(3, mode);
         // the cross-wave sums go through the operator buffers, so the screen's
         // first stage chunk is staged meanwhile
         double2 (*red)[kWave] = reinterpret_cast<double2 (*)[kWave]>(&opbuf[0][0][0]);
@@ -891,6 +918,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
         }
     }
 
+    phase_mark(4, mode);
     // 2. gradient screen on the tile
     if (screen) {
         double2 sg[R];
@@ -974,6 +1002,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
             if (nbuf > 0) flush();
         }
     }
+    phase_mark_last(5, mode);
 }
 
 // The screen's partials are summed in two launches that follow
@@ -2190,6 +2219,19 @@ void launch_kernel(int which, int dtype, int R, const InstDev *insts, const int2
     else
         launch_all<double2>(which, R, insts, blk, nblk, mode, s, j, th, ns, t0, t1);
     hip_check(hipGetLastError(), "kernel launch");
+}
+
+bool phase_trace_read(unsigned long long *out, size_t n) {
+#ifdef GOCP_PHASE_TRACE
+    hip_check(hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), n * sizeof(unsigned long long), 0,
+                                  hipMemcpyDeviceToHost),
+              "hipMemcpyFromSymbol(phase trace)");
+    return true;
+#else
+    (void)out;
+    (void)n;
+    return false;
+#endif
 }
 
 void launch_hvw_act(const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s, hipEvent_t t0,

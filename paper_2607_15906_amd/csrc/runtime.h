@@ -54,6 +54,9 @@ void launch_kernel(int which, int dtype, int R, const InstDev *insts, const int2
 void launch_hvw_act(const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s,
                     hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_basis(int dtype, void *psi, uint32_t dim, uint32_t index, hipStream_t s);
+// Copy n values of the phase trace (kPhaseRows x kPhases) from the current
+// device; false in builds without GOCP_PHASE_TRACE.
+bool phase_trace_read(unsigned long long *out, size_t n);
 void launch_scale_copy(int dtype, const void *src, void *dst, uint32_t dim, double scale, hipStream_t s);
 void launch_sector_weight(int dtype, const void *psi, uint32_t dim, const SectorRows &rows, double *part, int nblk,
                           hipStream_t s);

@@ -899,6 +899,19 @@ int gocp_ctx_set_stream(gocp_ctx *ctx, void *stream) {
     GOCP_GUARD_END
 }
 
+int gocp_phase_trace(gocp_ctx *ctx, uint64_t *out, int32_t n_rows, int32_t *n_phases) {
+    GOCP_GUARD_BEGIN
+    check_ctx(ctx);
+    if (n_phases) *n_phases = kPhases;
+    if (!out || n_rows <= 0 || n_rows > kPhaseRows) throw Error(GOCP_EINVAL, "bad phase trace buffer");
+    hip_check(hipStreamSynchronize(ctx->user_stream), "hipStreamSynchronize");
+    static_assert(sizeof(uint64_t) == sizeof(unsigned long long), "64-bit clock values");
+    if (!phase_trace_read(reinterpret_cast<unsigned long long *>(out), (size_t)n_rows * kPhases))
+        throw Error(GOCP_ENOTSUP, "this library records no phase trace (build it with GOCP_PHASE_TRACE)");
+    return GOCP_OK;
+    GOCP_GUARD_END
+}
+
 int gocp_ctx_synchronize(gocp_ctx *ctx) {
     GOCP_GUARD_BEGIN
     check_ctx(ctx);

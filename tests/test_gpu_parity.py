@@ -261,6 +261,17 @@ def test_adapt_register_blocked_schedules(g, ctx, schedule, nq, mapping):
     _check_against_oracle(s, r, psi, iters)
 
 
+def test_phase_trace_only_in_the_measurement_build(g, ctx):
+    """The product library records no phase trace: a valid request is
+    ENOTSUP, a bad row count EINVAL."""
+    with pytest.raises(g.GocpError) as e:
+        g.phase_trace(ctx, 0)
+    assert e.value.code == -1
+    with pytest.raises(g.GocpError) as e:
+        g.phase_trace(ctx, 4)
+    assert e.value.code == -5
+
+
 def test_adapt_bad_schedule_rejected(g, ctx):
     s = system(g, 4, "jw")
     with pytest.raises(g.GocpError) as e:
