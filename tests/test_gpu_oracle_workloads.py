@@ -198,6 +198,18 @@ def test_16q_two_adapt_iterations_against_oracle(g, ctx, mapping):
     compare_record(o, r, t.cpu().numpy(), "c128")
 
 
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("schedule", [1, 1 + 4 * 256])
+def test_16q_complex64_compacted_line_search_against_oracle(g, ctx, schedule):
+    """Complex64 at 16 qubits: H spans two LDS stage chunks, so the compacted
+    H v / H w launch walks the run tables of both chunks (8 or 4 parts)."""
+    _say(f"[oracle-workload] 16q c64 schedule {schedule}")
+    s = system(g, 16, "jw", 16)
+    r, t = run_gpu(g, ctx, s, 3, "c64", schedule=schedule)
+    o = oracle_following(s, r, 3)
+    compare_record(o, r, t.cpu().numpy().astype(np.complex128), "c64")
+
+
 # --------------------------------------------------------------- batch and serving members
 
 @pytest.mark.timeout(300)
