@@ -474,7 +474,9 @@ class Batch:
         return r.value
 
     def time_kernel(self, which: int, n_launch: int) -> float:
-        """Mean duration in ms of kernel `which` (0 H apply, 1 screen, 2 H v/H w)."""
+        """Mean duration in ms of launch `which` (gocp_batch_time_kernel: 0 energy and screen partials
+        with a fresh H psi, 1 H v / H w of the line search, 2 the partials with sigma carried, 3 the
+        reduction of the partials)."""
         ms = C.c_double()
         check(load().gocp_batch_time_kernel(self._b, int(which), int(n_launch), C.byref(ms)))
         return ms.value

@@ -1539,24 +1539,29 @@ __global__ __launch_bounds__(kNW *kWave) __attribute__((amdgpu_waves_per_eu(8)))
     line_hvw<T, 1>(insts, blk, mode);
 }
 
-// H applied to two vectors at the lane's amplitude d over the records
-// [c0, c1) of H's class table (global indices), every table value read
-// through the scalar cache (no LDS staging):
-//   acc[2 v + {0,1}] += f_c(d) vec_v(d ^ x_c),  v = 0, 1.
+// H applied to two vectors at the lane's amplitudes d[a], a < C, over the
+// records [c0, c1) of H's class table (global indices), every table value
+// read through the scalar cache (no LDS staging):
+//   acc[a][2 v + {0,1}] += f_c(d[a]) vec_v(d[a] ^ x_c),  v = 0, 1.
 // NB records per batch: the batch's records are read in one go, then every
-// record's first string group and its two gathers are issued together, then
-// the strings are summed (a record's further groups are read where they are
-// used).  Records past c1 re-read the run's last record and are not summed.
+// record's first string group and the gathers of all C amplitudes are issued
+// together, then the strings are summed (a record's further groups are read
+// where they are used); each record's table values serve all C amplitudes.
+// Records past c1 re-read the run's last record and are not summed.
 // Factored classes (kFactBit) hold one group of parameters (see fact_h).
-template <typename T, int NB>
+template <typename T, int NB, int C>
 __device__ __forceinline__ void walk_run_scalar(const HClass *hcls, const double *hcoef, const uint32_t *hzs,
-                                                int c0, int c1, uint32_t d, const void *v0, const void *v1,
-                                                double (&acc)[4]) {
+                                                int c0, int c1, const uint32_t (&d)[C], const void *v0,
+                                                const void *v1, double (&acc)[C][4]) {
     using Raw = typename Amp<T>::Raw;
     if (c0 >= c1) return;
-    uint32_t doff = d << Amp<T>::kShift;
-    asm volatile("" : "+v"(doff));      // keep the shifted offset: one XOR per gather
-    const uint32_t dz = with_sign_bit(d);
+    uint32_t doff[C], dz[C];
+#pragma unroll
+    for (int a = 0; a < C; ++a) {
+        doff[a] = d[a] << Amp<T>::kShift;
+        asm volatile("" : "+v"(doff[a]));      // keep the shifted offset: one XOR per gather
+        dz[a] = with_sign_bit(d[a]);
+    }
     const GOCP_AS4 HClass *rec = cptr(hcls);
     const GOCP_AS4 double *co = cptr(hcoef);
     const GOCP_AS4 uint32_t *zs = cptr(hzs);
@@ -1566,12 +1571,15 @@ __device__ __forceinline__ void walk_run_scalar(const HClass *hcls, const double
         for (int k = 0; k < NB; ++k) r[k] = load_rec(rec, min(c + k, c1 - 1));
         double cm[NB][kStrGroup];
         uint32_t zm[NB][kStrGroup];
-        Raw p[NB][2];
+        Raw p[NB][C][2];
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
-            const uint32_t o = doff ^ (r[k].x << Amp<T>::kShift);
-            p[k][0] = Amp<T>::raw_at(v0, o);
-            p[k][1] = Amp<T>::raw_at(v1, o);
+#pragma unroll
+            for (int a = 0; a < C; ++a) {
+                const uint32_t o = doff[a] ^ (r[k].x << Amp<T>::kShift);
+                p[k][a][0] = Amp<T>::raw_at(v0, o);
+                p[k][a][1] = Amp<T>::raw_at(v1, o);
+            }
 #pragma unroll
             for (int q = 0; q < kStrGroup; ++q) {
                 cm[k][q] = co[r[k].s0 + q];
@@ -1581,24 +1589,35 @@ __device__ __forceinline__ void walk_run_scalar(const HClass *hcls, const double
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
             if (c + k >= c1) break;
-            double f;
+            double f[C];
             if (r[k].x & kFactBit) {
-                f = fact_h(cm[k][0], zm[k][0], zm[k][1], zm[k][2], dz);
+#pragma unroll
+                for (int a = 0; a < C; ++a) f[a] = fact_h(cm[k][0], zm[k][0], zm[k][1], zm[k][2], dz[a]);
             } else {
-                double f0 = signed_cz(cm[k][0], zm[k][0], dz) + signed_cz(cm[k][2], zm[k][2], dz);
-                double f1 = signed_cz(cm[k][1], zm[k][1], dz) + signed_cz(cm[k][3], zm[k][3], dz);
-                for (int q = r[k].s0 + kStrGroup; q < r[k].s1; q += kStrGroup) {
-                    f0 += signed_cz(co[q], zs[q], dz) + signed_cz(co[q + 2], zs[q + 2], dz);
-                    f1 += signed_cz(co[q + 1], zs[q + 1], dz) + signed_cz(co[q + 3], zs[q + 3], dz);
+                double f0[C], f1[C];
+#pragma unroll
+                for (int a = 0; a < C; ++a) {
+                    f0[a] = signed_cz(cm[k][0], zm[k][0], dz[a]) + signed_cz(cm[k][2], zm[k][2], dz[a]);
+                    f1[a] = signed_cz(cm[k][1], zm[k][1], dz[a]) + signed_cz(cm[k][3], zm[k][3], dz[a]);
                 }
-                f = f0 + f1;
+                for (int q = r[k].s0 + kStrGroup; q < r[k].s1; q += kStrGroup) {
+#pragma unroll
+                    for (int a = 0; a < C; ++a) {
+                        f0[a] += signed_cz(co[q], zs[q], dz[a]) + signed_cz(co[q + 2], zs[q + 2], dz[a]);
+                        f1[a] += signed_cz(co[q + 1], zs[q + 1], dz[a]) + signed_cz(co[q + 3], zs[q + 3], dz[a]);
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < C; ++a) f[a] = f0[a] + f1[a];
             }
 #pragma unroll
-            for (int v = 0; v < 2; ++v) {
-                const double2 a = Amp<T>::cvt(p[k][v]);
-                acc[2 * v] = fma(f, a.x, acc[2 * v]);
-                acc[2 * v + 1] = fma(f, a.y, acc[2 * v + 1]);
-            }
+            for (int a = 0; a < C; ++a)
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    const double2 x = Amp<T>::cvt(p[k][a][v]);
+                    acc[a][2 * v] = fma(f[a], x.x, acc[a][2 * v]);
+                    acc[a][2 * v + 1] = fma(f[a], x.y, acc[a][2 * v + 1]);
+                }
         }
     }
 }
@@ -1610,7 +1629,8 @@ __device__ __forceinline__ void walk_run_scalar(const HClass *hcls, const double
 // Row (instance, slot P + part), P = hvw_parts (a power of two), slot <
 // min(kHvwSlots, pair blocks):
 // the workgroup takes the lists of pair blocks slot, slot + slots, ..., 64
-// entries at a time (one per lane), and wave w applies run `part` of its
+// entries at a time (one per lane; two blocks' entries per pass where both
+// have some left), and wave w applies run `part` of its
 // segment of H's classes (a 1 / (kNW P) share of H) with the table
 // read through the scalar cache.  Since the dots are linear in H v and H w,
 // each (block, tile, run) adds v* (H_run v) etc. at once; the workgroup writes
@@ -1652,24 +1672,55 @@ __global__ __launch_bounds__(kNW *kWave) __attribute__((amdgpu_waves_per_eu(8)))
     const uint32_t dim = 1u << nq;
     __shared__ double rsum[3][kNW];
     double p3 = 0.0, p5 = 0.0, p6 = 0.0;
-    for (int bk = slot; bk < nb; bk += nslot) {
+    // H applied over the wave's run (every stage chunk of H) at C amplitudes
+    auto walk = [&](auto cc, const auto &d, auto &acc) {
+        constexpr int C = decltype(cc)::value;
+        for (int k = 0; k < nhc; ++k) {
+            const int r = k * (kNW * np + 1) + r0;
+            const int c0 = k == 0 ? ra : cptr(hsegp)[r], c1 = k == 0 ? rb : cptr(hsegp)[r + 1];
+            // (records per batch: kHvwBatch for one amplitude, half for two,
+            // the same gathers per batch)
+            walk_run_scalar<T, (C > 1 ? kHvwBatch / 2 : kHvwBatch), C>(hcls, hcoef, hzs, c0, c1, d, vv, vw, acc);
+        }
+    };
+    auto entry = [&](int bk, int g, bool on, bool first) {
+        uint32_t d = first ? e0 : gptr(act)[(size_t)bk * kList + min(g, kList - 1)];
+        return on ? d & (dim - 1u) : 0u;
+    };
+    // (each amplitude's own v, w are loaded before its walk, so their
+    // latency passes under it)
+    auto add = [&](const double2 &ov, const double2 &ow, bool on, const double (&acc)[4]) {
+        if (on) {
+            p3 += ov.x * acc[0] + ov.y * acc[1];
+            p5 += ow.x * acc[2] + ow.y * acc[3];
+            p6 += ov.x * acc[2] + ov.y * acc[3];
+        }
+    };
+    // the slot's blocks two at a time (slot + 2 i nslot and the next one), 64
+    // entries of each per pass: one walk over the run serves both
+    for (int bk = slot; bk < nb; bk += 2 * nslot) {
+        const int bk2 = bk + nslot;
         const int cnt = min(max(bk == slot ? cnt0 : cptr(act_n)[bk], 0), kList);
-        for (int t = 0; t * kWave < cnt; ++t) {
+        const int cnt2 = bk2 < nb ? min(max(cptr(act_n)[bk2], 0), kList) : 0;
+        for (int t = 0; t * kWave < max(cnt, cnt2); ++t) {
             const int g = t * kWave + lane;
             const bool on = g < cnt;
-            uint32_t d = bk == slot && t == 0 ? e0 : gptr(act)[(size_t)bk * kList + min(g, kList - 1)];
-            d = on ? d & (dim - 1u) : 0u;
-            const double2 ov = Amp<T>::load(vv, d), ow = Amp<T>::load(vw, d);
-            double acc[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int k = 0; k < nhc; ++k) {
-                const int r = k * (kNW * np + 1) + r0;
-                const int c0 = k == 0 ? ra : cptr(hsegp)[r], c1 = k == 0 ? rb : cptr(hsegp)[r + 1];
-                walk_run_scalar<T, kHvwBatch>(hcls, hcoef, hzs, c0, c1, d, vv, vw, acc);
-            }
-            if (on) {
-                p3 += ov.x * acc[0] + ov.y * acc[1];
-                p5 += ow.x * acc[2] + ow.y * acc[3];
-                p6 += ov.x * acc[2] + ov.y * acc[3];
+            const uint32_t d = entry(bk, g, on, bk == slot && t == 0);
+            if (t * kWave < cnt2) {
+                const bool on2 = g < cnt2;
+                const uint32_t dd[2] = {d, entry(bk2, g, on2, false)};
+                const double2 ov = Amp<T>::load(vv, dd[0]), ow = Amp<T>::load(vw, dd[0]);
+                const double2 ov2 = Amp<T>::load(vv, dd[1]), ow2 = Amp<T>::load(vw, dd[1]);
+                double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+                walk(std::integral_constant<int, 2>(), dd, acc);
+                add(ov, ow, on, acc[0]);
+                add(ov2, ow2, on2, acc[1]);
+            } else {
+                const uint32_t dd[1] = {d};
+                const double2 ov = Amp<T>::load(vv, d), ow = Amp<T>::load(vw, d);
+                double acc[1][4] = {{0.0, 0.0, 0.0, 0.0}};
+                walk(std::integral_constant<int, 1>(), dd, acc);
+                add(ov, ow, on, acc[0]);
             }
         }
     }
