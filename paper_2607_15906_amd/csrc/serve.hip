@@ -215,15 +215,15 @@ void parse_record(Request *r) {
 
 // Adaptive schedule: one amplitude per lane while the active set has fewer
 // than four tiles of 64 amplitudes per compute unit (the launches are then
-// latency-bound and more tiles keep more units busy); otherwise wider blocking,
-// which cuts the work per amplitude (2 for complex128 states, whose widest
-// blocking runs short of registers; 4 for complex64).  The compacted H v, H w
-// launch's parts follow the group's parts rule.
+// latency-bound and more tiles keep more units busy); otherwise four, which
+// cuts the work per amplitude (the whole-state H v, H w launch of complex128
+// states keeps two, see Group::hvw_R).  The compacted H v, H w launch's parts
+// follow the group's parts rule.
 void gocp_server::choose_schedule() {
     if (schedule != 0) return;
     long tiles = 0;
     for (gocp::Request *r : active) tiles += gocp::tiles_for(r->ip.n_qubits, 1);
-    group.R = tiles < 4L * ctx->n_cu ? 1 : (dtype == GOCP_C128 ? 2 : 4);
+    group.R = tiles < 4L * ctx->n_cu ? 1 : 4;
     group.P = group.parts_rule();
 }
 
