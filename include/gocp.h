@@ -311,10 +311,7 @@ typedef struct {
     int32_t max_iter;       /* operators appended at most                            */
     int32_t use_graph;      /* 1: replay captured hipGraphs of the iteration         */
     int32_t schedule;       /* amplitudes per lane of the tile kernels, R = 1, 2
-                               or 4 (complex128 states: at most 2 in the
-                               whole-state H v, H w launch, whose two FP64
-                               vectors at 4 exceed the registers), plus 256 x 4
-                               to run the compacted H v, H w
+                               or 4, plus 256 x 4 to run the compacted H v, H w
                                launch (complex64 states) with 4 workgroups per
                                tile slot instead of 8; 0 = autotune (R timed on
                                the instances, the fastest kept and remembered
@@ -494,10 +491,8 @@ int gocp_request_bytes(const gocp_ham *h, const gocp_pool *p, int32_t max_iter, 
 /* Start a server on ctx's device with its own stream and worker thread; the
  * tile kernels run with amps_per_lane (1, 2 or 4) amplitudes per lane, or with
  * 0 a schedule chosen whenever the active set changes: 1 while the set has
- * fewer than four 64-amplitude tiles per compute unit, else 4 (complex128
- * states run their whole-state H v, H w launch at 2 amplitudes per lane
- * whenever the schedule asks for 4), and the compacted H v, H w launch's parts
- * by the rule of the
+ * fewer than four 64-amplitude tiles per compute unit, else 4, and the
+ * compacted H v, H w launch's parts by the rule of the
  * autotuned schedule (gocp_adapt_params.schedule).  A request's result is
  * bit-identical to adapt_solve with the same schedule (amps_per_lane, 8
  * parts); under the adaptive schedule it can change between steps, so results

@@ -82,10 +82,6 @@ struct Group {
     gocp_ctx *ctx = nullptr;
     int dtype = 0;
     int R = 1;                 // amplitudes per lane of the tile kernels
-    // Amplitudes per lane of the whole-state H v, H w launch: R, except that
-    // complex128 states take at most 2 there (two FP64 vectors at four
-    // amplitudes per lane exceed the registers and spill).
-    int hvw_R() const { return dtype == GOCP_C128 ? std::min(R, 2) : R; }
     int P = kHvwPartsHi;       // workgroups per tile slot of the compacted H v, H w launch
     std::vector<int> ntile;    // tiles of each member for R
     std::vector<int> ngroup;   // tile groups of each member (first reduction stage)
@@ -148,8 +144,8 @@ struct Group {
                 di.n_lpart = std::min(kHvwSlots, inst[i]->ip.n_pblk) * P;
                 for (int y = 0; y < di.n_lpart; ++y) ba.push_back(make_int2((int)i, y));
             } else {
-                di.n_lpart = tiles_for(di.n_qubits, hvw_R());
-                for (int t = 0; t < di.n_lpart; ++t) bh.push_back(make_int2((int)i, t));
+                di.n_lpart = di.n_tiles;
+                for (int t = 0; t < di.n_tiles; ++t) bh.push_back(make_int2((int)i, t));
             }
             d.push_back(di);
             ntile.push_back(di.n_tiles);
@@ -253,7 +249,7 @@ struct Group {
     // the first launch's start, t1 the second one's end.
     void launch_hvw(int mode, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) const {
         launch_hvw_act(desc, bact, na, mode, s, t0, nullptr);
-        launch_kernel(K_LINE_HVW, dtype, hvw_R(), desc, bhvw, nh, mode, s, 0, 0.0, 0, nullptr, t1);
+        launch_kernel(K_LINE_HVW, dtype, R, desc, bhvw, nh, mode, s, 0, 0.0, 0, nullptr, t1);
     }
 
     // Selection (energy, gradients, operator, record) of every member's

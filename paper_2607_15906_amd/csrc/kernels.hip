@@ -739,6 +739,33 @@ __device__ __forceinline__ void apply_classes(const InstDev &I, Stage &S, uint32
         int c = c0;
         uint32_t off[R];
         lane_offsets<R, Amp<T>::kShift>(d0, dim, off);
+        // Two FP64 vectors at four amplitudes per lane hold 32 VGPRs of
+        // gathers per class: they are issued at the start of their own
+        // class (their latency passes under its coefficients) instead of a
+        // class ahead, which would double that and spill.
+        constexpr bool ahead = !(NV == 2 && R == 4 && sizeof(typename Amp<T>::Raw) == 16);
+        if constexpr (!ahead) {
+            for (; c < c1; ++c) {
+                typename Amp<T>::Raw rc[NV][R];
+                const uint32_t xc = (uint32_t)uni((int)S.cls[c].x) << Amp<T>::kShift;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    rc[0][r] = Amp<T>::raw_at(v0, off[r] ^ xc);
+                    rc[NV - 1][r] = Amp<T>::raw_at(v1, off[r] ^ xc);
+                }
+                double f[R];
+                class_coeffs<R, kFactH>(S, zs, c, sb, d0, f);
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const double2 p = Amp<T>::cvt(rc[v][r]);
+                        acc[2 * (v * R + r)] = fma(f[r], p.x, acc[2 * (v * R + r)]);
+                        acc[2 * (v * R + r) + 1] = fma(f[r], p.y, acc[2 * (v * R + r) + 1]);
+                    }
+            }
+            continue;
+        }
         typename Amp<T>::Raw rn[NV][R];
         if (c < c1) {
             const uint32_t xn = (uint32_t)uni((int)S.cls[c].x) << Amp<T>::kShift;

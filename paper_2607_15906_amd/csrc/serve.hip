@@ -216,9 +216,8 @@ void parse_record(Request *r) {
 // Adaptive schedule: one amplitude per lane while the active set has fewer
 // than four tiles of 64 amplitudes per compute unit (the launches are then
 // latency-bound and more tiles keep more units busy); otherwise four, which
-// cuts the work per amplitude (the whole-state H v, H w launch of complex128
-// states keeps two, see Group::hvw_R).  The compacted H v, H w launch's parts
-// follow the group's parts rule.
+// cuts the work per amplitude.  The compacted H v, H w launch's parts follow
+// the group's parts rule.
 void gocp_server::choose_schedule() {
     if (schedule != 0) return;
     long tiles = 0;
