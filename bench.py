@@ -108,6 +108,65 @@ def _oracle_task(spec):
         return time.perf_counter() - t0
 
 
+def sparse_headline(nq, ne, mapping, seed, iters):
+    """The sparse-matrix CPU baseline (the paper's own engine's approach: H and
+    the pool as precomputed CSR matrices) on the first `iters` iterations of
+    the headline system, one host thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle.sparse import psum_csr, adapt_run_csr
+    H, ops, hf = _oracle_system(nq, ne, mapping, seed)
+    psi0 = np.zeros(1 << nq, dtype=np.complex128)
+    psi0[hf] = 1.0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        Hm = psum_csr(H, nq)
+        Ams = [psum_csr(A, nq) for A in ops]
+        norms = [sum(abs(c) for c in A.values()) for A in ops]
+        t1 = time.perf_counter()
+        adapt_run_csr(Hm, Ams, norms, psi0, iters)
+        t2 = time.perf_counter()
+    return {"value": round(iters / (t2 - t1), 3), "unit": "iters/s", "cores": 1, "kind": "sparse matrices",
+            "sample": f"first {iters} ADAPT iterations of the same 14q JW system from Hartree-Fock with H "
+                      f"({Hm.nnz} nonzeros) and the pool as scipy CSR matrices, one thread, {t2 - t1:.2f} s; "
+                      f"building the matrices took {t1 - t0:.2f} s more"}
+
+
+def _oracle_solve_task(spec):
+    """One served request solved by the oracle (one thread): seconds, iterations."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle.adapt import adapt_run
+    nq, ne, mapping, seed, max_iter, tol = spec
+    with threadpool_limits(limits=1):
+        H, ops, hf = _oracle_system(nq, ne, mapping, seed)
+        psi0 = np.zeros(1 << nq, dtype=np.complex128)
+        psi0[hf] = 1.0
+        t0 = time.perf_counter()
+        r = adapt_run(H, ops, psi0, max_iter, grad_tol=tol)
+        return time.perf_counter() - t0, len(r["ops"])
+
+
+def oracle_serving_baseline(n_req, workers, nq=8):
+    """The oracle solving the first `n_req` `nq`-qubit requests of the serving
+    stream (||g|| < 1e-3, at most 300 iterations) on `workers` processes
+    (forked before the GPU is touched); larger requests take the oracle
+    minutes each."""
+    import multiprocessing as mp
+    from workloads import serving_requests
+    specs = [(d["n_qubits"], d["n_electrons"], d["mapping"], d["seed"], 300, 1e-3)
+             for d in serving_requests(64 * n_req, rate_hz=1.0) if d["n_qubits"] == nq][:n_req]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        per = pool.map(_oracle_solve_task, specs, chunksize=1)
+    wall = time.perf_counter() - t0
+    return specs, {"value": round(len(specs) / wall, 3), "unit": "solves/s", "cores": workers, "kind": "oracle",
+                   "sample": f"the first {len(specs)} {nq}-qubit requests of the serving stream, FP64 NumPy "
+                             f"oracle on {workers} worker processes (one thread each); {wall:.1f} s wall, "
+                             f"{sum(t for t, _ in per):.1f} s of solves, {sum(k for _, k in per)} iterations"}
+
+
 def oracle_batch_baseline(iters, workers):
     """The oracle over the 64 batched instances, `iters` iterations each, on
     `workers` processes (forked before the GPU is touched)."""
@@ -343,7 +402,7 @@ def batched_block(g, ctx, schedule, oracle_baseline):
 
 
 def serving_block(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, loads=(0.7, 1.2), amps_per_lane=0,
-                  state="complex128", deadline_s=600.0):
+                  state="complex128", deadline_s=600.0, oracle_baseline=None):
     """The serving workload: a Poisson stream of ADAPT solves (8-16 qubits,
     ||g|| < 1e-3, at most 300 iterations).  Capacity is measured first with
     every request submitted at once; the stream then arrives at each `load`
@@ -351,7 +410,9 @@ def serving_block(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, loads=(0.
     figures), then `n_req` measured ones.  Latency is submission to
     completion on the library's clock; the baseline is sequential plain FP64
     adapt_solve on the same device, each solve at its autotuned schedule.  A second capacity run serves the same
-    requests with the other state precision."""
+    requests with the other state precision.  With `oracle_baseline` (the
+    oracle's requests and its solves/s on them) the server also solves those
+    requests alone, for the comparison."""
     import numpy as np
     import torch
     from workloads import serving_requests
@@ -457,12 +518,31 @@ def serving_block(g, ctx, n_req, warm, max_slots=32, iters_per_step=4, loads=(0.
     seq = n_req / (time.perf_counter() - t0)
     cap_dt = n_req / cap
     achieved = LANE_OPS_PER_STRING_AMP * screen_sa / cap_dt / 1e12
+    cpu = None
+    if oracle_baseline is not None:
+        ospecs, obase = oracle_baseline
+        sub = []
+        for (nqs, nes, ms, seeds, mi, tl) in ospecs:
+            Hs, Ps = _system(g, nqs, nes, ms, seeds)
+            sub.append((Hs, Ps))
+        srv = g.Server(ctx, budget, max_slots, dtype=code, iters_per_step=iters_per_step, amps_per_lane=amps_per_lane)
+        t0 = time.perf_counter()
+        pend, done_s = [srv.submit(Hs, Ps, max_iter, tol) for (Hs, Ps) in sub], {}
+        while pend:
+            drain(srv, pend, done_s, t0 + deadline_s)
+            time.sleep(0.0005)
+        same = len(sub) / (time.perf_counter() - t0)
+        srv.close()
+        cpu = dict(obase)
+        cpu["gpu_same_requests_solves_per_s"] = round(same, 2)
+        cpu["gpu_vs_cpu"] = round(same / obase["value"], 1)
     return {"requests": n_req, "warmup_requests": warm, "qubits": "uniform over {8,10,12,14,16}",
             "grad_tol": tol, "max_iter": max_iter, "state": state, "max_slots": max_slots,
             "iters_per_step": iters_per_step, "amps_per_lane": amps_per_lane if amps_per_lane else "adaptive",
             "hbm_budget_bytes": budget, "capacity_solves_per_s": round(cap, 2),
             "loads": runs, "sequential_fp64_solves_per_s": round(seq, 2),
             "capacity_vs_sequential_fp64": round(cap / seq, 3),
+            **({"cpu_baseline": cpu} if cpu else {}),
             "other_state": {"state": "complex64" if other == 1 else "complex128",
                             "capacity_solves_per_s": round(cap_other, 2),
                             "capacity_vs_sequential_fp64": round(cap_other / seq, 3),
@@ -528,6 +608,8 @@ def main():
     ap.add_argument("--serve-amps-per-lane", type=int, default=0, choices=(0, 1, 2, 4),
                     help="server schedule (0: chosen from the active set)")
     ap.add_argument("--serve-state", default="complex128", choices=("complex64", "complex128"))
+    ap.add_argument("--sparse-sample-iters", type=int, default=60,
+                    help="iterations of the sparse-matrix CPU baseline on the headline system (0 disables it)")
     ap.add_argument("--oracle-workers", type=int, default=0,
                     help="worker processes of the batched oracle baseline (0: min(16, CPUs))")
     ap.add_argument("--batch-oracle-iters", type=int, default=4)
@@ -563,11 +645,17 @@ def main():
     if args.cpu_sample_iters > 0 and not args.fused_step_only and not args.phase_trace:
         _say(f"[bench] CPU oracle: {args.cpu_sample_iters} iterations at 14q (one thread)")
         oracle = oracle_headline(nq, ne, mapping, seed, args.cpu_sample_iters)
-    batch_oracle = None
+    sparse = None
+    if args.sparse_sample_iters > 0 and not args.fused_step_only and not args.phase_trace:
+        _say(f"[bench] CPU sparse matrices: {args.sparse_sample_iters} iterations at 14q (one thread)")
+        sparse = sparse_headline(nq, ne, mapping, seed, args.sparse_sample_iters)
+    batch_oracle = serve_oracle = None
     if not args.no_forms and not args.fused_step_only and not args.phase_trace and args.batch_oracle_iters > 0:
         workers = args.oracle_workers or min(16, os.cpu_count() or 1)
         _say(f"[bench] CPU oracle: batched instances on {workers} workers")
         batch_oracle = oracle_batch_baseline(args.batch_oracle_iters, workers)
+        _say(f"[bench] CPU oracle: 8-qubit serving requests on {workers} workers")
+        serve_oracle = oracle_serving_baseline(32, workers)
 
     import numpy as np
     import torch
@@ -711,7 +799,8 @@ def main():
 
         _say(f"[bench] serving form: {args.serve_warmup} + {args.serve_requests} requests")
         out["serving"] = serving_block(g, ctx, n_req=args.serve_requests, warm=args.serve_warmup,
-                                       amps_per_lane=args.serve_amps_per_lane, state=args.serve_state)
+                                       amps_per_lane=args.serve_amps_per_lane, state=args.serve_state,
+                                       oracle_baseline=serve_oracle)
 
     if oracle is not None:
         n_it = args.cpu_sample_iters
@@ -721,6 +810,9 @@ def main():
                                          f"Hartree-Fock, FP64 NumPy oracle, {oracle['seconds']:.1f} s on one of "
                                          f"{os.cpu_count()} host CPUs"}
         out["vs_cpu_oracle"] = round(ips / out["cpu_baseline"]["value"], 1)
+    if sparse is not None:
+        out["cpu_sparse_baseline"] = sparse
+        out["vs_cpu_sparse"] = round(ips / sparse["value"], 1)
     print(json.dumps(out), flush=True)
 
 
