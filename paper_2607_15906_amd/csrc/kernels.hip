@@ -1359,11 +1359,20 @@ struct Landscape {
     __device__ double value(double th) const {
         double s, c;
         sincos(th, &s, &c);
+        return value_sc(s, c);
+    }
+    __device__ double value_sc(double s, double c) const {
         return uu + 2.0 * uv * c + 2.0 * uw * s + vv * c * c + 2.0 * vw * s * c + ww * s * s;
     }
     __device__ double deriv_sc(double s, double c) const {
         return -2.0 * uv * s + 2.0 * uw * c - 2.0 * vv * s * c + 2.0 * vw * (c * c - s * s) +
                2.0 * ww * s * c;
+    }
+    // the sum of the moduli of E''s terms: E' evaluated in double precision is
+    // exact to within a few units of rounding of this
+    __device__ double deriv_abs_sc(double s, double c) const {
+        return 2.0 * (fabs(uv * s) + fabs(uw * c) + fabs(vv * s * c) + fabs(vw * (c * c - s * s)) +
+                      fabs(ww * s * c));
     }
     __device__ double deriv(double th) const {
         double s, c;
@@ -1380,10 +1389,12 @@ struct Landscape {
 // one-degree bracket Newton steps on E' (E'' analytic) from the secant point
 // of the bracket's ends, each kept inside the bracket (a step that would
 // leave it goes to the bracket's midpoint instead) until the step no longer
-// moves the point.  Without a sign change within a full turn, the best
+// moves the point or E' there is zero to within its own rounding.  Without a sign change within a full turn, the best
 // sampled angle.  Called by all 64 lanes of one wave; returns the angle in
 // every lane.
-__device__ double line_search_wave(const Landscape &L, double g) {
+__device__ double line_search_wave(const Landscape &L, double g, double &s_out, double &c_out) {
+    s_out = 0.0;
+    c_out = 1.0;
     if (g == 0.0) return 0.0;
     const int lane = threadIdx.x & (kWave - 1);
     const double dir = g > 0.0 ? -1.0 : 1.0;
@@ -1427,6 +1438,7 @@ __device__ double line_search_wave(const Landscape &L, double g) {
                 bestk = kk;
             }
         }
+        sincos(dir * bestk * step, &s_out, &c_out);
         return dir * bestk * step;
     }
     // bracket: lo (E' not yet past zero) and hi = the first sample that is;
@@ -1451,17 +1463,25 @@ __device__ double line_search_wave(const Landscape &L, double g) {
         if (xs > fmin(lo, hi) && xs < fmax(lo, hi)) x = xs;
     }
     // (a run of midpoint steps alone halves the bracket each time, so the
-    // cap is reached only if Newton keeps failing)
+    // cap is reached only if Newton keeps failing).  The search ends at a
+    // step below 1e-15 of max(|x|, 1 degree), or where |E'| is below four
+    // units of rounding of its terms' moduli: there its sign is noise, and
+    // further steps (Newton's or the midpoint's) would only wander inside the
+    // rounding band around the root.
+    const double tol = 1e-15 * fmax(fabs(x), step);
+    constexpr double eps = 0x1p-52;   // double's machine epsilon
     for (int it = 0; it < 48; ++it) {
         sc_at(x, st, ct);
         const double d1 = L.deriv_sc(st, ct), d2v = L.deriv2_sc(st, ct);
+        if (fabs(d1) <= 4.0 * eps * L.deriv_abs_sc(st, ct)) break;
         if (dir * d1 >= 0.0) hi = x; else lo = x;
         double xn = d2v != 0.0 ? x - d1 / d2v : 0.5 * (lo + hi);
         if (!(xn > fmin(lo, hi) && xn < fmax(lo, hi))) xn = 0.5 * (lo + hi);
-        const bool done = fabs(xn - x) <= 1e-15 * fabs(x);
+        const bool done = fabs(xn - x) <= tol;
         x = xn;
         if (done) break;
     }
+    sc_at(x, s_out, c_out);
     return x;
 }
 
@@ -1781,6 +1801,9 @@ __global__ __launch_bounds__(kNW *kWave) __attribute__((amdgpu_waves_per_eu(8)))
 // are first used by choose_angle.
 struct AngleIn {
     double nrm, e_num, gj, onorm;
+    int it;                     // the state record's iteration and history arrays (for the writer)
+    int32_t *h_op, *h_ns;
+    double *h_th, *h_pr;
     double r[5];                // the thread's first share (masked by use3, use2)
     double q[5];                // the sum of its further shares
     bool use3, use2;
@@ -1791,6 +1814,11 @@ __device__ __forceinline__ void angle_loads(const AdaptState *st, const double *
     in.e_num = cptr(&st->e_num)[0];
     in.gj = cptr(g)[j];
     in.onorm = cptr(op_norm1)[j];
+    in.it = cptr(&st->iter)[0];
+    in.h_op = cptr(&st->hist_op)[0];
+    in.h_ns = cptr(&st->hist_nsub)[0];
+    in.h_th = cptr(&st->hist_theta)[0];
+    in.h_pr = cptr(&st->hist_pred)[0];
     // a thread's first share is loaded (at a clamped index) and left
     // unused until the angle is chosen, so nothing waits on it here; further
     // shares, for states with more partials than threads, are summed in
@@ -1849,44 +1877,51 @@ __device__ void choose_angle(const AngleIn &in, AdaptState *st, int j, bool writ
         L.vv = P3 * inv;
         L.vw = P6 * inv;
         L.ww = P5 * inv;
-        const double th = line_search_wave(L, gj);
+        double sth, cth;
+        const double th = line_search_wave(L, gj, sth, cth);
         if (lane == 0) {
             const int n = th == 0.0 ? 0 : max(1, (int)ceil(fabs(th) * onorm / 0.5));
             s_th = th;
             s_ns = n;
             if (writer) {
                 // T5(h) = I + a A + b A^2 once A^3 = -A (and A^4 = -A^2); the product
-                // of two such factors stays in that span, so the whole chain is
-                // I + al A + be A^2
+                // of such factors stays in that span and multiplies like the
+                // complex numbers (1 - b) + i a (A acts as i on its +-i
+                // eigenspaces), so the chain T5(h)^n is I + al A + be A^2 with
+                // (1 - be) + i al = ((1 - b) + i a)^n, formed by squaring
                 double al = 0.0, be = 0.0;
                 if (n > 0) {
                     const double h = th / n, h2 = h * h;
                     const double a = h * (1.0 - h2 / 6.0 * (1.0 - h2 / 20.0));   // h - h^3/6 + h^5/120
                     const double b = h2 * (0.5 - h2 / 24.0);                     // h^2/2 - h^4/24
-                    for (int k = 0; k < n; ++k) {
-                        const double na = al + a - al * b - be * a;
-                        const double nb = be + b + al * a - be * b;
-                        al = na;
-                        be = nb;
+                    double zr = 1.0 - b, zi = a, pr = 1.0, pi = 0.0;
+                    for (int k = n; k > 0; k >>= 1) {
+                        if (k & 1) {
+                            const double tr = pr * zr - pi * zi;
+                            pi = pr * zi + pi * zr;
+                            pr = tr;
+                        }
+                        const double sr = zr * zr - zi * zi;
+                        zi = 2.0 * zr * zi;
+                        zr = sr;
                     }
+                    al = pi;
+                    be = 1.0 - pr;
                 }
                 // global (not flat) stores; the history pointers are never
                 // written by a kernel
                 GOCP_AS1 AdaptState *gs = gmut(st);
-                const double pred = L.value(th);
+                const double pred = L.value_sc(sth, cth);
                 gs->upd_alpha = al;
                 gs->upd_beta = be;
                 gs->upd_scale = 1.0 / sqrt(nrm);
                 gs->theta = th;
                 gs->nsub = n;
                 gs->pred = pred;
-                const int it = cptr(&st->iter)[0];
-                int32_t *h_op = cptr(&st->hist_op)[0], *h_ns = cptr(&st->hist_nsub)[0];
-                double *h_th = cptr(&st->hist_theta)[0], *h_pr = cptr(&st->hist_pred)[0];
-                if (h_op) gmut(h_op)[it] = j;
-                if (h_th) gmut(h_th)[it] = th;
-                if (h_ns) gmut(h_ns)[it] = n;
-                if (h_pr) gmut(h_pr)[it] = pred;
+                if (in.h_op) gmut(in.h_op)[in.it] = j;
+                if (in.h_th) gmut(in.h_th)[in.it] = th;
+                if (in.h_ns) gmut(in.h_ns)[in.it] = n;
+                if (in.h_pr) gmut(in.h_pr)[in.it] = pred;
             }
         }
     }
