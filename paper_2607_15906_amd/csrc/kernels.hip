@@ -643,6 +643,26 @@ __device__ __forceinline__ void walk_groups_r1(const Stage &S, const GOCP_AS4 ui
             }
         }
     };
+    // The main part: while every group a pass loads lies below g1 the loads
+    // need no bounds select, and they use running table pointers (Z masks and
+    // X masks through the scalar cache, magnitudes through an LDS address
+    // held in a VGPR) with constant offsets, so a pass costs a few scalar
+    // instructions instead of an index computation and a select per group.
+    typedef __attribute__((address_space(3))) const double lds_f64;
+    auto load_zc_at = [&](Bat &b, const GOCP_AS4 uint32_t *zq, lds_f64 *cq, int off) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < kStrGroup; ++q) b.z[k][q] = zq[kStrGroup * (off + k) + q];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < (FG ? 1 : kStrGroup); ++q) b.c[k][q] = cq[kStrGroup * (off + k) + q];
+    };
+    auto load_x_at = [&](uint32_t (&x)[K], const GOCP_AS4 uint32_t *xq, int off) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = xq[off + k];
+    };
     Bat A, B;
     uint32_t xa[K], xb[K];
     load_x(xa, g0);
@@ -651,12 +671,42 @@ __device__ __forceinline__ void walk_groups_r1(const Stage &S, const GOCP_AS4 ui
     gather(A, xa);
     load_zc(A, g0);
     load_x(xb, g0 + K);
-    // One exit, after both steps: every load issued is consumed on every
-    // path (a load used only past a branch would be sunk into it, next to its
-    // use).  A step that starts past g1 sums zero magnitudes; the last pass
-    // reads ahead into the tables' zero padding and leaves those loads unused.
+    int g = g0;
+    if (g + 3 * K <= g1) {
+        const GOCP_AS4 uint32_t *zq = zs + kStrGroup * g, *xq = gx + g;
+        lds_f64 *cq = (lds_f64 *)(S.coef + kStrGroup * g);
+        do {
+            ready(A, xb);
+            __builtin_amdgcn_sched_barrier(0);
+            asm volatile("" : "+s"(zq), "+s"(xq), "+v"(cq));
+            gather(B, xb);
+            load_zc_at(B, zq, cq, K);
+            load_x_at(xa, xq, 2 * K);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(A);
+            __builtin_amdgcn_sched_barrier(0);
+            ready(B, xa);
+            __builtin_amdgcn_sched_barrier(0);
+            asm volatile("" : "+s"(zq), "+s"(xq), "+v"(cq));
+            gather(A, xa);
+            load_zc_at(A, zq, cq, 2 * K);
+            load_x_at(xb, xq, 3 * K);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(B);
+            __builtin_amdgcn_sched_barrier(0);
+            zq += kStrGroup * 2 * K;
+            xq += 2 * K;
+            cq += kStrGroup * 2 * K;
+            g += 2 * K;
+        } while (g + 3 * K <= g1);
+    }
+    // The rest (at most two passes), with the bounds selects.  One exit,
+    // after both steps: every load issued is consumed on every path (a load
+    // used only past a branch would be sunk into it, next to its use).  A
+    // step that starts past g1 sums zero magnitudes; the last pass reads ahead
+    // into the tables' zero padding and leaves those loads unused.
     // Scheduling barriers keep each step in the order wait, issue, compute.
-    for (int g = g0;; g += 2 * K) {
+    for (;; g += 2 * K) {
         ready(A, xb);
         __builtin_amdgcn_sched_barrier(0);
         gather(B, xb);
