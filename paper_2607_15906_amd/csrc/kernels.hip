@@ -137,6 +137,20 @@ __device__ __forceinline__ GOCP_AS1 T *gmut(T *p) {
     return (GOCP_AS1 T *)(uintptr_t)p;
 }
 
+// Complex128 element i through the global path (one 16-byte access).
+__device__ __forceinline__ double2 gload2(const double2 *p, size_t i) {
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const d2v v = ((const GOCP_AS1 d2v *)(uintptr_t)p)[i];
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void gstore2(double2 *p, size_t i, double2 a) {
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    d2v v;
+    v.x = a.x;
+    v.y = a.y;
+    ((GOCP_AS1 d2v *)(uintptr_t)p)[i] = v;
+}
+
 template <typename T>
 __device__ __forceinline__ const GOCP_AS4 T *cptr(const T *p) {
     return (const GOCP_AS4 T *)(uintptr_t)p;
@@ -957,7 +971,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                 if (valid) {
                     pe += own.x * ar + own.y * ai;
                     pn += own.x * own.x + own.y * own.y;
-                    if (!dry) I.sigma[d] = make_double2(ar, ai);
+                    if (!dry) gstore2(I.sigma, d, make_double2(ar, ai));
                 }
                 s_sig[r][lane] = valid ? make_double2(ar, ai) : make_double2(0.0, 0.0);
             }
@@ -973,13 +987,13 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                 const uint32_t d = d0 | ((uint32_t)r << 6);
                 double2 sg = make_double2(0.0, 0.0);
                 if (d < dim) {
-                    const double2 s0 = I.sigma[d], hv = I.hv[d], hw = I.hw[d];
+                    const double2 s0 = gload2(I.sigma, d), hv = gload2(I.hv, d), hw = gload2(I.hw, d);
                     sg.x = sc * (s0.x + al * hw.x - be * hv.x);
                     sg.y = sc * (s0.y + al * hw.y - be * hv.y);
                     const double2 own = Amp<T>::load(I.psi, d);
                     pe += own.x * sg.x + own.y * sg.y;
                     pn += own.x * own.x + own.y * own.y;
-                    if (!dry) I.sigma[d] = sg;
+                    if (!dry) gstore2(I.sigma, d, sg);
                 }
                 s_sig[r][lane] = sg;
             }
@@ -990,8 +1004,8 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
         pe = wave_sum(pe);
         pn = wave_sum(pn);
         if (lane == 0) {
-            I.part_e[b.y] = pe;
-            I.part_n[b.y] = pn;
+            gmut(I.part_e)[b.y] = pe;
+            gmut(I.part_n)[b.y] = pn;
         }
     }
 
@@ -1031,7 +1045,7 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                 const double t4 = (opbuf[wv][r][q] + opbuf[wv][r][q + 1]) + (opbuf[wv][r][q + 2] + opbuf[wv][r][q + 3]);
                 const double t = row_sum(r < nbuf ? t4 : 0.0);
                 // the operator's partial goes straight to its pool index
-                if ((lane & 15) == 0 && r < nbuf) I.part_g[(size_t)b.y * M + S.cls[obase + r].pad] = t;
+                if ((lane & 15) == 0 && r < nbuf) gmut(I.part_g)[(size_t)b.y * M + S.cls[obase + r].pad] = t;
                 nbuf = 0;
             };
             auto push = [&](int o, double v) {
