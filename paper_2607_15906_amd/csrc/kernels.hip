@@ -1145,31 +1145,58 @@ __global__ __launch_bounds__(kPairBlock) void k_screen_sum1(const InstDev *__res
         pg2[(size_t)b.y * M + j] = group_sum(gptr(pg) + (size_t)t0 * M + j, (size_t)M);
 }
 
+// The first kGroup group sums of the energy, the norm and the thread's first
+// operator column (indices clamped into range; surplus values are masked
+// where they are added).  A kernel issues these loads as early as it can,
+// ahead of the state record's test, and select_state adds them.
+struct SelPre {
+    double xe[kGroup], xn[kGroup], xg[kGroup];
+};
+__device__ __forceinline__ void sel_load(const InstDev &I, SelPre &p) {
+    const int M = I.M, ng = I.n_groups;
+    const GOCP_AS1 double *pe2 = gptr(I.part_e2), *pn2 = gptr(I.part_n2), *pg2 = gptr(I.part_g2);
+    const int jt = (int)threadIdx.x < M ? (int)threadIdx.x : 0;   // M = 0: one allocated column
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+        const int t = min(u, ng - 1);
+        p.xe[u] = pe2[t];
+        p.xn[u] = pn2[t];
+        p.xg[u] = pg2[(size_t)t * M + jt];
+    }
+}
+
 // Second stage: energy, norm and gradients of an instance from the group sums,
 // then the operator selection and whether the run ends (modes as
 // k_energy_screen).  Every workgroup that calls it computes the same values in
 // the same order: thread k adds operator columns k, k + NT, ... over the groups
 // in group order, per-thread results meet by wave sums in wave order, and the
 // tie band is searched in a second pass over the same sums.  `writer`
-// workgroups also write the record.  Returns the selected operator and
-// whether the run is over, in every thread.
+// workgroups also write the record.  pre holds the first batch of the group
+// sums (sel_load); max_iter is the state record's.  Returns the selected
+// operator and whether the run is over, in every thread.
 template <int NT>
-__device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it, bool writer, int &jsel,
-                             bool &done) {
+__device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it, int max_iter, bool writer,
+                             const SelPre &pre, int &jsel, bool &done) {
     __shared__ double red[2][NT / kWave];
     __shared__ int redi[NT / kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x >> 6;
     const bool oneshot = mode == 0 || mode >= 3, dry = mode >= 3;
     const int M = I.M, ng = I.n_groups;
-    const int max_iter = cptr(&st->max_iter)[0];
     const bool screen = M > 0 && (oneshot || it < max_iter);
     // sums over the groups in group order; loads go out kGroup at a time
     // (indices clamped into range, surplus values masked), so a sum waits
-    // once per kGroup groups instead of once per group
+    // once per kGroup groups instead of once per group; the first batch is
+    // the preloaded one
     const GOCP_AS1 double *pe2 = gptr(I.part_e2), *pn2 = gptr(I.part_n2), *pg2 = gptr(I.part_g2);
     double e_num = 0.0, nrm = 0.0;
-    for (int t0 = 0; t0 < ng; t0 += kGroup) {
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u)
+        if (u < ng) {
+            e_num += pre.xe[u];
+            nrm += pre.xn[u];
+        }
+    for (int t0 = kGroup; t0 < ng; t0 += kGroup) {
         double xe[kGroup], xn[kGroup];
 #pragma unroll
         for (int u = 0; u < kGroup; ++u) {
@@ -1187,7 +1214,14 @@ __device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it,
     const double inv = 2.0 / nrm;
     auto grad = [&](int j) {
         double a = 0.0;
-        for (int t0 = 0; t0 < ng; t0 += kGroup) {
+        int t0 = 0;
+        if (j == (int)threadIdx.x) {
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u)
+                if (u < ng) a += pre.xg[u];
+            t0 = kGroup;
+        }
+        for (; t0 < ng; t0 += kGroup) {
             double x[kGroup];
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) x[u] = pg2[(size_t)min(t0 + u, ng - 1) * M + j];
@@ -1286,6 +1320,9 @@ __global__ __launch_bounds__(kPairBlock) void k_screen_reduce(const InstDev *__r
                                                              const int2 *__restrict__ blk, int mode) {
     const InstDev &I = insts[work_row(blk).x];
     AdaptState *st = I.st;
+    SelPre pre;
+    sel_load(I, pre);
+    const int max_iter = cptr(&st->max_iter)[0];
     int it = 0;
     if (mode == kModePending) {
         if (state_done(st)) return;
@@ -1296,13 +1333,13 @@ __global__ __launch_bounds__(kPairBlock) void k_screen_reduce(const InstDev *__r
     const bool pending = mode == kModePending;
     if (pending) {
         const int m = cptr(&st->pend_mode)[0];
-        select_state<kPairBlock>(I, st, m, it, true, j, done);
+        select_state<kPairBlock>(I, st, m, it, max_iter, true, pre, j, done);
         if (threadIdx.x == 0) {
             st->sel_it = it;
             st->sel_mode = m;
         }
     } else {
-        select_state<kPairBlock>(I, st, mode, it, true, j, done);
+        select_state<kPairBlock>(I, st, mode, it, max_iter, true, pre, j, done);
     }
 }
 
@@ -1330,6 +1367,10 @@ __global__ __launch_bounds__(kPairBlock) void k_line_vw(const InstDev *__restric
                      "s"(psi), "s"(sigma));
     }
     const StHead h = load_head(st);
+    // the selection's first group sums go out with the head (vector loads:
+    // the head's test does not wait for them)
+    SelPre pre;
+    sel_load(I, pre);
     asm volatile("" ::"s"(h.done), "s"(h.pend_it), "s"(h.pend_mode), "s"(h.sel_it), "s"(h.sel_mode), "s"(h.jsel),
                  "s"(h.max_iter));
     if (h.done) return;
@@ -1341,7 +1382,7 @@ __global__ __launch_bounds__(kPairBlock) void k_line_vw(const InstDev *__restric
         j = h.jsel;
     } else {
         bool over;
-        select_state<kPairBlock>(I, st, h.pend_mode, h.pend_it, b.y == 0, j, over);
+        select_state<kPairBlock>(I, st, h.pend_mode, h.pend_it, h.max_iter, b.y == 0, pre, j, over);
         if (over) return;
     }
     const HClass C = load_rec(cptr(I.pop), j);
