@@ -1131,9 +1131,23 @@ __global__ __launch_bounds__(kPairBlock) void k_screen_sum1(const InstDev *__res
         return a;
     };
     const int j0 = threadIdx.x;
+    // the energy or norm column (threads 0 and 1) and the thread's operator
+    // column go out in one batch (every thread loads both, from clamped
+    // indices; M = 0 leaves one allocated column)
+    const GOCP_AS1 double *se = gptr(j0 == 0 ? pe : pn) + t0;
+    const GOCP_AS1 double *sg = gptr(pg) + (size_t)t0 * M + (j0 < M ? j0 : 0);
+    double xe[kGroup], xg[kGroup];
+#pragma unroll
+    for (int t = 0; t < kGroup; ++t) {
+        xe[t] = se[min(t, nt - 1)];
+        xg[t] = sg[(size_t)min(t, nt - 1) * M];
+    }
     double ae = 0.0, ag = 0.0;
-    if (j0 < 2) ae = group_sum(gptr(j0 == 0 ? pe : pn) + t0, 1);
-    if (j0 < M) ag = group_sum(gptr(pg) + (size_t)t0 * M + j0, (size_t)M);
+#pragma unroll
+    for (int t = 0; t < kGroup; ++t) {
+        ae += t < nt ? xe[t] : 0.0;
+        ag += t < nt ? xg[t] : 0.0;
+    }
     const bool oneshot = mode == 0 || mode >= 3;
     const bool live = oneshot || !h.done;
     const int it = mode == 2 ? h.iter + 1 : 0;
