@@ -235,14 +235,21 @@ __device__ __forceinline__ StHead load_head(const AdaptState *st) {
     return h;
 }
 
-// Sum over a wave with an xor butterfly: every lane ends with the same value.
 // DPP move of a double (as two 32-bit halves); lanes of rows outside ROW_MASK
-// receive 0.
+// receive 0.  With every row written and a pattern that reads inside the row
+// (the quad permutations and mirrors) no lane keeps its old value, so the
+// move takes none (no zeroing of the destination first).
 template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ double dpp_f64(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
-    return __hiloint2double(hi, lo);
+    if constexpr (ROW_MASK == 0xf && (CTRL <= 0xff || CTRL == 0x140 || CTRL == 0x141)) {
+        const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
+        return __hiloint2double(hi, lo);
+    } else {
+        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+        return __hiloint2double(hi, lo);
+    }
 }
 
 __device__ __forceinline__ double read_lane(double v, int l) {
