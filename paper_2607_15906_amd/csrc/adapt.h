@@ -83,6 +83,7 @@ struct Group {
     int dtype = 0;
     int R = 1;                 // amplitudes per lane of the tile kernels
     int P = kHvwPartsHi;       // workgroups per tile slot of the compacted H v, H w launch
+    bool xf = false;           // R = 1 and every member's pool has an X-class screen
     std::vector<int> ntile;    // tiles of each member for R
     std::vector<int> ngroup;   // tile groups of each member (first reduction stage)
     int ng = 0;
@@ -159,6 +160,8 @@ struct Group {
         }
         ng = (int)bg.size();
         nt = (int)bt.size();
+        xf = R == 1 && !inst.empty();
+        for (Instance *in : inst) xf = xf && in->desc.n_xchunks > 0;
         np = (int)bp.size();
         na = (int)ba.size();
         nh = (int)bh.size();
@@ -234,10 +237,10 @@ struct Group {
         };
         (void)n;
         const L seq[5] = {{K_LINE_VW, 1, bpair, np},       {K_LINE_HVW, 1, bhvw, nh},
-                          {K_TAYLOR, 1, bpair, np},        {K_ENERGY_SCREEN, 2, btile, nt},
+                          {K_TAYLOR, 1, bpair, np},        {es_kid(), 2, btile, nt},
                           {K_SCREEN_SUM1, 2, bgrp, ng}};
         for (const L &l : seq) {
-            const bool t = ev && l.kid == timed_kid;
+            const bool t = ev && (l.kid == K_ENERGY_SCREEN_X ? K_ENERGY_SCREEN : l.kid) == timed_kid;
             const hipEvent_t t0 = t ? ev[0] : nullptr, t1 = t ? ev[1] : nullptr;
             if (l.kid == K_LINE_HVW) launch_hvw(l.mode, s, t0, t1);
             else launch_kernel(l.kid, dtype, R, desc, l.rows, l.nrows, l.mode, s, 0, 0.0, 0, t0, t1);
@@ -306,13 +309,13 @@ struct Group {
         hip_check(hipEventCreate(&e0), "hipEventCreate");
         hip_check(hipEventCreate(&e1), "hipEventCreate");
         const int n = (int)inst.size();
-        launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 3, s);
+        launch_kernel(es_kid(), dtype, R, desc, btile, nt, 3, s);
         launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 3, s);
         launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, n, 3, s);
         launch_hvw(0, s);
         hip_check(hipEventRecord(e0, s), "hipEventRecord");
         for (int i = 0; i < reps; ++i) {
-            launch_kernel(K_ENERGY_SCREEN, dtype, R, desc, btile, nt, 3, s);
+            launch_kernel(es_kid(), dtype, R, desc, btile, nt, 3, s);
             launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 3, s);
             launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, n, 3, s);
             launch_hvw(0, s);
@@ -334,6 +337,8 @@ struct Group {
     // launches recompute values start() recomputes.
     void choose_schedule(int schedule, hipStream_t s);
     // The schedule in the encoding choose_schedule takes.
+    // the energy+screen launch of the group
+    int es_kid() const { return xf ? K_ENERGY_SCREEN_X : K_ENERGY_SCREEN; }
     int schedule_code() const { return R | (P == kHvwPartsHi ? 0 : P << 8); }
     // kHvwPartsLo when the compacted launch would have more than four
     // workgroups per compute unit with kHvwPartsHi (many instances: fewer,
@@ -347,7 +352,7 @@ struct Group {
 
     // Energy, screen and selection of the starting state of the given members.
     void start(const std::vector<int> &members, hipStream_t s) {
-        launch_subset(K_ENERGY_SCREEN, 1, members, 0, s);
+        launch_subset(es_kid(), 1, members, 0, s);
         launch_subset(K_SCREEN_SUM1, 1, members, 3, s);
         launch_subset(K_SCREEN_REDUCE, kModePending, members, 2, s);
     }

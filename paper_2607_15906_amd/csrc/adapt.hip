@@ -336,7 +336,7 @@ int gocp_batch_time_kernel(gocp_batch *b, int32_t which, int32_t n_launch, doubl
     check_ctx(b->group.ctx);
     hipStream_t s = b->group.ctx->user_stream;
     Group &g = b->group;
-    const int kid = which == 1 ? K_LINE_HVW : K_ENERGY_SCREEN;
+    const int kid = which == 1 ? K_LINE_HVW : g.es_kid();
     const int mode = which == 1 ? 0 : which == 2 ? 4 : 3;                // dry modes
     // which 3: both reduction stages
     auto launch = [&]() {

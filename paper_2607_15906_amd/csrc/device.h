@@ -180,6 +180,17 @@ struct InstDev {
     const HSub *psub;
     const int4 *pchunk;         // per LDS stage: operator range [x, y), string range [z, w)
     const int32_t *pseg;        // n_pchunks x (kNW + 1) operator boundaries of the waves
+    // pools of single-string operators, screen at one amplitude per lane: one
+    // record per X mask {x, s0, s1, count} whose strings [s0, s1) are
+    // operators (xop: their pool indices), so one gather serves them all;
+    // strings packed without padding inside an LDS stage chunk (n_xchunks = 0:
+    // not built)
+    const HClass *xrec;
+    const double *xcoef;
+    const uint32_t *xzs;
+    const int32_t *xop;
+    const int4 *xchunk;         // per LDS stage: record range [x, y), string range [z, w) (w padded)
+    const int32_t *xseg;        // n_xchunks x (kNW + 1) record boundaries of the waves
     // buffers (psi, v, w in the state precision; sigma FP64)
     void *psi;
     double2 *sigma;
@@ -204,6 +215,7 @@ struct InstDev {
     int32_t n_pblk;
     int32_t n_hchunks;
     int32_t n_pchunks;
+    int32_t n_xchunks;
     int32_t n_groups;
     int32_t n_lpart;            // workgroups of the H v, H w launch (partial triples)
     int32_t hvw_parts;          // P of the compacted H v, H w launch (kHvwPartsHi or kHvwPartsLo)
@@ -244,6 +256,14 @@ struct DevicePool {
     int4 *pchunk = nullptr;
     int32_t *pseg = nullptr;     // per chunk, kNW + 1 wave boundaries of its operators
     int n_chunks = 0;
+    // X-class screen of a pool of single-string operators (n_xchunks = 0: none)
+    HClass *xrec = nullptr;
+    double *xcoef = nullptr;
+    uint32_t *xzs = nullptr;
+    int32_t *xop = nullptr;
+    int4 *xchunk = nullptr;
+    int32_t *xseg = nullptr;
+    int n_xchunks = 0;
 };
 
 void hip_check(hipError_t e, const char *what);

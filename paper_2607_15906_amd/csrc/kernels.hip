@@ -899,7 +899,7 @@ __device__ __forceinline__ uint32_t insert_zero_bit(uint32_t p, int hb) {
 // mode 3: the work of mode 0 without writing sigma or the state record (kernel
 //         timing in the middle of a run); mode 4: likewise for the work of
 //         mode 2 when sigma is carried through the update.
-template <typename T, int R>
+template <typename T, int R, bool XF = false>
 __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__restrict__ insts,
                                                              const int2 *__restrict__ blk, int mode) {
     phase_mark(0, mode);
@@ -928,12 +928,24 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
     __shared__ Stage S;
     __shared__ double2 s_sig[R][kWave];
     __shared__ double opbuf[kNW][4][kWave];   // per wave: lane contributions of up to four operators
+    static_assert(!XF || R == 1, "the X-class screen runs at one amplitude per lane");
+    __shared__ int32_t s_xop[XF ? kStageTerms : 1];   // X-class screen: the strings' pool indices
+    // XF: every member's pool is single strings with an X-class screen (one
+    // gather per X mask serves all the operators of that mask)
+    constexpr bool xform = XF;
 
     // Stage chunk k of the screen's tables (operator records, sub-buckets
     // for R > 1, magnitudes) into S; the caller orders it with barriers.
-    const GOCP_AS4 int4 *pch = cptr(I.pchunk);
+    const GOCP_AS4 int4 *pch = cptr(xform ? I.xchunk : I.pchunk);
     auto stage_screen = [&](int k) {
         const int4 bd = load_rec(pch, k);
+        if constexpr (xform) {
+            stage_copy(S.cls, I.xrec + bd.x, bd.y - bd.x);
+            stage_coef(S, I.xcoef, bd.z, bd.w);
+            stage_copy(reinterpret_cast<u32x4 *>(s_xop), reinterpret_cast<const u32x4 *>(I.xop + bd.z),
+                       (bd.w - bd.z) / kStrGroup);
+            return;
+        }
         stage_copy(S.cls, I.sop + bd.x, bd.y - bd.x);
         if (R > 1) stage_copy(S.sub, I.psub + bd.x, bd.y - bd.x);
         stage_coef(S, I.scoef, bd.z, bd.w);
@@ -1022,9 +1034,9 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
         double2 sg[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) sg[r] = s_sig[r][lane];
-        const uint32_t *szs = I.szs;
-        const int32_t *pseg = I.pseg;
-        const int npc = I.n_pchunks;
+        const uint32_t *szs = xform ? I.xzs : I.szs;
+        const int32_t *pseg = xform ? I.xseg : I.pseg;
+        const int npc = xform ? I.n_xchunks : I.n_pchunks;
         for (int k = 0; k < npc; ++k) {
             const int4 bd = load_rec(pch, k);
             const int ob = bd.x, sb = bd.z;
@@ -1052,7 +1064,8 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                 const double t4 = (opbuf[wv][r][q] + opbuf[wv][r][q + 1]) + (opbuf[wv][r][q + 2] + opbuf[wv][r][q + 3]);
                 const double t = row_sum(r < nbuf ? t4 : 0.0);
                 // the operator's partial goes straight to its pool index
-                if ((lane & 15) == 0 && r < nbuf) gmut(I.part_g)[(size_t)b.y * M + S.cls[obase + r].pad] = t;
+                if ((lane & 15) == 0 && r < nbuf)
+                    gmut(I.part_g)[(size_t)b.y * M + (xform ? s_xop[obase + r] : S.cls[obase + r].pad)] = t;
                 nbuf = 0;
             };
             auto push = [&](int o, double v) {
@@ -1060,7 +1073,26 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                 opbuf[wv][nbuf][lane] = v;
                 if (++nbuf == 4) flush();
             };
-            if constexpr (R == 1) {
+            if constexpr (xform) {
+                // X-class records: one gather per record serves its member
+                // strings, each an operator pushed under its string index
+                // (a wave's strings are consecutive, so four pushes in a row
+                // are the strings obase .. obase + 3)
+                const uint32_t dd = d0 < dim ? d0 : 0u, dz = with_sign_bit(dd);
+                uint32_t doff = dd << Amp<T>::kShift;
+                asm volatile("" : "+v"(doff));
+                typename Amp<T>::Raw pn{};
+                if (o0 < o1) pn = Amp<T>::raw_at(I.psi, doff ^ ((uint32_t)uni((int)S.cls[o0].x) << Amp<T>::kShift));
+                for (int o = o0; o < o1; ++o) {
+                    const int s0 = uni(S.cls[o].s0) - sb, s1 = uni(S.cls[o].s1) - sb;
+                    const typename Amp<T>::Raw pc = pn;
+                    if (o + 1 < o1)
+                        pn = Amp<T>::raw_at(I.psi, doff ^ ((uint32_t)uni((int)S.cls[o + 1].x) << Amp<T>::kShift));
+                    const double2 a = Amp<T>::cvt(pc);
+                    const double q = sg[0].x * a.x + sg[0].y * a.y;
+                    for (int t = s0; t < s1; ++t) push(t, q * signed_cz(S.coef[t], zs[t], dz));
+                }
+            } else if constexpr (R == 1) {
                 walk_classes_r1<T, 1, kFactPool>(S, zs, o0, o1, sb, d0 < dim ? d0 : 0u, I.psi, nullptr,
                                       [&](int o, double h, const typename Amp<T>::Raw (&p)[1]) {
                                           const double2 a = Amp<T>::cvt(p[0]);
@@ -2410,7 +2442,10 @@ __global__ void k_basis(void *psi, uint32_t dim, uint32_t index) {
 template <typename T, int R>
 static void launch_tile(int which, const InstDev *insts, const int2 *blk, int nblk, int mode, hipStream_t s,
                         hipEvent_t t0, hipEvent_t t1) {
-    if (which == 0) {
+    if (which == 2) {
+        if constexpr (R == 1) GOCP_LAUNCH((k_energy_screen<T, 1, true>), nblk, kNW * kWave, insts, blk, mode);
+        else GOCP_LAUNCH((k_energy_screen<T, R>), nblk, kNW * kWave, insts, blk, mode);
+    } else if (which == 0) {
         GOCP_LAUNCH((k_energy_screen<T, R>), nblk, kNW * kWave, insts, blk, mode);
     } else if constexpr (R == 1) {
         GOCP_LAUNCH((k_line_hvw1<T>), nblk, kNW * kWave, insts, blk, mode);
@@ -2424,8 +2459,9 @@ static void launch_all(int which, int R, const InstDev *insts, const int2 *blk, 
                        hipStream_t s, int j, double th, int ns, hipEvent_t t0, hipEvent_t t1) {
     switch (which) {
     case 0:
-    case 3: {
-        const int w = which == 0 ? 0 : 1;
+    case 3:
+    case 8: {
+        const int w = which == 0 ? 0 : which == 8 ? 2 : 1;
         if (R == 4) launch_tile<T, 4>(w, insts, blk, nblk, mode, s, t0, t1);
         else if (R == 2) launch_tile<T, 2>(w, insts, blk, nblk, mode, s, t0, t1);
         else launch_tile<T, 1>(w, insts, blk, nblk, mode, s, t0, t1);

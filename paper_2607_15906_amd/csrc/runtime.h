@@ -29,7 +29,11 @@ namespace gocp {
 
 enum {
     K_ENERGY_SCREEN = 0, K_SCREEN_REDUCE = 1, K_LINE_VW = 2, K_LINE_HVW = 3, K_TAYLOR = 4,
-    K_NORMALIZE = 5, K_UNIT_NORM = 6, K_SCREEN_SUM1 = 7
+    K_NORMALIZE = 5, K_UNIT_NORM = 6, K_SCREEN_SUM1 = 7,
+    // the energy+screen launch with the X-class screen (members whose pools
+    // are single strings with such tables, one amplitude per lane; any other R
+    // launches K_ENERGY_SCREEN)
+    K_ENERGY_SCREEN_X = 8
 };
 
 // Re-optimisation layers (one block of kPairBlock pairs per 2 kPairBlock

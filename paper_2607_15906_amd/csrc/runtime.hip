@@ -321,6 +321,14 @@ DevicePool place_pool(const TableImage &im, char *base, int device) {
     rebase(d.psub, base);
     rebase(d.pchunk, base);
     rebase(d.pseg, base);
+    if (d.n_xchunks > 0) {
+        rebase(d.xrec, base);
+        rebase(d.xcoef, base);
+        rebase(d.xzs, base);
+        rebase(d.xop, base);
+        rebase(d.xchunk, base);
+        rebase(d.xseg, base);
+    }
     return d;
 }
 
@@ -442,6 +450,87 @@ const TableImage &ham_image_locked(const Ham &h) {
     return *h.img;
 }
 
+// The X-class screen of a pool whose operators are single Pauli strings: the
+// operators grouped by X mask (classes in the order of their first member in
+// family order, members in family order), one record {x, s0, s1, count} per
+// class, its members' strings |c|, z | sign << 31 and pool indices packed
+// without padding; LDS stage chunks of at most kStageCls records and
+// kStageTerms - kStrGroup strings, each padded to a multiple of kStrGroup
+// strings; records split over the waves as for the other tables.  Nothing is
+// added for other pools.
+void add_xclass_screen(const Pool &p, ImagePacker &pk, DevicePool *d) {
+    const int m = p.n_ops();
+    if (m == 0) return;
+    for (int k = 0; k < m; ++k)
+        if (p.op_off[k + 1] - p.op_off[k] != 1) return;
+    std::vector<uint32_t> xs;
+    std::vector<std::vector<int>> mem;
+    for (int r = 0; r < m; ++r) {
+        const int j = p.fam_members[r];
+        const uint32_t x = p.op_x[j];
+        size_t c = 0;
+        while (c < xs.size() && xs[c] != x) ++c;
+        if (c == xs.size()) {
+            xs.push_back(x);
+            mem.emplace_back();
+        }
+        mem[c].push_back(j);
+    }
+    const int nc = (int)xs.size();
+    std::vector<int32_t> ch{0};
+    for (int c = 0, start = 0, strings = 0; c < nc; ++c) {
+        const int n = (int)mem[c].size();
+        if (n > kStageTerms - kStrGroup) throw Error(GOCP_ENOTSUP, "an X class has more operators than one LDS stage holds");
+        if (c - start + 1 > kStageCls || strings + n > kStageTerms - kStrGroup) {
+            ch.push_back(c);
+            start = c;
+            strings = 0;
+        }
+        strings += n;
+    }
+    ch.push_back(nc);
+    // a record: a gather and its conversion, then a sign, a product and a
+    // share of the row reduction per member
+    std::vector<int> cost(nc);
+    for (int c = 0; c < nc; ++c) cost[c] = kOpCost / 2 + 12 * (int)mem[c].size();
+    std::vector<int32_t> order, seg;
+    for (size_t k = 0; k + 1 < ch.size(); ++k) wave_split(cost, ch[k], ch[k + 1], order, seg);
+    std::vector<HClass> rec;
+    std::vector<double> co;
+    std::vector<uint32_t> zs;
+    std::vector<int32_t> op;
+    std::vector<int4> bounds;
+    for (size_t k = 0; k + 1 < ch.size(); ++k) {
+        const int r0 = (int)rec.size(), s0 = (int)co.size();
+        for (int i = ch[k]; i < ch[k + 1]; ++i) {
+            const int c = order[i];
+            HClass h{xs[c], (int32_t)co.size(), 0, (int32_t)mem[c].size()};
+            for (int j : mem[c]) {
+                const int s = p.op_off[j];
+                if (p.str_z[s] >> 31) throw Error(GOCP_ENOTSUP, "Z mask beyond 31 qubits");
+                co.push_back(std::fabs(p.str_c[s]));
+                zs.push_back(p.str_z[s] | (std::signbit(p.str_c[s]) ? 1u << 31 : 0u));
+                op.push_back(j);
+            }
+            h.s1 = (int32_t)co.size();
+            rec.push_back(h);
+        }
+        while (co.size() % kStrGroup) {
+            co.push_back(0.0);
+            zs.push_back(0u);
+            op.push_back(-1);
+        }
+        bounds.push_back(make_int4(r0, (int)rec.size(), s0, (int)co.size()));
+    }
+    d->xrec = pk.add(rec);
+    d->xcoef = pk.add(co);
+    d->xzs = pk.add(zs);
+    d->xop = pk.add(op);
+    d->xchunk = pk.add(bounds);
+    d->xseg = pk.add(seg);
+    d->n_xchunks = (int)bounds.size();
+}
+
 // The device tables of a pool in one pinned host image (caller holds p.mu).
 const TableImage &pool_image_locked(const Pool &p) {
     if (p.img) return *p.img;
@@ -515,6 +604,7 @@ const TableImage &pool_image_locked(const Pool &p) {
     d->pchunk = pk.add(stage_bounds(pch, sop));
     d->pseg = pk.add(seg);
     d->n_chunks = (int)pch.size() - 1;
+    add_xclass_screen(p, pk, d);
     pk.finish(*im);
     p.img = im;
     return *p.img;
@@ -674,6 +764,13 @@ InstDev make_desc_at(const InstPlan &ip, char *b, const DeviceHam *dh, const Dev
         I.pchunk = dp->pchunk;
         I.pseg = dp->pseg;
         I.n_pchunks = dp->n_chunks;
+        I.xrec = dp->xrec;
+        I.xcoef = dp->xcoef;
+        I.xzs = dp->xzs;
+        I.xop = dp->xop;
+        I.xchunk = dp->xchunk;
+        I.xseg = dp->xseg;
+        I.n_xchunks = dp->n_xchunks;
     }
     I.psi = psi;
     I.sigma = sigma_override ? sigma_override : reinterpret_cast<double2 *>(b + ip.o_sigma);
@@ -769,6 +866,7 @@ struct OneShot {
     InstPlan ip;
     size_t o_desc = 0, o_btile = 0, o_bpair = 0;
     int nt = 0, np = 0;
+    bool xform = false;          // the pool has an X-class screen
     InstDev *desc = nullptr;
     int2 *btile = nullptr, *bpair = nullptr;
     char *base = nullptr;
@@ -828,6 +926,7 @@ OneShot one_shot(gocp_ctx *ctx, const Ham *h, const Pool *p, const void *psi, in
     o.bpair = reinterpret_cast<int2 *>(b + o.o_bpair);
     o.nt = (int)bt.size();
     o.np = (int)bp.size();
+    o.xform = I.n_xchunks > 0;
     return o;
 }
 
@@ -1025,7 +1124,8 @@ int pool_gradients(gocp_ctx *ctx, const gocp_ham *hh, const gocp_pool *pp, const
     const Ham *h = as_ham(hh);
     const Pool *p = as_pool(pp);
     OneShot o = one_shot(ctx, h, p, psi_dev, dtype);
-    launch_kernel(K_ENERGY_SCREEN, dtype, 1, o.desc, o.btile, o.nt, 0, ctx->user_stream);
+    launch_kernel(o.xform ? K_ENERGY_SCREEN_X : K_ENERGY_SCREEN, dtype, 1, o.desc, o.btile, o.nt, 0,
+                  ctx->user_stream);
     launch_kernel(K_SCREEN_SUM1, dtype, 1, o.desc, o.btile, o.ip.n_groups, 0, ctx->user_stream);
     launch_kernel(K_SCREEN_REDUCE, dtype, 1, o.desc, o.btile, 1, 0, ctx->user_stream);
     const size_t gbytes = (size_t)p->n_ops() * sizeof(double);
@@ -1068,7 +1168,7 @@ int pool_gradients_noalloc(gocp_ctx *ctx, const gocp_ham *hh, const gocp_pool *p
     hip_check(hipMemcpyAsync(b + ip.o_st, &st, sizeof(st), hipMemcpyHostToDevice, s), "H2D");
     // one instance: null row tables, the kernels take rows (0, workgroup)
     const InstDev *desc = reinterpret_cast<const InstDev *>(base);
-    launch_kernel(K_ENERGY_SCREEN, dtype, 1, desc, nullptr, ip.n_tiles, 0, s);
+    launch_kernel(I.n_xchunks > 0 ? K_ENERGY_SCREEN_X : K_ENERGY_SCREEN, dtype, 1, desc, nullptr, ip.n_tiles, 0, s);
     launch_kernel(K_SCREEN_SUM1, dtype, 1, desc, nullptr, ip.n_groups, 0, s);
     launch_kernel(K_SCREEN_REDUCE, dtype, 1, desc, nullptr, 1, 0, s);
     return GOCP_OK;
