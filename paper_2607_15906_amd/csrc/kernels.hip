@@ -6,8 +6,9 @@
 //
 // * Tile kernels (energy / H apply, gradient screen, the H v / H w products of
 //   the line search).  A workgroup owns 64 consecutive amplitudes, one per
-//   lane, and its 16 waves split the work items (X-mask classes of H, or the
-//   pool operators in GOCP family order) between them.  For one X mask the 64
+//   lane, and its 16 waves split the work items (X-mask classes of H; the
+//   pool operators in GOCP family order, or, for pools of single strings,
+//   their X masks with the member operators) between them.  For one X mask the 64
 //   gathered partners psi[d ^ x] form one aligned 64-amplitude block, so every
 //   gather is a fully coalesced, permuted block read.  Term tables are wave
 //   uniform and stream through scalar loads.  Per-wave partial results meet
