@@ -126,6 +126,27 @@ def test_pauli_pool_adapt_matches_oracle(g, ctx, nq, iters, mapping):
     assert r["energies"][-1] < r["energies"][0] - 1e-3
 
 
+@pytest.mark.parametrize("schedule", [2, 4])
+def test_pauli_pool_adapt_register_blocking(g, ctx, schedule):
+    """Two and four amplitudes per lane screen the per-operator table (one
+    amplitude per lane takes the X-class screen); both against the oracle."""
+    _say(f"[pauli adapt] 12q jw schedule={schedule}")
+    nq, iters = 12, 10
+    s = system(g, nq, "jw")
+    d = hf_dev(s, nq, "c128")
+    r = g.adapt_solve(ctx, s["gH"], s["gP"], d, iters, grad_tol=0.0, schedule=schedule)
+    psi_gpu = d.cpu().numpy()
+    hf = np.zeros(1 << nq, dtype=np.complex128)
+    hf[s["hf"]] = 1.0
+    o = adapt_run(s["H"], s["ops"], hf, iters, grad_tol=0.0, forced_ops=r["ops"] + [0], keep_gradients=True)
+    for k, j in enumerate(r["ops"]):
+        a = np.abs(o["grads"][k])
+        assert a[j] >= a.max() * (1 - 1e-9), (k, j, a[j], a.max())
+    assert np.abs(np.array(o["energies"]) - r["energies"]).max() <= 1e-10
+    assert np.abs(np.array(o["thetas"]) - r["thetas"]).max() <= 1e-8
+    assert abs(np.vdot(o["psi"], psi_gpu)) ** 2 >= 1 - 1e-12
+
+
 def test_pauli_pool_complex64_14q(g, ctx):
     """complex64 state with FP64 accumulation against the FP64 path, 14 qubits."""
     _say("[pauli c64] 14q jw")
