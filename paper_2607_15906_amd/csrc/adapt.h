@@ -84,6 +84,7 @@ struct Group {
     int R = 1;                 // amplitudes per lane of the tile kernels
     int P = kHvwPartsHi;       // workgroups per tile slot of the compacted H v, H w launch
     bool xf = false;           // R = 1 and every member's pool has an X-class screen
+    int scb = 1;               // operator column blocks of the first screen reduction stage
     std::vector<int> ntile;    // tiles of each member for R
     std::vector<int> ngroup;   // tile groups of each member (first reduction stage)
     int ng = 0;
@@ -161,7 +162,11 @@ struct Group {
         ng = (int)bg.size();
         nt = (int)bt.size();
         xf = R == 1 && !inst.empty();
-        for (Instance *in : inst) xf = xf && in->desc.n_xchunks > 0;
+        scb = 1;
+        for (Instance *in : inst) {
+            xf = xf && in->desc.n_xchunks > 0;
+            scb = std::max(scb, sum1_blocks(in->ip.M));
+        }
         np = (int)bp.size();
         na = (int)ba.size();
         nh = (int)bh.size();
@@ -243,7 +248,8 @@ struct Group {
             const bool t = ev && (l.kid == K_ENERGY_SCREEN_X ? K_ENERGY_SCREEN : l.kid) == timed_kid;
             const hipEvent_t t0 = t ? ev[0] : nullptr, t1 = t ? ev[1] : nullptr;
             if (l.kid == K_LINE_HVW) launch_hvw(l.mode, s, t0, t1);
-            else launch_kernel(l.kid, dtype, R, desc, l.rows, l.nrows, l.mode, s, 0, 0.0, 0, t0, t1);
+            else launch_kernel(l.kid, dtype, R, desc, l.rows, l.nrows, l.mode, s, l.kid == K_SCREEN_SUM1 ? scb : 0,
+                               0.0, 0, t0, t1);
         }
     }
 
@@ -298,7 +304,7 @@ struct Group {
         }
         if (rows.empty()) return;
         hip_check(hipMemcpyAsync(bsub, rows.data(), rows.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
-        launch_kernel(which, dtype, R, desc, bsub, (int)rows.size(), mode, s);
+        launch_kernel(which, dtype, R, desc, bsub, (int)rows.size(), mode, s, which == K_SCREEN_SUM1 ? scb : 0);
     }
 
     // Time one energy+screen launch and one line-search launch over the
@@ -310,13 +316,13 @@ struct Group {
         hip_check(hipEventCreate(&e1), "hipEventCreate");
         const int n = (int)inst.size();
         launch_kernel(es_kid(), dtype, R, desc, btile, nt, 3, s);
-        launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 3, s);
+        launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 3, s, scb);
         launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, n, 3, s);
         launch_hvw(0, s);
         hip_check(hipEventRecord(e0, s), "hipEventRecord");
         for (int i = 0; i < reps; ++i) {
             launch_kernel(es_kid(), dtype, R, desc, btile, nt, 3, s);
-            launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 3, s);
+            launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 3, s, scb);
             launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, n, 3, s);
             launch_hvw(0, s);
         }

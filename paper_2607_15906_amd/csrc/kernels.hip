@@ -1143,7 +1143,9 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
 //
 // First stage: workgroup (i, g) adds tiles g kGroup, ..., (g + 1) kGroup - 1
 // of instance i in tile order: the energy and norm partials, and every
-// operator's partial (thread = operator, all kGroup loads in flight).
+// operator's partial (thread = operator, all kGroup loads in flight).  The
+// grid's second dimension splits the operators into blocks of kPairBlock
+// columns (pools with many operators); block 0 also adds energy and norm.
 __global__ __launch_bounds__(kPairBlock) void k_screen_sum1(const InstDev *__restrict__ insts,
                                                            const int2 *__restrict__ blk, int mode) {
     const int2 b = work_row(blk);
@@ -1170,7 +1172,8 @@ __global__ __launch_bounds__(kPairBlock) void k_screen_sum1(const InstDev *__res
         for (int t = 0; t < kGroup; ++t) a += t < nt ? x[t] : 0.0;
         return a;
     };
-    const int j0 = threadIdx.x;
+    const bool en = blockIdx.y == 0;              // this block also adds energy and norm
+    const int j0 = blockIdx.y * kPairBlock + threadIdx.x;
     // the energy or norm column (threads 0 and 1) and the thread's operator
     // column go out in one batch (every thread loads both, from clamped
     // indices; M = 0 leaves one allocated column)
@@ -1192,10 +1195,10 @@ __global__ __launch_bounds__(kPairBlock) void k_screen_sum1(const InstDev *__res
     const bool live = oneshot || !h.done;
     const int it = mode == 2 ? h.iter + 1 : 0;
     const bool screen = live && M > 0 && (oneshot || it < h.max_iter);
-    if (live && j0 < 2) (j0 == 0 ? pe2 : pn2)[b.y] = ae;
+    if (en && live && j0 < 2) (j0 == 0 ? pe2 : pn2)[b.y] = ae;
     if (!screen) return;
     if (j0 < M) pg2[(size_t)b.y * M + j0] = ag;
-    for (int j = j0 + kPairBlock; j < M; j += kPairBlock)
+    for (int j = j0 + (int)gridDim.y * kPairBlock; j < M; j += (int)gridDim.y * kPairBlock)
         pg2[(size_t)b.y * M + j] = group_sum(gptr(pg) + (size_t)t0 * M + j, (size_t)M);
 }
 
@@ -2469,7 +2472,13 @@ static void launch_all(int which, int R, const InstDev *insts, const int2 *blk, 
         break;
     }
     case 1: GOCP_LAUNCH(k_screen_reduce, nblk, kPairBlock, insts, blk, mode); break;
-    case 7: GOCP_LAUNCH(k_screen_sum1, nblk, kPairBlock, insts, blk, mode); break;
+    case 7: {
+        // j: the operator column blocks (at least one)
+        const dim3 grid(nblk, std::max(1, j));
+        if (t0 || t1) hipExtLaunchKernelGGL(k_screen_sum1, grid, dim3(kPairBlock), 0, s, t0, t1, 0, insts, blk, mode);
+        else hipLaunchKernelGGL(k_screen_sum1, grid, dim3(kPairBlock), 0, s, insts, blk, mode);
+        break;
+    }
     case 2: GOCP_LAUNCH(k_line_vw<T>, nblk, kPairBlock, insts, blk); break;
     case 4:
         if (mode) GOCP_LAUNCH((k_taylor5<T, true>), nblk, kPairBlock, insts, blk, j, th, ns);

@@ -47,9 +47,12 @@ void launch_layer_adj(int dtype, const void *phi, double2 *lam, double *partial,
                       const AdaptState *st, hipStream_t s);
 
 // R = amplitudes per lane of the tile kernels (1, 2 or 4); the pair kernels ignore it.
+// For K_SCREEN_SUM1, j is the number of operator column blocks of kPairBlock
+// (sum1_blocks; 0 or 1: one block, whose threads loop over further columns).
 // t0 / t1, when set, take the dispatch's own start / end timestamps
 // (hipExtLaunchKernel), so the span between them holds the kernel alone and not
 // the queue's launch latency; with no rows to launch they are recorded at once.
+inline int sum1_blocks(int M) { return M > kPairBlock ? (M + kPairBlock - 1) / kPairBlock : 1; }
 void launch_kernel(int which, int dtype, int R, const InstDev *insts, const int2 *blk, int nblk, int mode,
                    hipStream_t s, int j = 0, double th = 0.0, int ns = 0, hipEvent_t t0 = nullptr,
                    hipEvent_t t1 = nullptr);
