@@ -1091,7 +1091,21 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                         pn = Amp<T>::raw_at(I.psi, doff ^ ((uint32_t)uni((int)S.cls[o + 1].x) << Amp<T>::kShift));
                     const double2 a = Amp<T>::cvt(pc);
                     const double q = sg[0].x * a.x + sg[0].y * a.y;
-                    for (int t = s0; t < s1; ++t) push(t, q * signed_cz(S.coef[t], zs[t], dz));
+                    // members eight at a time, their masks in one batch of
+                    // scalar loads (reads past s1 stay in the stage and in the
+                    // table's padding, and are not used)
+                    for (int t = s0; t < s1; t += 8) {
+                        uint32_t z[8];
+                        double c[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            z[u] = zs[t + u];
+                            c[u] = S.coef[t + u];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            if (t + u < s1) push(t + u, q * signed_cz(c[u], z[u], dz));
+                    }
                 }
             } else if constexpr (R == 1) {
                 walk_classes_r1<T, 1, kFactPool>(S, zs, o0, o1, sb, d0 < dim ? d0 : 0u, I.psi, nullptr,

@@ -455,9 +455,10 @@ const TableImage &ham_image_locked(const Ham &h) {
 // family order, members in family order), one record {x, s0, s1, count} per
 // class, its members' strings |c|, z | sign << 31 and pool indices packed
 // without padding; LDS stage chunks of at most kStageCls records and
-// kStageTerms - kStrGroup strings, each padded to a multiple of kStrGroup
-// strings; records split over the waves as for the other tables.  Nothing is
-// added for other pools.
+// kStageTerms - 2 kStrGroup strings, each padded to a multiple of kStrGroup
+// strings, and eight zero masks after the last (the walk reads members eight
+// at a time, up to seven past a record's end); records split over the waves as
+// for the other tables.  Nothing is added for other pools.
 void add_xclass_screen(const Pool &p, ImagePacker &pk, DevicePool *d) {
     const int m = p.n_ops();
     if (m == 0) return;
@@ -480,8 +481,9 @@ void add_xclass_screen(const Pool &p, ImagePacker &pk, DevicePool *d) {
     std::vector<int32_t> ch{0};
     for (int c = 0, start = 0, strings = 0; c < nc; ++c) {
         const int n = (int)mem[c].size();
-        if (n > kStageTerms - kStrGroup) throw Error(GOCP_ENOTSUP, "an X class has more operators than one LDS stage holds");
-        if (c - start + 1 > kStageCls || strings + n > kStageTerms - kStrGroup) {
+        if (n > kStageTerms - 2 * kStrGroup)
+            throw Error(GOCP_ENOTSUP, "an X class has more operators than one LDS stage holds");
+        if (c - start + 1 > kStageCls || strings + n > kStageTerms - 2 * kStrGroup) {
             ch.push_back(c);
             start = c;
             strings = 0;
@@ -522,6 +524,7 @@ void add_xclass_screen(const Pool &p, ImagePacker &pk, DevicePool *d) {
         }
         bounds.push_back(make_int4(r0, (int)rec.size(), s0, (int)co.size()));
     }
+    zs.resize(zs.size() + 8, 0u);
     d->xrec = pk.add(rec);
     d->xcoef = pk.add(co);
     d->xzs = pk.add(zs);
