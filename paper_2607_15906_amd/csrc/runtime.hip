@@ -10,6 +10,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "runtime.h"
@@ -466,16 +467,16 @@ void add_xclass_screen(const Pool &p, ImagePacker &pk, DevicePool *d) {
         if (p.op_off[k + 1] - p.op_off[k] != 1) return;
     std::vector<uint32_t> xs;
     std::vector<std::vector<int>> mem;
+    std::unordered_map<uint32_t, int> where;
     for (int r = 0; r < m; ++r) {
         const int j = p.fam_members[r];
         const uint32_t x = p.op_x[j];
-        size_t c = 0;
-        while (c < xs.size() && xs[c] != x) ++c;
-        if (c == xs.size()) {
+        const auto it = where.emplace(x, (int)xs.size()).first;
+        if (it->second == (int)xs.size()) {
             xs.push_back(x);
             mem.emplace_back();
         }
-        mem[c].push_back(j);
+        mem[it->second].push_back(j);
     }
     const int nc = (int)xs.size();
     std::vector<int32_t> ch{0};
