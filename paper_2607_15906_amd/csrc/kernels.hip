@@ -1222,11 +1222,13 @@ __global__ __launch_bounds__(kPairBlock) void k_screen_sum1(const InstDev *__res
 // ahead of the state record's test, and select_state adds them.
 struct SelPre {
     double xe[kGroup], xn[kGroup], xg[kGroup];
+    u32x4 rec;                  // the pool record (pool order) of the thread's first operator
 };
 __device__ __forceinline__ void sel_load(const InstDev &I, SelPre &p) {
     const int M = I.M, ng = I.n_groups;
     const GOCP_AS1 double *pe2 = gptr(I.part_e2), *pn2 = gptr(I.part_n2), *pg2 = gptr(I.part_g2);
     const int jt = (int)threadIdx.x < M ? (int)threadIdx.x : 0;   // M = 0: one allocated column
+    p.rec = ((const GOCP_AS1 u32x4 *)(uintptr_t)I.pop)[jt];
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
         const int t = min(u, ng - 1);
@@ -1244,10 +1246,12 @@ __device__ __forceinline__ void sel_load(const InstDev &I, SelPre &p) {
 // tie band is searched in a second pass over the same sums.  `writer`
 // workgroups also write the record.  pre holds the first batch of the group
 // sums (sel_load); max_iter is the state record's.  Returns the selected
-// operator and whether the run is over, in every thread.
+// operator and whether the run is over, in every thread; with rec_out (LDS),
+// the thread that owns a selected operator below NT also leaves its pool
+// record there (visible after the return).
 template <int NT>
 __device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it, int max_iter, bool writer,
-                             const SelPre &pre, int &jsel, bool &done) {
+                             const SelPre &pre, int &jsel, bool &done, HClass *rec_out = nullptr) {
     __shared__ double red[2][NT / kWave];
     __shared__ int redi[NT / kWave];
     const int lane = threadIdx.x & (kWave - 1);
@@ -1343,6 +1347,8 @@ __device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it,
         if (lane == 0) redi[wv] = jm;
         __syncthreads();
         for (int w = 0; w < NT / kWave; ++w) jmin = min(jmin, redi[w]);
+        if (rec_out && (int)threadIdx.x == (jmin < M ? jmin : 0))
+            *rec_out = HClass{pre.rec.x, (int32_t)pre.rec.y, (int32_t)pre.rec.z, (int32_t)pre.rec.w};
         __syncthreads();
     }
     const double e = e_num / nrm;
@@ -1448,15 +1454,28 @@ __global__ __launch_bounds__(kPairBlock) void k_line_vw(const InstDev *__restric
     // selection of the partials the last k_energy_screen left, done by every
     // workgroup (the same sums in the same order) and recorded by pair block 0,
     // unless a standalone selection already recorded it
+    // (the selecting thread hands the operator's pool record over in LDS, so
+    // it is not loaded after the selection)
+    __shared__ HClass s_rec;
     int j;
+    bool have = false;
     if (h.sel_it == h.pend_it && h.sel_mode == h.pend_mode) {
         j = h.jsel;
     } else {
         bool over;
-        select_state<kPairBlock>(I, st, h.pend_mode, h.pend_it, h.max_iter, b.y == 0, pre, j, over);
+        select_state<kPairBlock>(I, st, h.pend_mode, h.pend_it, h.max_iter, b.y == 0, pre, j, over, &s_rec);
         if (over) return;
+        have = j < kPairBlock && j < I.M;
     }
-    const HClass C = load_rec(cptr(I.pop), j);
+    HClass C;
+    if (have) {
+        C.x = (uint32_t)uni((int)s_rec.x);
+        C.s0 = uni(s_rec.s0);
+        C.s1 = uni(s_rec.s1);
+        C.pad = 0;
+    } else {
+        C = load_rec(cptr(I.pop), j);
+    }
     const uint32_t m = C.x;
     const int hb = 31 - __clz(m);
     const uint32_t half = 1u << (I.n_qubits - 1);
