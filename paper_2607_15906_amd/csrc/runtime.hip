@@ -877,7 +877,7 @@ struct OneShot {
 };
 
 OneShot one_shot(gocp_ctx *ctx, const Ham *h, const Pool *p, const void *psi, int dtype,
-                 double2 *sigma_override = nullptr) {
+                 double2 *sigma_override = nullptr, bool with_state = true) {
     if (!psi) throw Error(GOCP_EINVAL, "null state pointer");
     check_dtype(dtype);
     const int nq = h ? h->n_qubits : p->n_qubits;
@@ -887,12 +887,9 @@ OneShot one_shot(gocp_ctx *ctx, const Ham *h, const Pool *p, const void *psi, in
     o.ip = plan_instance(nq, p ? p->n_ops() : 0, 0, dtype, false, false);
     Bump a;
     a.used = o.ip.bytes;
-    std::vector<int2> bt, bp;
-    for (int t = 0; t < o.ip.n_tiles; ++t) bt.push_back(make_int2(0, t));   // rows (0, g) double as group rows
-    for (int t = 0; t < o.ip.n_pblk; ++t) bp.push_back(make_int2(0, t));
     o.o_desc = a.take(sizeof(InstDev));
-    o.o_btile = a.take(bt.size() * sizeof(int2));
-    o.o_bpair = a.take(bp.size() * sizeof(int2));
+    o.o_btile = a.take((size_t)o.ip.n_tiles * sizeof(int2));
+    o.o_bpair = a.take((size_t)o.ip.n_pblk * sizeof(int2));
     if (ctx->arena_cap < a.used) {
         if (ctx->arena) {
             hip_check(hipStreamSynchronize(ctx->user_stream), "hipStreamSynchronize");
@@ -909,13 +906,18 @@ OneShot one_shot(gocp_ctx *ctx, const Ham *h, const Pool *p, const void *psi, in
     o.base = b;
     hipStream_t s = ctx->user_stream;
     InstDev I = make_desc(ctx->device, o.ip, b, h, p, const_cast<void *>(psi), sigma_override);
-    AdaptState st = make_state(o.ip, b, 0, 0.0, false);
-    hip_check(hipMemcpyAsync(b + o.ip.o_st, &st, sizeof(st), hipMemcpyHostToDevice, s), "H2D");
+    if (with_state) {   // (the Taylor kernels outside ADAPT never read the record)
+        AdaptState st = make_state(o.ip, b, 0, 0.0, false);
+        hip_check(hipMemcpyAsync(b + o.ip.o_st, &st, sizeof(st), hipMemcpyHostToDevice, s), "H2D");
+    }
     // the descriptor and row tables are a function of the key alone and no
     // kernel writes them: a call with the last call's key finds them in place
     const uint64_t kh = h ? h->uid : 0, kp = p ? p->uid : 0;
     if (ctx->shot_dtype != dtype || ctx->shot_h != kh || ctx->shot_p != kp || ctx->shot_psi != psi ||
         ctx->shot_sig != sigma_override) {
+        std::vector<int2> bt, bp;
+        for (int t = 0; t < o.ip.n_tiles; ++t) bt.push_back(make_int2(0, t));   // rows (0, g) double as group rows
+        for (int t = 0; t < o.ip.n_pblk; ++t) bp.push_back(make_int2(0, t));
         hip_check(hipMemcpyAsync(b + o.o_desc, &I, sizeof(I), hipMemcpyHostToDevice, s), "H2D");
         hip_check(hipMemcpyAsync(b + o.o_btile, bt.data(), bt.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
         hip_check(hipMemcpyAsync(b + o.o_bpair, bp.data(), bp.size() * sizeof(int2), hipMemcpyHostToDevice, s), "H2D");
@@ -928,8 +930,8 @@ OneShot one_shot(gocp_ctx *ctx, const Ham *h, const Pool *p, const void *psi, in
     o.desc = reinterpret_cast<InstDev *>(b + o.o_desc);
     o.btile = reinterpret_cast<int2 *>(b + o.o_btile);
     o.bpair = reinterpret_cast<int2 *>(b + o.o_bpair);
-    o.nt = (int)bt.size();
-    o.np = (int)bp.size();
+    o.nt = o.ip.n_tiles;
+    o.np = o.ip.n_pblk;
     o.xform = I.n_xchunks > 0;
     return o;
 }
@@ -1192,7 +1194,7 @@ int taylor5_apply(gocp_ctx *ctx, const gocp_pool *pp, int32_t k, double theta, v
         return GOCP_OK;
     }
     const int ns = std::max(1, (int)std::ceil(std::fabs(theta) * p->op_norm1[k] / 0.5));
-    OneShot o = one_shot(ctx, nullptr, p, psi_dev, dtype);
+    OneShot o = one_shot(ctx, nullptr, p, psi_dev, dtype, nullptr, false);
     launch_kernel(K_TAYLOR, dtype, 1, o.desc, o.bpair, o.np, 0, ctx->user_stream, k, theta, ns);
     launch_kernel(K_NORMALIZE, dtype, 1, o.desc, o.bpair, o.np, 0, ctx->user_stream);
     if (n_substeps_out) *n_substeps_out = ns;
@@ -1236,7 +1238,7 @@ int taylor5_apply_family(gocp_ctx *ctx, const gocp_pool *pp, int32_t n, const in
     if (n_substeps_out)
         for (int i = 0; i < n; ++i) n_substeps_out[i] = fa.ns[i];
     if (!any) return GOCP_OK;
-    OneShot o = one_shot(ctx, nullptr, p, psi_dev, dtype);
+    OneShot o = one_shot(ctx, nullptr, p, psi_dev, dtype, nullptr, false);
     launch_fused(dtype, n, o.desc, o.bpair, o.np, fa, ctx->user_stream);
     launch_kernel(K_NORMALIZE, dtype, 1, o.desc, o.bpair, o.np, 0, ctx->user_stream);
     return GOCP_OK;
