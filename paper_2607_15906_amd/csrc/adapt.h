@@ -85,6 +85,7 @@ struct Group {
     int P = kHvwPartsHi;       // workgroups per tile slot of the compacted H v, H w launch
     bool xf = false;           // R = 1 and every member's pool has an X-class screen
     int scb = 1;               // operator column blocks of the first screen reduction stage
+    bool wide = false;         // some member's pool has more than kPairBlock operators
     std::vector<int> ntile;    // tiles of each member for R
     std::vector<int> ngroup;   // tile groups of each member (first reduction stage)
     int ng = 0;
@@ -163,9 +164,11 @@ struct Group {
         nt = (int)bt.size();
         xf = R == 1 && !inst.empty();
         scb = 1;
+        wide = false;
         for (Instance *in : inst) {
             xf = xf && in->desc.n_xchunks > 0;
             scb = std::max(scb, sum1_blocks(in->ip.M));
+            wide = wide || in->ip.M > kPairBlock;
         }
         np = (int)bp.size();
         na = (int)ba.size();
@@ -241,11 +244,11 @@ struct Group {
             int nrows;
         };
         (void)n;
-        const L seq[5] = {{K_LINE_VW, 1, bpair, np},       {K_LINE_HVW, 1, bhvw, nh},
+        const L seq[5] = {{lv_kid(), 1, bpair, np},        {K_LINE_HVW, 1, bhvw, nh},
                           {K_TAYLOR, 1, bpair, np},        {es_kid(), 2, btile, nt},
                           {K_SCREEN_SUM1, 2, bgrp, ng}};
         for (const L &l : seq) {
-            const bool t = ev && (l.kid == K_ENERGY_SCREEN_X ? K_ENERGY_SCREEN : l.kid) == timed_kid;
+            const bool t = ev && base_kid(l.kid) == timed_kid;
             const hipEvent_t t0 = t ? ev[0] : nullptr, t1 = t ? ev[1] : nullptr;
             if (l.kid == K_LINE_HVW) launch_hvw(l.mode, s, t0, t1);
             else launch_kernel(l.kid, dtype, R, desc, l.rows, l.nrows, l.mode, s, l.kid == K_SCREEN_SUM1 ? scb : 0,
@@ -265,7 +268,7 @@ struct Group {
     // pending partials; selecting them again later writes the same record.
     void select_pending(hipStream_t s) const {
         if (inst.empty()) return;
-        launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, (int)inst.size(), kModePending, s);
+        launch_kernel(sr_kid(), dtype, R, desc, binst, (int)inst.size(), kModePending, s);
     }
 
     void capture() {
@@ -317,13 +320,13 @@ struct Group {
         const int n = (int)inst.size();
         launch_kernel(es_kid(), dtype, R, desc, btile, nt, 3, s);
         launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 3, s, scb);
-        launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, n, 3, s);
+        launch_kernel(sr_kid(), dtype, R, desc, binst, n, 3, s);
         launch_hvw(0, s);
         hip_check(hipEventRecord(e0, s), "hipEventRecord");
         for (int i = 0; i < reps; ++i) {
             launch_kernel(es_kid(), dtype, R, desc, btile, nt, 3, s);
             launch_kernel(K_SCREEN_SUM1, dtype, R, desc, bgrp, ng, 3, s, scb);
-            launch_kernel(K_SCREEN_REDUCE, dtype, R, desc, binst, n, 3, s);
+            launch_kernel(sr_kid(), dtype, R, desc, binst, n, 3, s);
             launch_hvw(0, s);
         }
         hip_check(hipEventRecord(e1, s), "hipEventRecord");
@@ -345,6 +348,9 @@ struct Group {
     // The schedule in the encoding choose_schedule takes.
     // the energy+screen launch of the group
     int es_kid() const { return xf ? K_ENERGY_SCREEN_X : K_ENERGY_SCREEN; }
+    // the selection launches of the group
+    int lv_kid() const { return wide ? K_LINE_VW_W : K_LINE_VW; }
+    int sr_kid() const { return wide ? K_SCREEN_REDUCE_W : K_SCREEN_REDUCE; }
     int schedule_code() const { return R | (P == kHvwPartsHi ? 0 : P << 8); }
     // kHvwPartsLo when the compacted launch would have more than four
     // workgroups per compute unit with kHvwPartsHi (many instances: fewer,
@@ -360,7 +366,7 @@ struct Group {
     void start(const std::vector<int> &members, hipStream_t s) {
         launch_subset(es_kid(), 1, members, 0, s);
         launch_subset(K_SCREEN_SUM1, 1, members, 3, s);
-        launch_subset(K_SCREEN_REDUCE, kModePending, members, 2, s);
+        launch_subset(sr_kid(), kModePending, members, 2, s);
     }
 
     // Scale the states of the given members to unit norm (their renormalisation

@@ -342,7 +342,7 @@ int gocp_batch_time_kernel(gocp_batch *b, int32_t which, int32_t n_launch, doubl
     auto launch = [&]() {
         if (which == 3) {
             launch_kernel(K_SCREEN_SUM1, g.dtype, g.R, g.desc, g.bgrp, g.ng, mode, s, g.scb);
-            launch_kernel(K_SCREEN_REDUCE, g.dtype, g.R, g.desc, g.binst, (int)g.inst.size(), mode, s);
+            launch_kernel(g.sr_kid(), g.dtype, g.R, g.desc, g.binst, (int)g.inst.size(), mode, s);
         } else if (kid == K_LINE_HVW) {
             g.launch_hvw(mode, s);
         } else {

@@ -1248,8 +1248,11 @@ __device__ __forceinline__ void sel_load(const InstDev &I, SelPre &p) {
 // sums (sel_load); max_iter is the state record's.  Returns the selected
 // operator and whether the run is over, in every thread; with rec_out (LDS),
 // the thread that owns a selected operator below NT also leaves its pool
-// record there (visible after the return).
-template <int NT>
+// record there (visible after the return).  Wide (pools of more than NT
+// operators) sums a thread's later operator columns kCols at a time, with
+// their loads in flight together, and keeps all the sums it will test again
+// in registers; the same sums in the same order, so the same results.
+template <int NT, bool Wide = false>
 __device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it, int max_iter, bool writer,
                              const SelPre &pre, int &jsel, bool &done, HClass *rec_out = nullptr) {
     __shared__ double red[2][NT / kWave];
@@ -1306,20 +1309,73 @@ __device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it,
         }
         return a * inv;
     };
+    // the sums of kCols columns (jb, jb + NT, ...; indices clamped into
+    // range, surplus values unused) with all their loads in flight together,
+    // each added over the groups in group order as in grad
+    constexpr int kCols = 2;
+    auto cols = [&](int jb, double (&a)[kCols]) {
+        int jc[kCols];
+#pragma unroll
+        for (int c = 0; c < kCols; ++c) {
+            jc[c] = min(jb + c * NT, M - 1);
+            a[c] = 0.0;
+        }
+        for (int t0 = 0; t0 < ng; t0 += kGroup) {
+            double x[kCols][kGroup];
+#pragma unroll
+            for (int c = 0; c < kCols; ++c)
+#pragma unroll
+                for (int u = 0; u < kGroup; ++u) x[c][u] = pg2[(size_t)min(t0 + u, ng - 1) * M + jc[c]];
+#pragma unroll
+            for (int c = 0; c < kCols; ++c)
+#pragma unroll
+                for (int u = 0; u < kGroup; ++u)
+                    if (t0 + u < ng) a[c] += x[c][u];
+        }
+#pragma unroll
+        for (int c = 0; c < kCols; ++c) a[c] *= inv;
+    };
     double gmax = 0.0, gn = 0.0;
     int jmin = 0x7fffffff;
     if (screen) {
         // a thread's first kCache gradients are kept for the tie-band pass
-        constexpr int kCache = 4;
+        // (Wide: its own column, then kBat batches of kCols columns)
+        constexpr int kBat = 3, kCache = Wide ? 1 + kBat * kCols : 4;
+        const int j0 = threadIdx.x;
         double gc[kCache];
         double amax = 0.0, sq = 0.0;
         GOCP_AS1 double *gout = gmut(cptr(&st->g)[0]);
-        for (int j = threadIdx.x, i = 0; j < M; j += NT, ++i) {
-            const double g = grad(j);
-            if (i < kCache) gc[i] = g;
+        auto take = [&](int j, double g) {
             if (writer && !dry) gout[j] = g;
             amax = fmax(amax, fabs(g));
             sq += g * g;
+        };
+        if constexpr (Wide) {
+            gc[0] = j0 < M ? grad(j0) : 0.0;
+            if (j0 < M) take(j0, gc[0]);
+#pragma unroll
+            for (int bt = 0; bt < kBat; ++bt) {
+                const int c0 = 1 + bt * kCols;
+                double a[kCols];
+                if (c0 * NT < M) {
+                    cols(j0 + c0 * NT, a);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < kCols; ++c) a[c] = 0.0;
+                }
+#pragma unroll
+                for (int c = 0; c < kCols; ++c) {
+                    gc[c0 + c] = a[c];
+                    if (j0 + (c0 + c) * NT < M) take(j0 + (c0 + c) * NT, a[c]);
+                }
+            }
+            for (int j = j0 + kCache * NT; j < M; j += NT) take(j, grad(j));
+        } else {
+            for (int j = j0, i = 0; j < M; j += NT, ++i) {
+                const double g = grad(j);
+                if (i < kCache) gc[i] = g;
+                take(j, g);
+            }
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, kWave));
@@ -1337,11 +1393,23 @@ __device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it,
         // lowest index within the tie band of the largest magnitude
         const double thresh = gmax * (1.0 - 1e-12);
         int jm = 0x7fffffff;
-        for (int j = threadIdx.x, i = 0; j < M; j += NT, ++i)
-            if (fabs(i < kCache ? gc[i] : grad(j)) >= thresh) {
-                jm = j;
-                break;
-            }
+        if constexpr (Wide) {
+#pragma unroll
+            for (int c = kCache - 1; c >= 0; --c)     // the lowest cached match wins
+                if (j0 + c * NT < M && fabs(gc[c]) >= thresh) jm = j0 + c * NT;
+            if (jm == 0x7fffffff)
+                for (int j = j0 + kCache * NT; j < M; j += NT)
+                    if (fabs(grad(j)) >= thresh) {
+                        jm = j;
+                        break;
+                    }
+        } else {
+            for (int j = j0, i = 0; j < M; j += NT, ++i)
+                if (fabs(i < kCache ? gc[i] : grad(j)) >= thresh) {
+                    jm = j;
+                    break;
+                }
+        }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) jm = min(jm, __shfl_xor(jm, off, kWave));
         if (lane == 0) redi[wv] = jm;
@@ -1393,6 +1461,7 @@ __device__ void select_state(const InstDev &I, AdaptState *st, int mode, int it,
 // or kModePending to select the partials the last k_energy_screen of an ADAPT
 // run left (their iteration and mode recorded by it; selecting the same
 // partials again writes the same record).
+template <bool Wide>
 __global__ __launch_bounds__(kPairBlock) void k_screen_reduce(const InstDev *__restrict__ insts,
                                                              const int2 *__restrict__ blk, int mode) {
     const InstDev &I = insts[work_row(blk).x];
@@ -1410,21 +1479,22 @@ __global__ __launch_bounds__(kPairBlock) void k_screen_reduce(const InstDev *__r
     const bool pending = mode == kModePending;
     if (pending) {
         const int m = cptr(&st->pend_mode)[0];
-        select_state<kPairBlock>(I, st, m, it, max_iter, true, pre, j, done);
+        select_state<kPairBlock, Wide>(I, st, m, it, max_iter, true, pre, j, done);
         if (threadIdx.x == 0) {
             st->sel_it = it;
             st->sel_mode = m;
         }
     } else {
-        select_state<kPairBlock>(I, st, mode, it, max_iter, true, pre, j, done);
+        select_state<kPairBlock, Wide>(I, st, mode, it, max_iter, true, pre, j, done);
     }
 }
 
 // ------------------------------------------------------------------ line search vectors
 
-// Selection of the generator (see select_state), then w = A psi and
-// v = -A w on its pairs and the partial dot products Re<v|sigma>, Re<sigma|w>.
-template <typename T>
+// Selection of the generator (see select_state; Wide for pools of more than
+// kPairBlock operators), then w = A psi and v = -A w on its pairs and the
+// partial dot products Re<v|sigma>, Re<sigma|w>.
+template <typename T, bool Wide>
 __global__ __launch_bounds__(kPairBlock) void k_line_vw(const InstDev *__restrict__ insts,
                                                        const int2 *__restrict__ blk) {
     const int2 b = work_row(blk);
@@ -1463,7 +1533,7 @@ __global__ __launch_bounds__(kPairBlock) void k_line_vw(const InstDev *__restric
         j = h.jsel;
     } else {
         bool over;
-        select_state<kPairBlock>(I, st, h.pend_mode, h.pend_it, h.max_iter, b.y == 0, pre, j, over, &s_rec);
+        select_state<kPairBlock, Wide>(I, st, h.pend_mode, h.pend_it, h.max_iter, b.y == 0, pre, j, over, &s_rec);
         if (over) return;
         have = j < kPairBlock && j < I.M;
     }
@@ -2504,7 +2574,8 @@ static void launch_all(int which, int R, const InstDev *insts, const int2 *blk, 
         else launch_tile<T, 1>(w, insts, blk, nblk, mode, s, t0, t1);
         break;
     }
-    case 1: GOCP_LAUNCH(k_screen_reduce, nblk, kPairBlock, insts, blk, mode); break;
+    case 1: GOCP_LAUNCH(k_screen_reduce<false>, nblk, kPairBlock, insts, blk, mode); break;
+    case 9: GOCP_LAUNCH(k_screen_reduce<true>, nblk, kPairBlock, insts, blk, mode); break;
     case 7: {
         // j: the operator column blocks (at least one)
         const dim3 grid(nblk, std::max(1, j));
@@ -2512,7 +2583,8 @@ static void launch_all(int which, int R, const InstDev *insts, const int2 *blk, 
         else hipLaunchKernelGGL(k_screen_sum1, grid, dim3(kPairBlock), 0, s, insts, blk, mode);
         break;
     }
-    case 2: GOCP_LAUNCH(k_line_vw<T>, nblk, kPairBlock, insts, blk); break;
+    case 2: GOCP_LAUNCH((k_line_vw<T, false>), nblk, kPairBlock, insts, blk); break;
+    case 10: GOCP_LAUNCH((k_line_vw<T, true>), nblk, kPairBlock, insts, blk); break;
     case 4:
         if (mode) GOCP_LAUNCH((k_taylor5<T, true>), nblk, kPairBlock, insts, blk, j, th, ns);
         else GOCP_LAUNCH((k_taylor5<T, false>), nblk, kPairBlock, insts, blk, j, th, ns);

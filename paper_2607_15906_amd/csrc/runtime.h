@@ -33,8 +33,19 @@ enum {
     // the energy+screen launch with the X-class screen (members whose pools
     // are single strings with such tables, one amplitude per lane; any other R
     // launches K_ENERGY_SCREEN)
-    K_ENERGY_SCREEN_X = 8
+    K_ENERGY_SCREEN_X = 8,
+    // the selection kernels for pools of more than kPairBlock operators (a
+    // thread sums several operator columns)
+    K_SCREEN_REDUCE_W = 9, K_LINE_VW_W = 10
 };
+
+// The kernel a variant id stands for (timing hooks name the plain ids).
+inline int base_kid(int kid) {
+    return kid == K_ENERGY_SCREEN_X ? K_ENERGY_SCREEN
+           : kid == K_SCREEN_REDUCE_W ? K_SCREEN_REDUCE
+           : kid == K_LINE_VW_W       ? K_LINE_VW
+                                      : kid;
+}
 
 // Re-optimisation layers (one block of kPairBlock pairs per 2 kPairBlock
 // amplitudes): out = T5(x)^ns in for pool generator j; and the backward step

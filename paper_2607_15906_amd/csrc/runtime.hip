@@ -1133,7 +1133,8 @@ int pool_gradients(gocp_ctx *ctx, const gocp_ham *hh, const gocp_pool *pp, const
     launch_kernel(o.xform ? K_ENERGY_SCREEN_X : K_ENERGY_SCREEN, dtype, 1, o.desc, o.btile, o.nt, 0,
                   ctx->user_stream);
     launch_kernel(K_SCREEN_SUM1, dtype, 1, o.desc, o.btile, o.ip.n_groups, 0, ctx->user_stream, sum1_blocks(o.ip.M));
-    launch_kernel(K_SCREEN_REDUCE, dtype, 1, o.desc, o.btile, 1, 0, ctx->user_stream);
+    launch_kernel(o.ip.M > kPairBlock ? K_SCREEN_REDUCE_W : K_SCREEN_REDUCE, dtype, 1, o.desc, o.btile, 1, 0,
+                  ctx->user_stream);
     const size_t gbytes = (size_t)p->n_ops() * sizeof(double);
     if (g_on_device) {
         hip_check(hipMemcpyAsync(g_out, o.base + o.ip.o_g, gbytes, hipMemcpyDeviceToDevice,
@@ -1176,7 +1177,7 @@ int pool_gradients_noalloc(gocp_ctx *ctx, const gocp_ham *hh, const gocp_pool *p
     const InstDev *desc = reinterpret_cast<const InstDev *>(base);
     launch_kernel(I.n_xchunks > 0 ? K_ENERGY_SCREEN_X : K_ENERGY_SCREEN, dtype, 1, desc, nullptr, ip.n_tiles, 0, s);
     launch_kernel(K_SCREEN_SUM1, dtype, 1, desc, nullptr, ip.n_groups, 0, s, sum1_blocks(ip.M));
-    launch_kernel(K_SCREEN_REDUCE, dtype, 1, desc, nullptr, 1, 0, s);
+    launch_kernel(ip.M > kPairBlock ? K_SCREEN_REDUCE_W : K_SCREEN_REDUCE, dtype, 1, desc, nullptr, 1, 0, s);
     return GOCP_OK;
     GOCP_GUARD_END
 }

@@ -76,7 +76,7 @@ def hf_dev(s, nq, dtype):
     return to_dev(psi, dtype)
 
 
-@pytest.mark.parametrize("nq", [4, 8, 12, 14])
+@pytest.mark.parametrize("nq", [4, 8, 12, 14, 16])
 @pytest.mark.parametrize("mapping", ["jw", "bk"])
 def test_pauli_pool_gradients(g, ctx, nq, mapping):
     _say(f"[pauli grad] nq={nq} {mapping}")
@@ -124,6 +124,28 @@ def test_pauli_pool_adapt_matches_oracle(g, ctx, nq, iters, mapping):
     assert o["substeps"] == r["substeps"]
     assert abs(np.vdot(o["psi"], psi_gpu)) ** 2 >= 1 - 1e-12
     assert r["energies"][-1] < r["energies"][0] - 1e-3
+
+
+def test_pauli_pool_wide_selection_16q(g, ctx):
+    """A 16-qubit pool of 2688 operators, more than the selection caches per
+    thread: two ADAPT iterations from a random state (the first selection in
+    the start-up reduction, the second in the line-search launch), each
+    choice a valid one in the oracle, with its max |g| and ||g||."""
+    _say("[pauli wide selection] nq=16 jw")
+    s = system(g, 16, "jw")
+    assert len(s["ops"]) > 7 * 256
+    psi = rand_state(16, 91)
+    d = to_dev(psi)
+    r = g.adapt_solve(ctx, s["gH"], s["gP"], d, 2, grad_tol=0.0, schedule=1)
+    o = adapt_run(s["H"], s["ops"], psi, 2, grad_tol=0.0, forced_ops=r["ops"] + [0], keep_gradients=True)
+    assert len(o["ops"]) == r["n_iter"] == 2
+    for k, j in enumerate(r["ops"]):
+        a = np.abs(o["grads"][k])
+        assert a[j] >= a.max() * (1 - 1e-9), (k, j, a[j], a.max())
+        assert abs(r["gmax"][k] - a.max()) <= 1e-12 * a.max()
+        assert abs(r["gnorms"][k] - np.linalg.norm(a)) <= 1e-12 * np.linalg.norm(a)
+    assert np.abs(np.array(o["energies"]) - r["energies"]).max() <= 1e-10
+    assert np.abs(np.array(o["thetas"]) - r["thetas"]).max() <= 1e-8
 
 
 @pytest.mark.parametrize("schedule", [2, 4])
