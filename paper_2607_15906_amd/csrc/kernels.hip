@@ -279,6 +279,42 @@ __device__ __forceinline__ double wave_sum(double v) {
     return read_lane(v, kWave - 1);
 }
 
+// a + b after exchanging halves (W = 32: lanes 32-63 of a with lanes 0-31 of
+// b, v_permlane32_swap) or odd and even rows (W = 16: v_permlane16_swap):
+// lanes 0-31 (W = 32) or rows 0 and 2 (W = 16) end with the pair sums of a,
+// the others with those of b.
+template <int W>
+__device__ __forceinline__ double swap_add(double a, double b) {
+    const unsigned al = (unsigned)__double2loint(a), ah = (unsigned)__double2hiint(a);
+    const unsigned bl = (unsigned)__double2loint(b), bh = (unsigned)__double2hiint(b);
+    if constexpr (W == 32) {
+        const auto l = __builtin_amdgcn_permlane32_swap(al, bl, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(ah, bh, false, false);
+        return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+    } else {
+        const auto l = __builtin_amdgcn_permlane16_swap(al, bl, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(ah, bh, false, false);
+        return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+    }
+}
+
+// Sums over the 64 lanes of eight values at once: halves of the wave, then
+// rows, then the two halves of each row (row mirror) and the eight lanes of
+// each half-row.  Lane l ends with the sum of v[l >> 3].  Register moves
+// only; every lane of the wave active.
+__device__ __forceinline__ double fold8(const double (&v)[8]) {
+    double w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = swap_add<32>(v[i], v[i + 4]);
+    const double u0 = swap_add<16>(w[0], w[2]), u1 = swap_add<16>(w[1], w[3]);
+    const bool up = threadIdx.x & 8;
+    double t = (up ? u1 : u0) + dpp_f64<0x140>(up ? u0 : u1);   // row_mirror
+    t += dpp_f64<0xB1>(t);          // quad_perm [1,0,3,2]
+    t += dpp_f64<0x4E>(t);          // quad_perm [2,3,0,1]
+    t += dpp_f64<0x141>(t);         // row_half_mirror
+    return t;
+}
+
 __device__ __forceinline__ int wave_id() {
     return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 }
@@ -1093,7 +1129,11 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                     const double q = sg[0].x * a.x + sg[0].y * a.y;
                     // members eight at a time, their masks in one batch of
                     // scalar loads (reads past s1 stay in the stage and in the
-                    // table's padding, and are not used)
+                    // table's padding, and are not used); a full batch of
+                    // eight is summed over the wave in registers (fold8) and
+                    // stored by one lane per operator, a shorter one goes
+                    // through the buffer (emptied first, so that it holds
+                    // consecutive strings)
                     for (int t = s0; t < s1; t += 8) {
                         uint32_t z[8];
                         double c[8];
@@ -1102,9 +1142,19 @@ __global__ __launch_bounds__(kNW *kWave) void k_energy_screen(const InstDev *__r
                             z[u] = zs[t + u];
                             c[u] = S.coef[t + u];
                         }
+                        if (t + 8 <= s1) {
+                            if (nbuf > 0) flush();
+                            double v[8];
 #pragma unroll
-                        for (int u = 0; u < 8; ++u)
-                            if (t + u < s1) push(t + u, q * signed_cz(c[u], z[u], dz));
+                            for (int u = 0; u < 8; ++u) v[u] = q * signed_cz(c[u], z[u], dz);
+                            const double r = fold8(v);
+                            if ((lane & 7) == 0)
+                                gmut(I.part_g)[(size_t)b.y * M + s_xop[t + (lane >> 3)]] = r;
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < 8; ++u)
+                                if (t + u < s1) push(t + u, q * signed_cz(c[u], z[u], dz));
+                        }
                     }
                 }
             } else if constexpr (R == 1) {
