@@ -23,7 +23,11 @@
 // waves inside a workgroup.  Every cross-workgroup sum is formed by a later
 // launch that reads the plain-stored per-workgroup partials in a fixed order
 // (no atomics, no arrival counters, no floating-point atomics), so results are
-// bit-reproducible and do not depend on which instances share a launch.
+// bit-reproducible and do not depend on which instances share a launch (one
+// exception: a pool of single strings is screened by the X-class launch only
+// when every member of the launch has such a pool, and that launch sums a
+// record's members over the wave in another order than the per-operator one,
+// so such a member's gradients can differ in the last bits between the two).
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
