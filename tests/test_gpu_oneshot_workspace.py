@@ -60,3 +60,32 @@ def test_one_shot_workspace_reuse_follows_every_key():
         assert np.abs(p32.cpu().numpy().astype(np.complex128) - ref32).max() <= 1e-6
         del P
         gc.collect()
+
+
+def test_one_shot_taylor_calls_between_state_calls():
+    """Taylor calls upload no state record (their kernels read none); energy
+    and gradient calls around them, with the descriptor of the same key in
+    place or not, still start from a fresh record and follow the oracle."""
+    import paper_2607_15906_amd as g
+    print("[oneshot] Taylor calls between energy and gradient calls", flush=True)
+    ctx = g.Context(0)
+    nq = 10
+    ne = electron_count(nq // 2)
+    h1, eri, ec = molecular_integrals(nq // 2, 5)
+    gH, oH = g.pauli_hamiltonian_load(h1, eri, ec, "jw"), hamiltonian(h1, eri, ec, "jw")
+    P = g.pool_build(nq, ne, "jw")
+    ops = [A for _, _, A in pool_operators(nq, ne, "jw")]
+    rng = np.random.default_rng(21)
+    s = rng.standard_normal(1 << nq) + 1j * rng.standard_normal(1 << nq)
+    s /= np.linalg.norm(s)
+    psi = torch.from_numpy(s.copy()).to("cuda")
+    for j, th in ((5, 0.7), (5, -0.2), (17, 1.3)):
+        for _ in range(2):                         # the second time with every key already in place
+            gg = g.pool_gradients(ctx, gH, P, psi)
+            ref = o_gradients(ops, s, apply_h(oH, s))
+            assert np.abs(gg - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+            e = g.energy(ctx, gH, psi)
+            assert abs(e - o_energy(oH, s)) <= 1e-12 * max(1.0, abs(e))
+        g.taylor5_apply(ctx, P, j, th, psi)
+        s, _ = o_taylor5(ops[j], th, s)
+        assert np.abs(psi.cpu().numpy() - s).max() <= 1e-13
